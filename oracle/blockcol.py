@@ -1,0 +1,103 @@
+"""Block-column-wise Householder BLR-QR (paper Alg. 2 with the operations of
+Section 3.2) and left multiplication by Q / Q^T (Alg. 3).
+
+Step k:
+  1. stack the left-orthogonal row factors of block column k,
+     [A_kk; Av_{k+1,k}; ...; Av_{p,k}] with Av = A (dense) or V^T (low-rank),
+     and take its Householder QR: R_kk, Y_k = [Y_kk; Y_{k+1,k}; ...], T_k
+     (eq. blr_bch_col_qr); Ytilde_ik = Au_ik Y_ik (I or U_ik);
+  2. for every j > k: Z_j = sum_i Ytilde_ik^T A_ij (low-rank accumulation by
+     rounded addition, in order i = k, k+1, ...; dense as soon as one term is
+     dense), W_j = T_k^T Z_j, A_ij -= Ytilde_ik W_j (eq.
+     blr_bch_apply_bc_reflector).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import blrops, dense
+from .blrmat import BLR, DENSE, LOWRANK
+from .factor import Factor
+
+
+class BlockColumnFactor(Factor):
+    def __init__(self, blr: BLR, eps: float, cap: int):
+        super().__init__(blr, eps, cap)
+        self.Tk = {}
+
+    def yrep(self, i, k):
+        if i == k:
+            return ("D", self.Ykk[k])
+        return self.ytilde(i, k)
+
+    def panel(self, k):
+        A, b = self.A, self.b
+        parts = [A.D[(k, k)]]
+        for i in range(k + 1, self.p):
+            parts.append(A.D[(i, k)] if A.fmt[i, k] == DENSE else A.V[(i, k)].T)
+        F, tau, T = dense.householder_qr(np.concatenate(parts, axis=0))
+        Y = dense.unit_lower(F)
+        A.D[(k, k)] = F[:b].copy()
+        self.Ykk[k] = Y[:b].copy()
+        self.Tk[k] = T
+        off = b
+        for i in range(k + 1, self.p):
+            h = parts[i - k].shape[0]
+            Yi = Y[off:off + h].copy()
+            off += h
+            if A.fmt[i, k] == DENSE:
+                A.D[(i, k)] = Yi
+                self.Yfmt[(i, k)] = DENSE
+            else:
+                self.Yl[(i, k)] = Yi
+                A.V.pop((i, k))
+                self.Yfmt[(i, k)] = LOWRANK
+
+    def apply_column(self, k, j):
+        e, c, st = self.eps, self.cap, self.stats
+        Z = None
+        for i in range(k, self.p):
+            term = blrops.yt_times(self.yrep(i, k), self.val(i, j))
+            Z = term if Z is None else blrops.add(Z, term, 1.0, e, c, st)
+        W = blrops.t_times(self.Tk[k], Z, True)
+        for i in range(k, self.p):
+            upd = blrops.y_times(self.yrep(i, k), W)
+            self.store(i, j, blrops.add(self.val(i, j), upd, -1.0, e, c, st))
+
+    def run(self, stop_after_k=None):
+        kend = self.q if stop_after_k is None else min(self.q, stop_after_k)
+        for k in range(kend):
+            self.panel(k)
+            for j in range(k + 1, self.q):
+                self.apply_column(k, j)
+        self.steps_done = kend
+        return self
+
+    def _apply(self, B, k, transpose):
+        b = self.b
+        W = np.zeros((b, B.shape[1]))
+        for i in range(k, self.p):
+            Yr = self.yrep(i, k)
+            Bi = B[i * b:(i + 1) * b]
+            W += Yr[1].T @ Bi if Yr[0] == "D" else Yr[2].T @ (Yr[1].T @ Bi)
+        W = (self.Tk[k].T if transpose else self.Tk[k]) @ W
+        for i in range(k, self.p):
+            B[i * b:(i + 1) * b] -= blrops.dense_of(blrops.y_times(self.yrep(i, k), ("D", W)))
+
+    def apply_qt(self, B: np.ndarray) -> np.ndarray:
+        B = np.array(B, dtype=np.float64, copy=True)
+        for k in range(self.steps_done):
+            self._apply(B, k, True)
+        return B
+
+    def apply_q(self, B: np.ndarray) -> np.ndarray:
+        B = np.array(B, dtype=np.float64, copy=True)
+        for k in range(self.steps_done - 1, -1, -1):
+            self._apply(B, k, False)
+        return B
+
+
+def factor(blr: BLR, eps: float, cap: int, stop_after_k=None,
+           copy: bool = True) -> BlockColumnFactor:
+    f = BlockColumnFactor(blr.copy() if copy else blr, eps, cap)
+    return f.run(stop_after_k)

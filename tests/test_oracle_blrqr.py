@@ -1,0 +1,243 @@
+"""Pins of the oracle's BLR-QR (tiled Alg. 4 / Section 3.3 and block-column
+Alg. 2 / Section 3.2) against dense LAPACK QR, invariants, the paper's Table
+res-acc-random, least-squares optimality and the task/cost model."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import blockcol, blrmat, ledger, metrics, tiled
+from oracle.blrmat import DENSE, LOWRANK
+from oracle.factor import SingularR
+
+U = np.finfo(np.float64).eps
+VARIANTS = [tiled, blockcol]
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def all_dense(A, b):
+    m, n = A.shape
+    return blrmat.compress(A, b, 1e-12, b, np.zeros((m // b, n // b), bool))
+
+
+def kernel_blr(seed, m, n, b, eps, cap, rule="adjacent", kern="log2d", dim=2,
+               overflow="dense"):
+    x, y = synth.kernel_points(seed, m, n, dim)
+    A = blrmat.kernel_matrix(x, y, kern)
+    mask = blrmat.lowrank_mask(x, y, b, rule, m // b, n // b)
+    return A, blrmat.compress(A, b, eps, cap, mask, overflow)
+
+
+# X1: dense special case ------------------------------------------------------
+@pytest.mark.parametrize("mod", VARIANTS)
+@pytest.mark.parametrize("shape", [(8, 8, 2), (16, 8, 4), (48, 24, 8), (64, 64, 16), (96, 32, 16)])
+def test_all_dense_reduces_to_householder_qr(mod, shape):
+    m, n, b = shape
+    A = np.random.default_rng(m * n + b).standard_normal((m, n))
+    f = mod.factor(all_dense(A, b), 1e-12, b)
+    R = f.r_dense()
+    Rl = np.linalg.qr(A, mode="r")
+    kappa = np.linalg.cond(A)
+    assert metrics.r_rel_diff(R, Rl) <= 10 * n * U * kappa
+    assert metrics.res(f, A) <= 10 * n * U
+    assert metrics.orth(f) <= 10 * np.sqrt(n) * U
+
+
+@pytest.mark.parametrize("mod", VARIANTS)
+def test_exact_compression_reduces_to_dense_qr(mod):
+    """eps far below rounding and cap = b: low-rank tiles are exact, so R is
+    the dense R up to row signs."""
+    m, n, b = 128, 64, 16
+    A, blr = kernel_blr(1, m, n, b, 1e-15, b)
+    assert np.any(blr.fmt == LOWRANK)
+    f = mod.factor(blr, 1e-15, b)
+    Rl = np.linalg.qr(A, mode="r")
+    kappa = np.linalg.cond(A)
+    assert metrics.r_rel_diff(f.r_dense(), Rl) <= 1e-13 * kappa
+    assert metrics.res(f, A) <= 1e-13
+
+
+# X2 / X3: invariants -----------------------------------------------------------
+@pytest.mark.parametrize("mod", VARIANTS)
+def test_invariants_kernel_matrix(mod):
+    m, n, b, eps = 256, 128, 32, 1e-8
+    A, blr = kernel_blr(2, m, n, b, eps, 16)
+    At = blr.to_dense()
+    f = mod.factor(blr, eps, 16)
+    assert metrics.res(f, At) <= 10 * eps
+    assert metrics.orth(f) <= 1e3 * U
+    Bm = np.random.default_rng(0).standard_normal((m, 3))
+    assert np.allclose(f.apply_qt(f.apply_q(Bm)), Bm, atol=1e-13)
+    assert np.allclose(f.apply_q(f.apply_qt(Bm)), Bm, atol=1e-13)
+    # every low-rank R tile has an orthonormal basis (X3)
+    for k in range(f.q):
+        for j in range(k + 1, f.q):
+            if f.A.fmt[k, j] == LOWRANK:
+                Uk = f.A.U[(k, j)]
+                assert np.linalg.norm(Uk.T @ Uk - np.eye(Uk.shape[1])) <= 1e3 * U
+    # Q^T A~ is [R; 0]
+    QtA = f.apply_qt(At)
+    assert np.linalg.norm(QtA[n:]) <= 10 * eps * np.linalg.norm(At)
+    assert np.allclose(np.tril(f.r_dense(), -1), 0.0)
+
+
+def test_lowrank_tpqrt_eliminates_exactly():
+    """Section 3.3.3: with U orthonormal, the T of [R; V^T] makes
+    I - [I; U Y] T [I; U Y]^T an orthogonal factor that zeroes U V^T."""
+    from oracle import dense
+    rng = np.random.default_rng(11)
+    b, r = 12, 3
+    R0 = np.triu(rng.standard_normal((b, b)))
+    Uo = np.linalg.qr(rng.standard_normal((b, r)))[0]
+    V = rng.standard_normal((b, r))
+    Rn, Y, tau, T = dense.tpqrt(R0, V.T)
+    Yt = Uo @ Y
+    Vs = np.vstack([np.eye(b), Yt])
+    Q = np.eye(2 * b) - Vs @ T @ Vs.T
+    assert np.allclose(Q.T @ Q, np.eye(2 * b), atol=1e-13)
+    out = Q.T @ np.vstack([R0, Uo @ V.T])
+    assert np.allclose(out[:b], Rn, atol=1e-12)
+    assert np.max(np.abs(out[b:])) <= 1e-12
+
+
+# X4: the paper's Table res-acc-random (order of magnitude) -------------------
+@pytest.mark.slow
+def test_random_blr_matches_table_res_acc_random():
+    gold = json.load(open(os.path.join(HERE, "golden", "table_res_acc_random.json")))
+    row = gold["rows"][0]
+    m, n = row["m"], row["n"]
+    b = int(2 * np.sqrt(n))
+    A = synth.random_blr_dense(0, m, n, b, 1)
+    mask = blrmat.lowrank_mask(None, None, b, "weak", m // b, n // b)
+    blr = blrmat.compress(A, b, 1e-10, b, mask)
+    assert {blr.rank(i, j) for i in range(m // b) for j in range(n // b)} == {-1, 1}
+    ft = tiled.factor(blr, 1e-10, b)
+    fb = blockcol.factor(blr, 1e-10, b)
+    # at least as accurate as the paper's figures (within one order of magnitude)
+    assert metrics.res(ft, A) <= 10 * row["tiled_res"]
+    assert metrics.orth(ft) <= 10 * row["tiled_orth"]
+    assert metrics.res(fb, A) <= 10 * max(row["blocked_res"], 1e-14)
+    assert metrics.orth(fb) <= 10 * max(row["blocked_orth"], 1e-14)
+    # the structure is kept under weak admissibility: no fill-in
+    assert np.array_equal(ft.A.fmt, blr.fmt) and np.array_equal(fb.A.fmt, blr.fmt)
+
+
+# X5: least squares --------------------------------------------------------------
+@pytest.mark.parametrize("mod", VARIANTS)
+def test_lstsq_normal_equations(mod):
+    m, n, b, eps = 192, 96, 16, 1e-8
+    A, blr = kernel_blr(3, m, n, b, eps, 16, kern="inv_r", dim=3, rule="dist_gt_diam")
+    At = blr.to_dense()
+    f = mod.factor(blr, eps, 16)
+    B = synth.rhs(3, m, 4)
+    X = f.lstsq(B)
+    # optimality for the matrix actually factored (Q R)
+    QR = f.q_times_r()
+    assert np.all(metrics.eta_ne(QR, X, B) <= 10 * n * U * 100)
+    Xref = np.linalg.lstsq(At, B, rcond=None)[0]
+    kappa = np.linalg.cond(At)
+    assert np.linalg.norm(X - Xref) / np.linalg.norm(Xref) <= kappa * 10 * eps
+
+
+@pytest.mark.parametrize("mod", VARIANTS)
+def test_singular_r_detected(mod):
+    A = np.random.default_rng(4).standard_normal((32, 16))
+    A[:, 5] = 0.0
+    f = mod.factor(all_dense(A, 8), 1e-12, 8)
+    with pytest.raises(SingularR):
+        f.lstsq(np.ones((32, 1)))
+
+
+# X6: schedule independence ------------------------------------------------------
+def test_any_topological_order_is_bitwise_identical():
+    A, blr = kernel_blr(5, 128, 64, 16, 1e-8, 8)
+    f0 = tiled.factor(blr, 1e-8, 8)
+    for order, seed in [("random", 1), ("random", 2), ("priority", 0)]:
+        f = tiled.factor(blr, 1e-8, 8, order=order, seed=seed)
+        assert np.array_equal(f.r_dense(), f0.r_dense())
+        for key in f0.Tik:
+            assert np.array_equal(f.Tik[key], f0.Tik[key])
+
+
+def test_dag_edges_follow_the_paper():
+    tasks = tiled.task_list(3, 3)
+    deps = tiled.build_dag(tasks)
+    idx = {t: i for i, t in enumerate(tasks)}
+    d = lambda t: {tasks[j] for j in deps[idx[t]]}
+    assert d(("larfb", 0, 1)) == {("geqrt", 0)}
+    assert ("tpqrt", 1, 0) in d(("tpqrt", 2, 0))
+    assert d(("tpmqrt", 2, 0, 1)) >= {("tpqrt", 2, 0), ("tpmqrt", 1, 0, 1)}
+    # LARFB(k,j) and TPQRT(i,k) touch different parts of the diagonal tile
+    assert ("larfb", 0, 1) not in d(("tpqrt", 1, 0))
+    assert d(("geqrt", 1)) == {("tpmqrt", 1, 0, 1)}
+
+
+# X7: task counts and cost model --------------------------------------------------
+def test_task_counts_and_cost_sums():
+    for p, q in [(16, 8), (128, 64), (5, 5)]:
+        tasks = tiled.task_list(p, q)
+        got = {k: sum(1 for t in tasks if t[0] == k) for k in ("geqrt", "larfb", "tpqrt", "tpmqrt")}
+        assert got == ledger.tiled_task_counts(p, q)
+    assert ledger.tiled_task_counts(128, 64) == {"geqrt": 64, "larfb": 2016, "tpqrt": 6112, "tpmqrt": 214368}
+    for (m, n, b, r) in [(2048, 1024, 64, 1), (32768, 16384, 256, 16), (4096, 4096, 128, 7)]:
+        assert ledger.t_blocked_sum(m, n, b, r) == pytest.approx(ledger.t_blocked_printed(m, n, b, r), rel=1e-12)
+        assert ledger.t_tiled_sum(m, n, b, r) == pytest.approx(ledger.t_tiled_closed(m, n, b, r), rel=1e-12)
+    # the printed closed form of T_tiled does not equal its own sum (q = 1:
+    # the sum is p b^3 while the printed form gives p b^3 - 5 b^2 r / 6)
+    assert ledger.t_tiled_printed(256, 128, 128, 4) != pytest.approx(ledger.t_tiled_sum(256, 128, 128, 4))
+
+
+def test_tiled_counts_executed():
+    A, blr = kernel_blr(6, 128, 64, 16, 1e-8, 8)
+    f = tiled.factor(blr, 1e-8, 8)
+    assert f.counts == ledger.tiled_task_counts(8, 4)
+
+
+# X8: the two variants agree -------------------------------------------------------
+def test_variants_agree():
+    m, n, b, eps = 256, 128, 32, 1e-9
+    A, blr = kernel_blr(7, m, n, b, eps, 32, kern="inv_r", dim=3, rule="dist_gt_diam")
+    ft = tiled.factor(blr, eps, 32)
+    fb = blockcol.factor(blr, eps, 32)
+    kappa = np.linalg.cond(A)
+    assert metrics.r_rel_diff(ft.r_dense(), fb.r_dense()) <= 10 * kappa * eps
+
+
+# stop-after-K prefix ----------------------------------------------------------------
+@pytest.mark.parametrize("mod", VARIANTS)
+def test_prefix_factor(mod):
+    A = np.random.default_rng(8).standard_normal((64, 32))
+    blr = all_dense(A, 8)
+    f = mod.factor(blr, 1e-12, 8, stop_after_k=2)
+    QtA = f.apply_qt(A)
+    Rl = np.linalg.qr(A, mode="r")
+    # the first two block columns are triangularised
+    assert np.allclose(np.tril(QtA[:, :16], -1), 0.0, atol=1e-12)
+    assert metrics.r_rel_diff(np.triu(QtA[:16, :16]), Rl[:16, :16]) < 1e-13
+
+
+def test_fill_in_rule_under_strong_admissibility():
+    """OP1: a low-rank target that receives a dense update becomes dense."""
+    m, n, b, eps = 256, 128, 32, 1e-8
+    A, blr = kernel_blr(9, m, n, b, eps, 32, kern="inv_r", dim=3, rule="dist_gt_diam")
+    f = tiled.factor(blr, eps, 32)
+    before, after = blr.fmt, f.A.fmt
+    assert np.all(after <= before)            # formats only go low-rank -> dense
+
+
+# planted mistakes: each plausible slip in the oracle must fail a pin ---------------
+@pytest.mark.parametrize("slip", ["no_transpose", "drop_update", "wrong_sign"])
+def test_planted_mistakes_fail_the_dense_pin(monkeypatch, slip):
+    from oracle import blrops
+    orig_t, orig_add = blrops.t_times, blrops.add
+    if slip == "no_transpose":
+        monkeypatch.setattr(blrops, "t_times", lambda T, X, trans: orig_t(T, X, False))
+    elif slip == "drop_update":
+        monkeypatch.setattr(blrops, "add", lambda X, Y, s, *a: orig_add(X, Y, 0.0 if s < 0 else s, *a))
+    else:
+        monkeypatch.setattr(blrops, "add", lambda X, Y, s, *a: orig_add(X, Y, -s, *a))
+    A = np.random.default_rng(9).standard_normal((48, 24))
+    f = tiled.factor(all_dense(A, 8), 1e-12, 8)
+    assert metrics.r_rel_diff(f.r_dense(), np.linalg.qr(A, mode="r")) > 1e-6
