@@ -1,0 +1,203 @@
+/*
+ * blrqr — Householder QR of Block Low-Rank (BLR) matrices on AMD MI355X (gfx950).
+ *
+ * C ABI of libblrqr.so.  All entry points return a blr_status and never throw
+ * or abort; blr_last_error() gives a thread-local description of the last
+ * failure.  Method: Apriansyah & Yokota, "Parallel QR Factorization of Block
+ * Low-Rank Matrices" (arXiv 2208.06194).
+ *
+ * Storage model.  A BLR matrix A~ (m x n, m >= n) has p x q tiles of size
+ * b x b (p = m/b, q = n/b; b must divide m and n).  Tile (i,j) is dense or
+ * low-rank U V^T with U orthonormal (Section 3.1, eq. blr_matrix_def).  The
+ * handle owns every device buffer (tiles, reflectors, T factors, workspace).
+ * Device pointers passed in are borrowed until the work enqueued on the
+ * given stream completes; the library copies what it keeps.  Calls on one
+ * handle must be serialised by the caller; different handles are independent.
+ *
+ * Errors.  Argument errors are detected synchronously before any work is
+ * enqueued.  A device fault surfaces as BLR_ERR_DEVICE at the next call that
+ * synchronises.  Truncation at the rank cap is not an error: it is counted in
+ * blr_info.
+ */
+#ifndef BLRQR_H
+#define BLRQR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum blr_status {
+  BLR_OK = 0,
+  BLR_ERR_INVALID = 1,   /* bad argument (null, m < n, b does not divide m or n, tol <= 0, ...) */
+  BLR_ERR_STATE = 2,     /* call not valid in the handle's state (e.g. factor twice) */
+  BLR_ERR_OOM = 3,       /* device allocation failed */
+  BLR_ERR_DEVICE = 4,    /* HIP runtime or kernel error (text in blr_last_error) */
+  BLR_ERR_NONFINITE = 5, /* NaN or Inf in the input matrix */
+  BLR_ERR_SINGULAR = 6   /* least squares: some |R_jj| <= n * u * ||R||_F */
+} blr_status;
+
+typedef struct blr_matrix_s* blr_matrix;
+
+/* Source of the matrix for blr_compress. */
+enum { BLR_SRC_KERNEL = 0, BLR_SRC_DENSE = 1 };
+/* Kernel functions: A_ij = f(|x_i - y_j|). */
+enum { BLR_KERNEL_LOG2D = 0 /* -log(d + reg) */, BLR_KERNEL_INV_R = 1 /* 1/(d + reg) */ };
+/* Admissibility rules (Section 3.1).  Diagonal tiles (k,k), k < q, are always dense.
+ * ADJACENT:      dense iff the cluster boxes touch (Euclidean gap 0).
+ * DIST_GT_DIAM:  low-rank iff gap > max(diameter of the two boxes).
+ * WEAK:          every off-diagonal tile is low-rank.
+ * MASK:          caller-supplied p x q mask. */
+enum { BLR_ADM_ADJACENT = 0, BLR_ADM_DIST_GT_DIAM = 1, BLR_ADM_WEAK = 2, BLR_ADM_MASK = 3 };
+/* What compression does with a tile whose eps-rank exceeds max_rank. */
+enum { BLR_OVERFLOW_DENSE = 0, BLR_OVERFLOW_TRUNCATE = 1 };
+/* Factorization variants: tiled (Alg. 4, Section 3.3) and block-column (Alg. 2, Section 3.2). */
+enum { BLR_TILED = 0, BLR_BLOCK_COLUMN = 1 };
+/* Precision: all FP64, or reflector-apply products in FP32 on the matrix
+ * cores (FP32 inputs, FP32 accumulation) with reflector generation, the R
+ * diagonal and every recompression in FP64. */
+enum { BLR_FP64 = 0, BLR_MIXED_FP32 = 1 };
+/* Handle states. */
+enum { BLR_STATE_COMPRESSED = 0, BLR_STATE_FACTORED = 1 };
+
+typedef struct blr_source {
+  int32_t kind;             /* BLR_SRC_KERNEL or BLR_SRC_DENSE */
+  /* KERNEL: device pointers to row points x (m x dim) and column points
+   * y (n x dim), row-major FP64, used in the order given (callers sort them,
+   * e.g. in Morton order, so that consecutive points are close). */
+  const double* x;
+  const double* y;
+  int32_t dim;              /* 2 or 3 */
+  int32_t kernel;           /* BLR_KERNEL_* */
+  double reg;               /* regularisation added to the distance (1e-3) */
+  /* DENSE: device pointer to A, column-major, leading dimension lda >= m. */
+  const double* A;
+  int64_t lda;
+  /* Admissibility (BLR_ADM_*).  ADJACENT and DIST_GT_DIAM need KERNEL. */
+  int32_t admissibility;
+  /* MASK: host array p*q, element i*q + j, nonzero = low-rank. */
+  const int8_t* mask;
+} blr_source;
+
+typedef struct blr_compress_opts {
+  int64_t m, n;             /* matrix size, m >= n >= 1 */
+  int32_t tile;             /* b: 16 <= b <= 1024, multiple of 16, divides m and n */
+  double tol;               /* eps > 0: per-tile ||A~_ij - A_ij||_F <= eps ||A_ij||_F */
+  int32_t max_rank;         /* rank cap, 1 <= max_rank <= min(b, 128) */
+  int32_t overflow;         /* BLR_OVERFLOW_* */
+  uint64_t seed;            /* seed of the random test matrix of the range finder */
+} blr_compress_opts;
+
+typedef struct blr_factor_opts {
+  int32_t variant;          /* BLR_TILED or BLR_BLOCK_COLUMN */
+  int32_t precision;        /* BLR_FP64 or BLR_MIXED_FP32 */
+  int32_t ib;               /* inner block of reflector generation (0 = default 32) */
+  int32_t stop_after_k;     /* debug: factor only block columns 0..K-1 (-1 = all) */
+} blr_factor_opts;
+
+typedef struct blr_info {
+  int64_t m, n;
+  int32_t tile, p, q;
+  int32_t max_rank;         /* truncation cap */
+  int32_t rank_capacity;    /* columns of a low-rank slot (max_rank rounded up to 16) */
+  int32_t state;            /* BLR_STATE_* */
+  int32_t variant, precision, ib;
+  int64_t n_dense, n_lowrank;     /* current tile formats */
+  int64_t n_fill_in;              /* low-rank tiles turned dense by the factorization */
+  int64_t device_bytes;           /* device memory owned by the handle */
+  int64_t compress_overflow;      /* tiles whose eps-rank exceeded max_rank at compression */
+  int64_t factor_overflow;        /* recompressions truncated at the cap during the factor */
+  double max_dropped_rel;         /* largest dropped relative singular-value tail */
+  double flops_factor;            /* algorithmic flops of the last factorization */
+  int64_t kernel_launches;        /* kernels enqueued by the last factorization */
+} blr_info;
+
+/* Host copies of the tile data (blr_import / blr_export).  Every array is
+ * caller-owned and sized for all p*q tiles, tile t = i*q + j:
+ *   fmt   [p*q]          0 = dense, 1 = low-rank
+ *   rank  [p*q]          rank of low-rank tiles (ignored for dense tiles)
+ *   dense [p*q*b*b]      tile t at t*b*b, column-major b x b
+ *   U     [p*q*b*rc]     tile t at t*b*rc, column-major b x rc (first rank columns used)
+ *   V     [p*q*b*rc]     tile t at t*b*rc, column-major b x rc, so A_ij = U V^T
+ * rc = blr_info.rank_capacity.  After the factorization, export also fills
+ *   Y     [p*q*rc*b]     for low-rank tiles below the diagonal: the reflector rows
+ *                        Y_ik (rc x b, column-major), with Ytilde_ik = U_ik Y_ik
+ *   T     [p*q*b*b]      tiled: T of tile (i,k), i >= k;  block column: T_k at tile (k,k)
+ * and dense holds R (upper part of diagonal tiles, tiles right of the
+ * diagonal) and the dense reflector blocks Y (strict lower part of diagonal
+ * tiles, dense tiles below the diagonal).  Pointers may be NULL to skip. */
+typedef struct blr_tiles_host {
+  int8_t* fmt;
+  int32_t* rank;
+  double* dense;
+  double* U;
+  double* V;
+  double* Y;
+  double* T;
+} blr_tiles_host;
+
+/* Compress a kernel or dense matrix into a new BLR handle (Section 3.1:
+ * admissibility, then a truncated SVD of each admissible tile to the
+ * smallest rank meeting the tolerance; U orthonormal, V = W Sigma).
+ * Synchronises the stream (the tile formats are read back to plan the
+ * factorization).  On success *out is a new handle in state COMPRESSED. */
+blr_status blr_compress(const blr_source* src, const blr_compress_opts* opts,
+                        void* hip_stream, blr_matrix* out);
+
+/* Build a handle from host tiles (fmt, rank, dense, U, V of blr_tiles_host).
+ * Only m, n, tile, tol, max_rank of opts are used.  Low-rank U must have
+ * orthonormal columns (the factorization relies on it, Section 3.2.1).
+ * Synchronises the stream. */
+blr_status blr_import(const blr_compress_opts* opts, const blr_tiles_host* tiles,
+                      void* hip_stream, blr_matrix* out);
+
+/* Copy the handle's tiles to host arrays (see blr_tiles_host).  Synchronises. */
+blr_status blr_export(blr_matrix h, blr_tiles_host* tiles);
+
+/* Householder QR of the BLR matrix, in place (tiled: Alg. 4 with the
+ * operations of Section 3.3; block column: Alg. 2 with Section 3.2).
+ * The handle goes from COMPRESSED to FACTORED; a second call returns
+ * BLR_ERR_STATE.  Enqueued on hip_stream (asynchronous). */
+blr_status blr_qr_factor(blr_matrix h, const blr_factor_opts* opts, void* hip_stream);
+
+/* B <- Q^T B (trans = 0) or B <- Q B (trans = 1), replaying the stored
+ * reflectors (Alg. 3 / Alg. 5).  B: device, column-major m x nrhs, ldb >= m,
+ * overwritten.  Requires FACTORED.  Asynchronous. */
+blr_status blr_apply_qt(blr_matrix h, int32_t trans, double* B, int64_t ldb,
+                        int32_t nrhs, void* hip_stream);
+
+/* Least squares X = argmin ||A~ X - B||_F column by column, X = R^{-1}
+ * (Q^T B)[0:n] with tile back-substitution through the BLR factor R.
+ * B: device m x nrhs (ldb >= m), not modified.  X: device n x nrhs
+ * (ldx >= n).  max_refine: reserved, must be 0.  resid_norms: optional
+ * device array of nrhs doubles receiving ||(Q^T B)[n:m]|| per column (the
+ * least-squares residual norm).  Requires FACTORED.  Synchronises the stream
+ * (the singularity check reads the diagonal of R). */
+blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X,
+                           int64_t ldx, int32_t nrhs, int32_t max_refine,
+                           double* resid_norms, void* hip_stream);
+
+/* Shape, formats, state, memory and counters of a handle.  Synchronises. */
+blr_status blr_query(blr_matrix h, blr_info* info);
+
+/* Release the handle and all its device memory (synchronises first). */
+void blr_destroy(blr_matrix h);
+
+const char* blr_status_string(blr_status s);
+const char* blr_last_error(void);
+
+/* Kernel-level timing of the next blr_qr_factor on this handle: when enabled,
+ * HIP events bracket every launch of the dense reflector-apply product (the
+ * dominant kernel) on the stream it is launched on.  After the factor,
+ * blr_profile_read returns the number of such launches, their total device
+ * time in milliseconds and their total algorithmic flops.  Synchronises. */
+blr_status blr_profile_enable(blr_matrix h, int32_t on);
+blr_status blr_profile_read(blr_matrix h, int64_t* launches, double* total_ms,
+                            double* total_flops);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLRQR_H */

@@ -1,0 +1,184 @@
+"""Thin Python binding of libblrqr (include/blrqr.h).
+
+Argument marshalling only: PyTorch supplies device memory and the current
+HIP stream; every step of compression, factorization, Q application and the
+least-squares solve runs in the library's kernels.  Matrices cross the
+boundary in column-major order: an (m, ncols) torch tensor is passed as the
+contiguous (ncols, m) tensor of its transpose.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+class BLRError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def _check(st: int):
+    if st != L.BLR_OK:
+        lib = L.load()
+        raise BLRError(st, f"{lib.blr_status_string(st).decode()}: {lib.blr_last_error().decode()}")
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _colmajor(t: torch.Tensor) -> torch.Tensor:
+    """(m, k) tensor -> contiguous (k, m) tensor holding its column-major image."""
+    if t.dim() == 1:
+        t = t[:, None]
+    return t.t().contiguous()
+
+
+def _ptr(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data
+
+
+class BLRMatrix:
+    """A BLR matrix owned by the library (one handle)."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+
+    def __del__(self):
+        try:
+            if self._h and self._h.value:
+                L.load().blr_destroy(self._h)
+                self._h = ctypes.c_void_p(0)
+        except Exception:
+            pass
+
+    # construction ------------------------------------------------------------
+    @staticmethod
+    def _opts(m, n, tile, tol, max_rank, overflow, seed):
+        return L.CompressOpts(m=m, n=n, tile=tile, tol=tol, max_rank=max_rank,
+                              overflow=L.OVERFLOW[overflow], seed=seed)
+
+    @classmethod
+    def compress_kernel(cls, x: torch.Tensor, y: torch.Tensor, kernel: str, tile: int, tol: float,
+                        max_rank: int, admissibility: str = "dist_gt_diam", overflow: str = "dense",
+                        reg: float = 1e-3, seed: int = 0, mask: np.ndarray | None = None, stream=None):
+        """Compress A_ij = f(|x_i - y_j|) given row/column points on the device."""
+        lib = L.load()
+        x = x.contiguous().to(torch.float64)
+        y = y.contiguous().to(torch.float64)
+        m, dim = x.shape
+        n = y.shape[0]
+        maskc = None if mask is None else np.ascontiguousarray(mask.astype(np.int8))
+        src = L.Source(kind=L.SRC_KERNEL, x=x.data_ptr(), y=y.data_ptr(), dim=dim,
+                       kernel={"log2d": L.KERNEL_LOG2D, "inv_r": L.KERNEL_INV_R}[kernel], reg=reg,
+                       A=None, lda=0, admissibility=L.ADM[admissibility], mask=_ptr(maskc))
+        o = cls._opts(m, n, tile, tol, max_rank, overflow, seed)
+        h = ctypes.c_void_p()
+        _check(lib.blr_compress(ctypes.byref(src), ctypes.byref(o), _stream(stream), ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def compress_dense(cls, A: torch.Tensor, tile: int, tol: float, max_rank: int,
+                       admissibility: str = "weak", mask: np.ndarray | None = None,
+                       overflow: str = "dense", seed: int = 0, stream=None):
+        """Compress a dense (m, n) device matrix (admissibility 'weak' or 'mask')."""
+        lib = L.load()
+        m, n = A.shape
+        Ac = _colmajor(A.to(torch.float64))
+        maskc = None if mask is None else np.ascontiguousarray(mask.astype(np.int8))
+        src = L.Source(kind=L.SRC_DENSE, x=None, y=None, dim=0, kernel=0, reg=0.0,
+                       A=Ac.data_ptr(), lda=m, admissibility=L.ADM[admissibility], mask=_ptr(maskc))
+        o = cls._opts(m, n, tile, tol, max_rank, overflow, seed)
+        h = ctypes.c_void_p()
+        _check(lib.blr_compress(ctypes.byref(src), ctypes.byref(o), _stream(stream), ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def import_tiles(cls, m, n, tile, tol, max_rank, fmt, rank, dense, U, V, stream=None):
+        """Build from host tiles (layout of blr_tiles_host; U and V are b x rc per tile)."""
+        lib = L.load()
+        keep = [np.ascontiguousarray(fmt, dtype=np.int8), np.ascontiguousarray(rank, dtype=np.int32),
+                np.ascontiguousarray(dense, dtype=np.float64), np.ascontiguousarray(U, dtype=np.float64),
+                np.ascontiguousarray(V, dtype=np.float64)]
+        t = L.TilesHost(fmt=_ptr(keep[0]), rank=_ptr(keep[1]), dense=_ptr(keep[2]), U=_ptr(keep[3]),
+                        V=_ptr(keep[4]), Y=None, T=None)
+        o = cls._opts(m, n, tile, tol, max_rank, "dense", 0)
+        h = ctypes.c_void_p()
+        _check(lib.blr_import(ctypes.byref(o), ctypes.byref(t), _stream(stream), ctypes.byref(h)))
+        return cls(h.value)
+
+    # queries -------------------------------------------------------------------
+    def info(self) -> dict:
+        inf = L.Info()
+        _check(L.load().blr_query(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in L.Info._fields_}
+
+    def export(self, with_factor: bool = False) -> dict:
+        inf = self.info()
+        p, q, b, rc = inf["p"], inf["q"], inf["tile"], inf["rank_capacity"]
+        nt = p * q
+        out = {
+            "fmt": np.zeros(nt, np.int8), "rank": np.zeros(nt, np.int32),
+            "dense": np.zeros(nt * b * b), "U": np.zeros(nt * b * rc), "V": np.zeros(nt * b * rc),
+        }
+        if with_factor:
+            out["Y"] = np.zeros(nt * rc * b)
+            out["T"] = np.zeros(nt * b * b)
+        t = L.TilesHost(fmt=_ptr(out["fmt"]), rank=_ptr(out["rank"]), dense=_ptr(out["dense"]),
+                        U=_ptr(out["U"]), V=_ptr(out["V"]), Y=_ptr(out.get("Y")), T=_ptr(out.get("T")))
+        _check(L.load().blr_export(self._h, ctypes.byref(t)))
+        shaped = {
+            "fmt": out["fmt"].reshape(p, q), "rank": out["rank"].reshape(p, q),
+            # tile (i,j): column-major b x b -> stored transposed in C order
+            "dense": out["dense"].reshape(p, q, b, b).transpose(0, 1, 3, 2),
+            "U": out["U"].reshape(p, q, rc, b).transpose(0, 1, 3, 2),
+            "V": out["V"].reshape(p, q, rc, b).transpose(0, 1, 3, 2),
+        }
+        if with_factor:
+            shaped["Y"] = out["Y"].reshape(p, q, b, rc).transpose(0, 1, 3, 2)
+            shaped["T"] = out["T"].reshape(p, q, b, b).transpose(0, 1, 3, 2)
+        shaped["info"] = inf
+        return shaped
+
+    # the hot path ----------------------------------------------------------------
+    def factor(self, variant: str = "tiled", precision: str = "fp64", stop_after_k: int = -1,
+               ib: int = 0, stream=None):
+        o = L.FactorOpts(variant=L.VARIANT[variant], precision=L.PRECISION[precision], ib=ib,
+                         stop_after_k=stop_after_k)
+        _check(L.load().blr_qr_factor(self._h, ctypes.byref(o), _stream(stream)))
+        return self
+
+    def apply_qt(self, B: torch.Tensor, trans: bool = False, stream=None) -> torch.Tensor:
+        """Return Q^T B (trans=False) or Q B (trans=True) for a (m, nrhs) device tensor."""
+        Bc = _colmajor(B.to(torch.float64))
+        nrhs, m = Bc.shape
+        _check(L.load().blr_apply_qt(self._h, 1 if trans else 0, Bc.data_ptr(), m, nrhs, _stream(stream)))
+        return Bc.t()
+
+    def lstsq(self, B: torch.Tensor, with_resid: bool = False, stream=None):
+        """X = argmin ||A X - B||_F for a (m, nrhs) device tensor; returns (n, nrhs)."""
+        inf = self.info()
+        m, n = inf["m"], inf["n"]
+        Bc = _colmajor(B.to(torch.float64))
+        nrhs = Bc.shape[0]
+        Xc = torch.empty((nrhs, n), dtype=torch.float64, device=B.device)
+        res = torch.empty(nrhs, dtype=torch.float64, device=B.device) if with_resid else None
+        _check(L.load().blr_lstsq_solve(self._h, Bc.data_ptr(), m, Xc.data_ptr(), n, nrhs, 0,
+                                        None if res is None else res.data_ptr(), _stream(stream)))
+        X = Xc.t()
+        return (X, torch.sqrt(res)) if with_resid else X
+
+    def profile(self, on: bool = True):
+        _check(L.load().blr_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        n, ms, fl = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        _check(L.load().blr_profile_read(self._h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)))
+        return n.value, ms.value, fl.value

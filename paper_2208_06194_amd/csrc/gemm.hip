@@ -1,0 +1,212 @@
+// Matrix-core GEMM for gfx950: 256 threads = 4 waves in a 2 x 2 grid, each
+// wave owning a (BM/2) x (BN/2) block of 16 x 16 MFMA tiles.  K advances in
+// steps of 16 through LDS (k-major, padded), with the next step prefetched
+// into registers while the matrix cores work on the current one.
+#include "device_common.h"
+#include "gemm.h"
+
+namespace {
+
+template <typename CT>
+struct AccT;
+template <>
+struct AccT<double> {
+  typedef v4d T;
+};
+template <>
+struct AccT<float> {
+  typedef v4f T;
+};
+
+__device__ __forceinline__ v4d mfma_op(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma_op(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ double unit_lower_mask(double x, int64_t row, int64_t col) {
+  return row > col ? x : (row == col ? 1.0 : 0.0);
+}
+
+template <typename CT, int BM, int BN>
+__global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs, int ndesc,
+                                              const GemmSeg* __restrict__ segs) {
+  constexpr int BK = 16;
+  constexpr int PAD = 4;
+  constexpr int AE = BM * BK / 256;
+  constexpr int BE = BN * BK / 256;
+  constexpr int TM = BM / 32;
+  constexpr int TN = BN / 32;
+  typedef typename AccT<CT>::T acc_t;
+
+  __shared__ CT As[BK][BM + PAD];
+  __shared__ CT Bs[BK][BN + PAD];
+
+  const int wg = blockIdx.x;
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].tile_begin <= wg)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const GemmDesc d = descs[lo];
+  const int t = wg - d.tile_begin;
+  const int m0 = (t % d.tilesM) * BM;
+  const int n0 = (t / d.tilesM) * BN;
+  const int M = d.M, N = d.N;
+  if (n0 >= N || m0 >= M) return;
+  if ((d.flags & DESC_LOWER_ONLY) && m0 + BM <= n0) return;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+
+  acc_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
+
+  for (int s = 0; s < d.nseg; ++s) {
+    const GemmSeg sg = segs[d.seg_begin + s];
+    const bool ta = sg.flags & SEG_TRANS_A;
+    const bool tb = sg.flags & SEG_TRANS_B;
+    const bool aul = sg.flags & SEG_A_UNIT_LOWER;
+    const bool bul = sg.flags & SEG_B_UNIT_LOWER;
+    int kbeg = 0, kend = sg.K;
+    if (aul) {
+      if (ta) kbeg = max(kbeg, m0);
+      else kend = min(kend, m0 + BM);
+    }
+    if (sg.flags & SEG_A_UPPER) {
+      if (ta) kend = min(kend, m0 + BM);
+      else kbeg = max(kbeg, m0);
+    }
+    if (bul) {
+      if (tb) kend = min(kend, n0 + BN);
+      else kbeg = max(kbeg, n0);
+    }
+    kbeg = (kbeg / BK) * BK;
+    if (kbeg >= kend) continue;
+
+    const double* __restrict__ Ap = sg.A;
+    const double* __restrict__ Bp = sg.B;
+    const int64_t lda = sg.lda, ldb = sg.ldb;
+
+    CT ra[AE], rb[BE];
+    auto load = [&](int k0) {
+#pragma unroll
+      for (int i = 0; i < AE; ++i) {
+        const int e = tid + 256 * i;
+        const int mm = ta ? e / BK : e % BM;
+        const int kk = ta ? e % BK : e / BM;
+        const int gm = m0 + mm, gk = k0 + kk;
+        double x = 0.0;
+        if (gm < M && gk < kend) {
+          const int64_t row = ta ? gk : gm, col = ta ? gm : gk;
+          x = Ap[row + col * lda];
+          if (aul) x = unit_lower_mask(x, row, col);
+        }
+        ra[i] = (CT)x;
+      }
+#pragma unroll
+      for (int i = 0; i < BE; ++i) {
+        const int e = tid + 256 * i;
+        const int nn = tb ? e % BN : e / BK;
+        const int kk = tb ? e / BN : e % BK;
+        const int gn = n0 + nn, gk = k0 + kk;
+        double x = 0.0;
+        if (gn < N && gk < kend) {
+          const int64_t row = tb ? gn : gk, col = tb ? gk : gn;
+          x = Bp[row + col * ldb];
+          if (bul) x = unit_lower_mask(x, row, col);
+        }
+        rb[i] = (CT)x;
+      }
+    };
+
+    load(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < AE; ++i) {
+        const int e = tid + 256 * i;
+        const int mm = ta ? e / BK : e % BM;
+        const int kk = ta ? e % BK : e / BM;
+        As[kk][mm] = ra[i];
+      }
+#pragma unroll
+      for (int i = 0; i < BE; ++i) {
+        const int e = tid + 256 * i;
+        const int nn = tb ? e % BN : e / BK;
+        const int kk = tb ? e / BN : e % BK;
+        Bs[kk][nn] = rb[i];
+      }
+      __syncthreads();
+      if (k0 + BK < kend) load(k0 + BK);
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        CT af[TM], bf[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) af[i] = As[kk + (lane >> 4)][wm * (BM / 2) + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) bf[j] = Bs[kk + (lane >> 4)][wn * (BN / 2) + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[i][j] = mfma_op(af[i], bf[j], acc[i][j]);
+      }
+    }
+  }
+
+  // epilogue: lane holds column lane%16 of each 16x16 tile; accumulator v is
+  // row 4*(lane/16)+v for the FP32 instruction and row 4*v+lane/16 for the
+  // FP64 instruction (measured layouts of v_mfma_f32/f64_16x16x4 on gfx950)
+  constexpr bool f64out = sizeof(CT) == 8;
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int col = n0 + wn * (BN / 2) + j * 16 + (lane & 15);
+      if (col >= N) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm * (BM / 2) + i * 16 + (f64out ? v * 4 + (lane >> 4) : (lane >> 4) * 4 + v);
+        if (row >= M) continue;
+        const double raw = (double)acc[i][j][v];
+        if (d.C) {
+          double c = d.alpha * raw;
+          if (d.Cin) c += d.beta * d.Cin[row + (int64_t)col * d.ldcin];
+          d.C[row + (int64_t)col * d.ldc] = c;
+        }
+        if (d.D2) d.D2[row + (int64_t)col * d.ldd2] = raw;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_gemm(const GemmDesc* d_descs, int ndesc, const GemmSeg* d_segs, int ntiles,
+                       int big, int fp32, hipStream_t stream) {
+  if (ndesc <= 0 || ntiles <= 0) return hipSuccess;
+  dim3 grid(ntiles), block(256);
+  if (big) {
+    if (fp32)
+      hipLaunchKernelGGL((k_gemm<float, 128, 128>), grid, block, 0, stream, d_descs, ndesc, d_segs);
+    else
+      hipLaunchKernelGGL((k_gemm<double, 128, 128>), grid, block, 0, stream, d_descs, ndesc, d_segs);
+  } else {
+    if (fp32)
+      hipLaunchKernelGGL((k_gemm<float, 64, 64>), grid, block, 0, stream, d_descs, ndesc, d_segs);
+    else
+      hipLaunchKernelGGL((k_gemm<double, 64, 64>), grid, block, 0, stream, d_descs, ndesc, d_segs);
+  }
+  return hipGetLastError();
+}

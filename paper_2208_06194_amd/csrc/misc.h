@@ -1,0 +1,43 @@
+// Element-wise / reduction kernels used by compression and the solve.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+struct TileFillDesc {
+  double* dst;   // b x b tile, ld b
+  int32_t ti, tj;
+};
+struct TileFillParams {
+  int b;
+  int src_dense;        // 1: copy from A; 0: evaluate the kernel from points
+  const double* A;
+  int64_t lda;
+  const double* x;
+  const double* y;
+  int dim;
+  int kernel;           // 0 log2d, 1 inv_r
+  double reg;
+};
+struct Frob2Desc {
+  const double* M;
+  int64_t ld;
+  int32_t rows, cols;
+  double* out;
+};
+struct DiagDesc {
+  const double* R;      // diagonal tile, b x b, ld b
+};
+
+hipError_t launch_fill_tiles(const TileFillDesc* d, int n, const TileFillParams& p, hipStream_t s);
+hipError_t launch_boxes(const double* pts, int npts, int dim, int b, double* lo, double* hi,
+                        hipStream_t s);
+hipError_t launch_gaussian(double* out, int64_t n, unsigned long long seed, unsigned long long stream,
+                           hipStream_t s);
+hipError_t launch_nonfinite(const double* a, int64_t rows, int64_t cols, int64_t ld, int* flag,
+                            hipStream_t s);
+hipError_t launch_frob2(const Frob2Desc* d, int n, hipStream_t s);
+hipError_t launch_trsm_upper(const double* R, int64_t ldr, int n, double* X, int64_t ldx, int nrhs,
+                             hipStream_t s);
+hipError_t launch_diag_absmin(const DiagDesc* d, int n, int b, double* out, hipStream_t s);

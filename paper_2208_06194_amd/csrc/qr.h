@@ -1,0 +1,32 @@
+// Reflector generation kernels (panel factorization, T factor).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+enum { PANEL_GEQRT = 0, PANEL_TPQRT = 1 };
+
+struct PanelArgs {
+  int mode;        // PANEL_GEQRT / PANEL_TPQRT
+  int h;           // rows of the panel (GEQRT: from the pivot row down; TPQRT: rows of B)
+  int ib;          // panel width (16 or 32)
+  double* X;       // panel start (GEQRT: element (c0,c0); TPQRT: B column c0)
+  int64_t ldx;
+  double* R;       // TPQRT: R element (c0,c0)
+  int64_t ldr;
+  double* T;       // T element (c0,c0): receives the IB x IB diagonal block
+  int64_t ldt;
+  double* tau;     // tau[c0 .. c0+ib)
+};
+
+struct TBackArgs {
+  int n;           // order of T
+  int ib;          // diagonal blocks of this size are already filled
+  const double* G; // Gram matrix, lower triangle valid (G[t + r*ldg], t > r)
+  int64_t ldg;
+  const double* tau;
+  double* T;
+  int64_t ldt;
+};
+
+hipError_t launch_panel(const PanelArgs& a, hipStream_t stream);
+hipError_t launch_t_backsolve(const TBackArgs& a, hipStream_t stream);

@@ -1,0 +1,1297 @@
+// Host runtime of libblrqr: the C ABI, device memory, and the launch plans
+// of compression, the tiled BLR-QR (Alg. 4 with Section 3.3 of arXiv
+// 2208.06194), the application of Q / Q^T (Alg. 5) and the least-squares
+// solve.
+//
+// Planning.  Tile formats evolve only through OP1 (a low-rank target that
+// receives a dense update becomes dense), which depends on formats alone, so
+// the host simulates the format evolution once and knows every launch of the
+// factorization before the first one is enqueued.  Ranks change on the device
+// (rounded additions); low-rank slots have a fixed capacity rc (zero padded),
+// so every product has a static shape and the device reads actual ranks only
+// inside the recompression kernel.
+#include "runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+
+namespace {
+thread_local std::string g_last_error;
+
+blr_status fail(blr_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+}  // namespace
+
+namespace blr {
+
+void hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return;
+  if (e == hipErrorOutOfMemory) throw Error(BLR_ERR_OOM, std::string(what) + ": out of device memory");
+  throw Error(BLR_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void* Arena::alloc(size_t n) {
+  if (n == 0) n = 256;
+  n = (n + 255) & ~(size_t)255;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, n);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(BLR_ERR_OOM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+  }
+  blocks.push_back(p);
+  bytes += (int64_t)n;
+  return p;
+}
+
+void Arena::release() {
+  for (void* p : blocks) (void)hipFree(p);
+  blocks.clear();
+  bytes = 0;
+}
+
+void Plan::gemm(double* C, int64_t ldc, const double* Cin, int64_t ldcin, double* D2, int64_t ldd2,
+                int M, int N, double alpha, double beta, const double* A, int64_t lda,
+                const double* B, int64_t ldb, int K, int segflags, int descflags) {
+  if (M <= 0 || N <= 0) return;
+  GemmDesc d{};
+  d.C = C;
+  d.ldc = ldc;
+  d.Cin = Cin;
+  d.ldcin = ldcin;
+  d.D2 = D2;
+  d.ldd2 = ldd2;
+  d.M = M;
+  d.N = N;
+  d.alpha = alpha;
+  d.beta = beta;
+  d.seg_begin = (int)curseg.size();
+  d.nseg = K > 0 ? 1 : 0;
+  d.flags = descflags;
+  if (K > 0) {
+    GemmSeg s{};
+    s.A = A;
+    s.B = B;
+    s.lda = lda;
+    s.ldb = ldb;
+    s.K = K;
+    s.flags = segflags;
+    curseg.push_back(s);
+  }
+  const bool tri = segflags & (SEG_A_UPPER | SEG_A_UNIT_LOWER);
+  curflops += 2.0 * M * N * (double)K * (tri ? 0.5 : 1.0);
+  cur.push_back(d);
+}
+
+void Plan::flush_gemm(int fp32, int prof) {
+  if (cur.empty()) return;
+  int mn = 1 << 30;
+  for (auto& d : cur) mn = std::min(mn, std::min(d.M, d.N));
+  const int big = mn >= 256 ? 1 : 0;
+  const int BM = big ? 128 : 64;
+  Op o;
+  o.kind = Op::GEMM;
+  o.off = (int)descs.size();
+  o.n = (int)cur.size();
+  o.big = big;
+  o.fp32 = fp32;
+  o.prof = prof;
+  o.flops = curflops;
+  const int segbase = (int)segs.size();
+  int tiles = 0;
+  for (auto& d : cur) {
+    d.tilesM = (d.M + BM - 1) / BM;
+    d.tile_begin = tiles;
+    tiles += d.tilesM * ((d.N + BM - 1) / BM);
+    d.seg_begin += segbase;
+    descs.push_back(d);
+  }
+  segs.insert(segs.end(), curseg.begin(), curseg.end());
+  o.ntiles = tiles;
+  ops.push_back(o);
+  cur.clear();
+  curseg.clear();
+  curflops = 0.0;
+}
+
+void Plan::flush_rc() {
+  if (currc.empty()) return;
+  Op o;
+  o.kind = Op::RC;
+  o.off = (int)rcs.size();
+  o.n = (int)currc.size();
+  rcs.insert(rcs.end(), currc.begin(), currc.end());
+  ops.push_back(o);
+  currc.clear();
+}
+
+void Plan::upload(Arena& arena) {
+  if (!descs.empty()) {
+    d_descs = (GemmDesc*)arena.alloc(descs.size() * sizeof(GemmDesc));
+    HIPCHECK(hipMemcpy(d_descs, descs.data(), descs.size() * sizeof(GemmDesc), hipMemcpyHostToDevice));
+  }
+  if (!segs.empty()) {
+    d_segs = (GemmSeg*)arena.alloc(segs.size() * sizeof(GemmSeg));
+    HIPCHECK(hipMemcpy(d_segs, segs.data(), segs.size() * sizeof(GemmSeg), hipMemcpyHostToDevice));
+  }
+  if (!rcs.empty()) {
+    d_rcs = (RcDesc*)arena.alloc(rcs.size() * sizeof(RcDesc));
+    HIPCHECK(hipMemcpy(d_rcs, rcs.data(), rcs.size() * sizeof(RcDesc), hipMemcpyHostToDevice));
+  }
+}
+
+void Plan::clear() { *this = Plan(); }
+
+}  // namespace blr
+
+using namespace blr;
+
+namespace {
+
+int round_up(int x, int a) { return (x + a - 1) / a * a; }
+
+RcParams rc_params(blr_matrix h) {
+  RcParams p;
+  p.b = h->b;
+  p.rc = h->rc;
+  p.cap = h->cap;
+  p.eps = h->tol;
+  p.overflow_count = h->d_counters;
+  p.max_dropped_bits = h->d_counters + 1;
+  return p;
+}
+
+void execute(blr_matrix h, Plan& P, hipStream_t s) {
+  for (const Op& o : P.ops) {
+    switch (o.kind) {
+      case Op::GEMM: {
+        const bool rec = h->prof_on && o.prof;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (rec) {
+          HIPCHECK(hipEventCreate(&e0));
+          HIPCHECK(hipEventCreate(&e1));
+          HIPCHECK(hipEventRecord(e0, s));
+        }
+        HIPCHECK(launch_gemm(P.d_descs + o.off, o.n, P.d_segs, o.ntiles, o.big, o.fp32, s));
+        if (rec) {
+          HIPCHECK(hipEventRecord(e1, s));
+          h->prof_ev.push_back(e0);
+          h->prof_ev.push_back(e1);
+          h->prof_flops += o.flops;
+          h->prof_launches += 1;
+        }
+        break;
+      }
+      case Op::PANEL:
+        HIPCHECK(launch_panel(o.panel, s));
+        break;
+      case Op::TBACK:
+        HIPCHECK(launch_t_backsolve(o.tback, s));
+        break;
+      case Op::RC:
+        HIPCHECK(launch_recompress(P.d_rcs + o.off, o.n, rc_params(h), s));
+        break;
+      default:
+        break;
+    }
+    h->launches += 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Workspace of one factorization / application (single stream: reused by
+// every step, since the ops of consecutive steps are ordered on the stream).
+struct Work {
+  double *Wx, *Wx2, *Wg;                    // panel trailing updates, Gram matrix
+  std::vector<double*> X, X2;               // per column j: b x b
+  std::vector<double*> PU, WU, YWU, M2, Uw; // per j: b x rc
+  std::vector<double*> S, S2, Vtw;          // per j: rc x b
+  std::vector<double*> G, M1;               // per j: rc x rc
+  std::vector<int*> rankw;                  // per j
+  std::vector<double*> rcw;                 // recompression workspaces (2 per j)
+};
+
+Work make_work(blr_matrix h, int nrhs_cols) {
+  Work w;
+  const int b = h->b, rc = h->rc, q = std::max(h->q, 1);
+  const int wcols = std::max(b, nrhs_cols);
+  Arena& A = h->work;
+  w.Wx = (double*)A.alloc((size_t)b * wcols * 8);
+  w.Wx2 = (double*)A.alloc((size_t)b * wcols * 8);
+  w.Wg = (double*)A.alloc((size_t)b * b * 8);
+  double* big = (double*)A.alloc((size_t)2 * q * b * wcols * 8);
+  double* lr = (double*)A.alloc((size_t)q * (5 * (size_t)b * rc + 3 * (size_t)rc * b + 2 * (size_t)rc * rc) * 8);
+  int* rk = (int*)A.alloc((size_t)q * sizeof(int));
+  const size_t rcwd = rc_work_doubles(b, rc);
+  double* rcw = (double*)A.alloc((size_t)2 * q * rcwd * 8);
+  for (int j = 0; j < q; ++j) {
+    w.X.push_back(big + (size_t)(2 * j) * b * wcols);
+    w.X2.push_back(big + (size_t)(2 * j + 1) * b * wcols);
+    double* base = lr + (size_t)j * (5 * (size_t)b * rc + 3 * (size_t)rc * b + 2 * (size_t)rc * rc);
+    w.PU.push_back(base);
+    w.WU.push_back(base + (size_t)b * rc);
+    w.YWU.push_back(base + 2 * (size_t)b * rc);
+    w.M2.push_back(base + 3 * (size_t)b * rc);
+    w.Uw.push_back(base + 4 * (size_t)b * rc);
+    double* b2 = base + 5 * (size_t)b * rc;
+    w.S.push_back(b2);
+    w.S2.push_back(b2 + (size_t)rc * b);
+    w.Vtw.push_back(b2 + 2 * (size_t)rc * b);
+    double* b3 = b2 + 3 * (size_t)rc * b;
+    w.G.push_back(b3);
+    w.M1.push_back(b3 + (size_t)rc * rc);
+    w.rankw.push_back(rk + j);
+    w.rcw.push_back(rcw + (size_t)(2 * j) * rcwd);
+    w.rcw.push_back(rcw + (size_t)(2 * j + 1) * rcwd);
+  }
+  return w;
+}
+
+// Householder QR of one tile (GEQRT, Section 3.3.1) or of [R; B] (TPQRT,
+// Section 3.3.3), with inner blocking ib: a panel kernel generates ib
+// reflectors and their T block, three products update the rest of the tile,
+// and at the end the off-diagonal blocks of the full T come from the Gram
+// matrix of all reflectors.
+void plan_tile_qr(Plan& P, blr_matrix h, Work& w, bool tp, double* X, int64_t ldx, int hb, double* R,
+                  double* T, double* tau) {
+  const int b = h->b;
+  const int rowsh = tp ? hb : b;
+  int ib = (rowsh > 512) ? 16 : 32;
+  if (b % ib) ib = 16;
+  ib = std::min(ib, b);
+  for (int c0 = 0; c0 < b; c0 += ib) {
+    PanelArgs a{};
+    a.mode = tp ? PANEL_TPQRT : PANEL_GEQRT;
+    a.ib = ib;
+    a.T = T + c0 + (int64_t)c0 * b;
+    a.ldt = b;
+    a.tau = tau + c0;
+    if (tp) {
+      a.h = hb;
+      a.X = X + (int64_t)c0 * ldx;
+      a.ldx = ldx;
+      a.R = R + c0 + (int64_t)c0 * b;
+      a.ldr = b;
+    } else {
+      a.h = b - c0;
+      a.X = X + c0 + (int64_t)c0 * ldx;
+      a.ldx = ldx;
+    }
+    if (hb == 0 && tp) {
+      // an empty bottom block: the reflectors are the identity, tau = 0;
+      // the panel kernel still writes T = 0 and tau = 0
+    }
+    P.panel(a);
+    const int nt = b - c0 - ib;
+    if (nt <= 0) continue;
+    const double* Tl = T + c0 + (int64_t)c0 * b;
+    if (!tp) {
+      double* Vl = X + c0 + (int64_t)c0 * ldx;
+      double* C = X + c0 + (int64_t)(c0 + ib) * ldx;
+      P.gemm(w.Wx, ib, nullptr, 0, nullptr, 0, ib, nt, 1.0, 0.0, Vl, ldx, C, ldx, b - c0,
+             SEG_TRANS_A | SEG_A_UNIT_LOWER);
+      P.flush_gemm();
+      P.gemm(w.Wx2, ib, nullptr, 0, nullptr, 0, ib, nt, 1.0, 0.0, Tl, b, w.Wx, ib, ib,
+             SEG_TRANS_A | SEG_A_UPPER);
+      P.flush_gemm();
+      P.gemm(C, ldx, C, ldx, nullptr, 0, b - c0, nt, -1.0, 1.0, Vl, ldx, w.Wx2, ib, ib, SEG_A_UNIT_LOWER);
+      P.flush_gemm();
+    } else {
+      double* Vl = X + (int64_t)c0 * ldx;
+      double* Bt = X + (int64_t)(c0 + ib) * ldx;
+      double* Rr = R + c0 + (int64_t)(c0 + ib) * b;
+      P.gemm(w.Wx, ib, Rr, b, nullptr, 0, ib, nt, 1.0, 1.0, Vl, ldx, Bt, ldx, hb, SEG_TRANS_A);
+      P.flush_gemm();
+      P.gemm(Rr, b, Rr, b, w.Wx2, ib, ib, nt, -1.0, 1.0, Tl, b, w.Wx, ib, ib, SEG_TRANS_A | SEG_A_UPPER);
+      P.flush_gemm();
+      P.gemm(Bt, ldx, Bt, ldx, nullptr, 0, hb, nt, -1.0, 1.0, Vl, ldx, w.Wx2, ib, ib, 0);
+      P.flush_gemm();
+    }
+  }
+  if (b > ib) {
+    if (!tp)
+      P.gemm(w.Wg, b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, X, ldx, X, ldx, b,
+             SEG_TRANS_A | SEG_A_UNIT_LOWER | SEG_B_UNIT_LOWER, DESC_LOWER_ONLY);
+    else
+      P.gemm(w.Wg, b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, X, ldx, X, ldx, hb, SEG_TRANS_A,
+             DESC_LOWER_ONLY);
+    P.flush_gemm();
+    TBackArgs t{};
+    t.n = b;
+    t.ib = ib;
+    t.G = w.Wg;
+    t.ldg = b;
+    t.tau = tau;
+    t.T = T;
+    t.ldt = b;
+    P.tback(t);
+  }
+}
+
+enum Case { C_DDD, C_LDL, C_DLD, C_DLL, C_LLD, C_LLL };
+
+// Tiled BLR-QR plan (Alg. 4, Section 3.3).
+void plan_tiled(blr_matrix h, Plan& P, Work& w, int kend, bool fp32) {
+  const int b = h->b, rc = h->rc, p = h->p, q = h->q;
+  for (int k = 0; k < kend; ++k) {
+    Tile& Dkk = h->t(k, k);
+    double* Tkk = h->T[(size_t)k * q + k];
+    // GEQRT(k)
+    plan_tile_qr(P, h, w, false, Dkk.D, b, b, nullptr, Tkk, h->tau[(size_t)k * q + k]);
+    // LARFB(k, j > k): A_kj <- Qkk^T A_kj (dense tile or U of a low-rank tile)
+    if (k + 1 < q) {
+      for (int j = k + 1; j < q; ++j) {
+        Tile& t = h->t(k, j);
+        const bool d = t.fmt == DENSE;
+        P.gemm(w.X[j], b, nullptr, 0, nullptr, 0, b, d ? b : rc, 1.0, 0.0, Dkk.D, b, d ? t.D : t.U, b, b,
+               SEG_TRANS_A | SEG_A_UNIT_LOWER);
+      }
+      P.flush_gemm(fp32);
+      for (int j = k + 1; j < q; ++j) {
+        const bool d = h->t(k, j).fmt == DENSE;
+        P.gemm(w.X2[j], b, nullptr, 0, nullptr, 0, b, d ? b : rc, 1.0, 0.0, Tkk, b, w.X[j], b, b,
+               SEG_TRANS_A | SEG_A_UPPER);
+      }
+      P.flush_gemm(fp32);
+      for (int j = k + 1; j < q; ++j) {
+        Tile& t = h->t(k, j);
+        const bool d = t.fmt == DENSE;
+        double* C = d ? t.D : t.U;
+        P.gemm(C, b, C, b, nullptr, 0, b, d ? b : rc, -1.0, 1.0, Dkk.D, b, w.X2[j], b, b, SEG_A_UNIT_LOWER);
+      }
+      P.flush_gemm(fp32);
+    }
+    for (int i = k + 1; i < p; ++i) {
+      Tile& Aik = h->t(i, k);
+      const size_t ik = (size_t)i * q + k;
+      double* Tik = h->T[ik];
+      const bool yd = Aik.fmt == DENSE;
+      h->yfmt[ik] = Aik.fmt;
+      // TPQRT(i,k): QR of [R_kk; A_ik] (dense) or [R_kk; V_ik^T] (low-rank)
+      if (yd)
+        plan_tile_qr(P, h, w, true, Aik.D, b, b, Dkk.D, Tik, h->tau[ik]);
+      else
+        plan_tile_qr(P, h, w, true, Aik.Vt, rc, rc, Dkk.D, Tik, h->tau[ik]);
+      if (k + 1 >= q) continue;
+      double* Y = Aik.D;     // dense reflector block
+      double* UY = Aik.U;    // low-rank: Ytilde = UY * Yl
+      double* Yl = Aik.Vt;   // rc x b
+      // classify j, densify targets that OP1 turns dense
+      std::vector<int> cs(q, -1);
+      for (int j = k + 1; j < q; ++j) {
+        Tile& R = h->t(k, j);
+        Tile& A = h->t(i, j);
+        if (yd && R.fmt == LOWRANK && A.fmt == DENSE) {
+          P.gemm(R.D, b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, R.U, b, R.Vt, rc, rc, 0);
+          R.fmt = DENSE;
+          h->n_fill++;
+        }
+        if (yd && R.fmt == DENSE && A.fmt == LOWRANK) {
+          P.gemm(A.D, b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, A.U, b, A.Vt, rc, rc, 0);
+          A.fmt = DENSE;
+          h->n_fill++;
+        }
+        const bool rd = R.fmt == DENSE, ad = A.fmt == DENSE;
+        if (yd) cs[j] = (rd && ad) ? C_DDD : C_LDL;  // remaining dense-Y case has R and A low-rank
+        else cs[j] = rd ? (ad ? C_DLD : C_DLL) : (ad ? C_LLD : C_LLL);
+      }
+      P.flush_gemm();
+      // S1: pre-products
+      for (int j = k + 1; j < q; ++j) {
+        Tile& A = h->t(i, j);
+        switch (cs[j]) {
+          case C_LDL:
+            P.gemm(w.PU[j], b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, Y, b, A.U, b, b, SEG_TRANS_A);
+            break;
+          case C_DLD:
+          case C_LLD:
+            P.gemm(w.S[j], rc, nullptr, 0, nullptr, 0, rc, b, 1.0, 0.0, UY, b, A.D, b, b, SEG_TRANS_A);
+            break;
+          case C_DLL:
+          case C_LLL:
+            P.gemm(w.G[j], rc, nullptr, 0, nullptr, 0, rc, rc, 1.0, 0.0, UY, b, A.U, b, b, SEG_TRANS_A);
+            break;
+          default:
+            break;
+        }
+      }
+      P.flush_gemm();
+      for (int j = k + 1; j < q; ++j)
+        if (cs[j] == C_DLL || cs[j] == C_LLL)
+          P.gemm(w.PU[j], b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, Yl, rc, w.G[j], rc, rc, SEG_TRANS_A);
+      P.flush_gemm();
+      // S2: dense W0 = R + Ytilde^T A into X_j
+      for (int j = k + 1; j < q; ++j) {
+        Tile& R = h->t(k, j);
+        Tile& A = h->t(i, j);
+        if (cs[j] == C_DDD)
+          P.gemm(w.X[j], b, R.D, b, nullptr, 0, b, b, 1.0, 1.0, Y, b, A.D, b, b, SEG_TRANS_A);
+        else if (cs[j] == C_DLD)
+          P.gemm(w.X[j], b, R.D, b, nullptr, 0, b, b, 1.0, 1.0, Yl, rc, w.S[j], rc, rc, SEG_TRANS_A);
+        else if (cs[j] == C_DLL)
+          P.gemm(w.X[j], b, R.D, b, nullptr, 0, b, b, 1.0, 1.0, w.PU[j], b, A.Vt, rc, rc, 0);
+      }
+      P.flush_gemm(fp32, 1);
+      // RC1: low-rank W0 = R + Ytilde^T A (rounded addition)
+      for (int j = k + 1; j < q; ++j) {
+        Tile& R = h->t(k, j);
+        Tile& A = h->t(i, j);
+        if (cs[j] != C_LDL && cs[j] != C_LLD && cs[j] != C_LLL) continue;
+        RcDesc d{};
+        d.nterm = 2;
+        d.t[0] = RcTerm{R.U, R.Vt, R.rank, b, rc, 0, 0, 1.0};
+        if (cs[j] == C_LLD)
+          d.t[1] = RcTerm{Yl, w.S[j], Aik.rank, rc, rc, 0, 1, 1.0};
+        else
+          d.t[1] = RcTerm{w.PU[j], A.Vt, A.rank, b, rc, 0, 0, 1.0};
+        d.Uout = w.Uw[j];
+        d.Vtout = w.Vtw[j];
+        d.rank_out = w.rankw[j];
+        d.work = w.rcw[2 * j];
+        P.rc(d);
+      }
+      P.flush_rc();
+      // S3: W = T^T W0; dense: R -= W (W kept in X2_j); low-rank: WU = T^T Uw
+      for (int j = k + 1; j < q; ++j) {
+        Tile& R = h->t(k, j);
+        if (cs[j] == C_DDD || cs[j] == C_DLD || cs[j] == C_DLL)
+          P.gemm(R.D, b, R.D, b, w.X2[j], b, b, b, -1.0, 1.0, Tik, b, w.X[j], b, b, SEG_TRANS_A | SEG_A_UPPER);
+        else
+          P.gemm(w.WU[j], b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, Tik, b, w.Uw[j], b, b,
+                 SEG_TRANS_A | SEG_A_UPPER);
+      }
+      P.flush_gemm(fp32, 1);
+      // S4a
+      for (int j = k + 1; j < q; ++j) {
+        Tile& A = h->t(i, j);
+        switch (cs[j]) {
+          case C_DDD:
+            P.gemm(A.D, b, A.D, b, nullptr, 0, b, b, -1.0, 1.0, Y, b, w.X2[j], b, b, 0);
+            break;
+          case C_DLD:
+          case C_DLL:
+            P.gemm(w.S2[j], rc, nullptr, 0, nullptr, 0, rc, b, 1.0, 0.0, Yl, rc, w.X2[j], b, b, 0);
+            break;
+          case C_LDL:
+            P.gemm(w.YWU[j], b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, Y, b, w.WU[j], b, b, 0);
+            break;
+          case C_LLD:
+          case C_LLL:
+            P.gemm(w.M1[j], rc, nullptr, 0, nullptr, 0, rc, rc, 1.0, 0.0, Yl, rc, w.WU[j], b, b, 0);
+            break;
+        }
+      }
+      P.flush_gemm(fp32, 1);
+      // S4b
+      for (int j = k + 1; j < q; ++j) {
+        Tile& A = h->t(i, j);
+        if (cs[j] == C_DLD)
+          P.gemm(A.D, b, A.D, b, nullptr, 0, b, b, -1.0, 1.0, UY, b, w.S2[j], rc, rc, 0);
+        else if (cs[j] == C_LLD || cs[j] == C_LLL)
+          P.gemm(w.M2[j], b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, UY, b, w.M1[j], rc, rc, 0);
+      }
+      P.flush_gemm();
+      // S4c
+      for (int j = k + 1; j < q; ++j) {
+        Tile& A = h->t(i, j);
+        if (cs[j] == C_LLD)
+          P.gemm(A.D, b, A.D, b, nullptr, 0, b, b, -1.0, 1.0, w.M2[j], b, w.Vtw[j], rc, rc, 0);
+      }
+      P.flush_gemm();
+      // RC2: low-rank targets R_kj -= W, A_ij -= Ytilde W
+      for (int j = k + 1; j < q; ++j) {
+        Tile& R = h->t(k, j);
+        Tile& A = h->t(i, j);
+        const int c = cs[j];
+        if (c == C_LDL || c == C_LLD || c == C_LLL) {
+          RcDesc d{};
+          d.nterm = 2;
+          d.t[0] = RcTerm{R.U, R.Vt, R.rank, b, rc, 0, 0, 1.0};
+          d.t[1] = RcTerm{w.WU[j], w.Vtw[j], w.rankw[j], b, rc, 0, 0, -1.0};
+          d.Uout = R.U;
+          d.Vtout = R.Vt;
+          d.rank_out = R.rank;
+          d.work = w.rcw[2 * j];
+          P.rc(d);
+        }
+        if (c == C_DLL || c == C_LDL || c == C_LLL) {
+          RcDesc d{};
+          d.nterm = 2;
+          d.t[0] = RcTerm{A.U, A.Vt, A.rank, b, rc, 0, 0, 1.0};
+          if (c == C_DLL)
+            d.t[1] = RcTerm{UY, w.S2[j], Aik.rank, b, rc, 0, 0, -1.0};
+          else if (c == C_LDL)
+            d.t[1] = RcTerm{w.YWU[j], w.Vtw[j], w.rankw[j], b, rc, 0, 0, -1.0};
+          else
+            d.t[1] = RcTerm{w.M2[j], w.Vtw[j], w.rankw[j], b, rc, 0, 0, -1.0};
+          d.Uout = A.U;
+          d.Vtout = A.Vt;
+          d.rank_out = A.rank;
+          d.work = w.rcw[2 * j + 1];
+          P.rc(d);
+        }
+      }
+      P.flush_rc();
+    }
+  }
+}
+
+// B <- Q^T B (trans = 0) or Q B (trans = 1) for the tiled factor (Alg. 5,
+// update read as C <- (I - [I; Y] T [I; Y]^T) C).
+void plan_apply_tiled(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, int nrhs, int trans) {
+  const int b = h->b, rc = h->rc, p = h->p, q = h->q;
+  const int K = h->steps_done;
+  auto diag = [&](int k) {
+    Tile& Dkk = h->t(k, k);
+    double* Tkk = h->T[(size_t)k * q + k];
+    double* Bk = B + (int64_t)k * b;
+    P.gemm(w.Wx, b, nullptr, 0, nullptr, 0, b, nrhs, 1.0, 0.0, Dkk.D, b, Bk, ldb, b,
+           SEG_TRANS_A | SEG_A_UNIT_LOWER);
+    P.flush_gemm();
+    P.gemm(w.Wx2, b, nullptr, 0, nullptr, 0, b, nrhs, 1.0, 0.0, Tkk, b, w.Wx, b, b,
+           (trans ? 0 : SEG_TRANS_A) | SEG_A_UPPER);
+    P.flush_gemm();
+    P.gemm(Bk, ldb, Bk, ldb, nullptr, 0, b, nrhs, -1.0, 1.0, Dkk.D, b, w.Wx2, b, b, SEG_A_UNIT_LOWER);
+    P.flush_gemm();
+  };
+  auto pair = [&](int i, int k) {
+    Tile& Aik = h->t(i, k);
+    const size_t ik = (size_t)i * q + k;
+    const bool yd = h->yfmt[ik] == DENSE;
+    double* Bk = B + (int64_t)k * b;
+    double* Bi = B + (int64_t)i * b;
+    double* Xs = w.X[0];    // rc x nrhs scratch
+    if (yd) {
+      P.gemm(w.Wx, b, Bk, ldb, nullptr, 0, b, nrhs, 1.0, 1.0, Aik.D, b, Bi, ldb, b, SEG_TRANS_A);
+      P.flush_gemm();
+    } else {
+      P.gemm(Xs, rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, Aik.U, b, Bi, ldb, b, SEG_TRANS_A);
+      P.flush_gemm();
+      P.gemm(w.Wx, b, Bk, ldb, nullptr, 0, b, nrhs, 1.0, 1.0, Aik.Vt, rc, Xs, rc, rc, SEG_TRANS_A);
+      P.flush_gemm();
+    }
+    P.gemm(Bk, ldb, Bk, ldb, w.Wx2, b, b, nrhs, -1.0, 1.0, h->T[ik], b, w.Wx, b, b,
+           (trans ? 0 : SEG_TRANS_A) | SEG_A_UPPER);
+    P.flush_gemm();
+    if (yd) {
+      P.gemm(Bi, ldb, Bi, ldb, nullptr, 0, b, nrhs, -1.0, 1.0, Aik.D, b, w.Wx2, b, b, 0);
+      P.flush_gemm();
+    } else {
+      P.gemm(Xs, rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, Aik.Vt, rc, w.Wx2, b, b, 0);
+      P.flush_gemm();
+      P.gemm(Bi, ldb, Bi, ldb, nullptr, 0, b, nrhs, -1.0, 1.0, Aik.U, b, Xs, rc, rc, 0);
+      P.flush_gemm();
+    }
+  };
+  if (!trans) {
+    for (int k = 0; k < K; ++k) {
+      diag(k);
+      for (int i = k + 1; i < p; ++i) pair(i, k);
+    }
+  } else {
+    for (int k = K - 1; k >= 0; --k) {
+      for (int i = p - 1; i > k; --i) pair(i, k);
+      diag(k);
+    }
+  }
+}
+
+hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+blr_status run_guarded(const std::function<void()>& f) {
+  try {
+    f();
+    return BLR_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return BLR_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return BLR_ERR_DEVICE;
+  }
+}
+
+void alloc_common(blr_matrix h) {
+  const size_t nt = (size_t)h->p * h->q;
+  h->tiles.assign(nt, Tile());
+  h->yfmt.assign(nt, DENSE);
+  h->T.assign(nt, nullptr);
+  h->tau.assign(nt, nullptr);
+  h->d_rank = (int*)h->mem.alloc(nt * sizeof(int));
+  HIPCHECK(hipMemset(h->d_rank, 0, nt * sizeof(int)));
+  h->d_counters = (unsigned long long*)h->mem.alloc(4 * sizeof(unsigned long long));
+  HIPCHECK(hipMemset(h->d_counters, 0, 4 * sizeof(unsigned long long)));
+  for (size_t t = 0; t < nt; ++t) h->tiles[t].rank = h->d_rank + t;
+}
+
+// Allocate low-rank slots for the given tiles (one pool).
+void alloc_lowrank(blr_matrix h, const std::vector<int>& idx) {
+  if (idx.empty()) return;
+  const size_t per = 2 * (size_t)h->b * h->rc;
+  double* pool = (double*)h->mem.alloc(idx.size() * per * 8);
+  HIPCHECK(hipMemset(pool, 0, idx.size() * per * 8));
+  for (size_t a = 0; a < idx.size(); ++a) {
+    Tile& t = h->tiles[idx[a]];
+    t.U = pool + a * per;
+    t.Vt = t.U + (size_t)h->b * h->rc;
+  }
+}
+
+void alloc_dense(blr_matrix h, const std::vector<int>& idx) {
+  if (idx.empty()) return;
+  const size_t per = (size_t)h->b * h->b;
+  double* pool = (double*)h->mem.alloc(idx.size() * per * 8);
+  for (size_t a = 0; a < idx.size(); ++a) h->tiles[idx[a]].D = pool + a * per;
+}
+
+blr_status validate_opts(const blr_compress_opts* o) {
+  if (!o) return fail(BLR_ERR_INVALID, "opts is NULL");
+  if (o->m < 1 || o->n < 1 || o->m < o->n) return fail(BLR_ERR_INVALID, "need m >= n >= 1");
+  if (o->tile < 16 || o->tile > 1024 || o->tile % 16)
+    return fail(BLR_ERR_INVALID, "tile must be a multiple of 16 in [16, 1024]");
+  if (o->m % o->tile || o->n % o->tile) return fail(BLR_ERR_INVALID, "tile must divide m and n");
+  if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return fail(BLR_ERR_INVALID, "tol must be > 0");
+  if (o->max_rank < 1 || o->max_rank > o->tile || o->max_rank > 128)
+    return fail(BLR_ERR_INVALID, "max_rank must be in [1, min(tile, 128)]");
+  if (o->overflow != BLR_OVERFLOW_DENSE && o->overflow != BLR_OVERFLOW_TRUNCATE)
+    return fail(BLR_ERR_INVALID, "bad overflow policy");
+  if (o->m / o->tile > 1 << 15 || o->n / o->tile > 1 << 15) return fail(BLR_ERR_INVALID, "too many tiles");
+  return BLR_OK;
+}
+
+blr_matrix new_handle(const blr_compress_opts* o) {
+  blr_matrix h = new blr_matrix_s();
+  h->m = o->m;
+  h->n = o->n;
+  h->b = o->tile;
+  h->p = (int)(o->m / o->tile);
+  h->q = (int)(o->n / o->tile);
+  h->cap = o->max_rank;
+  h->rc = std::min(round_up(o->max_rank, 16), o->tile);
+  h->tol = o->tol;
+  h->overflow = o->overflow;
+  return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* blr_status_string(blr_status s) {
+  switch (s) {
+    case BLR_OK: return "ok";
+    case BLR_ERR_INVALID: return "invalid argument";
+    case BLR_ERR_STATE: return "invalid state";
+    case BLR_ERR_OOM: return "out of memory";
+    case BLR_ERR_DEVICE: return "device error";
+    case BLR_ERR_NONFINITE: return "non-finite input";
+    case BLR_ERR_SINGULAR: return "singular R";
+  }
+  return "unknown status";
+}
+
+const char* blr_last_error(void) { return g_last_error.c_str(); }
+
+blr_status blr_compress(const blr_source* src, const blr_compress_opts* o, void* stream, blr_matrix* out) {
+  if (!src || !out) return fail(BLR_ERR_INVALID, "NULL argument");
+  blr_status st = validate_opts(o);
+  if (st != BLR_OK) return st;
+  *out = nullptr;
+  const bool kern = src->kind == BLR_SRC_KERNEL;
+  if (kern) {
+    if (!src->x || !src->y) return fail(BLR_ERR_INVALID, "kernel source needs x and y");
+    if (src->dim < 1 || src->dim > 3) return fail(BLR_ERR_INVALID, "dim must be 1, 2 or 3");
+    if (src->kernel != BLR_KERNEL_LOG2D && src->kernel != BLR_KERNEL_INV_R)
+      return fail(BLR_ERR_INVALID, "bad kernel");
+  } else if (src->kind == BLR_SRC_DENSE) {
+    if (!src->A || src->lda < o->m) return fail(BLR_ERR_INVALID, "dense source needs A and lda >= m");
+    if (src->admissibility == BLR_ADM_ADJACENT || src->admissibility == BLR_ADM_DIST_GT_DIAM)
+      return fail(BLR_ERR_INVALID, "geometric admissibility needs a kernel source");
+  } else {
+    return fail(BLR_ERR_INVALID, "bad source kind");
+  }
+  if (src->admissibility < 0 || src->admissibility > BLR_ADM_MASK)
+    return fail(BLR_ERR_INVALID, "bad admissibility");
+  if (src->admissibility == BLR_ADM_MASK && !src->mask) return fail(BLR_ERR_INVALID, "mask is NULL");
+  blr_matrix h = new_handle(o);
+  hipStream_t s = as_stream(stream);
+  st = run_guarded([&] {
+    alloc_common(h);
+    const int b = h->b, p = h->p, q = h->q, rc = h->rc;
+    // finiteness of the input
+    int* flag = (int*)h->work.alloc(sizeof(int));
+    HIPCHECK(hipMemsetAsync(flag, 0, sizeof(int), s));
+    if (kern) {
+      HIPCHECK(launch_nonfinite(src->x, h->m * src->dim, 1, h->m * src->dim, flag, s));
+      HIPCHECK(launch_nonfinite(src->y, h->n * src->dim, 1, h->n * src->dim, flag, s));
+    } else {
+      HIPCHECK(launch_nonfinite(src->A, h->m, h->n, src->lda, flag, s));
+    }
+    int hflag = 0;
+    HIPCHECK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    if (hflag) throw Error(BLR_ERR_NONFINITE, "input contains NaN or Inf");
+    // admissibility mask (true = low-rank)
+    std::vector<int8_t> lr((size_t)p * q, 0);
+    if (src->admissibility == BLR_ADM_WEAK) {
+      std::fill(lr.begin(), lr.end(), 1);
+    } else if (src->admissibility == BLR_ADM_MASK) {
+      for (size_t t = 0; t < lr.size(); ++t) lr[t] = src->mask[t] ? 1 : 0;
+    } else {
+      const int d = src->dim;
+      double* bx = (double*)h->work.alloc((size_t)4 * (p + q) * d * 8);
+      double *rlo = bx, *rhi = bx + (size_t)p * d, *clo = bx + (size_t)2 * p * d, *chi = clo + (size_t)q * d;
+      HIPCHECK(launch_boxes(src->x, (int)h->m, d, b, rlo, rhi, s));
+      HIPCHECK(launch_boxes(src->y, (int)h->n, d, b, clo, chi, s));
+      std::vector<double> hb((size_t)2 * (p + q) * d);
+      HIPCHECK(hipMemcpyAsync(hb.data(), bx, hb.size() * 8, hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      const double *Rlo = hb.data(), *Rhi = Rlo + (size_t)p * d, *Clo = Rlo + (size_t)2 * p * d,
+                   *Chi = Clo + (size_t)q * d;
+      for (int i = 0; i < p; ++i)
+        for (int j = 0; j < q; ++j) {
+          double g2 = 0.0, dr2 = 0.0, dc2 = 0.0;
+          for (int c = 0; c < d; ++c) {
+            const double g = std::max(0.0, std::max(Rlo[i * d + c] - Chi[j * d + c], Clo[j * d + c] - Rhi[i * d + c]));
+            g2 += g * g;
+            dr2 += (Rhi[i * d + c] - Rlo[i * d + c]) * (Rhi[i * d + c] - Rlo[i * d + c]);
+            dc2 += (Chi[j * d + c] - Clo[j * d + c]) * (Chi[j * d + c] - Clo[j * d + c]);
+          }
+          const double gap = std::sqrt(g2);
+          bool low;
+          if (src->admissibility == BLR_ADM_ADJACENT) low = gap > 0.0;
+          else low = gap > std::max(std::sqrt(dr2), std::sqrt(dc2));
+          lr[(size_t)i * q + j] = low ? 1 : 0;
+        }
+    }
+    for (int k = 0; k < std::min(p, q); ++k) lr[(size_t)k * q + k] = 0;
+    std::vector<int> cand;
+    for (size_t t = 0; t < lr.size(); ++t)
+      if (lr[t]) cand.push_back((int)t);
+    alloc_lowrank(h, cand);
+    TileFillParams fp{};
+    fp.b = b;
+    fp.src_dense = kern ? 0 : 1;
+    fp.A = src->A;
+    fp.lda = src->lda;
+    fp.x = src->x;
+    fp.y = src->y;
+    fp.dim = src->dim;
+    fp.kernel = src->kernel;
+    fp.reg = src->reg;
+    std::vector<int> status(lr.size(), 0);
+    if (!cand.empty()) {
+      const int l = std::min(b, rc + 16);
+      const int NB = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cand.size(), (int64_t)(256LL << 20) / ((int64_t)b * b * 8)));
+      Arena cw;
+      double* Om = (double*)cw.alloc((size_t)b * l * 8);
+      HIPCHECK(launch_gaussian(Om, (int64_t)b * l, o->seed, 4, s));
+      double* As = (double*)cw.alloc((size_t)NB * b * b * 8);
+      double* Ys = (double*)cw.alloc((size_t)NB * b * l * 8);
+      double* Qs = (double*)cw.alloc((size_t)NB * b * l * 8);
+      double* Bs = (double*)cw.alloc((size_t)NB * l * b * 8);
+      double* nrm = (double*)cw.alloc((size_t)NB * 2 * 8);
+      int* stat = (int*)cw.alloc((size_t)NB * sizeof(int));
+      const size_t cwd = comp_work_doubles(b, l);
+      double* wk = (double*)cw.alloc((size_t)NB * cwd * 8);
+      TileFillDesc* dfd = (TileFillDesc*)cw.alloc((size_t)NB * sizeof(TileFillDesc));
+      Frob2Desc* dfr = (Frob2Desc*)cw.alloc((size_t)NB * 2 * sizeof(Frob2Desc));
+      CompDesc* dcd = (CompDesc*)cw.alloc((size_t)NB * sizeof(CompDesc));
+      GemmDesc* dgd = (GemmDesc*)cw.alloc((size_t)NB * 3 * sizeof(GemmDesc));
+      GemmSeg* dgs = (GemmSeg*)cw.alloc((size_t)NB * 3 * sizeof(GemmSeg));
+      for (size_t c0 = 0; c0 < cand.size(); c0 += NB) {
+        const int nb = (int)std::min<size_t>(NB, cand.size() - c0);
+        std::vector<TileFillDesc> fd(nb);
+        std::vector<Frob2Desc> fr(2 * nb);
+        std::vector<CompDesc> cd(nb);
+        Plan P;
+        for (int a = 0; a < nb; ++a) {
+          const int t = cand[c0 + a];
+          Tile& T = h->tiles[t];
+          double* A = As + (size_t)a * b * b;
+          fd[a] = TileFillDesc{A, t / q, t % q};
+          fr[a] = Frob2Desc{A, b, b, b, nrm + 2 * a};
+          fr[nb + a] = Frob2Desc{A, b, b, b, nrm + 2 * a + 1};
+          CompDesc& D = cd[a];
+          D.A = A;
+          D.Y = Ys + (size_t)a * b * l;
+          D.Q = Qs + (size_t)a * b * l;
+          D.B = Bs + (size_t)a * l * b;
+          D.Uout = T.U;
+          D.Vtout = T.Vt;
+          D.rank_out = T.rank;
+          D.status_out = stat + a;
+          D.work = wk + (size_t)a * cwd;
+          D.anorm2 = nrm + 2 * a;
+          D.enorm2 = nrm + 2 * a + 1;
+          P.gemm(D.Y, b, nullptr, 0, nullptr, 0, b, l, 1.0, 0.0, A, b, Om, b, b, 0);
+        }
+        HIPCHECK(hipMemcpy(dfd, fd.data(), nb * sizeof(TileFillDesc), hipMemcpyHostToDevice));
+        HIPCHECK(hipMemcpy(dfr, fr.data(), 2 * nb * sizeof(Frob2Desc), hipMemcpyHostToDevice));
+        HIPCHECK(hipMemcpy(dcd, cd.data(), nb * sizeof(CompDesc), hipMemcpyHostToDevice));
+        P.flush_gemm();
+        for (int a = 0; a < nb; ++a)
+          P.gemm(cd[a].B, l, nullptr, 0, nullptr, 0, l, b, 1.0, 0.0, cd[a].Q, b, cd[a].A, b, b, SEG_TRANS_A);
+        P.flush_gemm();
+        for (int a = 0; a < nb; ++a)
+          P.gemm(const_cast<double*>(cd[a].A), b, cd[a].A, b, nullptr, 0, b, b, -1.0, 1.0, cd[a].Q, b,
+                 cd[a].B, l, l, 0);
+        P.flush_gemm();
+        HIPCHECK(hipMemcpy(dgd, P.descs.data(), P.descs.size() * sizeof(GemmDesc), hipMemcpyHostToDevice));
+        HIPCHECK(hipMemcpy(dgs, P.segs.data(), P.segs.size() * sizeof(GemmSeg), hipMemcpyHostToDevice));
+        HIPCHECK(launch_fill_tiles(dfd, nb, fp, s));
+        HIPCHECK(launch_frob2(dfr, nb, s));
+        HIPCHECK(launch_gemm(dgd + P.ops[0].off, P.ops[0].n, dgs, P.ops[0].ntiles, P.ops[0].big, 0, s));
+        HIPCHECK(launch_rangefinder(dcd, nb, b, l, s));
+        HIPCHECK(launch_gemm(dgd + P.ops[1].off, P.ops[1].n, dgs, P.ops[1].ntiles, P.ops[1].big, 0, s));
+        HIPCHECK(launch_gemm(dgd + P.ops[2].off, P.ops[2].n, dgs, P.ops[2].ntiles, P.ops[2].big, 0, s));
+        HIPCHECK(launch_frob2(dfr + nb, nb, s));
+        CompParams cp{b, rc, l, h->cap, h->tol, h->overflow == BLR_OVERFLOW_TRUNCATE ? 1 : 0};
+        HIPCHECK(launch_comp_svd(dcd, nb, cp, s));
+        std::vector<int> hs(nb);
+        HIPCHECK(hipMemcpyAsync(hs.data(), stat, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        for (int a = 0; a < nb; ++a) status[cand[c0 + a]] = hs[a];
+      }
+    }
+    std::vector<int> dense;
+    for (size_t t = 0; t < lr.size(); ++t) {
+      if (!lr[t] || status[t] == 1) {
+        dense.push_back((int)t);
+        h->tiles[t].fmt = DENSE;
+        if (lr[t]) h->compress_overflow++;
+      } else {
+        h->tiles[t].fmt = LOWRANK;
+        if (status[t] == 2) h->compress_overflow++;
+      }
+    }
+    alloc_dense(h, dense);
+    for (size_t c0 = 0; c0 < dense.size(); c0 += 4096) {
+      const int nb = (int)std::min<size_t>(4096, dense.size() - c0);
+      std::vector<TileFillDesc> fd(nb);
+      for (int a = 0; a < nb; ++a) {
+        const int t = dense[c0 + a];
+        fd[a] = TileFillDesc{h->tiles[t].D, t / q, t % q};
+      }
+      TileFillDesc* dfd = (TileFillDesc*)h->work.alloc(nb * sizeof(TileFillDesc));
+      HIPCHECK(hipMemcpy(dfd, fd.data(), nb * sizeof(TileFillDesc), hipMemcpyHostToDevice));
+      HIPCHECK(launch_fill_tiles(dfd, nb, fp, s));
+    }
+    HIPCHECK(hipStreamSynchronize(s));
+    h->work.release();
+  });
+  if (st != BLR_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return BLR_OK;
+}
+
+blr_status blr_import(const blr_compress_opts* o, const blr_tiles_host* t, void* stream, blr_matrix* out) {
+  if (!t || !out || !t->fmt || !t->rank) return fail(BLR_ERR_INVALID, "NULL argument");
+  blr_compress_opts oo = *o;
+  oo.overflow = BLR_OVERFLOW_DENSE;
+  blr_status st = validate_opts(&oo);
+  if (st != BLR_OK) return st;
+  blr_matrix h = new_handle(&oo);
+  hipStream_t s = as_stream(stream);
+  st = run_guarded([&] {
+    alloc_common(h);
+    const int b = h->b, rc = h->rc;
+    const size_t nt = (size_t)h->p * h->q;
+    std::vector<int> dn, lo;
+    for (size_t i = 0; i < nt; ++i) {
+      const int r = t->rank[i];
+      if (t->fmt[i] == LOWRANK && (r < 0 || r > h->cap)) throw Error(BLR_ERR_INVALID, "rank out of range");
+      if (t->fmt[i] == LOWRANK && (i / h->q) == (i % h->q)) throw Error(BLR_ERR_INVALID, "diagonal tiles must be dense");
+      (t->fmt[i] == LOWRANK ? lo : dn).push_back((int)i);
+    }
+    if (!lo.empty() && (!t->U || !t->V)) throw Error(BLR_ERR_INVALID, "U and V needed for low-rank tiles");
+    if (!dn.empty() && !t->dense) throw Error(BLR_ERR_INVALID, "dense tiles needed");
+    alloc_dense(h, dn);
+    alloc_lowrank(h, lo);
+    for (int i : dn) {
+      h->tiles[i].fmt = DENSE;
+      const double* src = t->dense + (size_t)i * b * b;
+      for (size_t e = 0; e < (size_t)b * b; ++e)
+        if (!std::isfinite(src[e])) throw Error(BLR_ERR_NONFINITE, "non-finite dense tile");
+      HIPCHECK(hipMemcpy(h->tiles[i].D, src, (size_t)b * b * 8, hipMemcpyHostToDevice));
+    }
+    std::vector<double> Ub((size_t)b * rc), Vtb((size_t)rc * b);
+    std::vector<int> ranks(nt, 0);
+    for (int i : lo) {
+      h->tiles[i].fmt = LOWRANK;
+      const int r = t->rank[i];
+      ranks[i] = r;
+      std::fill(Ub.begin(), Ub.end(), 0.0);
+      std::fill(Vtb.begin(), Vtb.end(), 0.0);
+      const double* U = t->U + (size_t)i * b * rc;
+      const double* V = t->V + (size_t)i * b * rc;
+      for (int l = 0; l < r; ++l)
+        for (int e = 0; e < b; ++e) {
+          Ub[e + (size_t)l * b] = U[e + (size_t)l * b];
+          Vtb[l + (size_t)e * rc] = V[e + (size_t)l * b];
+        }
+      for (double v : Ub)
+        if (!std::isfinite(v)) throw Error(BLR_ERR_NONFINITE, "non-finite U");
+      for (double v : Vtb)
+        if (!std::isfinite(v)) throw Error(BLR_ERR_NONFINITE, "non-finite V");
+      HIPCHECK(hipMemcpy(h->tiles[i].U, Ub.data(), Ub.size() * 8, hipMemcpyHostToDevice));
+      HIPCHECK(hipMemcpy(h->tiles[i].Vt, Vtb.data(), Vtb.size() * 8, hipMemcpyHostToDevice));
+    }
+    HIPCHECK(hipMemcpy(h->d_rank, ranks.data(), nt * sizeof(int), hipMemcpyHostToDevice));
+    (void)s;
+  });
+  if (st != BLR_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return BLR_OK;
+}
+
+blr_status blr_export(blr_matrix h, blr_tiles_host* t) {
+  if (!h || !t) return fail(BLR_ERR_INVALID, "NULL argument");
+  return run_guarded([&] {
+    HIPCHECK(hipDeviceSynchronize());
+    const int b = h->b, rc = h->rc, q = h->q;
+    const size_t nt = (size_t)h->p * h->q;
+    std::vector<int> ranks(nt);
+    HIPCHECK(hipMemcpy(ranks.data(), h->d_rank, nt * sizeof(int), hipMemcpyDeviceToHost));
+    std::vector<double> tmp((size_t)b * std::max(b, rc));
+    for (size_t i = 0; i < nt; ++i) {
+      Tile& T = h->tiles[i];
+      if (t->fmt) t->fmt[i] = T.fmt;
+      if (t->rank) t->rank[i] = T.fmt == LOWRANK ? ranks[i] : -1;
+      if (T.fmt == DENSE || (h->state == BLR_STATE_FACTORED && T.D)) {
+        if (t->dense && T.D) HIPCHECK(hipMemcpy(t->dense + i * b * b, T.D, (size_t)b * b * 8, hipMemcpyDeviceToHost));
+      }
+      if (T.fmt == LOWRANK) {
+        if (t->U) HIPCHECK(hipMemcpy(t->U + i * b * rc, T.U, (size_t)b * rc * 8, hipMemcpyDeviceToHost));
+        const int row = (int)(i / q), col = (int)(i % q);
+        const bool holds_y = h->state == BLR_STATE_FACTORED && row > col && col < h->steps_done;
+        if (holds_y) {
+          if (t->Y) HIPCHECK(hipMemcpy(t->Y + i * rc * b, T.Vt, (size_t)rc * b * 8, hipMemcpyDeviceToHost));
+        } else if (t->V) {
+          HIPCHECK(hipMemcpy(tmp.data(), T.Vt, (size_t)rc * b * 8, hipMemcpyDeviceToHost));
+          double* V = t->V + i * b * rc;
+          for (int l = 0; l < rc; ++l)
+            for (int e = 0; e < b; ++e) V[e + (size_t)l * b] = tmp[l + (size_t)e * rc];
+        }
+      }
+      if (t->T && h->T[i]) HIPCHECK(hipMemcpy(t->T + i * b * b, h->T[i], (size_t)b * b * 8, hipMemcpyDeviceToHost));
+    }
+  });
+}
+
+blr_status blr_qr_factor(blr_matrix h, const blr_factor_opts* o, void* stream) {
+  if (!h || !o) return fail(BLR_ERR_INVALID, "NULL argument");
+  if (h->state != BLR_STATE_COMPRESSED) return fail(BLR_ERR_STATE, "matrix is already factored");
+  if (o->variant != BLR_TILED && o->variant != BLR_BLOCK_COLUMN) return fail(BLR_ERR_INVALID, "bad variant");
+  if (o->precision != BLR_FP64 && o->precision != BLR_MIXED_FP32) return fail(BLR_ERR_INVALID, "bad precision");
+  if (o->variant == BLR_BLOCK_COLUMN) return fail(BLR_ERR_INVALID, "block-column variant not available");
+  hipStream_t s = as_stream(stream);
+  return run_guarded([&] {
+    const int b = h->b, p = h->p, q = h->q;
+    const int kend = (o->stop_after_k < 0) ? q : std::min(q, o->stop_after_k);
+    h->variant = o->variant;
+    h->precision = o->precision;
+    // fill-in: simulate formats to find the tiles that need a dense slot
+    {
+      std::vector<int8_t> f((size_t)p * q);
+      for (size_t t = 0; t < f.size(); ++t) f[t] = h->tiles[t].fmt;
+      std::vector<int> need;
+      for (int k = 0; k < kend; ++k)
+        for (int i = k + 1; i < p; ++i) {
+          const bool yd = f[(size_t)i * q + k] == DENSE;
+          if (!yd) continue;
+          for (int j = k + 1; j < q; ++j) {
+            int8_t& R = f[(size_t)k * q + j];
+            int8_t& A = f[(size_t)i * q + j];
+            if (R == LOWRANK && A == DENSE) {
+              R = DENSE;
+              need.push_back(k * q + j);
+            }
+            if (R == DENSE && A == LOWRANK) {
+              A = DENSE;
+              need.push_back(i * q + j);
+            }
+          }
+        }
+      alloc_dense(h, need);
+    }
+    // T and tau storage for every (i,k), i >= k, k < kend
+    {
+      std::vector<int> idx;
+      for (int k = 0; k < kend; ++k)
+        for (int i = k; i < p; ++i) idx.push_back(i * q + k);
+      double* tp = (double*)h->mem.alloc(idx.size() * (size_t)b * b * 8);
+      HIPCHECK(hipMemset(tp, 0, idx.size() * (size_t)b * b * 8));
+      double* tu = (double*)h->mem.alloc(idx.size() * (size_t)b * 8);
+      HIPCHECK(hipMemset(tu, 0, idx.size() * (size_t)b * 8));
+      for (size_t a = 0; a < idx.size(); ++a) {
+        h->T[idx[a]] = tp + a * (size_t)b * b;
+        h->tau[idx[a]] = tu + a * (size_t)b;
+      }
+    }
+    h->work.release();
+    Work w = make_work(h, 0);
+    Plan P;
+    h->n_fill = 0;
+    plan_tiled(h, P, w, kend, o->precision == BLR_MIXED_FP32);
+    P.upload(h->work);
+    h->flops = 0.0;
+    for (auto& op : P.ops) h->flops += op.flops;
+    for (auto e : h->prof_ev) (void)hipEventDestroy(e);
+    h->prof_ev.clear();
+    h->prof_flops = 0.0;
+    h->prof_launches = 0;
+    h->launches = 0;
+    HIPCHECK(hipMemsetAsync(h->d_counters, 0, 4 * sizeof(unsigned long long), s));
+    execute(h, P, s);
+    h->steps_done = kend;
+    h->state = BLR_STATE_FACTORED;
+  });
+}
+
+blr_status blr_apply_qt(blr_matrix h, int32_t trans, double* B, int64_t ldb, int32_t nrhs, void* stream) {
+  if (!h || !B) return fail(BLR_ERR_INVALID, "NULL argument");
+  if (h->state != BLR_STATE_FACTORED) return fail(BLR_ERR_STATE, "matrix is not factored");
+  if (ldb < h->m || nrhs < 0 || (trans != 0 && trans != 1)) return fail(BLR_ERR_INVALID, "bad B shape or trans");
+  if (nrhs == 0) return BLR_OK;
+  hipStream_t s = as_stream(stream);
+  return run_guarded([&] {
+    HIPCHECK(hipDeviceSynchronize());
+    h->work.release();
+    Work w = make_work(h, nrhs);
+    Plan P;
+    plan_apply_tiled(h, P, w, B, ldb, nrhs, trans);
+    P.upload(h->work);
+    execute(h, P, s);
+  });
+}
+
+blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X, int64_t ldx, int32_t nrhs,
+                           int32_t max_refine, double* resid_norms, void* stream) {
+  if (!h || !B || !X) return fail(BLR_ERR_INVALID, "NULL argument");
+  if (h->state != BLR_STATE_FACTORED) return fail(BLR_ERR_STATE, "matrix is not factored");
+  if (h->steps_done != h->q) return fail(BLR_ERR_STATE, "factorization is incomplete");
+  if (ldb < h->m || ldx < h->n || nrhs < 0) return fail(BLR_ERR_INVALID, "bad B or X shape");
+  if (max_refine != 0) return fail(BLR_ERR_INVALID, "max_refine must be 0");
+  if (nrhs == 0) return BLR_OK;
+  hipStream_t s = as_stream(stream);
+  return run_guarded([&] {
+    const int b = h->b, q = h->q, rc = h->rc;
+    const int64_t m = h->m, n = h->n;
+    HIPCHECK(hipDeviceSynchronize());
+    h->work.release();
+    // singularity check: min |R_jj| against n u ||R||_F
+    {
+      Plan P0;
+      std::vector<DiagDesc> dd(q);
+      for (int k = 0; k < q; ++k) dd[k].R = h->t(k, k).D;
+      DiagDesc* ddd = (DiagDesc*)h->work.alloc(q * sizeof(DiagDesc));
+      double* out = (double*)h->work.alloc((size_t)2 * q * 8);
+      HIPCHECK(hipMemcpy(ddd, dd.data(), q * sizeof(DiagDesc), hipMemcpyHostToDevice));
+      HIPCHECK(launch_diag_absmin(ddd, q, b, out, s));
+      std::vector<Frob2Desc> fr;
+      double* fo = (double*)h->work.alloc((size_t)q * q * 8 + 8);
+      for (int k = 0; k < q; ++k)
+        for (int j = k + 1; j < q; ++j) {
+          Tile& t = h->t(k, j);
+          double* o = fo + fr.size();
+          if (t.fmt == DENSE) fr.push_back(Frob2Desc{t.D, b, b, b, o});
+          else fr.push_back(Frob2Desc{t.Vt, rc, rc, b, o});
+        }
+      if (!fr.empty()) {
+        Frob2Desc* dfr = (Frob2Desc*)h->work.alloc(fr.size() * sizeof(Frob2Desc));
+        HIPCHECK(hipMemcpy(dfr, fr.data(), fr.size() * sizeof(Frob2Desc), hipMemcpyHostToDevice));
+        HIPCHECK(launch_frob2(dfr, (int)fr.size(), s));
+      }
+      std::vector<double> ho(2 * q), hf(fr.size());
+      HIPCHECK(hipMemcpyAsync(ho.data(), out, 2 * q * 8, hipMemcpyDeviceToHost, s));
+      if (!fr.empty()) HIPCHECK(hipMemcpyAsync(hf.data(), fo, fr.size() * 8, hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      double r2 = 0.0, mn = 1e300;
+      for (int k = 0; k < q; ++k) {
+        mn = std::min(mn, ho[2 * k]);
+        r2 += ho[2 * k + 1];
+      }
+      for (double v : hf) r2 += v;
+      const double thr = (double)n * 2.220446049250313e-16 * std::sqrt(r2);
+      if (!(mn > thr)) throw Error(BLR_ERR_SINGULAR, "R is numerically singular");
+      h->work.release();
+    }
+    Work w = make_work(h, nrhs);
+    double* C = (double*)h->work.alloc((size_t)m * nrhs * 8);
+    HIPCHECK(hipMemcpy2DAsync(C, m * 8, B, ldb * 8, m * 8, nrhs, hipMemcpyDeviceToDevice, s));
+    Plan P;
+    plan_apply_tiled(h, P, w, C, m, nrhs, 0);
+    P.upload(h->work);
+    execute(h, P, s);
+    if (resid_norms) {
+      std::vector<Frob2Desc> fr(nrhs);
+      for (int c = 0; c < nrhs; ++c) fr[c] = Frob2Desc{C + n + (int64_t)c * m, m, (int)(m - n), 1, resid_norms + c};
+      Frob2Desc* dfr = (Frob2Desc*)h->work.alloc(nrhs * sizeof(Frob2Desc));
+      HIPCHECK(hipMemcpy(dfr, fr.data(), nrhs * sizeof(Frob2Desc), hipMemcpyHostToDevice));
+      if (m > n) HIPCHECK(launch_frob2(dfr, nrhs, s));
+      else HIPCHECK(hipMemsetAsync(resid_norms, 0, nrhs * 8, s));
+    }
+    HIPCHECK(hipMemcpy2DAsync(X, ldx * 8, C, m * 8, n * 8, nrhs, hipMemcpyDeviceToDevice, s));
+    // back-substitution through the BLR R
+    Plan Q;
+    double* Sx = (double*)h->work.alloc((size_t)q * rc * nrhs * 8);  // rc x nrhs per j
+    for (int k = q - 1; k >= 0; --k) {
+      double* Xk = X + (int64_t)k * b;
+      bool any_lr = false;
+      for (int j = k + 1; j < q; ++j) {
+        Tile& t = h->t(k, j);
+        if (t.fmt == LOWRANK) {
+          Q.gemm(Sx + (size_t)j * rc * nrhs, rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, t.Vt, rc,
+                 X + (int64_t)j * b, ldx, b, 0);
+          any_lr = true;
+        }
+      }
+      if (any_lr) Q.flush_gemm();
+      if (k + 1 < q) {
+        GemmDesc d{};
+        // multi-segment descriptor: X_k -= sum_j R_kj X_j
+        Q.cur.push_back(d);
+        GemmDesc& dd = Q.cur.back();
+        dd.C = Xk;
+        dd.ldc = ldx;
+        dd.Cin = Xk;
+        dd.ldcin = ldx;
+        dd.M = b;
+        dd.N = nrhs;
+        dd.alpha = -1.0;
+        dd.beta = 1.0;
+        dd.seg_begin = 0;
+        dd.nseg = q - k - 1;
+        for (int j = k + 1; j < q; ++j) {
+          Tile& t = h->t(k, j);
+          GemmSeg sg{};
+          if (t.fmt == DENSE) {
+            sg.A = t.D;
+            sg.lda = b;
+            sg.B = X + (int64_t)j * b;
+            sg.ldb = ldx;
+            sg.K = b;
+          } else {
+            sg.A = t.U;
+            sg.lda = b;
+            sg.B = Sx + (size_t)j * rc * nrhs;
+            sg.ldb = rc;
+            sg.K = rc;
+          }
+          Q.curseg.push_back(sg);
+          Q.curflops += 2.0 * b * nrhs * sg.K;
+        }
+        Q.flush_gemm();
+      }
+      Op o;
+      o.kind = Op::TRSM;
+      o.off = k;
+      Q.ops.push_back(o);
+    }
+    Q.upload(h->work);
+    for (const Op& o : Q.ops) {
+      if (o.kind == Op::TRSM) {
+        const int k = o.off;
+        HIPCHECK(launch_trsm_upper(h->t(k, k).D, b, b, X + (int64_t)k * b, ldx, nrhs, s));
+      } else {
+        HIPCHECK(launch_gemm(Q.d_descs + o.off, o.n, Q.d_segs, o.ntiles, o.big, 0, s));
+      }
+    }
+    HIPCHECK(hipStreamSynchronize(s));
+  });
+}
+
+blr_status blr_query(blr_matrix h, blr_info* info) {
+  if (!h || !info) return fail(BLR_ERR_INVALID, "NULL argument");
+  return run_guarded([&] {
+    HIPCHECK(hipDeviceSynchronize());
+    std::memset(info, 0, sizeof(*info));
+    info->m = h->m;
+    info->n = h->n;
+    info->tile = h->b;
+    info->p = h->p;
+    info->q = h->q;
+    info->max_rank = h->cap;
+    info->rank_capacity = h->rc;
+    info->state = h->state;
+    info->variant = h->variant;
+    info->precision = h->precision;
+    info->ib = h->ib;
+    for (auto& t : h->tiles) (t.fmt == DENSE ? info->n_dense : info->n_lowrank)++;
+    info->n_fill_in = h->n_fill;
+    info->device_bytes = h->mem.bytes + h->work.bytes;
+    info->compress_overflow = h->compress_overflow;
+    unsigned long long c[2] = {0, 0};
+    HIPCHECK(hipMemcpy(c, h->d_counters, sizeof(c), hipMemcpyDeviceToHost));
+    info->factor_overflow = (int64_t)c[0];
+    double md;
+    std::memcpy(&md, &c[1], sizeof(md));
+    info->max_dropped_rel = md;
+    info->flops_factor = h->flops;
+    info->kernel_launches = h->launches;
+  });
+}
+
+void blr_destroy(blr_matrix h) {
+  if (!h) return;
+  (void)hipDeviceSynchronize();
+  for (auto e : h->prof_ev) (void)hipEventDestroy(e);
+  delete h;
+}
+
+blr_status blr_profile_enable(blr_matrix h, int32_t on) {
+  if (!h) return fail(BLR_ERR_INVALID, "NULL argument");
+  h->prof_on = on != 0;
+  return BLR_OK;
+}
+
+blr_status blr_profile_read(blr_matrix h, int64_t* launches, double* total_ms, double* total_flops) {
+  if (!h || !launches || !total_ms || !total_flops) return fail(BLR_ERR_INVALID, "NULL argument");
+  return run_guarded([&] {
+    HIPCHECK(hipDeviceSynchronize());
+    double ms = 0.0;
+    for (size_t a = 0; a + 1 < h->prof_ev.size(); a += 2) {
+      float t = 0.f;
+      HIPCHECK(hipEventElapsedTime(&t, h->prof_ev[a], h->prof_ev[a + 1]));
+      ms += t;
+    }
+    *launches = h->prof_launches;
+    *total_ms = ms;
+    *total_flops = h->prof_flops;
+  });
+}
+
+}  // extern "C"
+
+#include "../../include/blrqr_selftest.h"
+
+extern "C" blr_status blr_selftest_gemm(int32_t flags, int32_t M, int32_t N, int32_t K, double alpha,
+                                        const double* A, int64_t lda, const double* B, int64_t ldb,
+                                        double beta, double* C, int64_t ldc, int32_t fp32, void* stream) {
+  if (!A || !B || !C || M < 0 || N < 0 || K < 0) return fail(BLR_ERR_INVALID, "bad arguments");
+  return run_guarded([&] {
+    Arena ar;
+    Plan P;
+    P.gemm(C, ldc, C, ldc, nullptr, 0, M, N, alpha, beta, A, lda, B, ldb, K, flags);
+    P.flush_gemm(fp32);
+    if (P.ops.empty()) return;
+    P.upload(ar);
+    HIPCHECK(launch_gemm(P.d_descs, P.ops[0].n, P.d_segs, P.ops[0].ntiles, P.ops[0].big, fp32,
+                         as_stream(stream)));
+    HIPCHECK(hipStreamSynchronize(as_stream(stream)));
+  });
+}

@@ -1,0 +1,110 @@
+// Host runtime of libblrqr: handle, device memory, launch plans.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/blrqr.h"
+#include "gemm.h"
+#include "lowrank.h"
+#include "misc.h"
+#include "qr.h"
+
+namespace blr {
+
+enum Fmt : int8_t { DENSE = 0, LOWRANK = 1 };
+
+struct Error : std::runtime_error {
+  blr_status code;
+  Error(blr_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void hip_check(hipError_t e, const char* what);
+#define HIPCHECK(x) ::blr::hip_check((x), #x)
+
+struct Tile {
+  int8_t fmt = DENSE;
+  double* D = nullptr;   // dense slot b x b (ld b)
+  double* U = nullptr;   // low-rank slot b x rc (ld b)
+  double* Vt = nullptr;  // low-rank slot rc x b (ld rc); after TPQRT of a low-rank tile it holds Y
+  int* rank = nullptr;   // device rank
+};
+
+// Device arena: every allocation is released by the owner's destructor.
+struct Arena {
+  std::vector<void*> blocks;
+  int64_t bytes = 0;
+  void* alloc(size_t n);
+  void release();
+  ~Arena() { release(); }
+};
+
+// One enqueued operation of a plan.
+struct Op {
+  enum Kind { GEMM, PANEL, TBACK, RC, TRSM, DENSE_COPY } kind;
+  int off = 0, n = 0, ntiles = 0, big = 0, fp32 = 0, prof = 0;
+  double flops = 0.0;
+  PanelArgs panel{};
+  TBackArgs tback{};
+};
+
+// Launch list with host-side descriptor arrays, uploaded once.
+struct Plan {
+  std::vector<Op> ops;
+  std::vector<GemmDesc> descs;
+  std::vector<GemmSeg> segs;
+  std::vector<RcDesc> rcs;
+  GemmDesc* d_descs = nullptr;
+  GemmSeg* d_segs = nullptr;
+  RcDesc* d_rcs = nullptr;
+  // building helpers
+  std::vector<GemmDesc> cur;     // descriptors of the GEMM op being built
+  std::vector<GemmSeg> curseg;
+  double curflops = 0.0;
+  std::vector<RcDesc> currc;
+
+  // add one descriptor with a single K segment
+  void gemm(double* C, int64_t ldc, const double* Cin, int64_t ldcin, double* D2, int64_t ldd2,
+            int M, int N, double alpha, double beta, const double* A, int64_t lda, const double* B,
+            int64_t ldb, int K, int segflags, int descflags = 0);
+  void flush_gemm(int fp32 = 0, int prof = 0);
+  void rc(const RcDesc& d) { currc.push_back(d); }
+  void flush_rc();
+  void panel(const PanelArgs& a) { Op o; o.kind = Op::PANEL; o.panel = a; ops.push_back(o); }
+  void tback(const TBackArgs& a) { Op o; o.kind = Op::TBACK; o.tback = a; ops.push_back(o); }
+  void upload(Arena& arena);
+  void clear();
+};
+
+}  // namespace blr
+
+struct blr_matrix_s {
+  int64_t m = 0, n = 0;
+  int b = 0, p = 0, q = 0, cap = 0, rc = 0;
+  double tol = 0.0;
+  int overflow = 0;
+  int state = BLR_STATE_COMPRESSED;
+  int variant = 0, precision = 0, ib = 32;
+  int steps_done = 0;
+  std::vector<blr::Tile> tiles;          // p*q, i*q + j
+  std::vector<int8_t> yfmt;              // p*q: format of Ytilde_ik after the factor
+  std::vector<double*> T;                // p*q: T of tile (tiled) or of column (block column, at (k,k))
+  std::vector<double*> tau;              // p*q
+  int* d_rank = nullptr;
+  unsigned long long* d_counters = nullptr;  // [0] overflow count, [1] max dropped bits
+  blr::Arena mem;                        // tiles, T, ranks
+  blr::Arena work;                       // factor workspaces and plans
+  int64_t compress_overflow = 0;
+  int64_t n_fill = 0;
+  double flops = 0.0;
+  int64_t launches = 0;
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;
+  double prof_flops = 0.0;
+  int64_t prof_launches = 0;
+
+  blr::Tile& t(int i, int j) { return tiles[(size_t)i * q + j]; }
+};

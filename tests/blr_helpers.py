@@ -1,0 +1,62 @@
+"""Helpers shared by the GPU tests: moving tiles between the oracle's BLR
+container and the library's host tile layout, and reading R off an export."""
+import numpy as np
+
+from oracle.blrmat import BLR, DENSE, LOWRANK
+
+
+def rank_capacity(cap: int, b: int) -> int:
+    return min((cap + 15) // 16 * 16, b)
+
+
+def blr_to_host(blr: BLR, cap: int):
+    """Oracle BLR -> (fmt, rank, dense, U, V) arrays in the blr_tiles_host layout."""
+    p, q, b = blr.p, blr.q, blr.b
+    rc = rank_capacity(cap, b)
+    fmt = np.zeros(p * q, np.int8)
+    rank = np.zeros(p * q, np.int32)
+    dense = np.zeros((p * q, b, b))
+    U = np.zeros((p * q, rc, b))
+    V = np.zeros((p * q, rc, b))
+    for i in range(p):
+        for j in range(q):
+            t = i * q + j
+            if blr.fmt[i, j] == DENSE:
+                dense[t] = blr.D[(i, j)].T          # column-major b x b
+            else:
+                r = blr.rank(i, j)
+                assert r <= cap
+                fmt[t] = 1
+                rank[t] = r
+                U[t, :r] = blr.U[(i, j)].T
+                V[t, :r] = blr.V[(i, j)].T
+    return fmt, rank, dense.ravel(), U.ravel(), V.ravel()
+
+
+def export_tile(ex, i, j):
+    """Dense value of tile (i,j) of an export (R tiles and untouched tiles)."""
+    if ex["fmt"][i, j] == 0:
+        return ex["dense"][i, j]
+    r = ex["rank"][i, j]
+    return ex["U"][i, j][:, :r] @ ex["V"][i, j][:, :r].T
+
+
+def export_r(ex):
+    p, q = ex["fmt"].shape
+    b = ex["dense"].shape[2]
+    R = np.zeros((q * b, q * b))
+    for k in range(q):
+        for j in range(k, q):
+            blk = np.triu(ex["dense"][k, k]) if j == k else export_tile(ex, k, j)
+            R[k * b:(k + 1) * b, j * b:(j + 1) * b] = blk
+    return R
+
+
+def export_dense(ex):
+    p, q = ex["fmt"].shape
+    b = ex["dense"].shape[2]
+    A = np.zeros((p * b, q * b))
+    for i in range(p):
+        for j in range(q):
+            A[i * b:(i + 1) * b, j * b:(j + 1) * b] = export_tile(ex, i, j)
+    return A

@@ -1,0 +1,134 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle on the same
+seeded inputs.  Tolerances: identical algorithms in FP64 differ only in
+rounding order, so dense tiles agree to a few n*u*kappa; where truncation
+decides a rank, products agree to a few eps*kappa (ranks near the threshold
+may differ by one)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import blockcol, blrmat, metrics, tiled
+from oracle.blrmat import DENSE, LOWRANK
+
+from tests.blr_helpers import blr_to_host, export_dense, export_r, export_tile
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+U = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2208_06194_amd as P
+    assert torch.cuda.is_available()
+    return P
+
+
+def log_case(**kw):
+    print("case:", kw, flush=True)
+
+
+def gpu_import(P, blr, eps, cap):
+    fmt, rank, dense, Uh, Vh = blr_to_host(blr, cap)
+    return P.BLRMatrix.import_tiles(blr.m, blr.n, blr.b, eps, cap, fmt, rank, dense, Uh, Vh)
+
+
+@pytest.mark.parametrize("m,n,b", [(64, 64, 32), (256, 128, 64), (192, 96, 48), (512, 256, 64), (256, 256, 128)])
+def test_all_dense_tiled_matches_oracle(lib, m, n, b):
+    log_case(test="all_dense", m=m, n=n, b=b)
+    A = np.random.default_rng(m + b).standard_normal((m, n))
+    blr = blrmat.compress(A, b, 1e-12, b, np.zeros((m // b, n // b), bool))
+    f = tiled.factor(blr, 1e-12, b)
+    G = gpu_import(lib, blr, 1e-12, b)
+    G.factor("tiled")
+    ex = G.export(with_factor=True)
+    kappa = np.linalg.cond(A)
+    tol = 10 * n * U * kappa
+    # R, the reflector blocks and the T factors, tile by tile
+    Rg, Ro = export_r(ex), f.r_dense()
+    assert np.linalg.norm(Rg - Ro) / np.linalg.norm(Ro) <= tol
+    for k in range(f.q):
+        assert np.allclose(np.tril(ex["dense"][k, k], -1), np.tril(f.A.D[(k, k)], -1), atol=tol * 10)
+        assert np.allclose(ex["T"][k, k], f.Tkk[k], atol=tol * 10 * np.abs(f.Tkk[k]).max())
+        for i in range(k + 1, f.p):
+            assert np.allclose(ex["dense"][i, k], f.A.D[(i, k)], atol=tol * 10)
+            assert np.allclose(ex["T"][i, k], f.Tik[(i, k)], atol=tol * 10 * np.abs(f.Tik[(i, k)]).max())
+    # Q^T A = [R; 0] and Q Q^T B = B through the library
+    At = torch.tensor(A, device="cuda")
+    QtA = G.apply_qt(At).cpu().numpy()
+    assert np.linalg.norm(QtA[:n] - Rg) / np.linalg.norm(A) <= tol
+    assert np.linalg.norm(QtA[n:]) / np.linalg.norm(A) <= tol
+    B = torch.tensor(synth.rhs(1, m, 3), device="cuda")
+    back = G.apply_qt(G.apply_qt(B), trans=True)
+    assert torch.allclose(back, B, atol=1e-12)
+
+
+def kernel_case(seed, m, n, b, eps, cap, kern, dim, rule):
+    x, y = synth.kernel_points(seed, m, n, dim)
+    A = blrmat.kernel_matrix(x, y, kern)
+    mask = blrmat.lowrank_mask(x, y, b, rule, m // b, n // b)
+    return x, y, A, mask
+
+
+CASES = [
+    # (seed, m, n, b, eps, cap, kernel, dim, rule)
+    (0, 512, 256, 64, 1e-8, 16, "log2d", 2, "adjacent"),
+    (1, 512, 256, 32, 1e-8, 32, "inv_r", 3, "dist_gt_diam"),
+    (2, 384, 192, 48, 1e-6, 16, "log2d", 2, "weak"),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_tiled_factor_of_imported_blr_matches_oracle(lib, case):
+    seed, m, n, b, eps, cap, kern, dim, rule = case
+    log_case(test="tiled_import", case=case)
+    x, y, A, mask = kernel_case(seed, m, n, b, eps, cap, kern, dim, rule)
+    blr = blrmat.compress(A, b, eps, cap, mask, "dense")
+    At = blr.to_dense()
+    f = tiled.factor(blr, eps, cap)
+    G = gpu_import(lib, blr, eps, cap)
+    G.factor("tiled")
+    ex = G.export(with_factor=True)
+    # the same fill-in (OP1) decisions
+    assert np.array_equal(ex["fmt"], f.A.fmt)
+    kappa = np.linalg.cond(At)
+    Rg, Ro = export_r(ex), f.r_dense()
+    rel = np.linalg.norm(metrics.sign_fix(Rg, Ro) - Ro) / np.linalg.norm(Ro)
+    print("R rel diff", rel, "kappa", kappa, flush=True)
+    assert rel <= 10 * kappa * eps
+    # factorization residual of the GPU result, through the library's Q
+    RR = np.zeros((m, n))
+    RR[:n] = Rg
+    QR = G.apply_qt(torch.tensor(RR, device="cuda"), trans=True).cpu().numpy()
+    res = np.linalg.norm(QR - At) / np.linalg.norm(At)
+    print("Res_At", res, "oracle", metrics.res(f, At), flush=True)
+    assert res <= 10 * eps
+    info = G.info()
+    assert info["state"] == 1
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_compression_matches_oracle(lib, case):
+    seed, m, n, b, eps, cap, kern, dim, rule = case
+    log_case(test="compress", case=case)
+    x, y, A, mask = kernel_case(seed, m, n, b, eps, cap, kern, dim, rule)
+    blr = blrmat.compress(A, b, eps, cap, mask, "dense")
+    G = lib.BLRMatrix.compress_kernel(torch.tensor(x, device="cuda"), torch.tensor(y, device="cuda"),
+                                      kern, b, eps, cap, admissibility=rule, overflow="dense")
+    ex = G.export()
+    p, q = m // b, n // b
+    lr_o = blr.fmt == LOWRANK
+    lr_g = ex["fmt"] == 1
+    # admissibility is exact; overflow decisions may differ only at the threshold
+    assert np.all(lr_g <= mask) and np.all(lr_o <= mask)
+    assert np.sum(lr_g != lr_o) <= max(1, lr_o.sum() // 20)
+    for i in range(p):
+        for j in range(q):
+            blk = A[i * b:(i + 1) * b, j * b:(j + 1) * b]
+            err = np.linalg.norm(export_tile(ex, i, j) - blk)
+            assert err <= eps * np.linalg.norm(blk) * (1 + 1e-6) + 1e-300
+            if lr_g[i, j]:
+                Ug = ex["U"][i, j][:, :ex["rank"][i, j]]
+                assert np.linalg.norm(Ug.T @ Ug - np.eye(Ug.shape[1])) <= 1e3 * U
+                if lr_o[i, j]:
+                    assert abs(int(ex["rank"][i, j]) - blr.rank(i, j)) <= 1
