@@ -169,7 +169,8 @@ void execute(blr_matrix h, Plan& P, hipStream_t s) {
   for (const Op& o : P.ops) {
     switch (o.kind) {
       case Op::GEMM: {
-        const bool rec = h->prof_on && o.prof;
+        // the dominant kernel: 128x128 products in the factor's compute precision
+        const bool rec = h->prof_on && o.big && o.fp32 == (h->precision == BLR_MIXED_FP32 ? 1 : 0);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (rec) {
           HIPCHECK(hipEventCreate(&e0));
