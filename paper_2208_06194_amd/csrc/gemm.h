@@ -43,8 +43,17 @@ struct GemmDesc {
   int32_t pad_;
 };
 
-// Launch host wrapper: descs / segs are device arrays; ntiles = total WG tiles.
-// big = 1 selects 128x128 tiles (else 64x64); fp32 = 1 computes in FP32 on
+// Kernel variants: generic 64x64 and 128x128 tiles (any shape, masks, several
+// K segments) and the fast 128x128 path (full tiles, one K segment, K % 16 == 0,
+// 16-byte aligned operands and even leading dimensions, no masked triangles),
+// specialised on the two transposes.
+enum GemmMode {
+  GEMM_SMALL = 0, GEMM_BIG = 1,
+  GEMM_FAST_NN = 2, GEMM_FAST_TN = 3, GEMM_FAST_NT = 4, GEMM_FAST_TT = 5,
+};
+
+// Launch host wrapper: descs / segs are device arrays; ntiles = total WG tiles
+// (tiles of 64 for GEMM_SMALL, 128 otherwise).  fp32 = 1 computes in FP32 on
 // the matrix cores (operands rounded to FP32, FP32 accumulation).
 hipError_t launch_gemm(const GemmDesc* d_descs, int ndesc, const GemmSeg* d_segs, int ntiles,
-                       int big, int fp32, hipStream_t stream);
+                       int mode, int fp32, hipStream_t stream);

@@ -191,22 +191,165 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   }
 }
 
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const d2v gd2v;
+
+// Fast path for full 128 x 128 output tiles with one K segment (K a multiple
+// of 16, 16-byte aligned operands, no masked triangles; an upper triangular A
+// only prunes the K range).  Transposes are compile-time; global loads are
+// 16-byte vectors from precomputed per-thread addresses; LDS is double
+// buffered so each K step needs a single barrier.
+template <typename CT, bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm_fast(const GemmDesc* __restrict__ descs, int ndesc,
+                                                   const GemmSeg* __restrict__ segs) {
+  constexpr int BM = 128, BN = 128, BK = 16, PAD = 2;
+  typedef typename AccT<CT>::T acc_t;
+  __shared__ CT As[2][BK][BM + PAD];
+  __shared__ CT Bs[2][BK][BN + PAD];
+
+  const int wg = blockIdx.x;
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].tile_begin <= wg) lo = mid;
+    else hi = mid - 1;
+  }
+  const GemmDesc d = descs[lo];
+  const int t = wg - d.tile_begin;
+  const int m0 = (t % d.tilesM) * BM;
+  const int n0 = (t / d.tilesM) * BN;
+  if ((d.flags & DESC_LOWER_ONLY) && m0 + BM <= n0) return;
+  const GemmSeg sg = segs[d.seg_begin];
+  int kbeg = 0, kend = sg.K;
+  if (sg.flags & SEG_A_UPPER) {
+    if (TA) kend = min(kend, m0 + BM);
+    else kbeg = m0;
+  }
+  if (d.nseg == 0) kend = kbeg;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  // per-thread load coordinates: 8 consecutive doubles per operand per K step
+  const int a_mk = TA ? (tid >> 1) : (tid >> 4);        // TA: m; else k
+  const int a_8 = TA ? (tid & 1) * 8 : (tid & 15) * 8;  // TA: k offset; else m offset
+  const int b_nk = TB ? (tid >> 4) : (tid >> 1);        // TB: k; else n
+  const int b_8 = TB ? (tid & 15) * 8 : (tid & 1) * 8;  // TB: n offset; else k offset
+  const double* ap = TA ? sg.A + (int64_t)(m0 + a_mk) * sg.lda + kbeg + a_8
+                        : sg.A + (int64_t)(kbeg + a_mk) * sg.lda + m0 + a_8;
+  const double* bp = TB ? sg.B + (int64_t)(kbeg + b_nk) * sg.ldb + n0 + b_8
+                        : sg.B + (int64_t)(n0 + b_nk) * sg.ldb + kbeg + b_8;
+  const int64_t astep = TA ? BK : (int64_t)BK * sg.lda;
+  const int64_t bstep = TB ? (int64_t)BK * sg.ldb : BK;
+
+  acc_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
+
+  d2v ra[4], rb[4];
+  auto gload = [&](int step) {
+    const gd2v* pa = (const gd2v*)(ap + step * astep);
+    const gd2v* pb = (const gd2v*)(bp + step * bstep);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ra[q] = pa[q];
+      rb[q] = pb[q];
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        if (TA) As[buf][a_8 + 2 * q + e][a_mk] = (CT)ra[q][e];
+        else As[buf][a_mk][a_8 + 2 * q + e] = (CT)ra[q][e];
+        if (TB) Bs[buf][b_nk][b_8 + 2 * q + e] = (CT)rb[q][e];
+        else Bs[buf][b_8 + 2 * q + e][b_nk] = (CT)rb[q][e];
+      }
+  };
+
+  const int nsteps = (kend - kbeg) / BK;
+  if (nsteps > 0) {
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int st = 0; st < nsteps; ++st) {
+      const int buf = st & 1;
+      const bool more = st + 1 < nsteps;
+      if (more) gload(st + 1);
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        CT af[4], bf[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) af[i] = As[buf][kk + (lane >> 4)][wm * 64 + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bf[j] = Bs[buf][kk + (lane >> 4)][wn * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = mfma_op(af[i], bf[j], acc[i][j]);
+      }
+      if (more) lstore(buf ^ 1);
+      __syncthreads();
+    }
+  }
+
+  constexpr bool f64out = sizeof(CT) == 8;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm * 64 + i * 16 + (f64out ? v * 4 + (lane >> 4) : (lane >> 4) * 4 + v);
+        const double raw = (double)acc[i][j][v];
+        if (d.C) {
+          double c = d.alpha * raw;
+          if (d.Cin) c += d.beta * d.Cin[row + (int64_t)col * d.ldcin];
+          d.C[row + (int64_t)col * d.ldc] = c;
+        }
+        if (d.D2) d.D2[row + (int64_t)col * d.ldd2] = raw;
+      }
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_gemm(const GemmDesc* d_descs, int ndesc, const GemmSeg* d_segs, int ntiles,
-                       int big, int fp32, hipStream_t stream) {
+                       int mode, int fp32, hipStream_t stream) {
   if (ndesc <= 0 || ntiles <= 0) return hipSuccess;
   dim3 grid(ntiles), block(256);
-  if (big) {
-    if (fp32)
-      hipLaunchKernelGGL((k_gemm<float, 128, 128>), grid, block, 0, stream, d_descs, ndesc, d_segs);
-    else
-      hipLaunchKernelGGL((k_gemm<double, 128, 128>), grid, block, 0, stream, d_descs, ndesc, d_segs);
-  } else {
-    if (fp32)
-      hipLaunchKernelGGL((k_gemm<float, 64, 64>), grid, block, 0, stream, d_descs, ndesc, d_segs);
-    else
-      hipLaunchKernelGGL((k_gemm<double, 64, 64>), grid, block, 0, stream, d_descs, ndesc, d_segs);
+#define BLR_FAST(CT, TA, TB) \
+  hipLaunchKernelGGL((k_gemm_fast<CT, TA, TB>), grid, block, 0, stream, d_descs, ndesc, d_segs)
+  switch (mode) {
+    case GEMM_SMALL:
+      if (fp32) hipLaunchKernelGGL((k_gemm<float, 64, 64>), grid, block, 0, stream, d_descs, ndesc, d_segs);
+      else hipLaunchKernelGGL((k_gemm<double, 64, 64>), grid, block, 0, stream, d_descs, ndesc, d_segs);
+      break;
+    case GEMM_BIG:
+      if (fp32) hipLaunchKernelGGL((k_gemm<float, 128, 128>), grid, block, 0, stream, d_descs, ndesc, d_segs);
+      else hipLaunchKernelGGL((k_gemm<double, 128, 128>), grid, block, 0, stream, d_descs, ndesc, d_segs);
+      break;
+    case GEMM_FAST_NN:
+      if (fp32) BLR_FAST(float, false, false); else BLR_FAST(double, false, false);
+      break;
+    case GEMM_FAST_TN:
+      if (fp32) BLR_FAST(float, true, false); else BLR_FAST(double, true, false);
+      break;
+    case GEMM_FAST_NT:
+      if (fp32) BLR_FAST(float, false, true); else BLR_FAST(double, false, true);
+      break;
+    case GEMM_FAST_TT:
+      if (fp32) BLR_FAST(float, true, true); else BLR_FAST(double, true, true);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
+#undef BLR_FAST
   return hipGetLastError();
 }

@@ -30,3 +30,6 @@ struct TBackArgs {
 
 hipError_t launch_panel(const PanelArgs& a, hipStream_t stream);
 hipError_t launch_t_backsolve(const TBackArgs& a, hipStream_t stream);
+// Fused trailing update of the nt columns right of panel a (same PanelArgs:
+// X points at the panel's first column / first row, T at its diagonal block).
+hipError_t launch_panel_apply(const PanelArgs& a, int nt, hipStream_t stream);

@@ -23,107 +23,117 @@
 
 namespace {
 
-template <int ROWS, int IB>
-__global__ __launch_bounds__(256) void k_panel(PanelArgs a) {
-  __shared__ double red[4][IB];      // per-wave partial dot products
-  __shared__ double prow[IB];        // pivot row (GEQRT) / R row (TPQRT)
-  __shared__ double top[IB][IB + 1]; // TPQRT: R diagonal block
-  __shared__ double Tl[IB][IB + 1];  // T of this panel
+// Owner-wave panel factorization: 1024 threads, wave w owns panel columns
+// w*CPW .. w*CPW+CPW-1 (IB = 16*CPW), lane l holds rows l + 64*s, s < RS.
+// Column jj: the owner wave reduces the tail norm and writes the scaled
+// reflector to LDS; every wave then forms the dot products of the reflector
+// with its own columns by one wavefront reduction per column and applies the
+// rank-one update in registers.
+template <int RS, int CPW>
+__global__ __launch_bounds__(1024) void k_panel(PanelArgs a) {
+  constexpr int IB = 16 * CPW;
+  __shared__ double vbuf[64 * RS];
+  __shared__ double top[IB][IB + 1];
+  __shared__ double Tl[IB][IB + 1];
   __shared__ double gcol[IB];
+  __shared__ double sc[2];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const bool tp = a.mode == PANEL_TPQRT;
   const int h = a.h;
   double* X = a.X;
   const int64_t ldx = a.ldx;
 
-  double x[ROWS][IB];
+  double x[CPW][RS];
 #pragma unroll
-  for (int rr = 0; rr < ROWS; ++rr) {
-    const int r = tid + 256 * rr;
+  for (int cc = 0; cc < CPW; ++cc)
 #pragma unroll
-    for (int c = 0; c < IB; ++c) x[rr][c] = (r < h) ? X[r + c * ldx] : 0.0;
-  }
-  if (tp) {
-    for (int e = tid; e < IB * IB; e += 256) {
-      const int r = e % IB, c = e / IB;
-      top[r][c] = (r <= c) ? a.R[r + c * a.ldr] : 0.0;
+    for (int s = 0; s < RS; ++s) {
+      const int r = lane + 64 * s;
+      x[cc][s] = (r < h) ? X[r + (int64_t)(w * CPW + cc) * ldx] : 0.0;
     }
+  for (int e = tid; e < IB * IB; e += 1024) {
+    const int r = e % IB, c = e / IB;
+    top[r][c] = (tp && r <= c) ? a.R[r + (int64_t)c * a.ldr] : 0.0;
+    Tl[r][c] = 0.0;
   }
-  for (int e = tid; e < IB * IB; e += 256) Tl[e % IB][e / IB] = 0.0;
   __syncthreads();
 
   for (int jj = 0; jj < IB; ++jj) {
-    // extract column jj, pivot row values
-    double v[ROWS];
-    bool tail[ROWS];
+    const int ow = jj / CPW, oc = jj % CPW;
+    const int ps = jj >> 6, pl = jj & 63;   // GEQRT pivot: slot and lane of row jj
+    if (w == ow) {
+      double val[RS];
 #pragma unroll
-    for (int rr = 0; rr < ROWS; ++rr) {
-      const int r = tid + 256 * rr;
-      double s = 0.0;
+      for (int s = 0; s < RS; ++s) {
+        double t = 0.0;
 #pragma unroll
-      for (int c = 0; c < IB; ++c) s = (c == jj) ? x[rr][c] : s;
-      v[rr] = s;
-      tail[rr] = tp ? (r < h) : (r > jj && r < h);
-      if (!tp && r == jj) {
-#pragma unroll
-        for (int c = 0; c < IB; ++c) prow[c] = x[rr][c];
+        for (int cc = 0; cc < CPW; ++cc) t = (cc == oc) ? x[cc][s] : t;
+        val[s] = t;
       }
-    }
-    if (tp && tid < IB) prow[tid] = (tid > jj) ? top[jj][tid] : 0.0;
-    double ss = 0.0;
+      double ss = 0.0, piv = 0.0;
 #pragma unroll
-    for (int rr = 0; rr < ROWS; ++rr) ss += tail[rr] ? v[rr] * v[rr] : 0.0;
-    const double xnorm2 = block_sum(ss, &red[0][0]);   // has barriers: prow visible after
-    const double alpha = tp ? top[jj][jj] : prow[jj];
-    double beta, tau, scal;
-    larfg_scalars(alpha, xnorm2, &beta, &tau, &scal);
+      for (int s = 0; s < RS; ++s) {
+        const int r = lane + 64 * s;
+        const bool tail = tp ? (r < h) : (r > jj && r < h);
+        ss += tail ? val[s] * val[s] : 0.0;
+        piv = (s == ps) ? val[s] : piv;
+      }
+      ss = wave_sum(ss);
+      const double alpha = tp ? top[jj][jj] : __shfl(piv, pl, 64);
+      double beta, tau, scal;
+      larfg_scalars(alpha, ss, &beta, &tau, &scal);
 #pragma unroll
-    for (int rr = 0; rr < ROWS; ++rr) v[rr] = tail[rr] ? v[rr] * scal : 0.0;
-    // dot products of the new reflector with every other panel column
-    double part[IB];
+      for (int s = 0; s < RS; ++s) {
+        const int r = lane + 64 * s;
+        const bool tail = tp ? (r < h) : (r > jj && r < h);
+        const double v = tail ? val[s] * scal : 0.0;
+        vbuf[r] = v;
+        const double nv = tail ? v : ((!tp && r == jj) ? beta : val[s]);
 #pragma unroll
-    for (int c = 0; c < IB; ++c) {
-      double s = 0.0;
-#pragma unroll
-      for (int rr = 0; rr < ROWS; ++rr) s += v[rr] * x[rr][c];
-      part[c] = wave_sum(s);
-    }
-    __syncthreads();  // all reads of red / prow done
-    if (lane == 0) {
-#pragma unroll
-      for (int c = 0; c < IB; ++c) red[wave][c] = part[c];
+        for (int cc = 0; cc < CPW; ++cc)
+          if (cc == oc) x[cc][s] = nv;
+      }
+      if (lane == 0) {
+        sc[0] = tau;
+        sc[1] = beta;
+        Tl[jj][jj] = tau;
+        a.tau[jj] = tau;
+        if (tp) top[jj][jj] = beta;
+      }
     }
     __syncthreads();
-    double w[IB];
+    const double tau = sc[0];
+    double v[RS];
 #pragma unroll
-    for (int c = 0; c < IB; ++c) {
-      const double pr = (!tp || c > jj) ? prow[c] : 0.0;
-      w[c] = pr + red[0][c] + red[1][c] + red[2][c] + red[3][c];
-    }
-    // store the reflector into column jj and update the later columns
+    for (int s = 0; s < RS; ++s) v[s] = vbuf[lane + 64 * s];
 #pragma unroll
-    for (int rr = 0; rr < ROWS; ++rr) {
-      const int r = tid + 256 * rr;
+    for (int cc = 0; cc < CPW; ++cc) {
+      const int c = w * CPW + cc;
+      if (c == jj) continue;
+      double d = 0.0, prow = 0.0;
 #pragma unroll
-      for (int c = 0; c < IB; ++c) {
-        if (c == jj) {
-          if (tail[rr]) x[rr][c] = v[rr];
-          else if (!tp && r == jj) x[rr][c] = beta;
-        } else if (c > jj) {
-          if (tail[rr]) x[rr][c] -= tau * w[c] * v[rr];
-          else if (!tp && r == jj) x[rr][c] -= tau * w[c];
+      for (int s = 0; s < RS; ++s) {
+        d += v[s] * x[cc][s];
+        prow = (s == ps) ? x[cc][s] : prow;
+      }
+      d = wave_sum(d);
+      // pivot-row term: GEQRT row jj of column c; TPQRT R(jj, c) for c > jj
+      const double pr = tp ? (c > jj ? top[jj][c] : 0.0) : __shfl(prow, pl, 64);
+      const double wc = d + pr;
+      if (c > jj && tau != 0.0) {
+#pragma unroll
+        for (int s = 0; s < RS; ++s) x[cc][s] -= tau * wc * v[s];
+        if (!tp) {
+#pragma unroll
+          for (int s = 0; s < RS; ++s)
+            if (s == ps && lane == pl) x[cc][s] -= tau * wc;
+        } else if (lane == 0) {
+          top[jj][c] -= tau * wc;
         }
       }
+      if (c < jj && lane == 0) gcol[c] = wc;
     }
-    if (tid < IB) {
-      const double pr = (!tp || tid > jj) ? prow[tid] : 0.0;
-      const double wt = pr + red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-      gcol[tid] = wt;
-      if (tp && tid > jj) top[jj][tid] -= tau * wt;
-    }
-    if (tp && tid == 0) top[jj][jj] = beta;
-    if (tid == 0) Tl[jj][jj] = tau;
     __syncthreads();
     // T column jj of this panel: T[c][jj] = -tau * sum_{t=c}^{jj-1} T[c][t] g_t
     if (tid < jj) {
@@ -131,31 +141,152 @@ __global__ __launch_bounds__(256) void k_panel(PanelArgs a) {
       for (int tt = tid; tt < jj; ++tt) s += Tl[tid][tt] * gcol[tt];
       Tl[tid][jj] = -tau * s;
     }
-    if (tid == 0) a.tau[jj] = tau;
     __syncthreads();
   }
 
 #pragma unroll
-  for (int rr = 0; rr < ROWS; ++rr) {
-    const int r = tid + 256 * rr;
-    if (r < h) {
+  for (int cc = 0; cc < CPW; ++cc)
 #pragma unroll
-      for (int c = 0; c < IB; ++c) X[r + c * ldx] = x[rr][c];
+    for (int s = 0; s < RS; ++s) {
+      const int r = lane + 64 * s;
+      if (r < h) X[r + (int64_t)(w * CPW + cc) * ldx] = x[cc][s];
     }
-  }
-  if (tp) {
-    for (int e = tid; e < IB * IB; e += 256) {
-      const int r = e % IB, c = e / IB;
-      if (r <= c) a.R[r + c * a.ldr] = top[r][c];
-    }
-  }
-  for (int e = tid; e < IB * IB; e += 256) {
+  for (int e = tid; e < IB * IB; e += 1024) {
     const int r = e % IB, c = e / IB;
-    if (r <= c) a.T[r + c * a.ldt] = Tl[r][c];
+    if (r <= c) {
+      if (tp) a.R[r + (int64_t)c * a.ldr] = top[r][c];
+      a.T[r + (int64_t)c * a.ldt] = Tl[r][c];
+    }
   }
 }
 
-// One wave per column c of T (n x n); rows above the IB-block of c.
+// Trailing update of one panel, fused, on the matrix cores: for a block of
+// NC = 32 trailing columns,
+//   TPQRT: W = R_rows + V^T B;  W2 = T^T W;  R_rows -= W2;  B -= V W2
+//   GEQRT: W = V^T C;           W2 = T^T W;  C -= V W2   (V unit lower)
+// One workgroup (4 waves) per column block.  V and B are staged through LDS
+// in chunks of 64 rows (column-contiguous global reads); V^T B splits each
+// chunk's rows over the 4 waves (partial sums reduced in LDS), V W2 gives
+// each wave 16 rows of the chunk.
+template <int IB>
+__global__ __launch_bounds__(256) void k_panel_apply(PanelArgs a, int nt) {
+  constexpr int NC = 32, CH = 64, MT = IB / 16;
+  __shared__ double Vs[CH][IB + 1];
+  __shared__ double Bs[CH][NC + 1];
+  __shared__ double Wp[4][IB][NC + 1];
+  __shared__ double Tt[IB][IB + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const bool tp = a.mode == PANEL_TPQRT;
+  const int c0 = blockIdx.x * NC;
+  const int nc = min(NC, nt - c0);
+  const int h = a.h;
+  const double* V = a.X;
+  double* B = a.X + (int64_t)(IB + c0) * a.ldx;
+  const int64_t ld = a.ldx;
+  for (int e = tid; e < IB * IB; e += 256) Tt[e % IB][e / IB] = a.T[(e % IB) + (int64_t)(e / IB) * a.ldt];
+
+  auto load_v = [&](int r0) {
+    for (int e = tid; e < CH * IB; e += 256) {
+      const int r = e % CH, l = e / CH, gr = r0 + r;
+      double v = 0.0;
+      if (gr < h) {
+        v = V[gr + (int64_t)l * ld];
+        if (!tp) v = gr > l ? v : (gr == l ? 1.0 : 0.0);
+      }
+      Vs[r][l] = v;
+    }
+  };
+
+  // phase 1: W = V^T B
+  v4d acc[MT][2];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[mt][j][v] = 0.0;
+  for (int r0 = 0; r0 < h; r0 += CH) {
+    __syncthreads();
+    load_v(r0);
+    for (int e = tid; e < CH * NC; e += 256) {
+      const int r = e % CH, c = e / CH, gr = r0 + r;
+      Bs[r][c] = (gr < h && c < nc) ? B[gr + (int64_t)c * ld] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int kr = 16 * w + 4 * ks + (lane >> 4);
+      double af[MT], bf[2];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) af[mt] = Vs[kr][mt * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bf[j] = Bs[kr][j * 16 + (lane & 15)];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[mt][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mt], bf[j], acc[mt][j], 0, 0, 0);
+    }
+  }
+  // f64 MFMA output layout: accumulator v of lane l is row 4v + l/16, column l%16
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Wp[w][mt * 16 + 4 * v + (lane >> 4)][j * 16 + (lane & 15)] = acc[mt][j][v];
+  __syncthreads();
+  for (int e = tid; e < IB * NC; e += 256) {
+    const int l = e % IB, c = e / IB;
+    double s = Wp[0][l][c] + Wp[1][l][c] + Wp[2][l][c] + Wp[3][l][c];
+    if (tp && c < nc) s += a.R[l + (int64_t)(IB + c0 + c) * a.ldr];
+    Wp[0][l][c] = s;
+  }
+  __syncthreads();
+  // W2 = T^T W (T upper triangular), kept in Wp[1]; R_rows -= W2
+  for (int e = tid; e < IB * NC; e += 256) {
+    const int l = e % IB, c = e / IB;
+    double s = 0.0;
+    for (int m = 0; m <= l; ++m) s += Tt[m][l] * Wp[0][m][c];
+    Wp[1][l][c] = s;
+    if (tp && c < nc) a.R[l + (int64_t)(IB + c0 + c) * a.ldr] -= s;
+  }
+  // phase 3: B -= V W2, 64 rows per chunk, wave w computes rows 16w..16w+15
+  for (int r0 = 0; r0 < h; r0 += CH) {
+    __syncthreads();
+    load_v(r0);
+    __syncthreads();
+    v4d p[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) p[j][v] = 0.0;
+#pragma unroll
+    for (int ks = 0; ks < IB / 4; ++ks) {
+      const double af = Vs[16 * w + (lane & 15)][4 * ks + (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const double bf = Wp[1][4 * ks + (lane >> 4)][j * 16 + (lane & 15)];
+        p[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, p[j], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Bs[16 * w + 4 * v + (lane >> 4)][j * 16 + (lane & 15)] = p[j][v];
+    __syncthreads();
+    for (int e = tid; e < CH * NC; e += 256) {
+      const int r = e % CH, c = e / CH, gr = r0 + r;
+      if (gr < h && c < nc) B[gr + (int64_t)c * ld] -= Bs[r][c];
+    }
+  }
+}
+
+// One wave per column c of T (n x n); rows above the IB-block of c are
+// filled by back-substitution in blocks of 8 rows: the 8 dot products with
+// the already known part of the column are formed together (their loads and
+// reductions overlap), then the 8 x 8 triangle is solved redundantly by every
+// lane.  Lane l owns x[t] for t = l (mod 64) in LDS.
 __global__ __launch_bounds__(256) void k_t_backsolve(TBackArgs a) {
   extern __shared__ double xs[];  // 4 waves x n
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -165,38 +296,70 @@ __global__ __launch_bounds__(256) void k_t_backsolve(TBackArgs a) {
   const int bs = (c / a.ib) * a.ib;
   const double* G = a.G;
   const int64_t ldg = a.ldg;
-  // lane l owns entries t = l (mod 64) of x: it is the only lane that writes
-  // or reads them, so no cross-lane synchronisation is needed
   for (int t = bs + ((lane - bs) & 63); t <= c; t += 64) x[t] = a.T[t + (int64_t)c * a.ldt];
-  for (int r = bs - 1; r >= 0; --r) {
-    double s = 0.0;
-    for (int t = r + 1 + ((lane - (r + 1)) & 63); t <= c; t += 64) s += G[t + (int64_t)r * ldg] * x[t];
-    s = wave_sum(s);
-    const double xr = -a.tau[r] * s;
-    if ((r & 63) == lane) x[r] = xr;
-    if (lane == 0) a.T[r + (int64_t)c * a.ldt] = xr;
+  for (int r1 = bs - 1; r1 >= 0; r1 -= 8) {
+    const int r0 = r1 - 7;   // block rows r0..r1 (bs is a multiple of 8)
+    double d[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) d[q] = 0.0;
+    for (int t = r1 + 1 + ((lane - (r1 + 1)) & 63); t <= c; t += 64) {
+      const double xt = x[t];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) d[q] += G[t + (int64_t)(r0 + q) * ldg] * xt;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) d[q] = wave_sum(d[q]);
+    // within-block triangle: rows r1 down to r0
+    double xb[8];
+#pragma unroll
+    for (int q = 7; q >= 0; --q) {
+      double s = d[q];
+#pragma unroll
+      for (int u = q + 1; u < 8; ++u) s += G[(r0 + u) + (int64_t)(r0 + q) * ldg] * xb[u];
+      xb[q] = -a.tau[r0 + q] * s;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int r = r0 + q;
+      if ((r & 63) == lane) x[r] = xb[q];
+      if (lane == q) a.T[r + (int64_t)c * a.ldt] = xb[q];
+    }
   }
-  // zero the strictly lower part of column c
   for (int r = c + 1 + lane; r < a.n; r += 64) a.T[r + (int64_t)c * a.ldt] = 0.0;
 }
 
 }  // namespace
 
 hipError_t launch_panel(const PanelArgs& a, hipStream_t stream) {
-  const int rows = (a.h + 255) / 256;
-  dim3 grid(1), block(256);
+  const int rs = (a.h + 63) / 64;
+  dim3 grid(1), block(1024);
+#define BLR_PANEL(RSV, CPWV) hipLaunchKernelGGL((k_panel<RSV, CPWV>), grid, block, 0, stream, a)
   if (a.ib == 32) {
-    if (rows <= 1) hipLaunchKernelGGL((k_panel<1, 32>), grid, block, 0, stream, a);
-    else if (rows <= 2) hipLaunchKernelGGL((k_panel<2, 32>), grid, block, 0, stream, a);
+    if (rs <= 1) BLR_PANEL(1, 2);
+    else if (rs <= 2) BLR_PANEL(2, 2);
+    else if (rs <= 4) BLR_PANEL(4, 2);
+    else if (rs <= 8) BLR_PANEL(8, 2);
     else return hipErrorInvalidValue;  // tall panels use ib = 16 (register budget)
   } else if (a.ib == 16) {
-    if (rows <= 1) hipLaunchKernelGGL((k_panel<1, 16>), grid, block, 0, stream, a);
-    else if (rows <= 2) hipLaunchKernelGGL((k_panel<2, 16>), grid, block, 0, stream, a);
-    else if (rows <= 4) hipLaunchKernelGGL((k_panel<4, 16>), grid, block, 0, stream, a);
+    if (rs <= 1) BLR_PANEL(1, 1);
+    else if (rs <= 2) BLR_PANEL(2, 1);
+    else if (rs <= 4) BLR_PANEL(4, 1);
+    else if (rs <= 8) BLR_PANEL(8, 1);
+    else if (rs <= 16) BLR_PANEL(16, 1);
     else return hipErrorInvalidValue;
   } else {
     return hipErrorInvalidValue;
   }
+#undef BLR_PANEL
+  return hipGetLastError();
+}
+
+hipError_t launch_panel_apply(const PanelArgs& a, int nt, hipStream_t stream) {
+  if (nt <= 0) return hipSuccess;
+  dim3 grid((nt + 31) / 32), block(256);
+  if (a.ib == 32) hipLaunchKernelGGL((k_panel_apply<32>), grid, block, 0, stream, a, nt);
+  else if (a.ib == 16) hipLaunchKernelGGL((k_panel_apply<16>), grid, block, 0, stream, a, nt);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

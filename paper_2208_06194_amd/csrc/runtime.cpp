@@ -91,8 +91,26 @@ void Plan::flush_gemm(int fp32, int prof) {
   if (cur.empty()) return;
   int mn = 1 << 30;
   for (auto& d : cur) mn = std::min(mn, std::min(d.M, d.N));
-  const int big = mn >= 256 ? 1 : 0;
-  const int BM = big ? 128 : 64;
+  int big = mn >= 256 ? GEMM_BIG : GEMM_SMALL;
+  if (big == GEMM_BIG) {
+    // fast path: full tiles, single uniform segment, aligned, no masks
+    bool ok = true;
+    int tflags = -1;
+    auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+    for (auto& d : cur) {
+      if (d.M % 128 || d.N % 128 || d.nseg != 1) { ok = false; break; }
+      const GemmSeg& sg = curseg[d.seg_begin];
+      const int tf = sg.flags & (SEG_TRANS_A | SEG_TRANS_B);
+      if (tflags < 0) tflags = tf;
+      if (tf != tflags || (sg.flags & (SEG_A_UNIT_LOWER | SEG_B_UNIT_LOWER)) || sg.K % 16 ||
+          !al(sg.A) || !al(sg.B) || (sg.lda & 1) || (sg.ldb & 1)) { ok = false; break; }
+    }
+    if (ok) {
+      const bool ta = tflags & SEG_TRANS_A, tb = tflags & SEG_TRANS_B;
+      big = ta ? (tb ? GEMM_FAST_TT : GEMM_FAST_TN) : (tb ? GEMM_FAST_NT : GEMM_FAST_NN);
+    }
+  }
+  const int BM = big == GEMM_SMALL ? 64 : 128;
   Op o;
   o.kind = Op::GEMM;
   o.off = (int)descs.size();
@@ -112,6 +130,7 @@ void Plan::flush_gemm(int fp32, int prof) {
   }
   segs.insert(segs.end(), curseg.begin(), curseg.end());
   o.ntiles = tiles;
+  o.stream = cur_stream;
   ops.push_back(o);
   cur.clear();
   curseg.clear();
@@ -124,6 +143,7 @@ void Plan::flush_rc() {
   o.kind = Op::RC;
   o.off = (int)rcs.size();
   o.n = (int)currc.size();
+  o.stream = cur_stream;
   rcs.insert(rcs.end(), currc.begin(), currc.end());
   ops.push_back(o);
   currc.clear();
@@ -165,41 +185,91 @@ RcParams rc_params(blr_matrix h) {
   return p;
 }
 
+constexpr int kStreams = 4;
+
+void ensure_streams(blr_matrix h) {
+  while ((int)h->streams.size() < kStreams) {
+    hipStream_t st;
+    HIPCHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    h->streams.push_back(st);
+  }
+}
+
+// Enqueue a plan.  Ops name one of the handle's look-ahead streams; the
+// caller's stream s is joined before the first op and after the last one.
 void execute(blr_matrix h, Plan& P, hipStream_t s) {
+  int nstreams = 1;
+  for (const Op& o : P.ops) nstreams = std::max(nstreams, o.stream + 1);
+  std::vector<hipStream_t> st(nstreams, s);
+  std::vector<hipEvent_t> ev(P.n_events, nullptr);
+  hipEvent_t join = nullptr;
+  if (nstreams > 1) {
+    ensure_streams(h);
+    for (int a = 0; a < nstreams; ++a) st[a] = h->streams[a];
+    HIPCHECK(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+    HIPCHECK(hipEventRecord(join, s));
+    for (int a = 0; a < nstreams; ++a) HIPCHECK(hipStreamWaitEvent(st[a], join, 0));
+    for (auto& e : ev) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
   for (const Op& o : P.ops) {
+    hipStream_t q = st[o.stream];
     switch (o.kind) {
       case Op::GEMM: {
         // the dominant kernel: 128x128 products in the factor's compute precision
-        const bool rec = h->prof_on && o.big && o.fp32 == (h->precision == BLR_MIXED_FP32 ? 1 : 0);
+        const bool rec = h->prof_on && o.big >= GEMM_FAST_NN && o.fp32 == (h->precision == BLR_MIXED_FP32 ? 1 : 0);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (rec) {
           HIPCHECK(hipEventCreate(&e0));
           HIPCHECK(hipEventCreate(&e1));
-          HIPCHECK(hipEventRecord(e0, s));
+          HIPCHECK(hipEventRecord(e0, q));
         }
-        HIPCHECK(launch_gemm(P.d_descs + o.off, o.n, P.d_segs, o.ntiles, o.big, o.fp32, s));
+        HIPCHECK(launch_gemm(P.d_descs + o.off, o.n, P.d_segs, o.ntiles, o.big, o.fp32, q));
         if (rec) {
-          HIPCHECK(hipEventRecord(e1, s));
+          HIPCHECK(hipEventRecord(e1, q));
           h->prof_ev.push_back(e0);
           h->prof_ev.push_back(e1);
           h->prof_flops += o.flops;
           h->prof_launches += 1;
         }
+        h->launches += 1;
         break;
       }
       case Op::PANEL:
-        HIPCHECK(launch_panel(o.panel, s));
+        HIPCHECK(launch_panel(o.panel, q));
+        h->launches += 1;
+        break;
+      case Op::PANEL_APPLY:
+        HIPCHECK(launch_panel_apply(o.panel, o.n, q));
+        h->launches += 1;
         break;
       case Op::TBACK:
-        HIPCHECK(launch_t_backsolve(o.tback, s));
+        HIPCHECK(launch_t_backsolve(o.tback, q));
+        h->launches += 1;
         break;
       case Op::RC:
-        HIPCHECK(launch_recompress(P.d_rcs + o.off, o.n, rc_params(h), s));
+        HIPCHECK(launch_recompress(P.d_rcs + o.off, o.n, rc_params(h), q));
+        h->launches += 1;
+        break;
+      case Op::WAIT:
+        if (nstreams > 1) HIPCHECK(hipStreamWaitEvent(q, ev[o.event], 0));
+        break;
+      case Op::RECORD:
+        if (nstreams > 1) HIPCHECK(hipEventRecord(ev[o.event], q));
         break;
       default:
         break;
     }
-    h->launches += 1;
+  }
+  if (nstreams > 1) {
+    for (int a = 0; a < nstreams; ++a) {
+      hipEvent_t e;
+      HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      HIPCHECK(hipEventRecord(e, st[a]));
+      HIPCHECK(hipStreamWaitEvent(s, e, 0));
+      HIPCHECK(hipEventDestroy(e));
+    }
+    for (auto& e : ev) HIPCHECK(hipEventDestroy(e));
+    HIPCHECK(hipEventDestroy(join));
   }
 }
 
@@ -282,35 +352,12 @@ void plan_tile_qr(Plan& P, blr_matrix h, Work& w, bool tp, double* X, int64_t ld
       a.X = X + c0 + (int64_t)c0 * ldx;
       a.ldx = ldx;
     }
-    if (hb == 0 && tp) {
-      // an empty bottom block: the reflectors are the identity, tau = 0;
-      // the panel kernel still writes T = 0 and tau = 0
-    }
     P.panel(a);
+    P.ops.back().flops = 2.0 * a.h * ib * ib;
     const int nt = b - c0 - ib;
-    if (nt <= 0) continue;
-    const double* Tl = T + c0 + (int64_t)c0 * b;
-    if (!tp) {
-      double* Vl = X + c0 + (int64_t)c0 * ldx;
-      double* C = X + c0 + (int64_t)(c0 + ib) * ldx;
-      P.gemm(w.Wx, ib, nullptr, 0, nullptr, 0, ib, nt, 1.0, 0.0, Vl, ldx, C, ldx, b - c0,
-             SEG_TRANS_A | SEG_A_UNIT_LOWER);
-      P.flush_gemm();
-      P.gemm(w.Wx2, ib, nullptr, 0, nullptr, 0, ib, nt, 1.0, 0.0, Tl, b, w.Wx, ib, ib,
-             SEG_TRANS_A | SEG_A_UPPER);
-      P.flush_gemm();
-      P.gemm(C, ldx, C, ldx, nullptr, 0, b - c0, nt, -1.0, 1.0, Vl, ldx, w.Wx2, ib, ib, SEG_A_UNIT_LOWER);
-      P.flush_gemm();
-    } else {
-      double* Vl = X + (int64_t)c0 * ldx;
-      double* Bt = X + (int64_t)(c0 + ib) * ldx;
-      double* Rr = R + c0 + (int64_t)(c0 + ib) * b;
-      P.gemm(w.Wx, ib, Rr, b, nullptr, 0, ib, nt, 1.0, 1.0, Vl, ldx, Bt, ldx, hb, SEG_TRANS_A);
-      P.flush_gemm();
-      P.gemm(Rr, b, Rr, b, w.Wx2, ib, ib, nt, -1.0, 1.0, Tl, b, w.Wx, ib, ib, SEG_TRANS_A | SEG_A_UPPER);
-      P.flush_gemm();
-      P.gemm(Bt, ldx, Bt, ldx, nullptr, 0, hb, nt, -1.0, 1.0, Vl, ldx, w.Wx2, ib, ib, 0);
-      P.flush_gemm();
+    if (nt > 0) {
+      P.panel_apply(a, nt);
+      P.ops.back().flops = 4.0 * a.h * ib * nt + (double)ib * ib * nt;
     }
   }
   if (b > ib) {
@@ -330,15 +377,26 @@ void plan_tile_qr(Plan& P, blr_matrix h, Work& w, bool tp, double* X, int64_t ld
     t.T = T;
     t.ldt = b;
     P.tback(t);
+    P.ops.back().flops = (double)b * b * b / 3.0;
   }
 }
 
 enum Case { C_DDD, C_LDL, C_DLD, C_DLL, C_LLD, C_LLL };
 
 // Tiled BLR-QR plan (Alg. 4, Section 3.3).
-void plan_tiled(blr_matrix h, Plan& P, Work& w, int kend, bool fp32) {
+// Look-ahead: block column k runs on stream k % kStreams.  Before touching
+// tile row i it waits for event E(i, k-1), recorded after column k-1 applied
+// its reflector (i, k-1) to that tile row; so the TPQRT chains of
+// neighbouring columns overlap while every tile sees its updates in the
+// order of Alg. 4.
+void plan_tiled(blr_matrix h, Plan& P, std::vector<Work>& works, int kend, bool fp32) {
   const int b = h->b, rc = h->rc, p = h->p, q = h->q;
+  const int ns = (int)works.size();
+  auto ev = [&](int i, int k) { return i * q + k; };
   for (int k = 0; k < kend; ++k) {
+    P.cur_stream = k % ns;
+    Work& w = works[k % ns];
+    if (k > 0) P.wait(ev(k, k - 1));
     Tile& Dkk = h->t(k, k);
     double* Tkk = h->T[(size_t)k * q + k];
     // GEQRT(k)
@@ -367,6 +425,7 @@ void plan_tiled(blr_matrix h, Plan& P, Work& w, int kend, bool fp32) {
       P.flush_gemm(fp32);
     }
     for (int i = k + 1; i < p; ++i) {
+      if (k > 0 && i > k) P.wait(ev(i, k - 1));
       Tile& Aik = h->t(i, k);
       const size_t ik = (size_t)i * q + k;
       double* Tik = h->T[ik];
@@ -378,6 +437,14 @@ void plan_tiled(blr_matrix h, Plan& P, Work& w, int kend, bool fp32) {
       else
         plan_tile_qr(P, h, w, true, Aik.Vt, rc, rc, Dkk.D, Tik, h->tau[ik]);
       if (k + 1 >= q) continue;
+      struct Rec {
+        Plan& P;
+        int e;
+        bool on;
+        ~Rec() {
+          if (on) P.record(e);
+        }
+      } rec{P, ev(i, k), k + 1 < kend};
       double* Y = Aik.D;     // dense reflector block
       double* UY = Aik.U;    // low-rank: Ytilde = UY * Yl
       double* Yl = Aik.Vt;   // rc x b
@@ -1044,10 +1111,11 @@ blr_status blr_qr_factor(blr_matrix h, const blr_factor_opts* o, void* stream) {
       }
     }
     h->work.release();
-    Work w = make_work(h, 0);
+    std::vector<Work> works;
+    for (int a = 0; a < kStreams; ++a) works.push_back(make_work(h, 0));
     Plan P;
     h->n_fill = 0;
-    plan_tiled(h, P, w, kend, o->precision == BLR_MIXED_FP32);
+    plan_tiled(h, P, works, kend, o->precision == BLR_MIXED_FP32);
     P.upload(h->work);
     h->flops = 0.0;
     for (auto& op : P.ops) h->flops += op.flops;
@@ -1251,6 +1319,7 @@ void blr_destroy(blr_matrix h) {
   if (!h) return;
   (void)hipDeviceSynchronize();
   for (auto e : h->prof_ev) (void)hipEventDestroy(e);
+  for (auto st : h->streams) (void)hipStreamDestroy(st);
   delete h;
 }
 

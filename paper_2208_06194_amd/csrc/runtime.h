@@ -44,8 +44,10 @@ struct Arena {
 
 // One enqueued operation of a plan.
 struct Op {
-  enum Kind { GEMM, PANEL, TBACK, RC, TRSM, DENSE_COPY } kind;
+  enum Kind { GEMM, PANEL, PANEL_APPLY, TBACK, RC, TRSM, WAIT, RECORD } kind;
   int off = 0, n = 0, ntiles = 0, big = 0, fp32 = 0, prof = 0;
+  int stream = 0;   // index into the plan's streams
+  int event = -1;   // WAIT / RECORD: event index
   double flops = 0.0;
   PanelArgs panel{};
   TBackArgs tback{};
@@ -65,6 +67,8 @@ struct Plan {
   std::vector<GemmSeg> curseg;
   double curflops = 0.0;
   std::vector<RcDesc> currc;
+  int cur_stream = 0;
+  int n_events = 0;
 
   // add one descriptor with a single K segment
   void gemm(double* C, int64_t ldc, const double* Cin, int64_t ldcin, double* D2, int64_t ldd2,
@@ -73,8 +77,12 @@ struct Plan {
   void flush_gemm(int fp32 = 0, int prof = 0);
   void rc(const RcDesc& d) { currc.push_back(d); }
   void flush_rc();
-  void panel(const PanelArgs& a) { Op o; o.kind = Op::PANEL; o.panel = a; ops.push_back(o); }
-  void tback(const TBackArgs& a) { Op o; o.kind = Op::TBACK; o.tback = a; ops.push_back(o); }
+  void push(Op o) { o.stream = cur_stream; ops.push_back(o); }
+  void panel(const PanelArgs& a) { Op o; o.kind = Op::PANEL; o.panel = a; push(o); }
+  void panel_apply(const PanelArgs& a, int nt) { Op o; o.kind = Op::PANEL_APPLY; o.panel = a; o.n = nt; push(o); }
+  void tback(const TBackArgs& a) { Op o; o.kind = Op::TBACK; o.tback = a; push(o); }
+  void wait(int e) { Op o; o.kind = Op::WAIT; o.event = e; push(o); n_events = std::max(n_events, e + 1); }
+  void record(int e) { Op o; o.kind = Op::RECORD; o.event = e; push(o); n_events = std::max(n_events, e + 1); }
   void upload(Arena& arena);
   void clear();
 };
@@ -103,6 +111,7 @@ struct blr_matrix_s {
   int64_t launches = 0;
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;
+  std::vector<hipStream_t> streams;      // look-ahead streams (created on first use)
   double prof_flops = 0.0;
   int64_t prof_launches = 0;
 

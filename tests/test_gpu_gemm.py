@@ -52,12 +52,14 @@ def test_gemm_fp64(lib, shape, flags):
 
 
 @pytest.mark.parametrize("flags", [1 | 4, 4, 1 | 8, 8, 1 | 4 | 16, 2 | 16])
-def test_gemm_triangular_modes(lib, flags):
-    print("case: gemm triangular", flags, flush=True)
-    assert run(lib, flags, 192, 160, 192) <= 1e-13
+@pytest.mark.parametrize("shape", [(192, 160, 192), (256, 384, 256)])
+def test_gemm_triangular_modes(lib, flags, shape):
+    # 256 x 384 runs the fast full-tile kernel for the upper-triangular A modes
+    print("case: gemm triangular", flags, shape, flush=True)
+    assert run(lib, flags, *shape) <= 1e-13
 
 
-@pytest.mark.parametrize("shape", [(256, 256, 256), (130, 70, 50)])
+@pytest.mark.parametrize("shape", [(256, 256, 256), (130, 70, 50), (512, 256, 1024)])
 def test_gemm_fp32_compute(lib, shape):
     print("case: gemm fp32", shape, flush=True)
     M, N, K = shape
