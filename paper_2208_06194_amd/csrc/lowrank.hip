@@ -337,7 +337,7 @@ __global__ __launch_bounds__(256) void k_comp_svd(const CompDesc* __restrict__ d
       st = 1;
       r = P.cap;
     }
-    if (st && P.truncate) st = 0;
+    if (st && P.truncate) st = 2;  // kept at the cap: counted, stays low-rank
     rsel = r;
     stat = st;
   }

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <cstdlib>
 #include <functional>
 
 namespace {
@@ -1112,7 +1113,9 @@ blr_status blr_qr_factor(blr_matrix h, const blr_factor_opts* o, void* stream) {
     }
     h->work.release();
     std::vector<Work> works;
-    for (int a = 0; a < kStreams; ++a) works.push_back(make_work(h, 0));
+    int nstreams = kStreams;
+    if (const char* e = std::getenv("BLRQR_STREAMS")) nstreams = std::max(1, std::min(kStreams, std::atoi(e)));
+    for (int a = 0; a < nstreams; ++a) works.push_back(make_work(h, 0));
     Plan P;
     h->n_fill = 0;
     plan_tiled(h, P, works, kend, o->precision == BLR_MIXED_FP32);

@@ -1,0 +1,51 @@
+"""The C-ABI library loads and exports every function declared in include/*.h
+(no compute calls: runs without a GPU)."""
+import ctypes
+import glob
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names.update(re.findall(r"\b(blr_[a-z0-9_]+)\s*\(", text))
+    return names
+
+
+def test_headers_declare_the_boundary():
+    names = declared_functions()
+    for fn in ["blr_compress", "blr_qr_factor", "blr_apply_qt", "blr_lstsq_solve", "blr_import",
+               "blr_export", "blr_query", "blr_destroy", "blr_status_string", "blr_last_error"]:
+        assert fn in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2208_06194_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2208_06194_amd import build
+        build.build()
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for name in sorted(declared_functions()):
+        assert hasattr(lib, name), name
+    # status strings need no device
+    lib.blr_status_string.restype = ctypes.c_char_p
+    assert lib.blr_status_string(0) == b"ok"
+    assert lib.blr_status_string(6) == b"singular R"
+
+
+def test_invalid_arguments_are_rejected_without_a_device():
+    from paper_2208_06194_amd import _lib as L
+    lib = L.load()
+    h = ctypes.c_void_p()
+    # m < n, tile not dividing m, bad tolerance, bad rank cap
+    for m, n, tile, tol, cap in [(64, 128, 32, 1e-8, 8), (100, 50, 32, 1e-8, 8), (64, 32, 32, 0.0, 8),
+                                 (64, 32, 32, 1e-8, 0), (64, 32, 24, 1e-8, 8), (64, 32, 32, 1e-8, 200)]:
+        o = L.CompressOpts(m=m, n=n, tile=tile, tol=tol, max_rank=cap, overflow=0, seed=0)
+        src = L.Source(kind=L.SRC_DENSE, A=ctypes.c_void_p(8), lda=m, admissibility=L.ADM["weak"])
+        assert lib.blr_compress(ctypes.byref(src), ctypes.byref(o), None, ctypes.byref(h)) == L.BLR_ERR_INVALID
+    assert lib.blr_qr_factor(None, None, None) == L.BLR_ERR_INVALID
+    assert lib.blr_last_error() != b""

@@ -94,8 +94,10 @@ def test_tiled_factor_of_imported_blr_matches_oracle(lib, case):
     kappa = np.linalg.cond(At)
     Rg, Ro = export_r(ex), f.r_dense()
     rel = np.linalg.norm(metrics.sign_fix(Rg, Ro) - Ro) / np.linalg.norm(Ro)
-    print("R rel diff", rel, "kappa", kappa, flush=True)
+    print("R rel diff (up to row signs)", rel, "kappa", kappa, flush=True)
     assert rel <= 10 * kappa * eps
+    # the GPU result is a QR factorization of A~ to rounding, not only to eps
+    assert rel <= 1e3 * n * U * kappa or f.stats.recompressions > 0
     # factorization residual of the GPU result, through the library's Q
     RR = np.zeros((m, n))
     RR[:n] = Rg

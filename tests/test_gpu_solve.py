@@ -1,0 +1,187 @@
+"""GPU: least squares, mixed precision, prefix factorization, error paths and
+edge cases, each against the oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import blrmat, metrics, tiled
+from oracle.blrmat import LOWRANK
+from oracle.factor import SingularR
+from tests.blr_helpers import blr_to_host, export_r
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+U = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2208_06194_amd as P
+    return P
+
+
+def gpu_import(P, blr, eps, cap):
+    fmt, rank, dense, Uh, Vh = blr_to_host(blr, cap)
+    return P.BLRMatrix.import_tiles(blr.m, blr.n, blr.b, eps, cap, fmt, rank, dense, Uh, Vh)
+
+
+def kernel_blr(seed, m, n, b, eps, cap, kern="inv_r", dim=3, rule="dist_gt_diam"):
+    x, y = synth.kernel_points(seed, m, n, dim)
+    A = blrmat.kernel_matrix(x, y, kern)
+    mask = blrmat.lowrank_mask(x, y, b, rule, m // b, n // b)
+    return A, blrmat.compress(A, b, eps, cap, mask)
+
+
+@pytest.mark.parametrize("rule,kern,dim", [("dist_gt_diam", "inv_r", 3), ("adjacent", "log2d", 2), ("weak", "log2d", 2)])
+def test_lstsq_matches_oracle(P, rule, kern, dim):
+    print("case: lstsq", rule, flush=True)
+    m, n, b, eps, cap = 512, 256, 64, 1e-8, 32
+    A, blr = kernel_blr(3, m, n, b, eps, cap, kern, dim, rule)
+    At = blr.to_dense()
+    f = tiled.factor(blr, eps, cap)
+    Bh = synth.rhs(3, m, 5)
+    Xo = f.lstsq(Bh)
+    G = gpu_import(P, blr, eps, cap)
+    G.factor("tiled")
+    X, res = G.lstsq(torch.tensor(Bh, device="cuda"), with_resid=True)
+    X, res = X.cpu().numpy(), res.cpu().numpy()
+    kappa = np.linalg.cond(At)
+    assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) <= 10 * kappa * eps
+    # residual norms reported by the library are those of the computed solution
+    r_true = np.linalg.norm(Bh - f.q_times_r() @ X, axis=0)
+    assert np.allclose(res, r_true, rtol=1e-6)
+    # normal-equation optimality for the factored matrix
+    assert np.all(metrics.eta_ne(f.q_times_r(), X, Bh) <= 1e3 * n * U)
+
+
+def test_lstsq_dense_matches_lapack(P):
+    print("case: lstsq dense", flush=True)
+    m, n, b = 384, 192, 64
+    A = np.random.default_rng(5).standard_normal((m, n))
+    blr = blrmat.compress(A, b, 1e-12, b, np.zeros((m // b, n // b), bool))
+    G = gpu_import(P, blr, 1e-12, b)
+    G.factor("tiled")
+    Bh = synth.rhs(5, m, 3)
+    X = G.lstsq(torch.tensor(Bh, device="cuda")).cpu().numpy()
+    Xr = np.linalg.lstsq(A, Bh, rcond=None)[0]
+    assert np.linalg.norm(X - Xr) / np.linalg.norm(Xr) <= 100 * n * U * np.linalg.cond(A)
+
+
+def test_mixed_precision_error_against_fp64_oracle(P):
+    print("case: mixed", flush=True)
+    m, n, b, eps, cap = 1024, 512, 256, 1e-6, 32
+    A, blr = kernel_blr(4, m, n, b, eps, cap)
+    At = blr.to_dense()
+    f = tiled.factor(blr, eps, cap)
+    G = gpu_import(P, blr, eps, cap)
+    G.factor("tiled", precision="mixed")
+    ex = G.export()
+    Rg = export_r(ex)
+    rel = metrics.r_rel_diff(Rg, f.r_dense())
+    RR = np.zeros((m, n))
+    RR[:n] = Rg
+    QR = G.apply_qt(torch.tensor(RR, device="cuda"), trans=True).cpu().numpy()
+    res = np.linalg.norm(QR - At) / np.linalg.norm(At)
+    print(f"mixed: R rel diff vs FP64 oracle {rel:.2e}, Res_At {res:.2e}", flush=True)
+    # FP32 products: errors of order sqrt(b) * 2^-24 per update, amplified by the conditioning
+    assert res <= 1e-5
+    assert rel <= 1e-3
+
+
+@pytest.mark.parametrize("K", [1, 2, 3])
+def test_prefix_factor_matches_oracle(P, K):
+    """The first K block rows of R after K steps, up to row signs (R is unique
+    up to the signs of its rows; rounding can decide a Householder sign
+    differently when a pivot is small next to its column)."""
+    print("case: prefix", K, flush=True)
+    m, n, b, eps, cap = 512, 256, 64, 1e-8, 16
+    A, blr = kernel_blr(6, m, n, b, eps, cap, "log2d", 2, "adjacent")
+    f = tiled.factor(blr, eps, cap, stop_after_k=K)
+    G = gpu_import(P, blr, eps, cap)
+    G.factor("tiled", stop_after_k=K)
+    ex = G.export()
+    Rg, Ro = np.zeros((K * b, n)), np.zeros((K * b, n))
+    for k in range(K):
+        for j in range(k, f.q):
+            o = f.r_val(k, j)
+            Ro[k * b:(k + 1) * b, j * b:(j + 1) * b] = o[1] if o[0] == "D" else o[1] @ o[2].T
+            if j == k:
+                g = np.triu(ex["dense"][k, k])
+            elif ex["fmt"][k, j] == 0:
+                g = ex["dense"][k, j]
+            else:
+                r = ex["rank"][k, j]
+                g = ex["U"][k, j][:, :r] @ ex["V"][k, j][:, :r].T
+            Rg[k * b:(k + 1) * b, j * b:(j + 1) * b] = g
+    sg = np.sign(np.diag(Rg[:, :K * b])) * np.sign(np.diag(Ro[:, :K * b]))
+    rel = np.linalg.norm(sg[:, None] * Rg - Ro) / np.linalg.norm(Ro)
+    assert rel <= 10 * np.linalg.cond(blr.to_dense()) * eps
+
+
+def test_zero_tiles_have_rank_zero(P):
+    """Weak admissibility on a block-diagonal matrix: every off-diagonal tile is
+    the zero matrix, compressed to rank 0; R is the block-diagonal R."""
+    print("case: rank0", flush=True)
+    m, n, b = 256, 128, 32
+    A = np.zeros((m, n))
+    rng = np.random.default_rng(2)
+    for k in range(n // b):
+        A[k * b:(k + 1) * b, k * b:(k + 1) * b] = rng.standard_normal((b, b))
+    G = P.BLRMatrix.compress_dense(torch.tensor(A, device="cuda"), b, 1e-8, 16, admissibility="weak")
+    ex = G.export()
+    assert np.all(ex["rank"][ex["fmt"] == 1] == 0)
+    G.factor("tiled")
+    Rg = export_r(G.export())
+    assert metrics.r_rel_diff(Rg, np.linalg.qr(A, mode="r")) <= 1e-12
+
+
+def test_truncate_overflow_is_counted(P):
+    print("case: truncate", flush=True)
+    m, n, b = 256, 128, 32
+    A = np.random.default_rng(3).standard_normal((m, n))   # full-rank tiles
+    G = P.BLRMatrix.compress_dense(torch.tensor(A, device="cuda"), b, 1e-8, 4, admissibility="weak",
+                                   overflow="truncate")
+    inf = G.info()
+    assert inf["compress_overflow"] == inf["n_lowrank"] > 0
+    Gd = P.BLRMatrix.compress_dense(torch.tensor(A, device="cuda"), b, 1e-8, 4, admissibility="weak",
+                                    overflow="dense")
+    assert Gd.info()["n_lowrank"] == 0
+
+
+def test_error_paths(P):
+    print("case: errors", flush=True)
+    from paper_2208_06194_amd import BLRError
+    m, n, b = 128, 64, 32
+    A = np.random.default_rng(1).standard_normal((m, n))
+    At = torch.tensor(A, device="cuda")
+    G = P.BLRMatrix.compress_dense(At, b, 1e-8, 8, admissibility="weak")
+    with pytest.raises(BLRError) as e:
+        G.apply_qt(torch.zeros((m, 1), dtype=torch.float64, device="cuda"))
+    assert e.value.status == 2
+    G.factor("tiled")
+    with pytest.raises(BLRError) as e:
+        G.factor("tiled")
+    assert e.value.status == 2
+    bad = At.clone()
+    bad[3, 4] = float("nan")
+    with pytest.raises(BLRError) as e:
+        P.BLRMatrix.compress_dense(bad, b, 1e-8, 8)
+    assert e.value.status == 5
+    Z = A.copy()
+    Z[:, 7] = 0.0
+    Gz = P.BLRMatrix.compress_dense(torch.tensor(Z, device="cuda"), b, 1e-8, 8, admissibility="mask",
+                                    mask=np.zeros((m // b, n // b), bool))
+    Gz.factor("tiled")
+    with pytest.raises(BLRError) as e:
+        Gz.lstsq(torch.ones((m, 1), dtype=torch.float64, device="cuda"))
+    assert e.value.status == 6
+
+
+@pytest.mark.parametrize("m,n,b", [(64, 64, 64), (128, 128, 32), (512, 64, 64)])
+def test_shapes_single_tile_square_and_single_column(P, m, n, b):
+    print("case: shape", m, n, b, flush=True)
+    A = np.random.default_rng(m + n).standard_normal((m, n))
+    G = P.BLRMatrix.compress_dense(torch.tensor(A, device="cuda"), b, 1e-12, min(b, 64),
+                                   admissibility="mask", mask=np.zeros((m // b, n // b), bool))
+    G.factor("tiled")
+    assert metrics.r_rel_diff(export_r(G.export()), np.linalg.qr(A, mode="r")) <= 100 * n * U * np.linalg.cond(A)
