@@ -6,10 +6,11 @@ Step k:
      [A_kk; Av_{k+1,k}; ...; Av_{p,k}] with Av = A (dense) or V^T (low-rank),
      and take its Householder QR: R_kk, Y_k = [Y_kk; Y_{k+1,k}; ...], T_k
      (eq. blr_bch_col_qr); Ytilde_ik = Au_ik Y_ik (I or U_ik);
-  2. for every j > k: Z_j = sum_i Ytilde_ik^T A_ij (low-rank accumulation by
-     rounded addition, in order i = k, k+1, ...; dense as soon as one term is
-     dense), W_j = T_k^T Z_j, A_ij -= Ytilde_ik W_j (eq.
-     blr_bch_apply_bc_reflector).
+  2. for every j > k: Z_j = sum_i Ytilde_ik^T A_ij, W_j = T_k^T Z_j,
+     A_ij -= Ytilde_ik W_j (eq. blr_bch_apply_bc_reflector).  Reading of the
+     accumulation: if any term is dense the sum is dense (OP1) and all terms
+     are added exactly; otherwise the low-rank terms are accumulated by
+     rounded addition in the order i = k, k+1, ... (OP2, Alg. 6).
 """
 from __future__ import annotations
 
@@ -55,10 +56,13 @@ class BlockColumnFactor(Factor):
 
     def apply_column(self, k, j):
         e, c, st = self.eps, self.cap, self.stats
-        Z = None
-        for i in range(k, self.p):
-            term = blrops.yt_times(self.yrep(i, k), self.val(i, j))
-            Z = term if Z is None else blrops.add(Z, term, 1.0, e, c, st)
+        terms = [blrops.yt_times(self.yrep(i, k), self.val(i, j)) for i in range(k, self.p)]
+        if any(t[0] == "D" for t in terms):
+            Z = ("D", sum(blrops.dense_of(t) for t in terms))
+        else:
+            Z = terms[0]
+            for t in terms[1:]:
+                Z = blrops.add(Z, t, 1.0, e, c, st)
         W = blrops.t_times(self.Tk[k], Z, True)
         for i in range(k, self.p):
             upd = blrops.y_times(self.yrep(i, k), W)

@@ -219,13 +219,6 @@ __global__ __launch_bounds__(256) void k_gemm_fast(const GemmDesc* __restrict__ 
   const int m0 = (t % d.tilesM) * BM;
   const int n0 = (t / d.tilesM) * BN;
   if ((d.flags & DESC_LOWER_ONLY) && m0 + BM <= n0) return;
-  const GemmSeg sg = segs[d.seg_begin];
-  int kbeg = 0, kend = sg.K;
-  if (sg.flags & SEG_A_UPPER) {
-    if (TA) kend = min(kend, m0 + BM);
-    else kbeg = m0;
-  }
-  if (d.nseg == 0) kend = kbeg;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
@@ -234,12 +227,6 @@ __global__ __launch_bounds__(256) void k_gemm_fast(const GemmDesc* __restrict__ 
   const int a_8 = TA ? (tid & 1) * 8 : (tid & 15) * 8;  // TA: k offset; else m offset
   const int b_nk = TB ? (tid >> 4) : (tid >> 1);        // TB: k; else n
   const int b_8 = TB ? (tid & 15) * 8 : (tid & 1) * 8;  // TB: n offset; else k offset
-  const double* ap = TA ? sg.A + (int64_t)(m0 + a_mk) * sg.lda + kbeg + a_8
-                        : sg.A + (int64_t)(kbeg + a_mk) * sg.lda + m0 + a_8;
-  const double* bp = TB ? sg.B + (int64_t)(kbeg + b_nk) * sg.ldb + n0 + b_8
-                        : sg.B + (int64_t)(n0 + b_nk) * sg.ldb + kbeg + b_8;
-  const int64_t astep = TA ? BK : (int64_t)BK * sg.lda;
-  const int64_t bstep = TB ? (int64_t)BK * sg.ldb : BK;
 
   acc_t acc[4][4];
 #pragma unroll
@@ -250,30 +237,43 @@ __global__ __launch_bounds__(256) void k_gemm_fast(const GemmDesc* __restrict__ 
       for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
 
   d2v ra[4], rb[4];
-  auto gload = [&](int step) {
-    const gd2v* pa = (const gd2v*)(ap + step * astep);
-    const gd2v* pb = (const gd2v*)(bp + step * bstep);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      ra[q] = pa[q];
-      rb[q] = pb[q];
+  for (int sgi = 0; sgi < d.nseg; ++sgi) {
+    const GemmSeg sg = segs[d.seg_begin + sgi];
+    int kbeg = 0, kend = sg.K;
+    if (sg.flags & SEG_A_UPPER) {
+      if (TA) kend = min(kend, m0 + BM);
+      else kbeg = m0;
     }
-  };
-  auto lstore = [&](int buf) {
+    const double* ap = TA ? sg.A + (int64_t)(m0 + a_mk) * sg.lda + kbeg + a_8
+                          : sg.A + (int64_t)(kbeg + a_mk) * sg.lda + m0 + a_8;
+    const double* bp = TB ? sg.B + (int64_t)(kbeg + b_nk) * sg.ldb + n0 + b_8
+                          : sg.B + (int64_t)(n0 + b_nk) * sg.ldb + kbeg + b_8;
+    const int64_t astep = TA ? BK : (int64_t)BK * sg.lda;
+    const int64_t bstep = TB ? (int64_t)BK * sg.ldb : BK;
+    auto gload = [&](int step) {
+      const gd2v* pa = (const gd2v*)(ap + step * astep);
+      const gd2v* pb = (const gd2v*)(bp + step * bstep);
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        if (TA) As[buf][a_8 + 2 * q + e][a_mk] = (CT)ra[q][e];
-        else As[buf][a_mk][a_8 + 2 * q + e] = (CT)ra[q][e];
-        if (TB) Bs[buf][b_nk][b_8 + 2 * q + e] = (CT)rb[q][e];
-        else Bs[buf][b_8 + 2 * q + e][b_nk] = (CT)rb[q][e];
+      for (int q = 0; q < 4; ++q) {
+        ra[q] = pa[q];
+        rb[q] = pb[q];
       }
-  };
-
-  const int nsteps = (kend - kbeg) / BK;
-  if (nsteps > 0) {
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          if (TA) As[buf][a_8 + 2 * q + e][a_mk] = (CT)ra[q][e];
+          else As[buf][a_mk][a_8 + 2 * q + e] = (CT)ra[q][e];
+          if (TB) Bs[buf][b_nk][b_8 + 2 * q + e] = (CT)rb[q][e];
+          else Bs[buf][b_8 + 2 * q + e][b_nk] = (CT)rb[q][e];
+        }
+    };
+    const int nsteps = (kend - kbeg) / BK;
+    if (nsteps <= 0) continue;
     gload(0);
+    __syncthreads();  // previous segment's last reads of buffer 0 are done
     lstore(0);
     __syncthreads();
     for (int st = 0; st < nsteps; ++st) {

@@ -28,7 +28,33 @@ struct TBackArgs {
   int64_t ldt;
 };
 
+struct TallArgs {
+  double* X;       // panel pivot (c0, c0) of the stack
+  int64_t ldx;
+  int h;           // rows from the pivot down
+  int ib;          // panel width (<= 32)
+  int jj;          // column of the panel being factored
+  double* part;    // partials: (G + 1) x 2*ib doubles
+  double* T;       // T element (c0, c0)
+  int64_t ldt;
+  double* tau;     // tau[c0 ..]
+};
+
+struct CopyDesc {
+  const double* src;
+  double* dst;
+  int64_t lds, ldd;
+  int32_t rows, cols;
+  int32_t unit_lower;   // write the unit lower triangular part of src (diag 1, upper 0)
+  int32_t pad_;
+};
+
 hipError_t launch_panel(const PanelArgs& a, hipStream_t stream);
+// Two launches per column of a tall panel (see qr.hip); groups = row groups.
+hipError_t launch_tall_column(const TallArgs& a, int groups, hipStream_t stream);
+// Split-K trailing update of a tall panel; part: slices * ceil(nt/32) * ib * 32 doubles.
+hipError_t launch_tall_apply(const PanelArgs& a, int nt, int slices, double* part, hipStream_t stream);
+hipError_t launch_copy_blocks(const CopyDesc* d, int n, int64_t max_elems, hipStream_t stream);
 hipError_t launch_t_backsolve(const TBackArgs& a, hipStream_t stream);
 // Fused trailing update of the nt columns right of panel a (same PanelArgs:
 // X points at the panel's first column / first row, T at its diagonal block).

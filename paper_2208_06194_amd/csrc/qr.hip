@@ -21,6 +21,8 @@
 #include "device_common.h"
 #include "qr.h"
 
+#include <algorithm>
+
 namespace {
 
 // Owner-wave panel factorization: 1024 threads, wave w owns panel columns
@@ -328,7 +330,271 @@ __global__ __launch_bounds__(256) void k_t_backsolve(TBackArgs a) {
   for (int r = c + 1 + lane; r < a.n; r += 64) a.T[r + (int64_t)c * a.ldt] = 0.0;
 }
 
+
+// ---------------------------------------------------------------------------
+// Tall panels (block-column variant, stacks taller than 1024 rows).  The
+// panel is IB columns of the stack starting at its pivot (c0, c0): X points
+// there, h rows below it.  Column jj takes two launches over G row groups:
+//   k_tall_dots:   per group, the tail sum of squares of column jj and its
+//                  dot products with the other panel columns; group 0 also
+//                  snapshots the pivot row jj of the panel;
+//   k_tall_update: every group reduces the partials, forms the larfg scalars
+//                  and w_t = X(jj,t) + v^T x_t, scales its rows of column jj
+//                  and applies the rank-one update to the later columns;
+//                  group 0 writes the pivot row, tau and column jj of T.
+__global__ __launch_bounds__(256) void k_tall_dots(TallArgs a) {
+  __shared__ double red[4][33];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int jj = a.jj, ib = a.ib, G = gridDim.x, g = blockIdx.x;
+  const int64_t ld = a.ldx;
+  const int r0 = jj + 1;
+  const int len = a.h - r0;
+  const int chunk = (len + G - 1) / G;
+  const int rs = r0 + g * chunk, re = min(a.h, rs + chunk);
+  double part[33];
+  for (int t = 0; t <= 32; ++t) part[t] = 0.0;
+  const double* xc = a.X + (int64_t)jj * ld;
+  for (int r = rs + tid; r < re; r += 256) {
+    const double v = xc[r];
+#pragma unroll
+    for (int t = 0; t < 32; ++t)
+      if (t < ib) part[t] += (t == jj) ? v * v : v * a.X[r + (int64_t)t * ld];
+  }
+#pragma unroll
+  for (int t = 0; t < 32; ++t) {
+    const double s = wave_sum(part[t]);
+    if (lane == 0) red[w][t] = s;
+  }
+  __syncthreads();
+  if (tid < ib) a.part[(int64_t)g * (2 * ib) + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+  if (g == 0 && tid < ib) a.part[(int64_t)G * (2 * ib) + tid] = a.X[jj + (int64_t)tid * ld];
+}
+
+__global__ __launch_bounds__(256) void k_tall_update(TallArgs a) {
+  __shared__ double sv[64];   // [0, ib): reduced dots / ss; [32, 32+ib): pivot row
+  __shared__ double wv[32];
+  const int tid = threadIdx.x;
+  const int jj = a.jj, ib = a.ib, G = gridDim.x, g = blockIdx.x;
+  const int64_t ld = a.ldx;
+  if (tid < ib) {
+    double s = 0.0;
+    for (int q = 0; q < G; ++q) s += a.part[(int64_t)q * (2 * ib) + tid];
+    sv[tid] = s;
+    sv[32 + tid] = a.part[(int64_t)G * (2 * ib) + tid];
+  }
+  __syncthreads();
+  const double alpha = sv[32 + jj];
+  double beta, tau, scal;
+  larfg_scalars(alpha, sv[jj], &beta, &tau, &scal);
+  if (tid < ib) wv[tid] = sv[32 + tid] + scal * sv[tid];   // t > jj: w_t; t < jj: Gram g_t
+  __syncthreads();
+  const int r0 = jj + 1;
+  const int len = a.h - r0;
+  const int chunk = (len + G - 1) / G;
+  const int rs = r0 + g * chunk, re = min(a.h, rs + chunk);
+  double* xc = a.X + (int64_t)jj * ld;
+  for (int r = rs + tid; r < re; r += 256) {
+    const double v = xc[r] * scal;
+    xc[r] = v;
+    if (tau != 0.0)
+      for (int t = jj + 1; t < ib; ++t) a.X[r + (int64_t)t * ld] -= tau * wv[t] * v;
+  }
+  if (g == 0) {
+    if (tid == 0) {
+      a.X[jj + (int64_t)jj * ld] = beta;
+      a.tau[jj] = tau;
+      a.T[jj + (int64_t)jj * a.ldt] = tau;
+    }
+    if (tid > jj && tid < ib && tau != 0.0) a.X[jj + (int64_t)tid * ld] = sv[32 + tid] - tau * wv[tid];
+    // T[u][jj] = -tau * sum_{v=u}^{jj-1} T[u][v] g_v
+    if (tid < jj) {
+      double s = 0.0;
+      for (int v = tid; v < jj; ++v) s += a.T[tid + (int64_t)v * a.ldt] * wv[v];
+      a.T[tid + (int64_t)jj * a.ldt] = -tau * s;
+    }
+  }
+}
+
+// Split-K trailing update of a tall panel (V unit lower, h rows, IB columns)
+// applied to the nt columns right of it: grid (nt/32 column blocks) x S row
+// slices.  k_tall_apply_part writes each slice's V^T C into part;
+// k_tall_apply_upd sums the slices, forms W2 = T^T W and updates its slice:
+// C -= V W2.
+template <int IB>
+__global__ __launch_bounds__(256) void k_tall_apply_part(PanelArgs a, int nt, double* part) {
+  constexpr int NC = 32, CH = 64, MT = IB / 16;
+  __shared__ double Vs[CH][IB + 1];
+  __shared__ double Bs[CH][NC + 1];
+  __shared__ double Wp[4][IB][NC + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int cb = blockIdx.x, sl = blockIdx.y, S = gridDim.y;
+  const int c0 = cb * NC, nc = min(NC, nt - c0);
+  const int h = a.h;
+  const int slice = ((h + S - 1) / S + CH - 1) / CH * CH;
+  const int rb = sl * slice, rend = min(h, rb + slice);
+  const double* V = a.X;
+  const double* B = a.X + (int64_t)(IB + c0) * a.ldx;
+  const int64_t ld = a.ldx;
+  v4d acc[MT][2];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[mt][j][v] = 0.0;
+  for (int r0 = rb; r0 < rend; r0 += CH) {
+    __syncthreads();
+    for (int e = tid; e < CH * IB; e += 256) {
+      const int r = e % CH, l = e / CH, gr = r0 + r;
+      double v = 0.0;
+      if (gr < rend) {
+        v = V[gr + (int64_t)l * ld];
+        v = gr > l ? v : (gr == l ? 1.0 : 0.0);
+      }
+      Vs[r][l] = v;
+    }
+    for (int e = tid; e < CH * NC; e += 256) {
+      const int r = e % CH, c = e / CH, gr = r0 + r;
+      Bs[r][c] = (gr < rend && c < nc) ? B[gr + (int64_t)c * ld] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int kr = 16 * w + 4 * ks + (lane >> 4);
+      double af[MT], bf[2];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) af[mt] = Vs[kr][mt * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bf[j] = Bs[kr][j * 16 + (lane & 15)];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[mt][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mt], bf[j], acc[mt][j], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Wp[w][mt * 16 + 4 * v + (lane >> 4)][j * 16 + (lane & 15)] = acc[mt][j][v];
+  __syncthreads();
+  double* out = part + ((int64_t)sl * gridDim.x + cb) * IB * NC;
+  for (int e = tid; e < IB * NC; e += 256) {
+    const int l = e % IB, c = e / IB;
+    out[e] = Wp[0][l][c] + Wp[1][l][c] + Wp[2][l][c] + Wp[3][l][c];
+  }
+}
+
+template <int IB>
+__global__ __launch_bounds__(256) void k_tall_apply_upd(PanelArgs a, int nt, const double* part) {
+  constexpr int NC = 32, CH = 64;
+  __shared__ double Vs[CH][IB + 1];
+  __shared__ double Ps[CH][NC + 1];
+  __shared__ double W[IB][NC + 1];
+  __shared__ double W2[IB][NC + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int cb = blockIdx.x, sl = blockIdx.y, S = gridDim.y, NB = gridDim.x;
+  const int c0 = cb * NC, nc = min(NC, nt - c0);
+  const int h = a.h;
+  const int slice = ((h + S - 1) / S + CH - 1) / CH * CH;
+  const int rb = sl * slice, rend = min(h, rb + slice);
+  const double* V = a.X;
+  double* B = a.X + (int64_t)(IB + c0) * a.ldx;
+  const int64_t ld = a.ldx;
+  for (int e = tid; e < IB * NC; e += 256) {
+    double s = 0.0;
+    for (int q = 0; q < S; ++q) s += part[((int64_t)q * NB + cb) * IB * NC + e];
+    W[e % IB][e / IB] = s;
+  }
+  __syncthreads();
+  for (int e = tid; e < IB * NC; e += 256) {
+    const int l = e % IB, c = e / IB;
+    double s = 0.0;
+    for (int m = 0; m <= l; ++m) s += a.T[m + (int64_t)l * a.ldt] * W[m][c];
+    W2[l][c] = s;
+  }
+  for (int r0 = rb; r0 < rend; r0 += CH) {
+    __syncthreads();
+    for (int e = tid; e < CH * IB; e += 256) {
+      const int r = e % CH, l = e / CH, gr = r0 + r;
+      double v = 0.0;
+      if (gr < rend) {
+        v = V[gr + (int64_t)l * ld];
+        v = gr > l ? v : (gr == l ? 1.0 : 0.0);
+      }
+      Vs[r][l] = v;
+    }
+    __syncthreads();
+    v4d pr[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) pr[j][v] = 0.0;
+#pragma unroll
+    for (int ks = 0; ks < IB / 4; ++ks) {
+      const double af = Vs[16 * w + (lane & 15)][4 * ks + (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const double bf = W2[4 * ks + (lane >> 4)][j * 16 + (lane & 15)];
+        pr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, pr[j], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Ps[16 * w + 4 * v + (lane >> 4)][j * 16 + (lane & 15)] = pr[j][v];
+    __syncthreads();
+    for (int e = tid; e < CH * NC; e += 256) {
+      const int r = e % CH, c = e / CH, gr = r0 + r;
+      if (gr < rend && c < nc) B[gr + (int64_t)c * ld] -= Ps[r][c];
+    }
+  }
+}
+
+// Batched copy of column-major blocks (gather / scatter of the stacked
+// block column), and the explicit unit-lower form of a packed reflector block.
+__global__ void k_copy_blocks(const CopyDesc* __restrict__ d) {
+  const CopyDesc D = d[blockIdx.y];
+  const int64_t n = (int64_t)D.rows * D.cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e % D.rows, c = e / D.rows;
+    double v = D.src[r + c * D.lds];
+    if (D.unit_lower) v = r > c ? v : (r == c ? 1.0 : 0.0);
+    D.dst[r + c * D.ldd] = v;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_tall_column(const TallArgs& a, int groups, hipStream_t stream) {
+  hipLaunchKernelGGL(k_tall_dots, dim3(groups), dim3(256), 0, stream, a);
+  hipLaunchKernelGGL(k_tall_update, dim3(groups), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_tall_apply(const PanelArgs& a, int nt, int slices, double* part, hipStream_t stream) {
+  if (nt <= 0) return hipSuccess;
+  dim3 grid((nt + 31) / 32, slices), block(256);
+  if (a.ib == 32) {
+    hipLaunchKernelGGL((k_tall_apply_part<32>), grid, block, 0, stream, a, nt, part);
+    hipLaunchKernelGGL((k_tall_apply_upd<32>), grid, block, 0, stream, a, nt, (const double*)part);
+  } else if (a.ib == 16) {
+    hipLaunchKernelGGL((k_tall_apply_part<16>), grid, block, 0, stream, a, nt, part);
+    hipLaunchKernelGGL((k_tall_apply_upd<16>), grid, block, 0, stream, a, nt, (const double*)part);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_blocks(const CopyDesc* d, int n, int64_t max_elems, hipStream_t stream) {
+  if (n <= 0 || max_elems <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>((max_elems + 255) / 256, 256);
+  hipLaunchKernelGGL(k_copy_blocks, dim3(blocks, n), dim3(256), 0, stream, d);
+  return hipGetLastError();
+}
 
 hipError_t launch_panel(const PanelArgs& a, hipStream_t stream) {
   const int rs = (a.h + 63) / 64;

@@ -88,6 +88,30 @@ void Plan::gemm(double* C, int64_t ldc, const double* Cin, int64_t ldcin, double
   cur.push_back(d);
 }
 
+void Plan::gemm_multi(double* C, int64_t ldc, const double* Cin, int64_t ldcin, int M, int N, double alpha,
+                      double beta, const std::vector<GemmSeg>& sv) {
+  if (M <= 0 || N <= 0) return;
+  GemmDesc d{};
+  d.C = C;
+  d.ldc = ldc;
+  d.Cin = Cin;
+  d.ldcin = ldcin;
+  d.M = M;
+  d.N = N;
+  d.alpha = alpha;
+  d.beta = beta;
+  d.seg_begin = (int)curseg.size();
+  d.nseg = 0;
+  for (const GemmSeg& sg : sv) {
+    if (sg.K <= 0) continue;
+    curseg.push_back(sg);
+    d.nseg++;
+    const bool tri = sg.flags & (SEG_A_UPPER | SEG_A_UNIT_LOWER);
+    curflops += 2.0 * M * N * (double)sg.K * (tri ? 0.5 : 1.0);
+  }
+  cur.push_back(d);
+}
+
 void Plan::flush_gemm(int fp32, int prof) {
   if (cur.empty()) return;
   int mn = 1 << 30;
@@ -99,12 +123,16 @@ void Plan::flush_gemm(int fp32, int prof) {
     int tflags = -1;
     auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
     for (auto& d : cur) {
-      if (d.M % 128 || d.N % 128 || d.nseg != 1) { ok = false; break; }
-      const GemmSeg& sg = curseg[d.seg_begin];
-      const int tf = sg.flags & (SEG_TRANS_A | SEG_TRANS_B);
-      if (tflags < 0) tflags = tf;
-      if (tf != tflags || (sg.flags & (SEG_A_UNIT_LOWER | SEG_B_UNIT_LOWER)) || sg.K % 16 ||
-          !al(sg.A) || !al(sg.B) || (sg.lda & 1) || (sg.ldb & 1)) { ok = false; break; }
+      if (d.M % 128 || d.N % 128 || d.nseg < 1) { ok = false; break; }
+      for (int si = 0; si < d.nseg && ok; ++si) {
+        const GemmSeg& sg = curseg[d.seg_begin + si];
+        const int tf = sg.flags & (SEG_TRANS_A | SEG_TRANS_B);
+        if (tflags < 0) tflags = tf;
+        if (tf != tflags || (sg.flags & (SEG_A_UNIT_LOWER | SEG_B_UNIT_LOWER)) || sg.K % 16 ||
+            !al(sg.A) || !al(sg.B) || (sg.lda & 1) || (sg.ldb & 1))
+          ok = false;
+      }
+      if (!ok) break;
     }
     if (ok) {
       const bool ta = tflags & SEG_TRANS_A, tb = tflags & SEG_TRANS_B;
@@ -158,6 +186,10 @@ void Plan::upload(Arena& arena) {
   if (!segs.empty()) {
     d_segs = (GemmSeg*)arena.alloc(segs.size() * sizeof(GemmSeg));
     HIPCHECK(hipMemcpy(d_segs, segs.data(), segs.size() * sizeof(GemmSeg), hipMemcpyHostToDevice));
+  }
+  if (!copies.empty()) {
+    d_copies = (CopyDesc*)arena.alloc(copies.size() * sizeof(CopyDesc));
+    HIPCHECK(hipMemcpy(d_copies, copies.data(), copies.size() * sizeof(CopyDesc), hipMemcpyHostToDevice));
   }
   if (!rcs.empty()) {
     d_rcs = (RcDesc*)arena.alloc(rcs.size() * sizeof(RcDesc));
@@ -249,6 +281,18 @@ void execute(blr_matrix h, Plan& P, hipStream_t s) {
         break;
       case Op::RC:
         HIPCHECK(launch_recompress(P.d_rcs + o.off, o.n, rc_params(h), q));
+        h->launches += 1;
+        break;
+      case Op::TALL_COL:
+        HIPCHECK(launch_tall_column(o.tall, o.n, q));
+        h->launches += 2;
+        break;
+      case Op::TALL_APPLY:
+        HIPCHECK(launch_tall_apply(o.panel, o.ntiles, o.n, o.buf, q));
+        h->launches += 2;
+        break;
+      case Op::COPY:
+        HIPCHECK(launch_copy_blocks(P.d_copies + o.off, o.n, o.maxel, q));
         h->launches += 1;
         break;
       case Op::WAIT:
@@ -669,6 +713,432 @@ void plan_apply_tiled(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, in
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Block-column BLR-QR (Alg. 2 with Section 3.2).  Step k: gather the stack
+// [A_kk; Av_{k+1,k}; ...] (Av = A for dense tiles, V^T for low-rank tiles)
+// into one column-major buffer, take its Householder QR (the tile panel
+// kernels while it has at most 512/1024 rows, the tall-panel kernels
+// otherwise), build T_k, scatter R_kk and the reflector rows Y_ik back into
+// the tiles, then for every j > k form Z_j = sum_i Ytilde_ik^T A_ij,
+// W_j = T_k^T Z_j and apply A_ij -= Ytilde_ik W_j with the OP1/OP2 rules:
+// Z_j is dense if any term is dense, else the low-rank terms are summed by
+// rounded additions in order i = k, k+1, ...
+
+struct BcSlot {
+  double *Ua, *Ub;   // b x rc
+  double *Sa;        // rc x b
+  double *Sm;        // rc x rc
+  double *rcw;       // recompression workspace
+};
+
+struct BcWork {
+  double* stack = nullptr;      // m x b
+  double* Yf = nullptr;         // b x b explicit unit-lower Y_kk
+  double* tallpart = nullptr;   // (64 + 1) x 64
+  double* applypart = nullptr;  // 64 x ceil(b/32) x 32 x 32
+  std::vector<BcSlot> slots;
+};
+
+bool bc_zdense(blr_matrix h, const std::vector<int8_t>& f, int k, int j) {
+  const int q = h->q;
+  for (int i = k; i < h->p; ++i)
+    if ((i == k || f[(size_t)i * q + k] == DENSE) && f[(size_t)i * q + j] == DENSE) return true;
+  return false;
+}
+
+// Low-rank tiles that the block-column factorization turns dense (OP1): a
+// low-rank A_ij receiving a dense update Ytilde_ik W_j.  Also returns the
+// largest number of (i, j) pairs of one step that need low-rank temporaries.
+std::vector<int> bc_simulate(blr_matrix h, int kend, int* max_pairs) {
+  const int p = h->p, q = h->q;
+  std::vector<int8_t> f((size_t)p * q);
+  for (size_t t = 0; t < f.size(); ++t) f[t] = h->tiles[t].fmt;
+  std::vector<int> need;
+  int mp = 0;
+  for (int k = 0; k < kend; ++k) {
+    int pairs = 0;
+    for (int j = k + 1; j < q; ++j) {
+      const bool zd = bc_zdense(h, f, k, j);
+      for (int i = k; i < p; ++i) {
+        const bool yd = i == k || f[(size_t)i * q + k] == DENSE;
+        int8_t& A = f[(size_t)i * q + j];
+        if (!(yd && A == DENSE && zd)) pairs++;
+        if (zd && yd && A == LOWRANK) {
+          A = DENSE;
+          need.push_back(i * q + j);
+        }
+      }
+    }
+    mp = std::max(mp, pairs);
+  }
+  *max_pairs = mp;
+  return need;
+}
+
+BcWork make_bc_work(blr_matrix h, int npairs) {
+  BcWork bw;
+  const int b = h->b, rc = h->rc;
+  Arena& A = h->work;
+  bw.stack = (double*)A.alloc((size_t)h->m * b * 8);
+  bw.Yf = (double*)A.alloc((size_t)b * b * 8);
+  bw.tallpart = (double*)A.alloc((size_t)65 * 64 * 8);
+  bw.applypart = (double*)A.alloc((size_t)64 * ((b + 31) / 32) * 32 * 32 * 8);
+  const size_t rcwd = rc_work_doubles(b, rc);
+  const size_t per = 2 * (size_t)b * rc + (size_t)rc * b + (size_t)rc * rc + rcwd;
+  if (npairs > 0) {
+    double* base = (double*)A.alloc((size_t)npairs * per * 8);
+    for (int a = 0; a < npairs; ++a) {
+      double* x = base + (size_t)a * per;
+      BcSlot sl;
+      sl.Ua = x;
+      sl.Ub = x + (size_t)b * rc;
+      sl.Sa = x + 2 * (size_t)b * rc;
+      sl.Sm = sl.Sa + (size_t)rc * b;
+      sl.rcw = sl.Sm + (size_t)rc * rc;
+      bw.slots.push_back(sl);
+    }
+  }
+  return bw;
+}
+
+// Householder QR of the hs x b stack (ld hs) into T (b x b) and tau.
+void plan_stack_qr(Plan& P, blr_matrix h, Work& w, BcWork& bw, int hs, double* T, double* tau) {
+  const int b = h->b;
+  double* X = bw.stack;
+  // stacks of up to 512 (ib 32) or 1024 (ib 16) rows stay in the registers
+  // of the one-workgroup panel kernel; taller ones use the row-split kernels
+  const bool tall = hs > 1024;
+  int ib = (hs > 512 && !tall) ? 16 : 32;
+  if (b % ib) ib = 16;
+  ib = std::min(ib, b);
+  for (int c0 = 0; c0 < b; c0 += ib) {
+    const int hl = hs - c0;
+    const int nt = b - c0 - ib;
+    PanelArgs a{};
+    a.mode = PANEL_GEQRT;
+    a.ib = ib;
+    a.h = hl;
+    a.X = X + c0 + (int64_t)c0 * hs;
+    a.ldx = hs;
+    a.T = T + c0 + (int64_t)c0 * b;
+    a.ldt = b;
+    a.tau = tau + c0;
+    if (!tall) {
+      P.panel(a);
+      P.ops.back().flops = 2.0 * hl * ib * ib;
+      if (nt > 0) {
+        P.panel_apply(a, nt);
+        P.ops.back().flops = 4.0 * hl * ib * nt;
+      }
+    } else {
+      const int G = std::min(64, std::max(1, (hl + 4095) / 4096));
+      for (int jj = 0; jj < ib; ++jj) {
+        Op o;
+        o.kind = Op::TALL_COL;
+        o.tall = TallArgs{a.X, (int64_t)hs, hl, ib, jj, bw.tallpart, a.T, (int64_t)b, a.tau};
+        o.n = G;
+        o.flops = 4.0 * hl * ib;
+        P.push(o);
+      }
+      if (nt > 0) {
+        Op o;
+        o.kind = Op::TALL_APPLY;
+        o.panel = a;
+        o.ntiles = nt;
+        o.n = std::min(64, std::max(1, hl / 2048));
+        o.buf = bw.applypart;
+        o.flops = 4.0 * hl * ib * nt;
+        P.push(o);
+      }
+    }
+  }
+  if (b > ib) {
+    P.gemm(w.Wg, b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, X, hs, X, hs, hs,
+           SEG_TRANS_A | SEG_A_UNIT_LOWER | SEG_B_UNIT_LOWER, DESC_LOWER_ONLY);
+    P.flush_gemm();
+    TBackArgs t{};
+    t.n = b;
+    t.ib = ib;
+    t.G = w.Wg;
+    t.ldg = b;
+    t.tau = tau;
+    t.T = T;
+    t.ldt = b;
+    P.tback(t);
+    P.ops.back().flops = (double)b * b * b / 3.0;
+  }
+}
+
+void plan_blockcol(blr_matrix h, Plan& P, Work& w, BcWork& bw, int kend, bool fp32) {
+  const int b = h->b, rc = h->rc, p = h->p, q = h->q;
+  for (int k = 0; k < kend; ++k) {
+    // 1. gather the stack
+    std::vector<int64_t> off(p, 0);
+    std::vector<int> rows(p, 0);
+    std::vector<bool> yd(p, true);
+    int hs = 0;
+    for (int i = k; i < p; ++i) {
+      yd[i] = i == k || h->t(i, k).fmt == DENSE;
+      rows[i] = yd[i] ? b : rc;
+      off[i] = hs;
+      hs += rows[i];
+    }
+    std::vector<CopyDesc> cp;
+    for (int i = k; i < p; ++i) {
+      Tile& t = h->t(i, k);
+      cp.push_back(CopyDesc{yd[i] ? t.D : t.Vt, bw.stack + off[i], yd[i] ? (int64_t)b : (int64_t)rc, (int64_t)hs,
+                            rows[i], b, 0, 0});
+    }
+    P.copy(cp);
+    // 2. Householder QR of the stack, T_k
+    double* Tk = h->T[(size_t)k * q + k];
+    double* tauk = h->tau[(size_t)k * q + k];
+    plan_stack_qr(P, h, w, bw, hs, Tk, tauk);
+    // 3. scatter R_kk / Y back, explicit unit-lower Y_kk
+    cp.clear();
+    for (int i = k; i < p; ++i) {
+      Tile& t = h->t(i, k);
+      cp.push_back(CopyDesc{bw.stack + off[i], yd[i] ? t.D : t.Vt, (int64_t)hs, yd[i] ? (int64_t)b : (int64_t)rc,
+                            rows[i], b, 0, 0});
+      if (i > k) h->yfmt[(size_t)i * q + k] = yd[i] ? DENSE : LOWRANK;
+    }
+    cp.push_back(CopyDesc{bw.stack, bw.Yf, (int64_t)hs, (int64_t)b, b, b, 1, 0});
+    P.copy(cp);
+    if (k + 1 >= q) continue;
+    // 4. the projected update of every j > k
+    auto Yd = [&](int i) -> double* { return i == k ? bw.Yf : h->t(i, k).D; };
+    std::vector<bool> zd(q, false);
+    std::vector<int8_t> f((size_t)p * q);
+    for (size_t t = 0; t < f.size(); ++t) f[t] = h->tiles[t].fmt;
+    for (int j = k + 1; j < q; ++j) zd[j] = bc_zdense(h, f, k, j);
+    // slots for the pairs that need low-rank temporaries
+    std::vector<int> slot((size_t)p * q, -1);
+    int ns = 0;
+    for (int j = k + 1; j < q; ++j)
+      for (int i = k; i < p; ++i)
+        if (!(yd[i] && h->t(i, j).fmt == DENSE && zd[j])) slot[(size_t)i * q + j] = ns++;
+    if (ns > (int)bw.slots.size()) throw Error(BLR_ERR_DEVICE, "internal: block-column slot count");
+    auto S = [&](int i, int j) -> BcSlot& { return bw.slots[slot[(size_t)i * q + j]]; };
+    // 4a. pre-products of the low-rank terms
+    for (int j = k + 1; j < q; ++j)
+      for (int i = k; i < p; ++i) {
+        Tile& A = h->t(i, j);
+        Tile& Y = h->t(i, k);
+        const bool ad = A.fmt == DENSE;
+        if (yd[i] && ad) continue;
+        BcSlot& sl = S(i, j);
+        if (yd[i]) P.gemm(sl.Ua, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, Yd(i), b, A.U, b, b, SEG_TRANS_A);
+        else if (ad) P.gemm(sl.Sa, rc, nullptr, 0, nullptr, 0, rc, b, 1.0, 0.0, Y.U, b, A.D, b, b, SEG_TRANS_A);
+        else P.gemm(sl.Sm, rc, nullptr, 0, nullptr, 0, rc, rc, 1.0, 0.0, Y.U, b, A.U, b, b, SEG_TRANS_A);
+      }
+    P.flush_gemm();
+    for (int j = k + 1; j < q; ++j)
+      for (int i = k + 1; i < p; ++i)
+        if (!yd[i] && h->t(i, j).fmt == LOWRANK) {
+          BcSlot& sl = S(i, j);
+          P.gemm(sl.Ua, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, h->t(i, k).Vt, rc, sl.Sm, rc, rc, SEG_TRANS_A);
+        }
+    P.flush_gemm();
+    // 4b. dense Z_j: low-rank contributions, then the dense sum on top
+    std::vector<bool> zlr(q, false);
+    for (int j = k + 1; j < q; ++j) {
+      if (!zd[j]) continue;
+      std::vector<GemmSeg> sv;
+      for (int i = k; i < p; ++i) {
+        Tile& A = h->t(i, j);
+        if (yd[i] && A.fmt == DENSE) continue;
+        GemmSeg g{};
+        if (A.fmt == LOWRANK) {
+          g.A = S(i, j).Ua; g.lda = b; g.B = A.Vt; g.ldb = rc; g.K = rc; g.flags = 0;
+        } else {
+          g.A = h->t(i, k).Vt; g.lda = rc; g.B = S(i, j).Sa; g.ldb = rc; g.K = rc; g.flags = SEG_TRANS_A;
+        }
+        sv.push_back(g);
+      }
+      if (!sv.empty()) {
+        P.gemm_multi(w.X[j], b, nullptr, 0, b, b, 1.0, 0.0, sv);
+        zlr[j] = true;
+      }
+    }
+    P.flush_gemm();
+    for (int j = k + 1; j < q; ++j) {
+      if (!zd[j]) continue;
+      std::vector<GemmSeg> sv;
+      for (int i = k; i < p; ++i) {
+        Tile& A = h->t(i, j);
+        if (!(yd[i] && A.fmt == DENSE)) continue;
+        GemmSeg g{};
+        g.A = Yd(i); g.lda = b; g.B = A.D; g.ldb = b; g.K = b; g.flags = SEG_TRANS_A;
+        sv.push_back(g);
+      }
+      P.gemm_multi(w.X[j], b, zlr[j] ? w.X[j] : nullptr, b, b, b, 1.0, zlr[j] ? 1.0 : 0.0, sv);
+    }
+    P.flush_gemm(fp32, 1);
+    // 4c. low-rank Z_j: rounded additions of the terms in order i = k, k+1, ...
+    std::vector<RcTerm> zterm(q);
+    auto term = [&](int i, int j) -> RcTerm {
+      Tile& A = h->t(i, j);
+      if (A.fmt == LOWRANK) return RcTerm{S(i, j).Ua, A.Vt, A.rank, b, rc, 0, 0, 1.0};
+      return RcTerm{h->t(i, k).Vt, S(i, j).Sa, h->t(i, k).rank, rc, rc, 0, 1, 1.0};
+    };
+    for (int j = k + 1; j < q; ++j)
+      if (!zd[j]) zterm[j] = term(k, j);
+    for (int i = k + 1; i < p; ++i) {
+      for (int j = k + 1; j < q; ++j) {
+        if (zd[j]) continue;
+        RcDesc d{};
+        d.nterm = 2;
+        d.t[0] = zterm[j];
+        d.t[1] = term(i, j);
+        d.Uout = w.Uw[j];
+        d.Vtout = w.Vtw[j];
+        d.rank_out = w.rankw[j];
+        d.work = w.rcw[2 * j];
+        P.rc(d);
+        zterm[j] = RcTerm{w.Uw[j], w.Vtw[j], w.rankw[j], b, rc, 0, 0, 1.0};
+      }
+      P.flush_rc();
+    }
+    // 5. W_j = T_k^T Z_j
+    for (int j = k + 1; j < q; ++j) {
+      if (zd[j]) P.gemm(w.X2[j], b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, Tk, b, w.X[j], b, b, SEG_TRANS_A | SEG_A_UPPER);
+      else P.gemm(w.WU[j], b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, Tk, b, zterm[j].U, zterm[j].ldu, b,
+                  SEG_TRANS_A | SEG_A_UPPER);
+    }
+    P.flush_gemm(fp32, 1);
+    // 6. fill-in: low-rank targets of a dense update become dense (OP1)
+    for (int j = k + 1; j < q; ++j)
+      for (int i = k; i < p; ++i) {
+        Tile& A = h->t(i, j);
+        if (zd[j] && yd[i] && A.fmt == LOWRANK) {
+          P.gemm(A.D, b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, A.U, b, A.Vt, rc, rc, 0);
+          A.fmt = DENSE;
+          h->n_fill++;
+        }
+      }
+    P.flush_gemm();
+    // 7. updates A_ij -= Ytilde_ik W_j
+    for (int j = k + 1; j < q; ++j)
+      for (int i = k; i < p; ++i)
+        if (yd[i] && zd[j])
+          P.gemm(h->t(i, j).D, b, h->t(i, j).D, b, nullptr, 0, b, b, -1.0, 1.0, Yd(i), b, w.X2[j], b, b, 0);
+    P.flush_gemm(fp32, 1);
+    for (int j = k + 1; j < q; ++j)
+      for (int i = k; i < p; ++i) {
+        if (yd[i] && zd[j]) continue;
+        BcSlot& sl = S(i, j);
+        if (!yd[i] && zd[j])
+          P.gemm(sl.Sa, rc, nullptr, 0, nullptr, 0, rc, b, 1.0, 0.0, h->t(i, k).Vt, rc, w.X2[j], b, b, 0);
+        else if (yd[i])
+          P.gemm(sl.Ub, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, Yd(i), b, w.WU[j], b, b, 0);
+        else
+          P.gemm(sl.Sm, rc, nullptr, 0, nullptr, 0, rc, rc, 1.0, 0.0, h->t(i, k).Vt, rc, w.WU[j], b, b, 0);
+      }
+    P.flush_gemm();
+    for (int j = k + 1; j < q; ++j)
+      for (int i = k + 1; i < p; ++i)
+        if (!yd[i] && !zd[j]) {
+          BcSlot& sl = S(i, j);
+          P.gemm(sl.Ub, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, h->t(i, k).U, b, sl.Sm, rc, rc, 0);
+        }
+    P.flush_gemm();
+    for (int j = k + 1; j < q; ++j)
+      for (int i = k; i < p; ++i) {
+        if (yd[i] && zd[j]) continue;
+        Tile& A = h->t(i, j);
+        BcSlot& sl = S(i, j);
+        // the update as a low-rank product Uu Vu^T
+        const double* Uu;
+        const double* Vu;
+        const int* ru;
+        if (!yd[i] && zd[j]) { Uu = h->t(i, k).U; Vu = sl.Sa; ru = h->t(i, k).rank; }
+        else { Uu = sl.Ub; Vu = zterm[j].Vt; ru = zterm[j].rank_ptr; }
+        if (A.fmt == DENSE) {
+          P.gemm(A.D, b, A.D, b, nullptr, 0, b, b, -1.0, 1.0, Uu, b, Vu, rc, rc, 0);
+        } else {
+          RcDesc d{};
+          d.nterm = 2;
+          d.t[0] = RcTerm{A.U, A.Vt, A.rank, b, rc, 0, 0, 1.0};
+          d.t[1] = RcTerm{Uu, Vu, ru, b, rc, 0, 0, -1.0};
+          d.Uout = A.U;
+          d.Vtout = A.Vt;
+          d.rank_out = A.rank;
+          d.work = sl.rcw;
+          P.rc(d);
+        }
+      }
+    P.flush_gemm();
+    P.flush_rc();
+  }
+}
+
+// B <- Q^T B or Q B for the block-column factor (Alg. 3): per step k,
+// W = sum_i Ytilde_ik^T B_i, W = T_k^T W (or T_k W), B_i -= Ytilde_ik W.
+void plan_apply_blockcol(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, int nrhs, int trans,
+                         double* Sbuf) {
+  const int b = h->b, rc = h->rc, p = h->p, q = h->q;
+  const int K = h->steps_done;
+  auto step = [&](int k) {
+    double* Tk = h->T[(size_t)k * q + k];
+    for (int i = k + 1; i < p; ++i)
+      if (h->yfmt[(size_t)i * q + k] == LOWRANK)
+        P.gemm(Sbuf + (size_t)i * rc * nrhs, rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, h->t(i, k).U, b,
+               B + (int64_t)i * b, ldb, b, SEG_TRANS_A);
+    P.flush_gemm();
+    std::vector<GemmSeg> sv;
+    for (int i = k; i < p; ++i) {
+      GemmSeg g{};
+      if (i == k) {
+        g.A = h->t(k, k).D; g.lda = b; g.B = B + (int64_t)k * b; g.ldb = ldb; g.K = b;
+        g.flags = SEG_TRANS_A | SEG_A_UNIT_LOWER;
+      } else if (h->yfmt[(size_t)i * q + k] == DENSE) {
+        g.A = h->t(i, k).D; g.lda = b; g.B = B + (int64_t)i * b; g.ldb = ldb; g.K = b; g.flags = SEG_TRANS_A;
+      } else {
+        g.A = h->t(i, k).Vt; g.lda = rc; g.B = Sbuf + (size_t)i * rc * nrhs; g.ldb = rc; g.K = rc;
+        g.flags = SEG_TRANS_A;
+      }
+      sv.push_back(g);
+    }
+    P.gemm_multi(w.Wx, b, nullptr, 0, b, nrhs, 1.0, 0.0, sv);
+    P.flush_gemm();
+    P.gemm(w.Wx2, b, nullptr, 0, nullptr, 0, b, nrhs, 1.0, 0.0, Tk, b, w.Wx, b, b,
+           (trans ? 0 : SEG_TRANS_A) | SEG_A_UPPER);
+    P.flush_gemm();
+    for (int i = k; i < p; ++i) {
+      double* Bi = B + (int64_t)i * b;
+      if (i == k)
+        P.gemm(Bi, ldb, Bi, ldb, nullptr, 0, b, nrhs, -1.0, 1.0, h->t(k, k).D, b, w.Wx2, b, b, SEG_A_UNIT_LOWER);
+      else if (h->yfmt[(size_t)i * q + k] == DENSE)
+        P.gemm(Bi, ldb, Bi, ldb, nullptr, 0, b, nrhs, -1.0, 1.0, h->t(i, k).D, b, w.Wx2, b, b, 0);
+      else
+        P.gemm(Sbuf + (size_t)i * rc * nrhs, rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, h->t(i, k).Vt, rc,
+               w.Wx2, b, b, 0);
+    }
+    P.flush_gemm();
+    for (int i = k + 1; i < p; ++i)
+      if (h->yfmt[(size_t)i * q + k] == LOWRANK) {
+        double* Bi = B + (int64_t)i * b;
+        P.gemm(Bi, ldb, Bi, ldb, nullptr, 0, b, nrhs, -1.0, 1.0, h->t(i, k).U, b, Sbuf + (size_t)i * rc * nrhs, rc,
+               rc, 0);
+      }
+    P.flush_gemm();
+  };
+  if (!trans)
+    for (int k = 0; k < K; ++k) step(k);
+  else
+    for (int k = K - 1; k >= 0; --k) step(k);
+}
+
+void plan_apply(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, int nrhs, int trans) {
+  if (h->variant == BLR_BLOCK_COLUMN) {
+    double* S = (double*)h->work.alloc((size_t)h->p * h->rc * std::max(nrhs, 1) * 8);
+    plan_apply_blockcol(h, P, w, B, ldb, nrhs, trans, S);
+  } else {
+    plan_apply_tiled(h, P, w, B, ldb, nrhs, trans);
+  }
+}
+
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
 blr_status run_guarded(const std::function<void()>& f) {
@@ -1066,15 +1536,18 @@ blr_status blr_qr_factor(blr_matrix h, const blr_factor_opts* o, void* stream) {
   if (h->state != BLR_STATE_COMPRESSED) return fail(BLR_ERR_STATE, "matrix is already factored");
   if (o->variant != BLR_TILED && o->variant != BLR_BLOCK_COLUMN) return fail(BLR_ERR_INVALID, "bad variant");
   if (o->precision != BLR_FP64 && o->precision != BLR_MIXED_FP32) return fail(BLR_ERR_INVALID, "bad precision");
-  if (o->variant == BLR_BLOCK_COLUMN) return fail(BLR_ERR_INVALID, "block-column variant not available");
   hipStream_t s = as_stream(stream);
   return run_guarded([&] {
     const int b = h->b, p = h->p, q = h->q;
     const int kend = (o->stop_after_k < 0) ? q : std::min(q, o->stop_after_k);
     h->variant = o->variant;
     h->precision = o->precision;
+    const bool bc = o->variant == BLR_BLOCK_COLUMN;
+    int bc_pairs = 0;
     // fill-in: simulate formats to find the tiles that need a dense slot
-    {
+    if (bc) {
+      alloc_dense(h, bc_simulate(h, kend, &bc_pairs));
+    } else {
       std::vector<int8_t> f((size_t)p * q);
       for (size_t t = 0; t < f.size(); ++t) f[t] = h->tiles[t].fmt;
       std::vector<int> need;
@@ -1101,7 +1574,7 @@ blr_status blr_qr_factor(blr_matrix h, const blr_factor_opts* o, void* stream) {
     {
       std::vector<int> idx;
       for (int k = 0; k < kend; ++k)
-        for (int i = k; i < p; ++i) idx.push_back(i * q + k);
+        for (int i = k; i < (bc ? k + 1 : p); ++i) idx.push_back(i * q + k);
       double* tp = (double*)h->mem.alloc(idx.size() * (size_t)b * b * 8);
       HIPCHECK(hipMemset(tp, 0, idx.size() * (size_t)b * b * 8));
       double* tu = (double*)h->mem.alloc(idx.size() * (size_t)b * 8);
@@ -1113,12 +1586,18 @@ blr_status blr_qr_factor(blr_matrix h, const blr_factor_opts* o, void* stream) {
     }
     h->work.release();
     std::vector<Work> works;
-    int nstreams = kStreams;
-    if (const char* e = std::getenv("BLRQR_STREAMS")) nstreams = std::max(1, std::min(kStreams, std::atoi(e)));
+    int nstreams = bc ? 1 : kStreams;
+    if (const char* e = std::getenv("BLRQR_STREAMS"); e && !bc)
+      nstreams = std::max(1, std::min(kStreams, std::atoi(e)));
     for (int a = 0; a < nstreams; ++a) works.push_back(make_work(h, 0));
     Plan P;
     h->n_fill = 0;
-    plan_tiled(h, P, works, kend, o->precision == BLR_MIXED_FP32);
+    if (bc) {
+      BcWork bw = make_bc_work(h, bc_pairs);
+      plan_blockcol(h, P, works[0], bw, kend, o->precision == BLR_MIXED_FP32);
+    } else {
+      plan_tiled(h, P, works, kend, o->precision == BLR_MIXED_FP32);
+    }
     P.upload(h->work);
     h->flops = 0.0;
     for (auto& op : P.ops) h->flops += op.flops;
@@ -1145,7 +1624,7 @@ blr_status blr_apply_qt(blr_matrix h, int32_t trans, double* B, int64_t ldb, int
     h->work.release();
     Work w = make_work(h, nrhs);
     Plan P;
-    plan_apply_tiled(h, P, w, B, ldb, nrhs, trans);
+    plan_apply(h, P, w, B, ldb, nrhs, trans);
     P.upload(h->work);
     execute(h, P, s);
   });
@@ -1206,7 +1685,7 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
     double* C = (double*)h->work.alloc((size_t)m * nrhs * 8);
     HIPCHECK(hipMemcpy2DAsync(C, m * 8, B, ldb * 8, m * 8, nrhs, hipMemcpyDeviceToDevice, s));
     Plan P;
-    plan_apply_tiled(h, P, w, C, m, nrhs, 0);
+    plan_apply(h, P, w, C, m, nrhs, 0);
     P.upload(h->work);
     execute(h, P, s);
     if (resid_norms) {

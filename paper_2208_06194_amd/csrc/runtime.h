@@ -44,13 +44,16 @@ struct Arena {
 
 // One enqueued operation of a plan.
 struct Op {
-  enum Kind { GEMM, PANEL, PANEL_APPLY, TBACK, RC, TRSM, WAIT, RECORD } kind;
+  enum Kind { GEMM, PANEL, PANEL_APPLY, TBACK, RC, TRSM, WAIT, RECORD, TALL_COL, TALL_APPLY, COPY } kind;
   int off = 0, n = 0, ntiles = 0, big = 0, fp32 = 0, prof = 0;
   int stream = 0;   // index into the plan's streams
   int event = -1;   // WAIT / RECORD: event index
   double flops = 0.0;
   PanelArgs panel{};
   TBackArgs tback{};
+  TallArgs tall{};
+  double* buf = nullptr;   // TALL_APPLY: partial sums
+  int64_t maxel = 0;       // COPY: largest block
 };
 
 // Launch list with host-side descriptor arrays, uploaded once.
@@ -59,6 +62,8 @@ struct Plan {
   std::vector<GemmDesc> descs;
   std::vector<GemmSeg> segs;
   std::vector<RcDesc> rcs;
+  std::vector<CopyDesc> copies;
+  CopyDesc* d_copies = nullptr;
   GemmDesc* d_descs = nullptr;
   GemmSeg* d_segs = nullptr;
   RcDesc* d_rcs = nullptr;
@@ -74,6 +79,9 @@ struct Plan {
   void gemm(double* C, int64_t ldc, const double* Cin, int64_t ldcin, double* D2, int64_t ldd2,
             int M, int N, double alpha, double beta, const double* A, int64_t lda, const double* B,
             int64_t ldb, int K, int segflags, int descflags = 0);
+  // add one descriptor summing several K segments: C = alpha * sum_s op(A_s) op(B_s) + beta * Cin
+  void gemm_multi(double* C, int64_t ldc, const double* Cin, int64_t ldcin, int M, int N, double alpha,
+                  double beta, const std::vector<GemmSeg>& segs);
   void flush_gemm(int fp32 = 0, int prof = 0);
   void rc(const RcDesc& d) { currc.push_back(d); }
   void flush_rc();
@@ -81,6 +89,16 @@ struct Plan {
   void panel(const PanelArgs& a) { Op o; o.kind = Op::PANEL; o.panel = a; push(o); }
   void panel_apply(const PanelArgs& a, int nt) { Op o; o.kind = Op::PANEL_APPLY; o.panel = a; o.n = nt; push(o); }
   void tback(const TBackArgs& a) { Op o; o.kind = Op::TBACK; o.tback = a; push(o); }
+  void copy(const std::vector<CopyDesc>& v) {
+    if (v.empty()) return;
+    Op o;
+    o.kind = Op::COPY;
+    o.off = (int)copies.size();
+    o.n = (int)v.size();
+    for (auto& c : v) o.maxel = std::max<int64_t>(o.maxel, (int64_t)c.rows * c.cols);
+    copies.insert(copies.end(), v.begin(), v.end());
+    push(o);
+  }
   void wait(int e) { Op o; o.kind = Op::WAIT; o.event = e; push(o); n_events = std::max(n_events, e + 1); }
   void record(int e) { Op o; o.kind = Op::RECORD; o.event = e; push(o); n_events = std::max(n_events, e + 1); }
   void upload(Arena& arena);

@@ -1,0 +1,186 @@
+"""GPU parity of the block-column BLR-QR (Alg. 2 with Section 3.2) and its Q
+application (Alg. 3): the HIP path through the C ABI against the oracle's
+block-column factor on the same seeded inputs.  Stacks of up to 512 rows
+take the one-workgroup panel kernel with 32-column panels, up to 1024 rows
+with 16-column panels, taller stacks the row-split kernels: the shapes below
+cover all three and ragged stacks of low-rank row factors."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import blockcol, blrmat, metrics, tiled
+from oracle.blrmat import LOWRANK
+from tests.blr_helpers import blr_to_host, export_r
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+U = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2208_06194_amd as P
+    assert torch.cuda.is_available()
+    return P
+
+
+def gpu_import(P, blr, eps, cap):
+    fmt, rank, dense, Uh, Vh = blr_to_host(blr, cap)
+    return P.BLRMatrix.import_tiles(blr.m, blr.n, blr.b, eps, cap, fmt, rank, dense, Uh, Vh)
+
+
+def kernel_blr(seed, m, n, b, eps, cap, kern="inv_r", dim=3, rule="dist_gt_diam"):
+    x, y = synth.kernel_points(seed, m, n, dim)
+    A = blrmat.kernel_matrix(x, y, kern)
+    mask = blrmat.lowrank_mask(x, y, b, rule, m // b, n // b)
+    return A, blrmat.compress(A, b, eps, cap, mask)
+
+
+@pytest.mark.parametrize("m,n,b", [
+    (256, 128, 64),     # stacks <= 512 rows: 32-column register panels
+    (768, 256, 64),     # 512 < rows <= 1024: 16-column register panels
+    (192, 96, 48),      # b not a multiple of 32
+    (2048, 128, 64),    # stacks of 2048 .. 1984 rows: row-split panels
+    (1536, 512, 128),   # tall first stacks, register panels for the last
+])
+def test_all_dense_blockcol_matches_oracle(P, m, n, b):
+    print("case: blockcol all dense", m, n, b, flush=True)
+    A = np.random.default_rng(7 * m + b).standard_normal((m, n))
+    blr = blrmat.compress(A, b, 1e-12, b, np.zeros((m // b, n // b), bool))
+    f = blockcol.factor(blr, 1e-12, b)
+    G = gpu_import(P, blr, 1e-12, b)
+    G.factor("block_column")
+    ex = G.export(with_factor=True)
+    kappa = np.linalg.cond(A)
+    tol = 10 * n * U * kappa
+    Rg, Ro = export_r(ex), f.r_dense()
+    assert np.linalg.norm(Rg - Ro) / np.linalg.norm(Ro) <= tol
+    for k in range(f.q):
+        # reflectors of the stack and T_k
+        assert np.allclose(np.tril(ex["dense"][k, k], -1), np.tril(f.A.D[(k, k)], -1), atol=tol * 10)
+        assert np.allclose(ex["T"][k, k], f.Tk[k], atol=tol * 10 * np.abs(f.Tk[k]).max())
+        for i in range(k + 1, f.p):
+            assert np.allclose(ex["dense"][i, k], f.A.D[(i, k)], atol=tol * 10)
+    At = torch.tensor(A, device="cuda")
+    QtA = G.apply_qt(At).cpu().numpy()
+    assert np.linalg.norm(QtA[:n] - Rg) / np.linalg.norm(A) <= tol
+    assert np.linalg.norm(QtA[n:]) / np.linalg.norm(A) <= tol
+    B = torch.tensor(synth.rhs(2, m, 3), device="cuda")
+    Bo = B.cpu().numpy()
+    QtB = G.apply_qt(B).cpu().numpy()
+    assert np.allclose(QtB, f.apply_qt(Bo), atol=tol * np.abs(Bo).max())
+    back = G.apply_qt(torch.tensor(QtB, device="cuda"), trans=True)
+    assert torch.allclose(back, B, atol=1e-12)
+
+
+CASES = [
+    # (seed, m, n, b, eps, cap, kernel, dim, rule)
+    (0, 512, 256, 64, 1e-8, 16, "log2d", 2, "adjacent"),
+    (1, 512, 256, 32, 1e-8, 32, "inv_r", 3, "dist_gt_diam"),
+    (2, 384, 192, 48, 1e-6, 16, "log2d", 2, "weak"),
+    (3, 2048, 512, 64, 1e-8, 32, "inv_r", 3, "dist_gt_diam"),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_blockcol_factor_of_imported_blr_matches_oracle(P, case):
+    seed, m, n, b, eps, cap, kern, dim, rule = case
+    print("case: blockcol import", case, flush=True)
+    A, blr = kernel_blr(seed, m, n, b, eps, cap, kern, dim, rule)
+    At = blr.to_dense()
+    f = blockcol.factor(blr, eps, cap)
+    G = gpu_import(P, blr, eps, cap)
+    G.factor("block_column")
+    ex = G.export(with_factor=True)
+    # the same fill-in (OP1) decisions, the same reflector formats
+    assert np.array_equal(ex["fmt"], f.A.fmt)
+    # the first stack sees identical inputs: its reflector rows agree to rounding
+    kappa = np.linalg.cond(At)
+    for i in range(1, f.p):
+        if blr.fmt[i, 0] == LOWRANK:
+            r = blr.rank(i, 0)
+            assert np.allclose(ex["Y"][i, 0][:r], f.Yl[(i, 0)], atol=1e3 * m * U * kappa)
+    Rg, Ro = export_r(ex), f.r_dense()
+    rel = np.linalg.norm(metrics.sign_fix(Rg, Ro) - Ro) / np.linalg.norm(Ro)
+    print("R rel diff (up to row signs)", rel, "kappa", kappa, flush=True)
+    assert rel <= 10 * kappa * eps
+    assert rel <= 1e3 * n * U * kappa or f.stats.recompressions > 0
+    RR = np.zeros((m, n))
+    RR[:n] = Rg
+    QR = G.apply_qt(torch.tensor(RR, device="cuda"), trans=True).cpu().numpy()
+    res = np.linalg.norm(QR - At) / np.linalg.norm(At)
+    print("Res_At", res, "oracle", metrics.res(f, At), flush=True)
+    assert res <= 10 * eps
+    # orthogonality of the GPU Q on a block of unit vectors
+    E = np.eye(m)[:, :min(m, 64)]
+    QE = G.apply_qt(torch.tensor(E, device="cuda"), trans=True).cpu().numpy()
+    assert np.linalg.norm(QE.T @ QE - np.eye(E.shape[1])) <= 1e2 * m * U
+
+
+def test_blockcol_and_tiled_agree(P):
+    """Both variants factor the same matrix: R agrees up to row signs to the
+    compression tolerance (exactly, up to rounding, where nothing is
+    recompressed)."""
+    print("case: variants agree", flush=True)
+    m, n, b, eps, cap = 512, 256, 64, 1e-8, 32
+    A, blr = kernel_blr(11, m, n, b, eps, cap)
+    At = blr.to_dense()
+    Gt = gpu_import(P, blr, eps, cap)
+    Gt.factor("tiled")
+    Gb = gpu_import(P, blr, eps, cap)
+    Gb.factor("block_column")
+    Rt, Rb = export_r(Gt.export()), export_r(Gb.export())
+    kappa = np.linalg.cond(At)
+    rel = np.linalg.norm(metrics.sign_fix(Rb, Rt) - Rt) / np.linalg.norm(Rt)
+    print("tiled vs block column R", rel, flush=True)
+    assert rel <= 10 * kappa * eps
+
+
+def test_blockcol_lstsq_matches_oracle(P):
+    print("case: blockcol lstsq", flush=True)
+    m, n, b, eps, cap = 512, 256, 64, 1e-8, 32
+    A, blr = kernel_blr(5, m, n, b, eps, cap, "log2d", 2, "adjacent")
+    At = blr.to_dense()
+    f = blockcol.factor(blr, eps, cap)
+    Bh = synth.rhs(5, m, 4)
+    Xo = f.lstsq(Bh)
+    G = gpu_import(P, blr, eps, cap)
+    G.factor("block_column")
+    X, res = G.lstsq(torch.tensor(Bh, device="cuda"), with_resid=True)
+    X, res = X.cpu().numpy(), res.cpu().numpy()
+    kappa = np.linalg.cond(At)
+    assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) <= 10 * kappa * eps
+    r_true = np.linalg.norm(Bh - f.q_times_r() @ X, axis=0)
+    assert np.allclose(res, r_true, rtol=1e-6)
+
+
+def test_blockcol_prefix_matches_oracle(P):
+    print("case: blockcol prefix", flush=True)
+    m, n, b, eps, cap = 512, 256, 64, 1e-8, 32
+    A, blr = kernel_blr(6, m, n, b, eps, cap)
+    f = blockcol.factor(blr, eps, cap, stop_after_k=2)
+    G = gpu_import(P, blr, eps, cap)
+    G.factor("block_column", stop_after_k=2)
+    ex = G.export()
+    assert np.array_equal(ex["fmt"], f.A.fmt)
+    # the first two block rows of R, up to row signs; the trailing tiles as values
+    Ro = f.r_dense()[:2 * b]
+    Rg = export_r(ex)[:2 * b]
+    rel = np.linalg.norm(metrics.sign_fix(Rg, Ro) - Ro) / np.linalg.norm(Ro)
+    assert rel <= 1e3 * n * U * np.linalg.cond(blr.to_dense())
+
+
+def test_blockcol_mixed_precision(P):
+    print("case: blockcol mixed", flush=True)
+    m, n, b, eps, cap = 1024, 512, 128, 1e-6, 32
+    A, blr = kernel_blr(4, m, n, b, eps, cap)
+    At = blr.to_dense()
+    G = gpu_import(P, blr, eps, cap)
+    G.factor("block_column", precision="mixed")
+    Rg = export_r(G.export())
+    RR = np.zeros((m, n))
+    RR[:n] = Rg
+    QR = G.apply_qt(torch.tensor(RR, device="cuda"), trans=True).cpu().numpy()
+    res = np.linalg.norm(QR - At) / np.linalg.norm(At)
+    print("mixed Res", res, flush=True)
+    assert res <= 1e-5
