@@ -52,7 +52,7 @@ enum { BLR_KERNEL_LOG2D = 0 /* -log(d + reg) */, BLR_KERNEL_INV_R = 1 /* 1/(d + 
 enum { BLR_ADM_ADJACENT = 0, BLR_ADM_DIST_GT_DIAM = 1, BLR_ADM_WEAK = 2, BLR_ADM_MASK = 3 };
 /* What compression does with a tile whose eps-rank exceeds max_rank. */
 enum { BLR_OVERFLOW_DENSE = 0, BLR_OVERFLOW_TRUNCATE = 1 };
-/* Factorization variants: tiled (Alg. 4, Section 3.3) and block-column (Alg. 2, Section 3.2). */
+/* Factorization variants: tiled (Alg. 4, Section 3.4) and block-column (Alg. 2, Section 3.3). */
 enum { BLR_TILED = 0, BLR_BLOCK_COLUMN = 1 };
 /* Precision: all FP64, or reflector-apply products in FP32 on the matrix
  * cores (FP32 inputs, FP32 accumulation) with reflector generation, the R
@@ -147,7 +147,7 @@ blr_status blr_compress(const blr_source* src, const blr_compress_opts* opts,
 
 /* Build a handle from host tiles (fmt, rank, dense, U, V of blr_tiles_host).
  * Only m, n, tile, tol, max_rank of opts are used.  Low-rank U must have
- * orthonormal columns (the factorization relies on it, Section 3.2.1).
+ * orthonormal columns (the factorization relies on it, Section 3.3.1).
  * Synchronises the stream. */
 blr_status blr_import(const blr_compress_opts* opts, const blr_tiles_host* tiles,
                       void* hip_stream, blr_matrix* out);
@@ -156,7 +156,7 @@ blr_status blr_import(const blr_compress_opts* opts, const blr_tiles_host* tiles
 blr_status blr_export(blr_matrix h, blr_tiles_host* tiles);
 
 /* Householder QR of the BLR matrix, in place (tiled: Alg. 4 with the
- * operations of Section 3.3; block column: Alg. 2 with Section 3.2).
+ * operations of Section 3.4; block column: Alg. 2 with Section 3.3).
  * The handle goes from COMPRESSED to FACTORED; a second call returns
  * BLR_ERR_STATE.  Enqueued on hip_stream (asynchronous). */
 blr_status blr_qr_factor(blr_matrix h, const blr_factor_opts* opts, void* hip_stream);
@@ -166,6 +166,19 @@ blr_status blr_qr_factor(blr_matrix h, const blr_factor_opts* opts, void* hip_st
  * overwritten.  Requires FACTORED.  Asynchronous. */
 blr_status blr_apply_qt(blr_matrix h, int32_t trans, double* B, int64_t ldb,
                         int32_t nrhs, void* hip_stream);
+
+/* Products with the stored BLR matrix, for residual and orthogonality
+ * checks and refinement (eq. blr_matrix_def, eq. qr_fact):
+ *   BLR_MATMUL_A   Y = A~ X     requires COMPRESSED; X n x nrhs, Y m x nrhs
+ *   BLR_MATMUL_AT  Y = A~^T X   requires COMPRESSED; X m x nrhs, Y n x nrhs
+ *   BLR_MATMUL_R   Y = R X      requires a complete factor; X, Y n x nrhs
+ * X and Y: device, column-major (ldx, ldy at least their row counts), must
+ * not overlap; Y is overwritten.  Dense tiles multiply directly, low-rank
+ * tiles as U (V^T X) (or V (U^T X)); R uses the upper triangle of the
+ * diagonal tiles and the stored R_kj tiles.  Asynchronous on hip_stream. */
+typedef enum { BLR_MATMUL_A = 0, BLR_MATMUL_AT = 1, BLR_MATMUL_R = 2 } blr_matmul_op;
+blr_status blr_matmul(blr_matrix h, int32_t op, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                      int32_t nrhs, void* hip_stream);
 
 /* Least squares X = argmin ||A~ X - B||_F column by column, X = R^{-1}
  * (Q^T B)[0:n] with tile back-substitution through the BLR factor R.

@@ -1,5 +1,5 @@
 """Block-column-wise Householder BLR-QR (paper Alg. 2 with the operations of
-Section 3.2) and left multiplication by Q / Q^T (Alg. 3).
+Section 3.3) and left multiplication by Q / Q^T (Alg. 3).
 
 Step k:
   1. stack the left-orthogonal row factors of block column k,

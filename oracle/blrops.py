@@ -1,5 +1,5 @@
 """Format rules of BLR tile arithmetic (paper Section 3.1, OP1-OP4 and
-Alg. 6) as used by the reflector applications of Sections 3.2.2 and 3.3.4.
+Alg. 6) as used by the reflector applications of Sections 3.3.2 and 3.4.4.
 
 A tile value is ('D', M) or ('L', U, V) meaning U V^T.  A reflector block
 Ytilde is ('D', Y) or ('L', Uy, Yl) meaning Uy @ Yl (Yl is r x b).

@@ -64,8 +64,8 @@ def householder_qr(A: np.ndarray):
 
     Returns (F, tau, T): F holds R in its upper triangle and the reflector
     tails in its strict lower part; T is the nb x nb compact-WY factor.
-    Used for the diagonal tile (GEQRT, Section 3.3.1) and for the stacked
-    block column (Section 3.2.1)."""
+    Used for the diagonal tile (GEQRT, Section 3.4.1) and for the stacked
+    block column (Section 3.3.1)."""
     F = np.array(A, dtype=np.float64, copy=True)
     h, nb = F.shape
     tau = np.zeros(nb)
@@ -85,13 +85,13 @@ def householder_qr(A: np.ndarray):
 
 
 def geqrt(A: np.ndarray):
-    """QR of a dense b x b diagonal tile (Section 3.3.1): A = Qkk Rkk with
+    """QR of a dense b x b diagonal tile (Section 3.4.1): A = Qkk Rkk with
     Qkk = I - Y T Y^T.  Returns (F, tau, T) as householder_qr."""
     return householder_qr(A)
 
 
 def apply_qt_left(Y: np.ndarray, T: np.ndarray, C: np.ndarray) -> np.ndarray:
-    """C <- (I - Y T Y^T)^T C = C - Y T^T (Y^T C)  (Section 3.3.2)."""
+    """C <- (I - Y T Y^T)^T C = C - Y T^T (Y^T C)  (Section 3.4.2)."""
     return C - Y @ (T.T @ (Y.T @ C))
 
 
@@ -102,7 +102,7 @@ def apply_q_left(Y: np.ndarray, T: np.ndarray, C: np.ndarray) -> np.ndarray:
 
 def tpqrt(R: np.ndarray, B: np.ndarray):
     """QR of the stack [R; B], R upper triangular nb x nb, B mb x nb dense
-    (Section 3.3.3).  Reflector j is [e_j; y_j] with y_j in R^mb, so
+    (Section 3.4.3).  Reflector j is [e_j; y_j] with y_j in R^mb, so
     Q = I - [I; Y] T [I; Y]^T.  Returns (R', Y, tau, T)."""
     R = np.triu(np.array(R, dtype=np.float64, copy=True))
     Y = np.array(B, dtype=np.float64, copy=True)
@@ -123,7 +123,7 @@ def tpqrt(R: np.ndarray, B: np.ndarray):
 
 
 def tpmqrt_t(Y: np.ndarray, T: np.ndarray, C1: np.ndarray, C2: np.ndarray):
-    """[C1; C2] <- Q^T [C1; C2] with Q = I - [I; Y] T [I; Y]^T (Section 3.3.4):
+    """[C1; C2] <- Q^T [C1; C2] with Q = I - [I; Y] T [I; Y]^T (Section 3.4.4):
     W = T^T (C1 + Y^T C2);  C1 - W;  C2 - Y W."""
     W = T.T @ (C1 + Y.T @ C2)
     return C1 - W, C2 - Y @ W

@@ -1,5 +1,5 @@
 """Common state of a factored BLR matrix (both variants) and what is read
-off it: the BLR factor R (paper eq. qr_fact with Section 3.2/3.3: R has the
+off it: the BLR factor R (paper eq. qr_fact with Section 3.3/3.4: R has the
 same tile structure as A), the reflector blocks Ytilde_ik, and the BLR
 back-substitution used for least squares (the motivation in Section 1)."""
 from __future__ import annotations

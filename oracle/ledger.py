@@ -1,4 +1,4 @@
-"""Task counts and operation-count models of Sections 3.2.3 and 3.3.5
+"""Task counts and operation-count models of Sections 3.3.3 and 3.4.5
 (Tables blr_bch_operations and blr_bh_operations).  Indices are 1-based in
 the paper's sums; p = m/b, q = n/b, r the (fixed) low-rank rank."""
 from __future__ import annotations

@@ -1,13 +1,13 @@
-"""Tiled Householder BLR-QR (paper Alg. 4 with the operations of Section 3.3)
+"""Tiled Householder BLR-QR (paper Alg. 4 with the operations of Section 3.4)
 and left multiplication by Q / Q^T (Alg. 5).
 
-Task set of one k-iteration (Section 3.3, Table blr_bh_operations):
-  GEQRT(k)        QR of the diagonal tile (3.3.1)
-  LARFB(k,j)      R_kj = Qkk^T A_kj, j > k; a low-rank tile updates U only (3.3.2)
+Task set of one k-iteration (Section 3.4, Table blr_bh_operations):
+  GEQRT(k)        QR of the diagonal tile (3.4.1)
+  LARFB(k,j)      R_kj = Qkk^T A_kj, j > k; a low-rank tile updates U only (3.4.2)
   TPQRT(i,k)      QR of [R_kk; A_ik], i > k; for a low-rank A_ik the QR is of
-                  [R_kk; V_ik^T] and Ytilde_ik = U_ik Y_ik with the same T (3.3.3)
+                  [R_kk; V_ik^T] and Ytilde_ik = U_ik Y_ik with the same T (3.4.3)
   TPMQRT(i,k,j)   [R_kj; A_ij] -= [I; Ytilde_ik] T_ik^T (R_kj + Ytilde_ik^T A_ij)
-                  with the OP1-OP4 format rules (3.3.4)
+                  with the OP1-OP4 format rules (3.4.4)
 
 The DAG of Section 4.3 is derived from the tiles each task reads and writes;
 `run(order=...)` executes any topological order of it (the result does not

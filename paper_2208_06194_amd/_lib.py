@@ -12,9 +12,10 @@ c_int32, c_int64, c_double, c_void_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_
 EXPORTED = [
     "blr_compress", "blr_import", "blr_export", "blr_qr_factor", "blr_apply_qt",
     "blr_lstsq_solve", "blr_query", "blr_destroy", "blr_status_string", "blr_last_error",
-    "blr_profile_enable", "blr_profile_read",
+    "blr_profile_enable", "blr_profile_read", "blr_matmul",
 ]
 SELFTEST = ["blr_selftest_gemm"]
+MATMUL = {"A": 0, "AT": 1, "R": 2}
 
 BLR_OK, BLR_ERR_INVALID, BLR_ERR_STATE, BLR_ERR_OOM, BLR_ERR_DEVICE, BLR_ERR_NONFINITE, BLR_ERR_SINGULAR = range(7)
 SRC_KERNEL, SRC_DENSE = 0, 1
@@ -74,6 +75,7 @@ def load() -> ctypes.CDLL:
     lib.blr_apply_qt.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_int32, c_void_p]
     lib.blr_lstsq_solve.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int32, c_int32,
                                     c_void_p, c_void_p]
+    lib.blr_matmul.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_void_p, c_int64, c_int32, c_void_p]
     lib.blr_query.argtypes = [c_void_p, P(Info)]
     lib.blr_destroy.argtypes = [c_void_p]
     lib.blr_destroy.restype = None

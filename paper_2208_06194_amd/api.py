@@ -155,6 +155,19 @@ class BLRMatrix:
         _check(L.load().blr_qr_factor(self._h, ctypes.byref(o), _stream(stream)))
         return self
 
+    def matmul(self, X: torch.Tensor, op: str = "A", stream=None) -> torch.Tensor:
+        """A~ X (op "A", before the factorization), A~^T X ("AT") or R X ("R",
+        after it) for a device tensor X with one column per right-hand side."""
+        inf = self.info()
+        m, n = inf["m"], inf["n"]
+        Xc = _colmajor(X.to(torch.float64))
+        nrhs, xr = Xc.shape
+        yr = m if op == "A" else n
+        Yc = torch.empty((nrhs, yr), dtype=torch.float64, device=Xc.device)
+        _check(L.load().blr_matmul(self._h, L.MATMUL[op], Xc.data_ptr(), xr, Yc.data_ptr(), yr, nrhs,
+                                   _stream(stream)))
+        return Yc.t()
+
     def apply_qt(self, B: torch.Tensor, trans: bool = False, stream=None) -> torch.Tensor:
         """Return Q^T B (trans=False) or Q B (trans=True) for a (m, nrhs) device tensor."""
         Bc = _colmajor(B.to(torch.float64))

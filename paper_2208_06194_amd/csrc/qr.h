@@ -34,7 +34,7 @@ struct TallArgs {
   int h;           // rows from the pivot down
   int ib;          // panel width (<= 32)
   int jj;          // column of the panel being factored
-  double* part;    // partials: (G + 1) x 2*ib doubles
+  double* part;    // partials: 2 x (G + 1) x 2*ib doubles
   double* T;       // T element (c0, c0)
   int64_t ldt;
   double* tau;     // tau[c0 ..]
@@ -45,12 +45,16 @@ struct CopyDesc {
   double* dst;
   int64_t lds, ldd;
   int32_t rows, cols;
-  int32_t unit_lower;   // write the unit lower triangular part of src (diag 1, upper 0)
-  int32_t pad_;
+  int32_t unit_lower;   // 1: write the unit lower triangular part of src (diag 1, upper 0);
+                        // 2: write the upper triangular part (zeros below the diagonal)
+  int32_t nsum;         // > 1: dst = sum of nsum blocks of src, sstride doubles apart (split-K)
+  int64_t sstride;
 };
 
 hipError_t launch_panel(const PanelArgs& a, hipStream_t stream);
-// Two launches per column of a tall panel (see qr.hip); groups = row groups.
+// One launch per column of a tall panel (two for its first column), over
+// groups row groups (1 .. kTallMaxGroups); ib must be 16 or 32.
+constexpr int kTallMaxGroups = 512;
 hipError_t launch_tall_column(const TallArgs& a, int groups, hipStream_t stream);
 // Split-K trailing update of a tall panel; part: slices * ceil(nt/32) * ib * 32 doubles.
 hipError_t launch_tall_apply(const PanelArgs& a, int nt, int slices, double* part, hipStream_t stream);

@@ -1,4 +1,4 @@
-// Householder reflector generation on tiles (Sections 3.3.1 and 3.3.3 of
+// Householder reflector generation on tiles (Sections 3.4.1 and 3.4.3 of
 // arXiv 2208.06194) and the compact-WY factor T (eq. compact_wy).
 //
 // k_panel factors IB consecutive columns of a tile held in registers (one
@@ -334,78 +334,139 @@ __global__ __launch_bounds__(256) void k_t_backsolve(TBackArgs a) {
 // ---------------------------------------------------------------------------
 // Tall panels (block-column variant, stacks taller than 1024 rows).  The
 // panel is IB columns of the stack starting at its pivot (c0, c0): X points
-// there, h rows below it.  Column jj takes two launches over G row groups:
-//   k_tall_dots:   per group, the tail sum of squares of column jj and its
-//                  dot products with the other panel columns; group 0 also
-//                  snapshots the pivot row jj of the panel;
-//   k_tall_update: every group reduces the partials, forms the larfg scalars
-//                  and w_t = X(jj,t) + v^T x_t, scales its rows of column jj
-//                  and applies the rank-one update to the later columns;
-//                  group 0 writes the pivot row, tau and column jj of T.
-__global__ __launch_bounds__(256) void k_tall_dots(TallArgs a) {
-  __shared__ double red[4][33];
+// there, h rows below it.  The rows are split into G fixed groups (one
+// workgroup each).  One launch per column jj:
+//   - every group sums the G partial results of the previous launch (tail sum
+//     of squares of column jj, its dot products with the other panel columns,
+//     and the pivot row jj) and forms the larfg scalars and
+//     w_t = X(jj,t) + v^T x_t;
+//   - it scales its rows of column jj into the reflector, applies the
+//     rank-one update to the later columns, and on the same rows already
+//     accumulates the partials of column jj + 1 (the group holding row jj + 1
+//     also snapshots that row);
+//   - the group holding row jj writes the pivot row, tau and column jj of T.
+// Partials are double buffered: launch jj reads buffer jj % 2 and writes
+// buffer (jj + 1) % 2, each (G + 1) x 2 IB doubles.  k_tall_first seeds
+// buffer 0 for column 0.  The summation order is fixed, so the result does
+// not depend on timing.
+__device__ __forceinline__ void tall_rows(int h, int G, int g, int* rs, int* re) {
+  const int chunk = (h + G - 1) / G;
+  *rs = min(h, g * chunk);
+  *re = min(h, *rs + chunk);
+}
+
+template <int IB>
+__device__ __forceinline__ void tall_store_partials(double (&part)[IB], double (*red)[IB], double* out, int g) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int jj = a.jj, ib = a.ib, G = gridDim.x, g = blockIdx.x;
-  const int64_t ld = a.ldx;
-  const int r0 = jj + 1;
-  const int len = a.h - r0;
-  const int chunk = (len + G - 1) / G;
-  const int rs = r0 + g * chunk, re = min(a.h, rs + chunk);
-  double part[33];
-  for (int t = 0; t <= 32; ++t) part[t] = 0.0;
-  const double* xc = a.X + (int64_t)jj * ld;
-  for (int r = rs + tid; r < re; r += 256) {
-    const double v = xc[r];
 #pragma unroll
-    for (int t = 0; t < 32; ++t)
-      if (t < ib) part[t] += (t == jj) ? v * v : v * a.X[r + (int64_t)t * ld];
-  }
-#pragma unroll
-  for (int t = 0; t < 32; ++t) {
+  for (int t = 0; t < IB; ++t) {
     const double s = wave_sum(part[t]);
     if (lane == 0) red[w][t] = s;
   }
   __syncthreads();
-  if (tid < ib) a.part[(int64_t)g * (2 * ib) + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-  if (g == 0 && tid < ib) a.part[(int64_t)G * (2 * ib) + tid] = a.X[jj + (int64_t)tid * ld];
+  if (tid < IB) out[(int64_t)g * (2 * IB) + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
 }
 
-__global__ __launch_bounds__(256) void k_tall_update(TallArgs a) {
-  __shared__ double sv[64];   // [0, ib): reduced dots / ss; [32, 32+ib): pivot row
-  __shared__ double wv[32];
-  const int tid = threadIdx.x;
-  const int jj = a.jj, ib = a.ib, G = gridDim.x, g = blockIdx.x;
+template <int IB>
+__global__ __launch_bounds__(256) void k_tall_first(TallArgs a) {
+  __shared__ double red[4][IB];
+  const int tid = threadIdx.x, G = gridDim.x, g = blockIdx.x;
   const int64_t ld = a.ldx;
-  if (tid < ib) {
+  int rs, re;
+  tall_rows(a.h, G, g, &rs, &re);
+  double* out = a.part;
+  double part[IB];
+#pragma unroll
+  for (int t = 0; t < IB; ++t) part[t] = 0.0;
+  for (int r = max(rs, 1) + tid; r < re; r += 256) {
+    const double v = a.X[r];
+#pragma unroll
+    for (int t = 0; t < IB; ++t) part[t] += (t == 0) ? v * v : v * a.X[r + (int64_t)t * ld];
+  }
+  tall_store_partials<IB>(part, red, out, g);
+  if (rs == 0 && re > 0 && tid < IB) out[(int64_t)G * (2 * IB) + tid] = a.X[(int64_t)tid * ld];
+}
+
+template <int IB>
+__global__ __launch_bounds__(256) void k_tall_step(TallArgs a) {
+  __shared__ double acc[256 / IB][2 * IB];
+  __shared__ double sv[2 * IB];   // [0, IB): dots of column jj (its tail sum of squares at jj); [IB, 2 IB): pivot row
+  __shared__ double wv[IB];
+  __shared__ double red[4][IB];
+  const int tid = threadIdx.x, G = gridDim.x, g = blockIdx.x;
+  const int jj = a.jj;
+  const int64_t ld = a.ldx;
+  const int64_t bufsz = (int64_t)(G + 1) * (2 * IB);
+  const double* in = a.part + (jj & 1) * bufsz;
+  double* out = a.part + ((jj + 1) & 1) * bufsz;
+  // 1. sum the partials of column jj (fixed order: slice of groups per thread, then slices)
+  {
+    constexpr int NS = 256 / IB;
+    const int e = tid % IB, sl = tid / IB;
+    const int per = (G + NS - 1) / NS;
     double s = 0.0;
-    for (int q = 0; q < G; ++q) s += a.part[(int64_t)q * (2 * ib) + tid];
-    sv[tid] = s;
-    sv[32 + tid] = a.part[(int64_t)G * (2 * ib) + tid];
+    for (int q = sl * per; q < min(G, (sl + 1) * per); ++q) s += in[(int64_t)q * (2 * IB) + e];
+    acc[sl][e] = s;
+    __syncthreads();
+    if (tid < IB) {
+      double t = 0.0;
+      for (int q = 0; q < NS; ++q) t += acc[q][tid];
+      sv[tid] = t;
+      sv[IB + tid] = in[(int64_t)G * (2 * IB) + tid];
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  const double alpha = sv[32 + jj];
   double beta, tau, scal;
-  larfg_scalars(alpha, sv[jj], &beta, &tau, &scal);
-  if (tid < ib) wv[tid] = sv[32 + tid] + scal * sv[tid];   // t > jj: w_t; t < jj: Gram g_t
+  larfg_scalars(sv[IB + jj], sv[jj], &beta, &tau, &scal);
+  if (tid < IB) wv[tid] = sv[IB + tid] + scal * sv[tid];   // t > jj: w_t; t < jj: Gram entry g_t
   __syncthreads();
-  const int r0 = jj + 1;
-  const int len = a.h - r0;
-  const int chunk = (len + G - 1) / G;
-  const int rs = r0 + g * chunk, re = min(a.h, rs + chunk);
-  double* xc = a.X + (int64_t)jj * ld;
-  for (int r = rs + tid; r < re; r += 256) {
-    const double v = xc[r] * scal;
-    xc[r] = v;
-    if (tau != 0.0)
-      for (int t = jj + 1; t < ib; ++t) a.X[r + (int64_t)t * ld] -= tau * wv[t] * v;
+  int rs, re;
+  tall_rows(a.h, G, g, &rs, &re);
+  const int nx = jj + 1;   // next column
+  const bool more = nx < IB;
+  double part[IB];
+#pragma unroll
+  for (int t = 0; t < IB; ++t) part[t] = 0.0;
+  // 2. reflector column jj and rank-one update of the later columns on this group's rows
+  for (int r = max(rs, jj + 1) + tid; r < re; r += 256) {
+    // (register arrays are indexed by unrolled constants only: selects, no dynamic indexing)
+    double x[IB];
+#pragma unroll
+    for (int t = 0; t < IB; ++t) x[t] = (t >= jj || more) ? a.X[r + (int64_t)t * ld] : 0.0;
+    double xj = 0.0;
+#pragma unroll
+    for (int t = 0; t < IB; ++t) xj = (t == jj) ? x[t] : xj;
+    const double v = xj * scal;
+    a.X[r + (int64_t)jj * ld] = v;
+#pragma unroll
+    for (int t = 0; t < IB; ++t) {
+      if (t == jj) x[t] = v;
+      if (t > jj) {
+        x[t] -= tau * wv[t] * v;
+        a.X[r + (int64_t)t * ld] = x[t];
+      }
+    }
+    if (more) {
+      if (r > nx) {
+        double xn = 0.0;
+#pragma unroll
+        for (int t = 0; t < IB; ++t) xn = (t == nx) ? x[t] : xn;
+#pragma unroll
+        for (int t = 0; t < IB; ++t) part[t] += (t == nx) ? xn * xn : xn * x[t];
+      } else {   // r == nx: the next pivot row
+#pragma unroll
+        for (int t = 0; t < IB; ++t) out[(int64_t)G * (2 * IB) + t] = x[t];
+      }
+    }
   }
-  if (g == 0) {
+  // 3. the group holding row jj: pivot row, tau, column jj of T
+  if (rs <= jj && jj < re) {
     if (tid == 0) {
       a.X[jj + (int64_t)jj * ld] = beta;
       a.tau[jj] = tau;
       a.T[jj + (int64_t)jj * a.ldt] = tau;
     }
-    if (tid > jj && tid < ib && tau != 0.0) a.X[jj + (int64_t)tid * ld] = sv[32 + tid] - tau * wv[tid];
+    if (tid > jj && tid < IB) a.X[jj + (int64_t)tid * ld] = sv[IB + tid] - tau * wv[tid];
     // T[u][jj] = -tau * sum_{v=u}^{jj-1} T[u][v] g_v
     if (tid < jj) {
       double s = 0.0;
@@ -413,6 +474,8 @@ __global__ __launch_bounds__(256) void k_tall_update(TallArgs a) {
       a.T[tid + (int64_t)jj * a.ldt] = -tau * s;
     }
   }
+  // 4. partials of the next column
+  if (more) tall_store_partials<IB>(part, red, out, g);
 }
 
 // Split-K trailing update of a tall panel (V unit lower, h rows, IB columns)
@@ -561,7 +624,9 @@ __global__ void k_copy_blocks(const CopyDesc* __restrict__ d) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = e % D.rows, c = e / D.rows;
     double v = D.src[r + c * D.lds];
-    if (D.unit_lower) v = r > c ? v : (r == c ? 1.0 : 0.0);
+    for (int q = 1; q < D.nsum; ++q) v += D.src[r + c * D.lds + q * D.sstride];
+    if (D.unit_lower == 1) v = r > c ? v : (r == c ? 1.0 : 0.0);
+    else if (D.unit_lower == 2) v = r <= c ? v : 0.0;
     D.dst[r + c * D.ldd] = v;
   }
 }
@@ -569,8 +634,16 @@ __global__ void k_copy_blocks(const CopyDesc* __restrict__ d) {
 }  // namespace
 
 hipError_t launch_tall_column(const TallArgs& a, int groups, hipStream_t stream) {
-  hipLaunchKernelGGL(k_tall_dots, dim3(groups), dim3(256), 0, stream, a);
-  hipLaunchKernelGGL(k_tall_update, dim3(groups), dim3(256), 0, stream, a);
+  if (groups < 1 || groups > kTallMaxGroups) return hipErrorInvalidValue;
+  if (a.ib == 32) {
+    if (a.jj == 0) hipLaunchKernelGGL(k_tall_first<32>, dim3(groups), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_tall_step<32>, dim3(groups), dim3(256), 0, stream, a);
+  } else if (a.ib == 16) {
+    if (a.jj == 0) hipLaunchKernelGGL(k_tall_first<16>, dim3(groups), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_tall_step<16>, dim3(groups), dim3(256), 0, stream, a);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -1,5 +1,5 @@
 // Host runtime of libblrqr: the C ABI, device memory, and the launch plans
-// of compression, the tiled BLR-QR (Alg. 4 with Section 3.3 of arXiv
+// of compression, the tiled BLR-QR (Alg. 4 with Section 3.4 of arXiv
 // 2208.06194), the application of Q / Q^T (Alg. 5) and the least-squares
 // solve.
 //
@@ -367,8 +367,8 @@ Work make_work(blr_matrix h, int nrhs_cols) {
   return w;
 }
 
-// Householder QR of one tile (GEQRT, Section 3.3.1) or of [R; B] (TPQRT,
-// Section 3.3.3), with inner blocking ib: a panel kernel generates ib
+// Householder QR of one tile (GEQRT, Section 3.4.1) or of [R; B] (TPQRT,
+// Section 3.4.3), with inner blocking ib: a panel kernel generates ib
 // reflectors and their T block, three products update the rest of the tile,
 // and at the end the off-diagonal blocks of the full T come from the Gram
 // matrix of all reflectors.
@@ -428,7 +428,7 @@ void plan_tile_qr(Plan& P, blr_matrix h, Work& w, bool tp, double* X, int64_t ld
 
 enum Case { C_DDD, C_LDL, C_DLD, C_DLL, C_LLD, C_LLL };
 
-// Tiled BLR-QR plan (Alg. 4, Section 3.3).
+// Tiled BLR-QR plan (Alg. 4, Section 3.4).
 // Look-ahead: block column k runs on stream k % kStreams.  Before touching
 // tile row i it waits for event E(i, k-1), recorded after column k-1 applied
 // its reflector (i, k-1) to that tile row; so the TPQRT chains of
@@ -715,7 +715,7 @@ void plan_apply_tiled(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, in
 
 
 // ---------------------------------------------------------------------------
-// Block-column BLR-QR (Alg. 2 with Section 3.2).  Step k: gather the stack
+// Block-column BLR-QR (Alg. 2 with Section 3.3).  Step k: gather the stack
 // [A_kk; Av_{k+1,k}; ...] (Av = A for dense tiles, V^T for low-rank tiles)
 // into one column-major buffer, take its Householder QR (the tile panel
 // kernels while it has at most 512/1024 rows, the tall-panel kernels
@@ -724,6 +724,8 @@ void plan_apply_tiled(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, in
 // W_j = T_k^T Z_j and apply A_ij -= Ytilde_ik W_j with the OP1/OP2 rules:
 // Z_j is dense if any term is dense, else the low-rank terms are summed by
 // rounded additions in order i = k, k+1, ...
+
+constexpr int kGramSlices = 16;
 
 struct BcSlot {
   double *Ua, *Ub;   // b x rc
@@ -735,7 +737,8 @@ struct BcSlot {
 struct BcWork {
   double* stack = nullptr;      // m x b
   double* Yf = nullptr;         // b x b explicit unit-lower Y_kk
-  double* tallpart = nullptr;   // (64 + 1) x 64
+  double* tallpart = nullptr;   // 2 x (kTallMaxGroups + 1) x 64
+  double* gpart = nullptr;      // kGramSlices x b x b split-K Gram partials
   double* applypart = nullptr;  // 64 x ceil(b/32) x 32 x 32
   std::vector<BcSlot> slots;
 };
@@ -782,7 +785,8 @@ BcWork make_bc_work(blr_matrix h, int npairs) {
   Arena& A = h->work;
   bw.stack = (double*)A.alloc((size_t)h->m * b * 8);
   bw.Yf = (double*)A.alloc((size_t)b * b * 8);
-  bw.tallpart = (double*)A.alloc((size_t)65 * 64 * 8);
+  bw.tallpart = (double*)A.alloc((size_t)2 * (kTallMaxGroups + 1) * 64 * 8);
+  bw.gpart = (double*)A.alloc((size_t)kGramSlices * b * b * 8);
   bw.applypart = (double*)A.alloc((size_t)64 * ((b + 31) / 32) * 32 * 32 * 8);
   const size_t rcwd = rc_work_doubles(b, rc);
   const size_t per = 2 * (size_t)b * rc + (size_t)rc * b + (size_t)rc * rc + rcwd;
@@ -832,7 +836,7 @@ void plan_stack_qr(Plan& P, blr_matrix h, Work& w, BcWork& bw, int hs, double* T
         P.ops.back().flops = 4.0 * hl * ib * nt;
       }
     } else {
-      const int G = std::min(64, std::max(1, (hl + 4095) / 4096));
+      const int G = std::min(kTallMaxGroups, std::max(1, (hl + 511) / 512));
       for (int jj = 0; jj < ib; ++jj) {
         Op o;
         o.kind = Op::TALL_COL;
@@ -854,9 +858,23 @@ void plan_stack_qr(Plan& P, blr_matrix h, Work& w, BcWork& bw, int hs, double* T
     }
   }
   if (b > ib) {
-    P.gemm(w.Wg, b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, X, hs, X, hs, hs,
-           SEG_TRANS_A | SEG_A_UNIT_LOWER | SEG_B_UNIT_LOWER, DESC_LOWER_ONLY);
+    // Gram matrix Y^T Y of the stack's reflectors (lower triangle), split
+    // over row slices so that a tall stack fills the chip; the first slice
+    // holds the unit-lower diagonal block
+    const int S = std::min(kGramSlices, std::max(1, hs / 4096));
+    const int ks = std::max(b, (hs + S - 1) / S);
+    int ns = 0;
+    for (int r0 = 0; r0 < hs; r0 += ks, ++ns) {
+      const int kk = std::min(ks, hs - r0);
+      const int fl = r0 == 0 ? (SEG_TRANS_A | SEG_A_UNIT_LOWER | SEG_B_UNIT_LOWER) : SEG_TRANS_A;
+      P.gemm(S == 1 ? w.Wg : bw.gpart + (size_t)ns * b * b, b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, X + r0, hs,
+             X + r0, hs, kk, fl, DESC_LOWER_ONLY);
+    }
     P.flush_gemm();
+    if (S > 1) {
+      CopyDesc c{bw.gpart, w.Wg, (int64_t)b, (int64_t)b, b, b, 0, ns, (int64_t)b * b};
+      P.copy({c});
+    }
     TBackArgs t{};
     t.n = b;
     t.ib = ib;
@@ -1763,6 +1781,97 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
       }
     }
     HIPCHECK(hipStreamSynchronize(s));
+  });
+}
+
+blr_status blr_matmul(blr_matrix h, int32_t op, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                      int32_t nrhs, void* stream) {
+  if (!h || !X || !Y) return fail(BLR_ERR_INVALID, "NULL argument");
+  if (op != BLR_MATMUL_A && op != BLR_MATMUL_AT && op != BLR_MATMUL_R) return fail(BLR_ERR_INVALID, "bad op");
+  if (op == BLR_MATMUL_R) {
+    if (h->state != BLR_STATE_FACTORED) return fail(BLR_ERR_STATE, "matrix is not factored");
+    if (h->steps_done != h->q) return fail(BLR_ERR_STATE, "factorization is incomplete");
+  } else if (h->state != BLR_STATE_COMPRESSED) {
+    return fail(BLR_ERR_STATE, "the factorization has overwritten A");
+  }
+  const int64_t xr = op == BLR_MATMUL_AT ? h->m : h->n;
+  const int64_t yr = op == BLR_MATMUL_A ? h->m : h->n;
+  if (nrhs < 0 || ldx < xr || ldy < yr) return fail(BLR_ERR_INVALID, "bad X or Y shape");
+  if (nrhs == 0) return BLR_OK;
+  {
+    const char* xb = (const char*)X;
+    const char* yb = (const char*)Y;
+    const char* xe = xb + ((nrhs - 1) * ldx + xr) * 8;
+    const char* ye = yb + ((nrhs - 1) * ldy + yr) * 8;
+    if (xb < ye && yb < xe) return fail(BLR_ERR_INVALID, "X and Y overlap");
+  }
+  hipStream_t s = as_stream(stream);
+  return run_guarded([&] {
+    const int b = h->b, rc = h->rc, p = h->p, q = h->q;
+    HIPCHECK(hipDeviceSynchronize());
+    h->work.release();
+    // low-rank pre-products S_ij = V_ij^T X_j (A), U_ij^T X_i (A^T) or V_kj^T X_j (R)
+    const int rows = op == BLR_MATMUL_R ? q : p;
+    std::vector<int> slot((size_t)p * q, -1);
+    int nlr = 0;
+    for (int i = 0; i < rows; ++i)
+      for (int j = (op == BLR_MATMUL_R ? i + 1 : 0); j < q; ++j)
+        if (h->t(i, j).fmt == LOWRANK) slot[(size_t)i * q + j] = nlr++;
+    double* S = (double*)h->work.alloc((size_t)std::max(nlr, 1) * rc * nrhs * 8);
+    double* Dg = nullptr;
+    Plan P;
+    if (op == BLR_MATMUL_R) {
+      Dg = (double*)h->work.alloc((size_t)q * b * b * 8);
+      std::vector<CopyDesc> cp;
+      for (int k = 0; k < q; ++k)
+        cp.push_back(CopyDesc{h->t(k, k).D, Dg + (size_t)k * b * b, (int64_t)b, (int64_t)b, b, b, 2, 0});
+      P.copy(cp);
+    }
+    auto Sp = [&](int i, int j) { return S + (size_t)slot[(size_t)i * q + j] * rc * nrhs; };
+    for (int i = 0; i < rows; ++i)
+      for (int j = 0; j < q; ++j) {
+        if (slot[(size_t)i * q + j] < 0) continue;
+        Tile& t = h->t(i, j);
+        if (op == BLR_MATMUL_AT)
+          P.gemm(Sp(i, j), rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, t.U, b, X + (int64_t)i * b, ldx, b,
+                 SEG_TRANS_A);
+        else
+          P.gemm(Sp(i, j), rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, t.Vt, rc, X + (int64_t)j * b, ldx, b, 0);
+      }
+    P.flush_gemm();
+    const int outs = op == BLR_MATMUL_A ? p : q;
+    for (int o = 0; o < outs; ++o) {
+      std::vector<GemmSeg> sv;
+      if (op == BLR_MATMUL_AT) {
+        for (int i = 0; i < p; ++i) {
+          Tile& t = h->t(i, o);
+          GemmSeg g{};
+          if (t.fmt == DENSE) {
+            g.A = t.D; g.lda = b; g.B = X + (int64_t)i * b; g.ldb = ldx; g.K = b; g.flags = SEG_TRANS_A;
+          } else {
+            g.A = t.Vt; g.lda = rc; g.B = Sp(i, o); g.ldb = rc; g.K = rc; g.flags = SEG_TRANS_A;
+          }
+          sv.push_back(g);
+        }
+      } else {
+        for (int j = (op == BLR_MATMUL_R ? o : 0); j < q; ++j) {
+          Tile& t = h->t(o, j);
+          GemmSeg g{};
+          if (op == BLR_MATMUL_R && j == o) {
+            g.A = Dg + (size_t)o * b * b; g.lda = b; g.B = X + (int64_t)j * b; g.ldb = ldx; g.K = b; g.flags = 0;
+          } else if (t.fmt == DENSE) {
+            g.A = t.D; g.lda = b; g.B = X + (int64_t)j * b; g.ldb = ldx; g.K = b; g.flags = 0;
+          } else {
+            g.A = t.U; g.lda = b; g.B = Sp(o, j); g.ldb = rc; g.K = rc; g.flags = 0;
+          }
+          sv.push_back(g);
+        }
+      }
+      P.gemm_multi(Y + (int64_t)o * b, ldy, nullptr, 0, b, nrhs, 1.0, 0.0, sv);
+    }
+    P.flush_gemm();
+    P.upload(h->work);
+    execute(h, P, s);
   });
 }
 

@@ -1,4 +1,4 @@
-"""GPU parity of the block-column BLR-QR (Alg. 2 with Section 3.2) and its Q
+"""GPU parity of the block-column BLR-QR (Alg. 2 with Section 3.3) and its Q
 application (Alg. 3): the HIP path through the C ABI against the oracle's
 block-column factor on the same seeded inputs.  Stacks of up to 512 rows
 take the one-workgroup panel kernel with 32-column panels, up to 1024 rows

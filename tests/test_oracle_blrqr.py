@@ -1,5 +1,5 @@
-"""Pins of the oracle's BLR-QR (tiled Alg. 4 / Section 3.3 and block-column
-Alg. 2 / Section 3.2) against dense LAPACK QR, invariants, the paper's Table
+"""Pins of the oracle's BLR-QR (tiled Alg. 4 / Section 3.4 and block-column
+Alg. 2 / Section 3.3) against dense LAPACK QR, invariants, the paper's Table
 res-acc-random, least-squares optimality and the task/cost model."""
 import json
 import os
@@ -84,7 +84,7 @@ def test_invariants_kernel_matrix(mod):
 
 
 def test_lowrank_tpqrt_eliminates_exactly():
-    """Section 3.3.3: with U orthonormal, the T of [R; V^T] makes
+    """Section 3.4.3: with U orthonormal, the T of [R; V^T] makes
     I - [I; U Y] T [I; U Y]^T an orthogonal factor that zeroes U V^T."""
     from oracle import dense
     rng = np.random.default_rng(11)
