@@ -3,8 +3,11 @@
 
 A step = compress the synthetic kernel matrix (untimed; the factorization is
 in place, so every step starts from a freshly compressed matrix resident in
-HBM) and then factor it (timed with HIP events on the stream).  Prints one
-JSON line.  Workloads (synthetic points from the seeded splitmix64 generator,
+HBM) and then factor it (timed with HIP events on the stream).  By default
+the FP64 factor is the reported value and the mixed form (FP32 MFMA updates,
+FP64 reflector generation and recompression, compressed at 1e-6) is measured
+beside it; each states its Gaussian-probe estimate of ||A~ - QR|| / ||A~||.
+Prints one JSON line.  Workloads (synthetic points from the seeded splitmix64 generator,
 Morton sorted, kernel evaluated on the device):
   c1  2048 x 1024,     2D -log(r+1e-3),  b = 128,  adjacent boxes dense, eps 1e-8, cap 16
   c2  32768 x 16384,   3D 1/(r+1e-3),    b = 256,  gap > diameter low-rank, eps 1e-8, cap 32
@@ -30,18 +33,43 @@ CONFIGS = {
 }
 PEAK = {"fp64": 78.6e12, "mixed": 157.3e12}   # MI355X dense matrix-core peaks (FP64, FP32)
 
+# HBM traffic per launch of the dominant kernel, from two rocprofv3 --pmc passes
+# (FETCH_SIZE, WRITE_SIZE) over the factor's launches, scaled by what the same
+# counters read for a plain 1 GiB device copy (FETCH x 2.0, WRITE x 1.0); the
+# commands and raw figures are in profiles/.  Valid only for the kernel source
+# the counters were taken on (sha256 of csrc/gemm.hip); otherwise null.
+TRAFFIC = {
+    ("c3", "fp64", "block_column"): {
+        "gemm_sha256": "399ef48a14ecb46fb614f6668a757847afdbb79ad37f068c785162e1642f2ee9",
+        "bytes_per_launch": 196428776417,
+    },
+}
+
+
+def measured_traffic(config, precision, variant):
+    import hashlib
+    t = TRAFFIC.get((config, precision, variant))
+    if not t:
+        return None
+    src = os.path.join(ROOT, "paper_2208_06194_amd", "csrc", "gemm.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["gemm_sha256"]:
+            return None
+    return t["bytes_per_launch"]
+
 
 def dense_equiv_flops(m, n):
     return 2.0 * m * n * n - 2.0 / 3.0 * n ** 3
 
 
-def cpu_baseline(cfg, seed):
+def cpu_baseline(cfg, seed, variant):
     """The oracle (numpy FP64, untuned) timed on a bounded sample of the same
     workload: the leading (4b x 2b) block of the same kernel matrix with the
-    same tile size, rule and tolerance.  Scaled to the full matrix by
-    dense-equivalent flops (2mn^2 - 2n^3/3)."""
+    same tile size, rule and tolerance, factored by the same variant.  Scaled
+    to the full matrix by dense-equivalent flops (2mn^2 - 2n^3/3)."""
     import synth
-    from oracle import blrmat, tiled
+    from oracle import blockcol, blrmat, tiled
+    fac = tiled.factor if variant == "tiled" else blockcol.factor
     b = cfg["b"]
     x, y = synth.kernel_points(seed, cfg["m"], cfg["n"], cfg["dim"])
     ms, ns = min(4 * b, cfg["m"]), min(2 * b, cfg["n"])
@@ -52,10 +80,10 @@ def cpu_baseline(cfg, seed):
         mask = blrmat.lowrank_mask(xs, ys, b, cfg["rule"], ms // b, ns // b)
         blr = blrmat.compress(A, b, cfg["tol"], cfg["cap"], mask)
         t0 = time.perf_counter()
-        tiled.factor(blr, cfg["tol"], cfg["cap"], copy=False)
+        fac(blr, cfg["tol"], cfg["cap"], copy=False)
         el = time.perf_counter() - t0
         spent += el
-        # grow the sample until it holds about 8 s of work (or is the whole matrix)
+        # grow the sample until it holds a few seconds of work (or is the whole matrix)
         if el >= 4.0 or spent >= 15.0 or (ms == cfg["m"] and ns == cfg["n"]):
             break
         ms, ns = min(2 * ms, cfg["m"]), min(2 * ns, cfg["n"])
@@ -68,10 +96,91 @@ def cpu_baseline(cfg, seed):
     return {
         "value": dense_equiv_flops(cfg["m"], cfg["n"]) / rate, "unit": "s",
         "cores": cores, "kind": "oracle",
-        "sample": f"oracle tiled factor of the leading {ms}x{ns} block (b={b}) of the same matrix took "
+        "sample": f"oracle {variant} factor of the leading {ms}x{ns} block (b={b}) of the same matrix took "
                   f"{el:.2f} s ({rate / 1e9:.2f} GFLOP/s dense-equivalent); value extrapolated to "
                   f"{cfg['m']}x{cfg['n']} by dense-equivalent flops",
     }
+
+
+def accuracy_probes(G, probes, ax):
+    """Gaussian-probe estimates, from the factor of A~ and the products A~ G
+    taken before the factorization:  Res = ||(A~ - Q R) G||_F / ||A~ G||_F and
+    Orth = ||(Q1^T Q1 - I) G||_F / (sqrt(s) sqrt(n)), s probes."""
+    import torch
+    inf = G.info()
+    m, n = inf["m"], inf["n"]
+    s = probes.shape[1]
+    rg = G.matmul(probes, "R")
+    pad = torch.zeros((m, s), dtype=torch.float64, device=probes.device)
+    pad[:n] = rg
+    qr = G.apply_qt(pad, trans=True)
+    res = float(torch.linalg.norm(qr - ax) / torch.linalg.norm(ax))
+    pad.zero_()
+    pad[:n] = probes
+    back = G.apply_qt(G.apply_qt(pad, trans=True))
+    back[:n] -= probes
+    orth = float(torch.linalg.norm(back) / np.sqrt(s) / np.sqrt(n))
+    return res, orth
+
+
+def run(args, cfg, precision, tol, xd, yd, dev):
+    """Compress (untimed) and factor (timed) warmup + steps times; returns the
+    measurements of the timed steps."""
+    import torch
+    import synth
+    import paper_2208_06194_amd as P
+    times, comp_times = [], []
+    prof, info, acc = None, None, None
+    stream = torch.cuda.current_stream()
+    probes = torch.tensor(synth.rhs(args.seed + 17, cfg["n"], args.probes), device=dev)
+    for step in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        G = P.BLRMatrix.compress_kernel(xd, yd, cfg["kernel"], cfg["b"], tol, cfg["cap"],
+                                        admissibility=cfg["rule"], overflow="dense", seed=args.seed)
+        torch.cuda.synchronize()
+        comp_times.append(time.perf_counter() - tc)
+        timed = step >= args.warmup
+        last = step == args.warmup + args.steps - 1
+        ax = G.matmul(probes, "A") if (last and args.probes > 0) else None
+        if timed:
+            G.profile(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        G.factor(args.variant, precision, stop_after_k=args.stop_after_k)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        print(f"[bench] {precision} eps={tol:g} step {step} ({'timed' if timed else 'warmup'}): "
+              f"compress {comp_times[-1]:.2f}s factor {ms / 1e3:.3f}s", file=sys.stderr, flush=True)
+        if timed:
+            times.append(ms / 1e3)
+            n, tot_ms, tot_fl = G.profile_read()
+            prof = (prof[0] + n, prof[1] + tot_ms, prof[2] + tot_fl) if prof else (n, tot_ms, tot_fl)
+            info = G.info()
+        if ax is not None and args.stop_after_k < 0:
+            acc = accuracy_probes(G, probes, ax)
+            print(f"[bench] {precision}: Res~ {acc[0]:.2e} Orth {acc[1]:.2e}", file=sys.stderr, flush=True)
+        del G
+    value = float(np.median(times))
+    out = {"value": value, "compress_s": float(np.median(comp_times)), "info": info, "tol": tol,
+           "res_est": acc[0] if acc else None, "orth_est": acc[1] if acc else None}
+    if prof and prof[0] > 0:
+        avg_s = prof[1] / 1e3 / prof[0]
+        per_launch = prof[2] / prof[0]
+        ach = per_launch / avg_s
+        peak = PEAK[precision]
+        ct = "double" if precision == "fp64" else "float"
+        out["roofline"] = {
+            "bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": ach / peak, "traffic": measured_traffic(args.config, precision, args.variant),
+            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "kernel": f"k_gemm_fast<{ct}, false, false> (128x128 MFMA tiles, untransposed: trailing updates)",
+            "launches": prof[0], "avg_launch_ms": avg_s * 1e3, "flops_per_launch": per_launch,
+            "kernel_time_share": prof[1] / 1e3 / (value * args.steps),
+        }
+    return out
 
 
 def main():
@@ -80,8 +189,11 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--config", default=os.environ.get("BLR_BENCH_CONFIG", "c3"), choices=sorted(CONFIGS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--variant", default="tiled", choices=["tiled", "block_column"])
+    ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"],
+                    help="both: the FP64 factor (the reported value) and the mixed form beside it")
+    ap.add_argument("--mixed-tol", type=float, default=1e-6, help="compression tolerance of the mixed form")
+    ap.add_argument("--variant", default="block_column", choices=["tiled", "block_column"])
+    ap.add_argument("--probes", type=int, default=8, help="Gaussian probes for the Res / Orth estimates")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--stop-after-k", type=int, default=-1,
@@ -93,7 +205,6 @@ def main():
 
     import torch
     import synth
-    import paper_2208_06194_amd as P
 
     cfg = CONFIGS[args.config]
     dev = torch.device("cuda:0")
@@ -102,38 +213,10 @@ def main():
     xd, yd = torch.tensor(x, device=dev), torch.tensor(y, device=dev)
     print(f"[bench] {args.config}: points ready in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
 
-    times, comp_times = [], []
-    prof = None
-    info = None
-    stream = torch.cuda.current_stream()
-    for step in range(args.warmup + args.steps):
-        torch.cuda.synchronize()
-        tc = time.perf_counter()
-        G = P.BLRMatrix.compress_kernel(xd, yd, cfg["kernel"], cfg["b"], cfg["tol"], cfg["cap"],
-                                        admissibility=cfg["rule"], overflow="dense", seed=args.seed)
-        torch.cuda.synchronize()
-        comp_times.append(time.perf_counter() - tc)
-        timed = step >= args.warmup
-        if timed:
-            G.profile(True)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        G.factor(args.variant, args.precision, stop_after_k=args.stop_after_k)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        print(f"[bench] step {step} ({'timed' if timed else 'warmup'}): compress {comp_times[-1]:.2f}s "
-              f"factor {ms / 1e3:.3f}s", file=sys.stderr, flush=True)
-        if timed:
-            times.append(ms / 1e3)
-            n, tot_ms, tot_fl = G.profile_read()
-            prof = (prof[0] + n, prof[1] + tot_ms, prof[2] + tot_fl) if prof else (n, tot_ms, tot_fl)
-            info = G.info()
-        del G
-
-    value = float(np.median(times))
-    flops = info["flops_factor"]
+    main_prec = "mixed" if args.precision == "mixed" else "fp64"
+    r = run(args, cfg, main_prec, cfg["tol"] if main_prec == "fp64" else args.mixed_tol, xd, yd, dev)
+    info = r["info"]
+    value = r["value"]
     out = {
         "metric": "BLR-QR factor time (s) at 131k x 65k; FP64 vs mixed at stated ||A-QR||/||A||",
         "value": value,
@@ -145,38 +228,41 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32-mfma+f64",
+        "dtype": "f64" if main_prec == "fp64" else "f32-mfma+f64",
         "data": "synthetic",
         "config": {
             "workload": f"{cfg['m']}x{cfg['n']} {cfg['dim']}D {cfg['kernel']} kernel matrix, b={cfg['b']}, "
-                        f"{cfg['rule']}, eps={cfg['tol']:g}, cap={cfg['cap']}, {args.variant} {args.precision}",
-            "m": cfg["m"], "n": cfg["n"], "tile": cfg["b"], "tol": cfg["tol"], "max_rank": cfg["cap"],
-            "variant": args.variant, "precision": args.precision, "config_id": args.config,
+                        f"{cfg['rule']}, eps={r['tol']:g}, cap={cfg['cap']}, {args.variant} {main_prec}",
+            "m": cfg["m"], "n": cfg["n"], "tile": cfg["b"], "tol": r["tol"], "max_rank": cfg["cap"],
+            "variant": args.variant, "precision": main_prec, "config_id": args.config,
             **({"stop_after_k": args.stop_after_k} if args.stop_after_k >= 0 else {}),
         },
-        "ledger_flops": flops,
-        "gflops": flops / value / 1e9,
+        "res_est": r["res_est"],
+        "orth_est": r["orth_est"],
+        "accuracy_note": f"Gaussian-probe estimates ({args.probes} probes) of ||A~-QR||_F/||A~||_F and "
+                         "||Q1^T Q1 - I||_F/sqrt(n); A~ is the compressed matrix (||A~-A|| <= eps ||A|| per tile)",
+        "ledger_flops": info["flops_factor"],
+        "gflops": info["flops_factor"] / value / 1e9,
         "dense_equiv_tflops": dense_equiv_flops(cfg["m"], cfg["n"]) / value / 1e12,
-        "compress_s": float(np.median(comp_times)),
+        "compress_s": r["compress_s"],
         "tiles": {"dense": info["n_dense"], "lowrank": info["n_lowrank"], "fill_in": info["n_fill_in"],
                   "compress_overflow": info["compress_overflow"], "factor_overflow": info["factor_overflow"]},
         "kernel_launches": info["kernel_launches"],
     }
-    if prof and prof[0] > 0:
-        avg_s = prof[1] / 1e3 / prof[0]
-        per_launch = prof[2] / prof[0]
-        ach = per_launch / avg_s
-        peak = PEAK[args.precision]
-        out["roofline"] = {
-            "bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": ach / peak, "traffic": None,
-            "kernel": "k_gemm<%s,128,128> (reflector-apply products)" % ("double" if args.precision == "fp64" else "float"),
-            "launches": prof[0], "avg_launch_ms": avg_s * 1e3, "flops_per_launch": per_launch,
-            "kernel_time_share": prof[1] / 1e3 / (value * args.steps),
+    if "roofline" in r:
+        out["roofline"] = r["roofline"]
+    if args.precision == "both" and args.stop_after_k < 0:
+        mx = run(args, cfg, "mixed", args.mixed_tol, xd, yd, dev)
+        out["mixed"] = {
+            "value": mx["value"], "unit": "s", "tol": mx["tol"], "res_est": mx["res_est"],
+            "orth_est": mx["orth_est"], "speedup_vs_fp64": value / mx["value"],
+            "tiles": {"dense": mx["info"]["n_dense"], "lowrank": mx["info"]["n_lowrank"],
+                      "fill_in": mx["info"]["n_fill_in"], "factor_overflow": mx["info"]["factor_overflow"]},
+            **({"roofline": mx["roofline"]} if "roofline" in mx else {}),
         }
     if not args.no_cpu_baseline:
         tb = time.perf_counter()
-        out["cpu_baseline"] = cpu_baseline(cfg, args.seed)
+        out["cpu_baseline"] = cpu_baseline(cfg, args.seed, args.variant)
         print(f"[bench] cpu baseline sample done in {time.perf_counter() - tb:.1f}s", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 

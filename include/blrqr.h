@@ -201,8 +201,10 @@ const char* blr_status_string(blr_status s);
 const char* blr_last_error(void);
 
 /* Kernel-level timing of the next blr_qr_factor on this handle: when enabled,
- * HIP events bracket every launch of the dense reflector-apply product (the
- * dominant kernel) on the stream it is launched on.  After the factor,
+ * HIP events bracket every launch of the dominant kernel, the untransposed
+ * 128 x 128 matrix-core product of the trailing updates (k_gemm_fast with
+ * FP64 operands, or FP32 operands under BLR_MIXED_FP32), on the stream it is
+ * launched on.  After the factor,
  * blr_profile_read returns the number of such launches, their total device
  * time in milliseconds and their total algorithmic flops.  Synchronises. */
 blr_status blr_profile_enable(blr_matrix h, int32_t on);

@@ -54,6 +54,8 @@ enum GemmMode {
 
 // Launch host wrapper: descs / segs are device arrays; ntiles = total WG tiles
 // (tiles of 64 for GEMM_SMALL, 128 otherwise).  fp32 = 1 computes in FP32 on
-// the matrix cores (operands rounded to FP32, FP32 accumulation).
+// the matrix cores (operands rounded to FP32, FP32 accumulation); fp32 = 2
+// (fast modes) also rounds operands to FP32 but adds the FP32 partial sums
+// into FP64 accumulators every 1024 of K and at every segment end.
 hipError_t launch_gemm(const GemmDesc* d_descs, int ndesc, const GemmSeg* d_segs, int ntiles,
                        int mode, int fp32, hipStream_t stream);

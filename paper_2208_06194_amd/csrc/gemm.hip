@@ -199,9 +199,9 @@ typedef __attribute__((address_space(1))) const d2v gd2v;
 // only prunes the K range).  Transposes are compile-time; global loads are
 // 16-byte vectors from precomputed per-thread addresses; LDS is double
 // buffered so each K step needs a single barrier.
-template <typename CT, bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_gemm_fast(const GemmDesc* __restrict__ descs, int ndesc,
-                                                   const GemmSeg* __restrict__ segs) {
+template <typename CT, bool TA, bool TB, bool ACC64>
+__device__ __forceinline__ void gemm_fast_body(const GemmDesc* __restrict__ descs, int ndesc,
+                                               const GemmSeg* __restrict__ segs) {
   constexpr int BM = 128, BN = 128, BK = 16, PAD = 2;
   typedef typename AccT<CT>::T acc_t;
   __shared__ CT As[2][BK][BM + PAD];
@@ -235,6 +235,34 @@ __global__ __launch_bounds__(256) void k_gemm_fast(const GemmDesc* __restrict__ 
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
+  // ACC64 (FP32 operands only): the matrix-core partial sums cover at most
+  // 1024 of K (and at most one segment) before they are added into FP64
+  // accumulators, so the FP32 rounding of long sums (K up to the stack
+  // height) does not grow with K
+  static_assert(!ACC64 || sizeof(CT) == 4, "FP64 accumulation is for FP32 operands");
+  constexpr int kFlushSteps = 1024 / BK;
+  double acc64[4][4][4];
+  auto flush = [&]() {
+    if constexpr (ACC64) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            acc64[i][j][v] += (double)acc[i][j][v];
+            acc[i][j][v] = 0;
+          }
+    }
+  };
+  if constexpr (ACC64) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc64[i][j][v] = 0.0;
+  }
 
   d2v ra[4], rb[4];
   for (int sgi = 0; sgi < d.nseg; ++sgi) {
@@ -294,7 +322,9 @@ __global__ __launch_bounds__(256) void k_gemm_fast(const GemmDesc* __restrict__ 
       }
       if (more) lstore(buf ^ 1);
       __syncthreads();
+      if (ACC64 && (st + 1) % kFlushSteps == 0) flush();
     }
+    if (ACC64 && nsteps % kFlushSteps != 0) flush();
   }
 
   constexpr bool f64out = sizeof(CT) == 8;
@@ -306,7 +336,7 @@ __global__ __launch_bounds__(256) void k_gemm_fast(const GemmDesc* __restrict__ 
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = m0 + wm * 64 + i * 16 + (f64out ? v * 4 + (lane >> 4) : (lane >> 4) * 4 + v);
-        const double raw = (double)acc[i][j][v];
+        const double raw = ACC64 ? acc64[i][j][v] : (double)acc[i][j][v];
         if (d.C) {
           double c = d.alpha * raw;
           if (d.Cin) c += d.beta * d.Cin[row + (int64_t)col * d.ldcin];
@@ -318,14 +348,33 @@ __global__ __launch_bounds__(256) void k_gemm_fast(const GemmDesc* __restrict__ 
   }
 }
 
+template <typename CT, bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm_fast(const GemmDesc* __restrict__ descs, int ndesc,
+                                                   const GemmSeg* __restrict__ segs) {
+  gemm_fast_body<CT, TA, TB, false>(descs, ndesc, segs);
+}
+
+// FP32 operands, FP64 accumulation across K (long sums); two waves per SIMD
+// keep the extra accumulators resident without losing all latency hiding.
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256, 2) void k_gemm_fast_acc64(const GemmDesc* __restrict__ descs, int ndesc,
+                                                            const GemmSeg* __restrict__ segs) {
+  gemm_fast_body<float, TA, TB, true>(descs, ndesc, segs);
+}
+
 }  // namespace
 
 hipError_t launch_gemm(const GemmDesc* d_descs, int ndesc, const GemmSeg* d_segs, int ntiles,
                        int mode, int fp32, hipStream_t stream) {
   if (ndesc <= 0 || ntiles <= 0) return hipSuccess;
   dim3 grid(ntiles), block(256);
-#define BLR_FAST(CT, TA, TB) \
-  hipLaunchKernelGGL((k_gemm_fast<CT, TA, TB>), grid, block, 0, stream, d_descs, ndesc, d_segs)
+#define BLR_FAST(CT, TA, TB)                                                                      \
+  do {                                                                                            \
+    if (sizeof(CT) == 4 && fp32 == 2)                                                             \
+      hipLaunchKernelGGL((k_gemm_fast_acc64<TA, TB>), grid, block, 0, stream, d_descs, ndesc, d_segs); \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_gemm_fast<CT, TA, TB>), grid, block, 0, stream, d_descs, ndesc, d_segs);   \
+  } while (0)
   switch (mode) {
     case GEMM_SMALL:
       if (fp32) hipLaunchKernelGGL((k_gemm<float, 64, 64>), grid, block, 0, stream, d_descs, ndesc, d_segs);

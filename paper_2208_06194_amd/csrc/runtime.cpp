@@ -112,12 +112,12 @@ void Plan::gemm_multi(double* C, int64_t ldc, const double* Cin, int64_t ldcin, 
   cur.push_back(d);
 }
 
-void Plan::flush_gemm(int fp32, int prof) {
+void Plan::flush_gemm(int fp32, int prof, bool allow_fast) {
   if (cur.empty()) return;
   int mn = 1 << 30;
   for (auto& d : cur) mn = std::min(mn, std::min(d.M, d.N));
   int big = mn >= 256 ? GEMM_BIG : GEMM_SMALL;
-  if (big == GEMM_BIG) {
+  if (big == GEMM_BIG && allow_fast) {
     // fast path: full tiles, single uniform segment, aligned, no masks
     bool ok = true;
     int tflags = -1;
@@ -140,6 +140,16 @@ void Plan::flush_gemm(int fp32, int prof) {
     }
   }
   const int BM = big == GEMM_SMALL ? 64 : 128;
+  // FP32 products with long K sums accumulate in FP64 between K chunks
+  if (fp32 && big >= GEMM_FAST_NN) {
+    int64_t kmax = 0;
+    for (auto& d : cur) {
+      int64_t kt = 0;
+      for (int si = 0; si < d.nseg; ++si) kt += curseg[d.seg_begin + si].K;
+      kmax = std::max(kmax, kt);
+    }
+    if (kmax > 1024) fp32 = 2;
+  }
   Op o;
   o.kind = Op::GEMM;
   o.off = (int)descs.size();
@@ -248,8 +258,9 @@ void execute(blr_matrix h, Plan& P, hipStream_t s) {
     hipStream_t q = st[o.stream];
     switch (o.kind) {
       case Op::GEMM: {
-        // the dominant kernel: 128x128 products in the factor's compute precision
-        const bool rec = h->prof_on && o.big >= GEMM_FAST_NN && o.fp32 == (h->precision == BLR_MIXED_FP32 ? 1 : 0);
+        // the dominant kernel: k_gemm_fast<CT, false, false> (untransposed
+        // 128x128 products: the trailing updates) in the factor's precision
+        const bool rec = h->prof_on && o.big == GEMM_FAST_NN && o.fp32 == (h->precision == BLR_MIXED_FP32 ? 1 : 0);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (rec) {
           HIPCHECK(hipEventCreate(&e0));
@@ -1035,7 +1046,7 @@ void plan_blockcol(blr_matrix h, Plan& P, Work& w, BcWork& bw, int kend, bool fp
           h->n_fill++;
         }
       }
-    P.flush_gemm();
+    P.flush_gemm(fp32);
     // 7. updates A_ij -= Ytilde_ik W_j
     for (int j = k + 1; j < q; ++j)
       for (int i = k; i < p; ++i)
@@ -1086,7 +1097,7 @@ void plan_blockcol(blr_matrix h, Plan& P, Work& w, BcWork& bw, int kend, bool fp
           P.rc(d);
         }
       }
-    P.flush_gemm();
+    P.flush_gemm(fp32);
     P.flush_rc();
   }
 }
@@ -1393,14 +1404,14 @@ blr_status blr_compress(const blr_source* src, const blr_compress_opts* o, void*
         HIPCHECK(hipMemcpy(dfd, fd.data(), nb * sizeof(TileFillDesc), hipMemcpyHostToDevice));
         HIPCHECK(hipMemcpy(dfr, fr.data(), 2 * nb * sizeof(Frob2Desc), hipMemcpyHostToDevice));
         HIPCHECK(hipMemcpy(dcd, cd.data(), nb * sizeof(CompDesc), hipMemcpyHostToDevice));
-        P.flush_gemm();
+        P.flush_gemm(0, 0, false);
         for (int a = 0; a < nb; ++a)
           P.gemm(cd[a].B, l, nullptr, 0, nullptr, 0, l, b, 1.0, 0.0, cd[a].Q, b, cd[a].A, b, b, SEG_TRANS_A);
-        P.flush_gemm();
+        P.flush_gemm(0, 0, false);
         for (int a = 0; a < nb; ++a)
           P.gemm(const_cast<double*>(cd[a].A), b, cd[a].A, b, nullptr, 0, b, b, -1.0, 1.0, cd[a].Q, b,
                  cd[a].B, l, l, 0);
-        P.flush_gemm();
+        P.flush_gemm(0, 0, false);
         HIPCHECK(hipMemcpy(dgd, P.descs.data(), P.descs.size() * sizeof(GemmDesc), hipMemcpyHostToDevice));
         HIPCHECK(hipMemcpy(dgs, P.segs.data(), P.segs.size() * sizeof(GemmSeg), hipMemcpyHostToDevice));
         HIPCHECK(launch_fill_tiles(dfd, nb, fp, s));
@@ -1951,7 +1962,7 @@ extern "C" blr_status blr_selftest_gemm(int32_t flags, int32_t M, int32_t N, int
     P.flush_gemm(fp32);
     if (P.ops.empty()) return;
     P.upload(ar);
-    HIPCHECK(launch_gemm(P.d_descs, P.ops[0].n, P.d_segs, P.ops[0].ntiles, P.ops[0].big, fp32,
+    HIPCHECK(launch_gemm(P.d_descs, P.ops[0].n, P.d_segs, P.ops[0].ntiles, P.ops[0].big, P.ops[0].fp32,
                          as_stream(stream)));
     HIPCHECK(hipStreamSynchronize(as_stream(stream)));
   });

@@ -82,7 +82,9 @@ struct Plan {
   // add one descriptor summing several K segments: C = alpha * sum_s op(A_s) op(B_s) + beta * Cin
   void gemm_multi(double* C, int64_t ldc, const double* Cin, int64_t ldcin, int M, int N, double alpha,
                   double beta, const std::vector<GemmSeg>& segs);
-  void flush_gemm(int fp32 = 0, int prof = 0);
+  // allow_fast = false keeps the batch on the generic kernels (used outside
+  // the factorization, so that the fast kernels time only its products)
+  void flush_gemm(int fp32 = 0, int prof = 0, bool allow_fast = true);
   void rc(const RcDesc& d) { currc.push_back(d); }
   void flush_rc();
   void push(Op o) { o.stream = cur_stream; ops.push_back(o); }

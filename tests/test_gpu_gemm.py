@@ -70,3 +70,28 @@ def test_gemm_fp32_compute(lib, shape):
 def test_gemm_invalid_arguments(lib):
     st = lib.blr_selftest_gemm(0, -1, 4, 4, 1.0, None, 1, None, 1, 0.0, None, 1, 0, None)
     assert st == 1
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_gemm_fp32_long_k_accumulates_in_fp64(lib, flags):
+    """FP32 operands with K = 65536 (the stack heights of the block-column
+    products): the FP32 partial sums cover at most 1024 of K before they are
+    added in FP64, so the normwise error stays at the level of a 1024-long FP32
+    sum (about 2^-24 sqrt(256)) instead of growing with sqrt(K)."""
+    print("case: gemm fp32 long K", flags, flush=True)
+    M, N, K = 256, 256, 65536
+    rng = np.random.default_rng(99 + flags)
+    A = rng.standard_normal((K, M) if flags & 1 else (M, K))
+    B = rng.standard_normal((K, N))
+    Aop = A.T if flags & 1 else A
+    ref = Aop @ B
+    dA = torch.tensor(A.T.copy(), device="cuda")
+    dB = torch.tensor(B.T.copy(), device="cuda")
+    dC = torch.zeros((N, M), dtype=torch.float64, device="cuda")
+    st = lib.blr_selftest_gemm(flags, M, N, K, 1.0, dA.data_ptr(), A.shape[0], dB.data_ptr(), K,
+                               0.0, dC.data_ptr(), M, 1, torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    out = dC.cpu().numpy().T
+    rel = np.linalg.norm(out - ref) / np.linalg.norm(ref)
+    print("normwise error / 2^-24:", rel / 2.0 ** -24, flush=True)
+    assert rel <= 24 * 2.0 ** -24

@@ -185,3 +185,28 @@ def test_shapes_single_tile_square_and_single_column(P, m, n, b):
                                    admissibility="mask", mask=np.zeros((m // b, n // b), bool))
     G.factor("tiled")
     assert metrics.r_rel_diff(export_r(G.export()), np.linalg.qr(A, mode="r")) <= 100 * n * U * np.linalg.cond(A)
+
+
+@pytest.mark.parametrize("rule,kern,dim", [("dist_gt_diam", "inv_r", 3), ("weak", "log2d", 2)])
+def test_matmul_matches_host_products(P, rule, kern, dim):
+    """blr_matmul: A~ X and A~^T X before the factorization, R X after it,
+    against host products with the densified tiles."""
+    print("case: matmul", rule, flush=True)
+    m, n, b, eps, cap = 512, 256, 64, 1e-8, 32
+    A, blr = kernel_blr(8, m, n, b, eps, cap, kern, dim, rule)
+    At = blr.to_dense()
+    G = gpu_import(P, blr, eps, cap)
+    X = synth.rhs(8, n, 5)
+    Xm = synth.rhs(9, m, 3)
+    Y = G.matmul(torch.tensor(X, device="cuda"), "A").cpu().numpy()
+    assert np.linalg.norm(Y - At @ X) <= 1e-13 * np.linalg.norm(At) * np.linalg.norm(X)
+    Yt = G.matmul(torch.tensor(Xm, device="cuda"), "AT").cpu().numpy()
+    assert np.linalg.norm(Yt - At.T @ Xm) <= 1e-13 * np.linalg.norm(At) * np.linalg.norm(Xm)
+    with pytest.raises(P.BLRError):
+        G.matmul(torch.tensor(X, device="cuda"), "R")      # not factored yet
+    G.factor("block_column")
+    Rg = export_r(G.export())
+    YR = G.matmul(torch.tensor(X, device="cuda"), "R").cpu().numpy()
+    assert np.linalg.norm(YR - Rg @ X) <= 1e-13 * np.linalg.norm(Rg) * np.linalg.norm(X)
+    with pytest.raises(P.BLRError):
+        G.matmul(torch.tensor(X, device="cuda"), "A")      # A~ was overwritten
