@@ -44,9 +44,12 @@ struct GemmDesc {
 };
 
 // Kernel variants: generic 64x64 and 128x128 tiles (any shape, masks, several
-// K segments) and the fast 128x128 path (full tiles, one K segment, K % 16 == 0,
-// 16-byte aligned operands and even leading dimensions, no masked triangles),
-// specialised on the two transposes.
+// K segments) and the fast 128x128 path (full tiles, every K segment a multiple
+// of the K step, one transpose pattern per launch, 16-byte aligned operands and
+// even leading dimensions, no unit-lower masks), specialised on the two
+// transposes.  K step of the fast path: 16.
+constexpr int kFastKStep64 = 16;
+constexpr int kFastKStep32 = 16;
 enum GemmMode {
   GEMM_SMALL = 0, GEMM_BIG = 1,
   GEMM_FAST_NN = 2, GEMM_FAST_TN = 3, GEMM_FAST_NT = 4, GEMM_FAST_TT = 5,

@@ -199,10 +199,12 @@ typedef __attribute__((address_space(1))) const d2v gd2v;
 // only prunes the K range).  Transposes are compile-time; global loads are
 // 16-byte vectors from precomputed per-thread addresses; LDS is double
 // buffered so each K step needs a single barrier.
-template <typename CT, bool TA, bool TB, bool ACC64>
+template <typename CT, bool TA, bool TB, bool ACC64, int BK>
 __device__ __forceinline__ void gemm_fast_body(const GemmDesc* __restrict__ descs, int ndesc,
                                                const GemmSeg* __restrict__ segs) {
-  constexpr int BM = 128, BN = 128, BK = 16, PAD = 2;
+  constexpr int BM = 128, BN = 128, PAD = 2;
+  constexpr int E = BK / 2;      // elements of each operand one thread moves per K step
+  constexpr int NV = E / 2;      // ... as 16-byte vectors
   typedef typename AccT<CT>::T acc_t;
   __shared__ CT As[2][BK][BM + PAD];
   __shared__ CT Bs[2][BK][BN + PAD];
@@ -222,11 +224,13 @@ __device__ __forceinline__ void gemm_fast_body(const GemmDesc* __restrict__ desc
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  // per-thread load coordinates: 8 consecutive doubles per operand per K step
-  const int a_mk = TA ? (tid >> 1) : (tid >> 4);        // TA: m; else k
-  const int a_8 = TA ? (tid & 1) * 8 : (tid & 15) * 8;  // TA: k offset; else m offset
-  const int b_nk = TB ? (tid >> 4) : (tid >> 1);        // TB: k; else n
-  const int b_8 = TB ? (tid & 15) * 8 : (tid & 1) * 8;  // TB: n offset; else k offset
+  // per-thread load coordinates: E consecutive elements per operand per K step
+  // (along the operand's stored leading dimension)
+  constexpr int TPL = 128 / E;   // threads along a 128-long contiguous run
+  const int a_mk = TA ? (tid >> 1) : (tid / TPL);              // TA: m; else k
+  const int a_8 = TA ? (tid & 1) * E : (tid % TPL) * E;        // TA: k offset; else m offset
+  const int b_nk = TB ? (tid / TPL) : (tid >> 1);              // TB: k; else n
+  const int b_8 = TB ? (tid % TPL) * E : (tid & 1) * E;        // TB: n offset; else k offset
 
   acc_t acc[4][4];
 #pragma unroll
@@ -264,7 +268,7 @@ __device__ __forceinline__ void gemm_fast_body(const GemmDesc* __restrict__ desc
         for (int v = 0; v < 4; ++v) acc64[i][j][v] = 0.0;
   }
 
-  d2v ra[4], rb[4];
+  d2v ra[NV], rb[NV];
   for (int sgi = 0; sgi < d.nseg; ++sgi) {
     const GemmSeg sg = segs[d.seg_begin + sgi];
     int kbeg = 0, kend = sg.K;
@@ -282,14 +286,14 @@ __device__ __forceinline__ void gemm_fast_body(const GemmDesc* __restrict__ desc
       const gd2v* pa = (const gd2v*)(ap + step * astep);
       const gd2v* pb = (const gd2v*)(bp + step * bstep);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < NV; ++q) {
         ra[q] = pa[q];
         rb[q] = pb[q];
       }
     };
     auto lstore = [&](int buf) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < NV; ++q)
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
           if (TA) As[buf][a_8 + 2 * q + e][a_mk] = (CT)ra[q][e];
@@ -348,10 +352,13 @@ __device__ __forceinline__ void gemm_fast_body(const GemmDesc* __restrict__ desc
   }
 }
 
+#ifndef BLR_F64_WAVES
+#define BLR_F64_WAVES 2
+#endif
 template <typename CT, bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_gemm_fast(const GemmDesc* __restrict__ descs, int ndesc,
-                                                   const GemmSeg* __restrict__ segs) {
-  gemm_fast_body<CT, TA, TB, false>(descs, ndesc, segs);
+__global__ __launch_bounds__(256, sizeof(CT) == 8 ? BLR_F64_WAVES : 1) void k_gemm_fast(
+    const GemmDesc* __restrict__ descs, int ndesc, const GemmSeg* __restrict__ segs) {
+  gemm_fast_body<CT, TA, TB, false, sizeof(CT) == 8 ? kFastKStep64 : kFastKStep32>(descs, ndesc, segs);
 }
 
 // FP32 operands, FP64 accumulation across K (long sums); two waves per SIMD
@@ -359,7 +366,7 @@ __global__ __launch_bounds__(256) void k_gemm_fast(const GemmDesc* __restrict__ 
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256, 2) void k_gemm_fast_acc64(const GemmDesc* __restrict__ descs, int ndesc,
                                                             const GemmSeg* __restrict__ segs) {
-  gemm_fast_body<float, TA, TB, true>(descs, ndesc, segs);
+  gemm_fast_body<float, TA, TB, true, kFastKStep32>(descs, ndesc, segs);
 }
 
 }  // namespace

@@ -128,7 +128,8 @@ void Plan::flush_gemm(int fp32, int prof, bool allow_fast) {
         const GemmSeg& sg = curseg[d.seg_begin + si];
         const int tf = sg.flags & (SEG_TRANS_A | SEG_TRANS_B);
         if (tflags < 0) tflags = tf;
-        if (tf != tflags || (sg.flags & (SEG_A_UNIT_LOWER | SEG_B_UNIT_LOWER)) || sg.K % 16 ||
+        if (tf != tflags || (sg.flags & (SEG_A_UNIT_LOWER | SEG_B_UNIT_LOWER)) ||
+            sg.K % (fp32 ? kFastKStep32 : kFastKStep64) ||
             !al(sg.A) || !al(sg.B) || (sg.lda & 1) || (sg.ldb & 1))
           ok = false;
       }

@@ -40,7 +40,8 @@ def lib():
     return P.load()
 
 
-SHAPES = [(16, 16, 4), (64, 64, 64), (50, 70, 33), (300, 260, 130), (256, 512, 256), (1024, 128, 1024)]
+SHAPES = [(16, 16, 4), (64, 64, 64), (50, 70, 33), (300, 260, 130), (256, 512, 256), (1024, 128, 1024),
+          (256, 256, 272), (512, 384, 1056)]  # K % 32 == 16: FP64 leaves the 32-deep fast path
 
 
 @pytest.mark.parametrize("shape", SHAPES)
