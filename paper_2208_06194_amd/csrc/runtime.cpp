@@ -748,7 +748,7 @@ struct BcSlot {
 
 struct BcWork {
   double* stack = nullptr;      // m x b
-  double* Yf = nullptr;         // b x b explicit unit-lower Y_kk
+  double* Yf[2] = {nullptr, nullptr};  // b x b explicit unit-lower Y_kk (steps alternate)
   double* tallpart = nullptr;   // 2 x (kTallMaxGroups + 1) x 64
   double* gpart = nullptr;      // kGramSlices x b x b split-K Gram partials
   double* applypart = nullptr;  // 64 x ceil(b/32) x 32 x 32
@@ -796,7 +796,8 @@ BcWork make_bc_work(blr_matrix h, int npairs) {
   const int b = h->b, rc = h->rc;
   Arena& A = h->work;
   bw.stack = (double*)A.alloc((size_t)h->m * b * 8);
-  bw.Yf = (double*)A.alloc((size_t)b * b * 8);
+  bw.Yf[0] = (double*)A.alloc((size_t)b * b * 8);
+  bw.Yf[1] = (double*)A.alloc((size_t)b * b * 8);
   bw.tallpart = (double*)A.alloc((size_t)2 * (kTallMaxGroups + 1) * 64 * 8);
   bw.gpart = (double*)A.alloc((size_t)kGramSlices * b * b * 8);
   bw.applypart = (double*)A.alloc((size_t)64 * ((b + 31) / 32) * 32 * 32 * 8);
@@ -900,207 +901,254 @@ void plan_stack_qr(Plan& P, blr_matrix h, Work& w, BcWork& bw, int hs, double* T
   }
 }
 
-void plan_blockcol(blr_matrix h, Plan& P, Work& w, BcWork& bw, int kend, bool fp32) {
+// Panel of block-column step k (Section 3.3.1): gather the stack
+// [A_kk; Av_{k+1,k}; ...] (Av = A for dense tiles, V^T for low-rank tiles)
+// into one column-major buffer, take its Householder QR (the tile panel
+// kernels while it has at most 1024 rows, the row-split kernels otherwise),
+// build T_k and scatter R_kk and the reflector rows Y_ik back into the tiles,
+// with an explicit unit-lower copy of Y_kk.
+void plan_bc_panel(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k) {
   const int b = h->b, rc = h->rc, p = h->p, q = h->q;
-  for (int k = 0; k < kend; ++k) {
-    // 1. gather the stack
-    std::vector<int64_t> off(p, 0);
-    std::vector<int> rows(p, 0);
-    std::vector<bool> yd(p, true);
-    int hs = 0;
+  // 1. gather the stack
+  std::vector<int64_t> off(p, 0);
+  std::vector<int> rows(p, 0);
+  std::vector<bool> yd(p, true);
+  int hs = 0;
+  for (int i = k; i < p; ++i) {
+    yd[i] = i == k || h->t(i, k).fmt == DENSE;
+    rows[i] = yd[i] ? b : rc;
+    off[i] = hs;
+    hs += rows[i];
+  }
+  std::vector<CopyDesc> cp;
+  for (int i = k; i < p; ++i) {
+    Tile& t = h->t(i, k);
+    cp.push_back(CopyDesc{yd[i] ? t.D : t.Vt, bw.stack + off[i], yd[i] ? (int64_t)b : (int64_t)rc, (int64_t)hs,
+                          rows[i], b, 0, 0});
+  }
+  P.copy(cp);
+  // 2. Householder QR of the stack, T_k
+  double* Tk = h->T[(size_t)k * q + k];
+  double* tauk = h->tau[(size_t)k * q + k];
+  plan_stack_qr(P, h, w, bw, hs, Tk, tauk);
+  // 3. scatter R_kk / Y back, explicit unit-lower Y_kk
+  cp.clear();
+  for (int i = k; i < p; ++i) {
+    Tile& t = h->t(i, k);
+    cp.push_back(CopyDesc{bw.stack + off[i], yd[i] ? t.D : t.Vt, (int64_t)hs, yd[i] ? (int64_t)b : (int64_t)rc,
+                          rows[i], b, 0, 0});
+    if (i > k) h->yfmt[(size_t)i * q + k] = yd[i] ? DENSE : LOWRANK;
+  }
+  cp.push_back(CopyDesc{bw.stack, bw.Yf[k & 1], (int64_t)hs, (int64_t)b, b, b, 1, 0});
+  P.copy(cp);
+}
+
+// Trailing update of the columns j in [j0, j1) by the reflectors of step k
+// (Section 3.3.2): Z_j = sum_i Ytilde_ik^T A_ij, W_j = T_k^T Z_j and
+// A_ij -= Ytilde_ik W_j with the OP1/OP2 rules: Z_j is dense if any term is
+// dense, else the low-rank terms are summed by rounded additions in order
+// i = k, k+1, ...
+void plan_bc_update(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k, int j0, int j1, bool fp32) {
+  const int b = h->b, rc = h->rc, p = h->p, q = h->q;
+  if (j0 >= j1) return;
+  std::vector<bool> yd(p, true);
+  for (int i = k + 1; i < p; ++i) yd[i] = h->yfmt[(size_t)i * q + k] == DENSE;
+  double* Tk = h->T[(size_t)k * q + k];
+  auto Yd = [&](int i) -> double* { return i == k ? bw.Yf[k & 1] : h->t(i, k).D; };
+  std::vector<bool> zd(q, false);
+  std::vector<int8_t> f((size_t)p * q);
+  for (size_t t = 0; t < f.size(); ++t) f[t] = h->tiles[t].fmt;
+  for (int j = j0; j < j1; ++j) zd[j] = bc_zdense(h, f, k, j);
+  // slots for the pairs that need low-rank temporaries
+  std::vector<int> slot((size_t)p * q, -1);
+  int ns = 0;
+  for (int j = j0; j < j1; ++j)
+    for (int i = k; i < p; ++i)
+      if (!(yd[i] && h->t(i, j).fmt == DENSE && zd[j])) slot[(size_t)i * q + j] = ns++;
+  if (ns > (int)bw.slots.size()) throw Error(BLR_ERR_DEVICE, "internal: block-column slot count");
+  auto S = [&](int i, int j) -> BcSlot& { return bw.slots[slot[(size_t)i * q + j]]; };
+  // 4a. pre-products of the low-rank terms
+  for (int j = j0; j < j1; ++j)
     for (int i = k; i < p; ++i) {
-      yd[i] = i == k || h->t(i, k).fmt == DENSE;
-      rows[i] = yd[i] ? b : rc;
-      off[i] = hs;
-      hs += rows[i];
-    }
-    std::vector<CopyDesc> cp;
-    for (int i = k; i < p; ++i) {
-      Tile& t = h->t(i, k);
-      cp.push_back(CopyDesc{yd[i] ? t.D : t.Vt, bw.stack + off[i], yd[i] ? (int64_t)b : (int64_t)rc, (int64_t)hs,
-                            rows[i], b, 0, 0});
-    }
-    P.copy(cp);
-    // 2. Householder QR of the stack, T_k
-    double* Tk = h->T[(size_t)k * q + k];
-    double* tauk = h->tau[(size_t)k * q + k];
-    plan_stack_qr(P, h, w, bw, hs, Tk, tauk);
-    // 3. scatter R_kk / Y back, explicit unit-lower Y_kk
-    cp.clear();
-    for (int i = k; i < p; ++i) {
-      Tile& t = h->t(i, k);
-      cp.push_back(CopyDesc{bw.stack + off[i], yd[i] ? t.D : t.Vt, (int64_t)hs, yd[i] ? (int64_t)b : (int64_t)rc,
-                            rows[i], b, 0, 0});
-      if (i > k) h->yfmt[(size_t)i * q + k] = yd[i] ? DENSE : LOWRANK;
-    }
-    cp.push_back(CopyDesc{bw.stack, bw.Yf, (int64_t)hs, (int64_t)b, b, b, 1, 0});
-    P.copy(cp);
-    if (k + 1 >= q) continue;
-    // 4. the projected update of every j > k
-    auto Yd = [&](int i) -> double* { return i == k ? bw.Yf : h->t(i, k).D; };
-    std::vector<bool> zd(q, false);
-    std::vector<int8_t> f((size_t)p * q);
-    for (size_t t = 0; t < f.size(); ++t) f[t] = h->tiles[t].fmt;
-    for (int j = k + 1; j < q; ++j) zd[j] = bc_zdense(h, f, k, j);
-    // slots for the pairs that need low-rank temporaries
-    std::vector<int> slot((size_t)p * q, -1);
-    int ns = 0;
-    for (int j = k + 1; j < q; ++j)
-      for (int i = k; i < p; ++i)
-        if (!(yd[i] && h->t(i, j).fmt == DENSE && zd[j])) slot[(size_t)i * q + j] = ns++;
-    if (ns > (int)bw.slots.size()) throw Error(BLR_ERR_DEVICE, "internal: block-column slot count");
-    auto S = [&](int i, int j) -> BcSlot& { return bw.slots[slot[(size_t)i * q + j]]; };
-    // 4a. pre-products of the low-rank terms
-    for (int j = k + 1; j < q; ++j)
-      for (int i = k; i < p; ++i) {
-        Tile& A = h->t(i, j);
-        Tile& Y = h->t(i, k);
-        const bool ad = A.fmt == DENSE;
-        if (yd[i] && ad) continue;
-        BcSlot& sl = S(i, j);
-        if (yd[i]) P.gemm(sl.Ua, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, Yd(i), b, A.U, b, b, SEG_TRANS_A);
-        else if (ad) P.gemm(sl.Sa, rc, nullptr, 0, nullptr, 0, rc, b, 1.0, 0.0, Y.U, b, A.D, b, b, SEG_TRANS_A);
-        else P.gemm(sl.Sm, rc, nullptr, 0, nullptr, 0, rc, rc, 1.0, 0.0, Y.U, b, A.U, b, b, SEG_TRANS_A);
-      }
-    P.flush_gemm();
-    for (int j = k + 1; j < q; ++j)
-      for (int i = k + 1; i < p; ++i)
-        if (!yd[i] && h->t(i, j).fmt == LOWRANK) {
-          BcSlot& sl = S(i, j);
-          P.gemm(sl.Ua, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, h->t(i, k).Vt, rc, sl.Sm, rc, rc, SEG_TRANS_A);
-        }
-    P.flush_gemm();
-    // 4b. dense Z_j: low-rank contributions, then the dense sum on top
-    std::vector<bool> zlr(q, false);
-    for (int j = k + 1; j < q; ++j) {
-      if (!zd[j]) continue;
-      std::vector<GemmSeg> sv;
-      for (int i = k; i < p; ++i) {
-        Tile& A = h->t(i, j);
-        if (yd[i] && A.fmt == DENSE) continue;
-        GemmSeg g{};
-        if (A.fmt == LOWRANK) {
-          g.A = S(i, j).Ua; g.lda = b; g.B = A.Vt; g.ldb = rc; g.K = rc; g.flags = 0;
-        } else {
-          g.A = h->t(i, k).Vt; g.lda = rc; g.B = S(i, j).Sa; g.ldb = rc; g.K = rc; g.flags = SEG_TRANS_A;
-        }
-        sv.push_back(g);
-      }
-      if (!sv.empty()) {
-        P.gemm_multi(w.X[j], b, nullptr, 0, b, b, 1.0, 0.0, sv);
-        zlr[j] = true;
-      }
-    }
-    P.flush_gemm();
-    for (int j = k + 1; j < q; ++j) {
-      if (!zd[j]) continue;
-      std::vector<GemmSeg> sv;
-      for (int i = k; i < p; ++i) {
-        Tile& A = h->t(i, j);
-        if (!(yd[i] && A.fmt == DENSE)) continue;
-        GemmSeg g{};
-        g.A = Yd(i); g.lda = b; g.B = A.D; g.ldb = b; g.K = b; g.flags = SEG_TRANS_A;
-        sv.push_back(g);
-      }
-      P.gemm_multi(w.X[j], b, zlr[j] ? w.X[j] : nullptr, b, b, b, 1.0, zlr[j] ? 1.0 : 0.0, sv);
-    }
-    P.flush_gemm(fp32, 1);
-    // 4c. low-rank Z_j: rounded additions of the terms in order i = k, k+1, ...
-    std::vector<RcTerm> zterm(q);
-    auto term = [&](int i, int j) -> RcTerm {
       Tile& A = h->t(i, j);
-      if (A.fmt == LOWRANK) return RcTerm{S(i, j).Ua, A.Vt, A.rank, b, rc, 0, 0, 1.0};
-      return RcTerm{h->t(i, k).Vt, S(i, j).Sa, h->t(i, k).rank, rc, rc, 0, 1, 1.0};
-    };
-    for (int j = k + 1; j < q; ++j)
-      if (!zd[j]) zterm[j] = term(k, j);
-    for (int i = k + 1; i < p; ++i) {
-      for (int j = k + 1; j < q; ++j) {
-        if (zd[j]) continue;
-        RcDesc d{};
-        d.nterm = 2;
-        d.t[0] = zterm[j];
-        d.t[1] = term(i, j);
-        d.Uout = w.Uw[j];
-        d.Vtout = w.Vtw[j];
-        d.rank_out = w.rankw[j];
-        d.work = w.rcw[2 * j];
-        P.rc(d);
-        zterm[j] = RcTerm{w.Uw[j], w.Vtw[j], w.rankw[j], b, rc, 0, 0, 1.0};
-      }
-      P.flush_rc();
+      Tile& Y = h->t(i, k);
+      const bool ad = A.fmt == DENSE;
+      if (yd[i] && ad) continue;
+      BcSlot& sl = S(i, j);
+      if (yd[i]) P.gemm(sl.Ua, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, Yd(i), b, A.U, b, b, SEG_TRANS_A);
+      else if (ad) P.gemm(sl.Sa, rc, nullptr, 0, nullptr, 0, rc, b, 1.0, 0.0, Y.U, b, A.D, b, b, SEG_TRANS_A);
+      else P.gemm(sl.Sm, rc, nullptr, 0, nullptr, 0, rc, rc, 1.0, 0.0, Y.U, b, A.U, b, b, SEG_TRANS_A);
     }
-    // 5. W_j = T_k^T Z_j
-    for (int j = k + 1; j < q; ++j) {
-      if (zd[j]) P.gemm(w.X2[j], b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, Tk, b, w.X[j], b, b, SEG_TRANS_A | SEG_A_UPPER);
-      else P.gemm(w.WU[j], b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, Tk, b, zterm[j].U, zterm[j].ldu, b,
-                  SEG_TRANS_A | SEG_A_UPPER);
+  P.flush_gemm();
+  for (int j = j0; j < j1; ++j)
+    for (int i = k + 1; i < p; ++i)
+      if (!yd[i] && h->t(i, j).fmt == LOWRANK) {
+        BcSlot& sl = S(i, j);
+        P.gemm(sl.Ua, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, h->t(i, k).Vt, rc, sl.Sm, rc, rc, SEG_TRANS_A);
+      }
+  P.flush_gemm();
+  // 4b. dense Z_j: low-rank contributions, then the dense sum on top
+  std::vector<bool> zlr(q, false);
+  for (int j = j0; j < j1; ++j) {
+    if (!zd[j]) continue;
+    std::vector<GemmSeg> sv;
+    for (int i = k; i < p; ++i) {
+      Tile& A = h->t(i, j);
+      if (yd[i] && A.fmt == DENSE) continue;
+      GemmSeg g{};
+      if (A.fmt == LOWRANK) {
+        g.A = S(i, j).Ua; g.lda = b; g.B = A.Vt; g.ldb = rc; g.K = rc; g.flags = 0;
+      } else {
+        g.A = h->t(i, k).Vt; g.lda = rc; g.B = S(i, j).Sa; g.ldb = rc; g.K = rc; g.flags = SEG_TRANS_A;
+      }
+      sv.push_back(g);
     }
-    P.flush_gemm(fp32, 1);
-    // 6. fill-in: low-rank targets of a dense update become dense (OP1)
-    for (int j = k + 1; j < q; ++j)
-      for (int i = k; i < p; ++i) {
-        Tile& A = h->t(i, j);
-        if (zd[j] && yd[i] && A.fmt == LOWRANK) {
-          P.gemm(A.D, b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, A.U, b, A.Vt, rc, rc, 0);
-          A.fmt = DENSE;
-          h->n_fill++;
-        }
-      }
-    P.flush_gemm(fp32);
-    // 7. updates A_ij -= Ytilde_ik W_j
-    for (int j = k + 1; j < q; ++j)
-      for (int i = k; i < p; ++i)
-        if (yd[i] && zd[j])
-          P.gemm(h->t(i, j).D, b, h->t(i, j).D, b, nullptr, 0, b, b, -1.0, 1.0, Yd(i), b, w.X2[j], b, b, 0);
-    P.flush_gemm(fp32, 1);
-    for (int j = k + 1; j < q; ++j)
-      for (int i = k; i < p; ++i) {
-        if (yd[i] && zd[j]) continue;
-        BcSlot& sl = S(i, j);
-        if (!yd[i] && zd[j])
-          P.gemm(sl.Sa, rc, nullptr, 0, nullptr, 0, rc, b, 1.0, 0.0, h->t(i, k).Vt, rc, w.X2[j], b, b, 0);
-        else if (yd[i])
-          P.gemm(sl.Ub, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, Yd(i), b, w.WU[j], b, b, 0);
-        else
-          P.gemm(sl.Sm, rc, nullptr, 0, nullptr, 0, rc, rc, 1.0, 0.0, h->t(i, k).Vt, rc, w.WU[j], b, b, 0);
-      }
-    P.flush_gemm();
-    for (int j = k + 1; j < q; ++j)
-      for (int i = k + 1; i < p; ++i)
-        if (!yd[i] && !zd[j]) {
-          BcSlot& sl = S(i, j);
-          P.gemm(sl.Ub, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, h->t(i, k).U, b, sl.Sm, rc, rc, 0);
-        }
-    P.flush_gemm();
-    for (int j = k + 1; j < q; ++j)
-      for (int i = k; i < p; ++i) {
-        if (yd[i] && zd[j]) continue;
-        Tile& A = h->t(i, j);
-        BcSlot& sl = S(i, j);
-        // the update as a low-rank product Uu Vu^T
-        const double* Uu;
-        const double* Vu;
-        const int* ru;
-        if (!yd[i] && zd[j]) { Uu = h->t(i, k).U; Vu = sl.Sa; ru = h->t(i, k).rank; }
-        else { Uu = sl.Ub; Vu = zterm[j].Vt; ru = zterm[j].rank_ptr; }
-        if (A.fmt == DENSE) {
-          P.gemm(A.D, b, A.D, b, nullptr, 0, b, b, -1.0, 1.0, Uu, b, Vu, rc, rc, 0);
-        } else {
-          RcDesc d{};
-          d.nterm = 2;
-          d.t[0] = RcTerm{A.U, A.Vt, A.rank, b, rc, 0, 0, 1.0};
-          d.t[1] = RcTerm{Uu, Vu, ru, b, rc, 0, 0, -1.0};
-          d.Uout = A.U;
-          d.Vtout = A.Vt;
-          d.rank_out = A.rank;
-          d.work = sl.rcw;
-          P.rc(d);
-        }
-      }
-    P.flush_gemm(fp32);
+    if (!sv.empty()) {
+      P.gemm_multi(w.X[j], b, nullptr, 0, b, b, 1.0, 0.0, sv);
+      zlr[j] = true;
+    }
+  }
+  P.flush_gemm();
+  for (int j = j0; j < j1; ++j) {
+    if (!zd[j]) continue;
+    std::vector<GemmSeg> sv;
+    for (int i = k; i < p; ++i) {
+      Tile& A = h->t(i, j);
+      if (!(yd[i] && A.fmt == DENSE)) continue;
+      GemmSeg g{};
+      g.A = Yd(i); g.lda = b; g.B = A.D; g.ldb = b; g.K = b; g.flags = SEG_TRANS_A;
+      sv.push_back(g);
+    }
+    P.gemm_multi(w.X[j], b, zlr[j] ? w.X[j] : nullptr, b, b, b, 1.0, zlr[j] ? 1.0 : 0.0, sv);
+  }
+  P.flush_gemm(fp32, 1);
+  // 4c. low-rank Z_j: rounded additions of the terms in order i = k, k+1, ...
+  std::vector<RcTerm> zterm(q);
+  auto term = [&](int i, int j) -> RcTerm {
+    Tile& A = h->t(i, j);
+    if (A.fmt == LOWRANK) return RcTerm{S(i, j).Ua, A.Vt, A.rank, b, rc, 0, 0, 1.0};
+    return RcTerm{h->t(i, k).Vt, S(i, j).Sa, h->t(i, k).rank, rc, rc, 0, 1, 1.0};
+  };
+  for (int j = j0; j < j1; ++j)
+    if (!zd[j]) zterm[j] = term(k, j);
+  for (int i = k + 1; i < p; ++i) {
+    for (int j = j0; j < j1; ++j) {
+      if (zd[j]) continue;
+      RcDesc d{};
+      d.nterm = 2;
+      d.t[0] = zterm[j];
+      d.t[1] = term(i, j);
+      d.Uout = w.Uw[j];
+      d.Vtout = w.Vtw[j];
+      d.rank_out = w.rankw[j];
+      d.work = w.rcw[2 * j];
+      P.rc(d);
+      zterm[j] = RcTerm{w.Uw[j], w.Vtw[j], w.rankw[j], b, rc, 0, 0, 1.0};
+    }
     P.flush_rc();
   }
+  // 5. W_j = T_k^T Z_j
+  for (int j = j0; j < j1; ++j) {
+    if (zd[j]) P.gemm(w.X2[j], b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, Tk, b, w.X[j], b, b, SEG_TRANS_A | SEG_A_UPPER);
+    else P.gemm(w.WU[j], b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, Tk, b, zterm[j].U, zterm[j].ldu, b,
+                SEG_TRANS_A | SEG_A_UPPER);
+  }
+  P.flush_gemm(fp32, 1);
+  // 6. fill-in: low-rank targets of a dense update become dense (OP1)
+  for (int j = j0; j < j1; ++j)
+    for (int i = k; i < p; ++i) {
+      Tile& A = h->t(i, j);
+      if (zd[j] && yd[i] && A.fmt == LOWRANK) {
+        P.gemm(A.D, b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, A.U, b, A.Vt, rc, rc, 0);
+        A.fmt = DENSE;
+        h->n_fill++;
+      }
+    }
+  P.flush_gemm(fp32);
+  // 7. updates A_ij -= Ytilde_ik W_j
+  for (int j = j0; j < j1; ++j)
+    for (int i = k; i < p; ++i)
+      if (yd[i] && zd[j])
+        P.gemm(h->t(i, j).D, b, h->t(i, j).D, b, nullptr, 0, b, b, -1.0, 1.0, Yd(i), b, w.X2[j], b, b, 0);
+  P.flush_gemm(fp32, 1);
+  for (int j = j0; j < j1; ++j)
+    for (int i = k; i < p; ++i) {
+      if (yd[i] && zd[j]) continue;
+      BcSlot& sl = S(i, j);
+      if (!yd[i] && zd[j])
+        P.gemm(sl.Sa, rc, nullptr, 0, nullptr, 0, rc, b, 1.0, 0.0, h->t(i, k).Vt, rc, w.X2[j], b, b, 0);
+      else if (yd[i])
+        P.gemm(sl.Ub, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, Yd(i), b, w.WU[j], b, b, 0);
+      else
+        P.gemm(sl.Sm, rc, nullptr, 0, nullptr, 0, rc, rc, 1.0, 0.0, h->t(i, k).Vt, rc, w.WU[j], b, b, 0);
+    }
+  P.flush_gemm();
+  for (int j = j0; j < j1; ++j)
+    for (int i = k + 1; i < p; ++i)
+      if (!yd[i] && !zd[j]) {
+        BcSlot& sl = S(i, j);
+        P.gemm(sl.Ub, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, h->t(i, k).U, b, sl.Sm, rc, rc, 0);
+      }
+  P.flush_gemm();
+  for (int j = j0; j < j1; ++j)
+    for (int i = k; i < p; ++i) {
+      if (yd[i] && zd[j]) continue;
+      Tile& A = h->t(i, j);
+      BcSlot& sl = S(i, j);
+      // the update as a low-rank product Uu Vu^T
+      const double* Uu;
+      const double* Vu;
+      const int* ru;
+      if (!yd[i] && zd[j]) { Uu = h->t(i, k).U; Vu = sl.Sa; ru = h->t(i, k).rank; }
+      else { Uu = sl.Ub; Vu = zterm[j].Vt; ru = zterm[j].rank_ptr; }
+      if (A.fmt == DENSE) {
+        P.gemm(A.D, b, A.D, b, nullptr, 0, b, b, -1.0, 1.0, Uu, b, Vu, rc, rc, 0);
+      } else {
+        RcDesc d{};
+        d.nterm = 2;
+        d.t[0] = RcTerm{A.U, A.Vt, A.rank, b, rc, 0, 0, 1.0};
+        d.t[1] = RcTerm{Uu, Vu, ru, b, rc, 0, 0, -1.0};
+        d.Uout = A.U;
+        d.Vtout = A.Vt;
+        d.rank_out = A.rank;
+        d.work = sl.rcw;
+        P.rc(d);
+      }
+    }
+  P.flush_gemm(fp32);
+  P.flush_rc();
+}
+
+// Block-column BLR-QR (Alg. 2 with Section 3.3).  Look-ahead: stream 0 runs
+// the trailing updates, stream 1 the panels.  Step k first updates column
+// k + 1 and records E_col(k); the panel of column k + 1 waits for it and runs
+// beside the rest of step k's update; step k + 1 waits for E_panel(k + 1).
+// The two steps' explicit Y_kk copies alternate between two buffers.
+void plan_blockcol(blr_matrix h, Plan& P, Work& w, BcWork& bw, int kend, bool fp32, bool lookahead) {
+  const int q = h->q;
+  auto e_panel = [&](int k) { return k; };
+  auto e_col = [&](int k) { return q + k; };
+  const int ps = lookahead ? 1 : 0;
+  if (kend <= 0) return;
+  P.cur_stream = ps;
+  plan_bc_panel(h, P, w, bw, 0);
+  P.record(e_panel(0));
+  for (int k = 0; k < kend; ++k) {
+    P.cur_stream = 0;
+    P.wait(e_panel(k));
+    if (k + 1 >= q) continue;
+    plan_bc_update(h, P, w, bw, k, k + 1, k + 2, fp32);
+    if (k + 1 < kend) {
+      P.record(e_col(k));
+      P.cur_stream = ps;
+      P.wait(e_col(k));
+      plan_bc_panel(h, P, w, bw, k + 1);
+      P.record(e_panel(k + 1));
+      P.cur_stream = 0;
+    }
+    plan_bc_update(h, P, w, bw, k, k + 2, q, fp32);
+  }
+  P.cur_stream = 0;
 }
 
 // B <- Q^T B or Q B for the block-column factor (Alg. 3): per step k,
@@ -1624,7 +1672,9 @@ blr_status blr_qr_factor(blr_matrix h, const blr_factor_opts* o, void* stream) {
     h->n_fill = 0;
     if (bc) {
       BcWork bw = make_bc_work(h, bc_pairs);
-      plan_blockcol(h, P, works[0], bw, kend, o->precision == BLR_MIXED_FP32);
+      bool la = true;
+      if (const char* e = std::getenv("BLRQR_LOOKAHEAD")) la = std::atoi(e) != 0;
+      plan_blockcol(h, P, works[0], bw, kend, o->precision == BLR_MIXED_FP32, la);
     } else {
       plan_tiled(h, P, works, kend, o->precision == BLR_MIXED_FP32);
     }
