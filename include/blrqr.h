@@ -94,6 +94,9 @@ typedef struct blr_factor_opts {
   int32_t precision;        /* BLR_FP64 or BLR_MIXED_FP32 */
   int32_t ib;               /* inner block of reflector generation (0 = default 32) */
   int32_t stop_after_k;     /* debug: factor only block columns 0..K-1 (-1 = all) */
+  int32_t keep_a;           /* 1: keep a device copy of A~ (doubles the tile memory) so that
+                               blr_matmul with A~ and refined least squares work after the
+                               in-place factorization; 0: no copy */
 } blr_factor_opts;
 
 typedef struct blr_info {
@@ -169,8 +172,9 @@ blr_status blr_apply_qt(blr_matrix h, int32_t trans, double* B, int64_t ldb,
 
 /* Products with the stored BLR matrix, for residual and orthogonality
  * checks and refinement (eq. blr_matrix_def, eq. qr_fact):
- *   BLR_MATMUL_A   Y = A~ X     requires COMPRESSED; X n x nrhs, Y m x nrhs
- *   BLR_MATMUL_AT  Y = A~^T X   requires COMPRESSED; X m x nrhs, Y n x nrhs
+ *   BLR_MATMUL_A   Y = A~ X     requires COMPRESSED, or a factor made with keep_a;
+ *                               X n x nrhs, Y m x nrhs
+ *   BLR_MATMUL_AT  Y = A~^T X   same requirement; X m x nrhs, Y n x nrhs
  *   BLR_MATMUL_R   Y = R X      requires a complete factor; X, Y n x nrhs
  * X and Y: device, column-major (ldx, ldy at least their row counts), must
  * not overlap; Y is overwritten.  Dense tiles multiply directly, low-rank
@@ -183,10 +187,16 @@ blr_status blr_matmul(blr_matrix h, int32_t op, const double* X, int64_t ldx, do
 /* Least squares X = argmin ||A~ X - B||_F column by column, X = R^{-1}
  * (Q^T B)[0:n] with tile back-substitution through the BLR factor R.
  * B: device m x nrhs (ldb >= m), not modified.  X: device n x nrhs
- * (ldx >= n).  max_refine: reserved, must be 0.  resid_norms: optional
- * device array of nrhs doubles receiving ||(Q^T B)[n:m]|| per column (the
- * least-squares residual norm).  Requires FACTORED.  Synchronises the stream
- * (the singularity check reads the diagonal of R). */
+ * (ldx >= n).  max_refine > 0 (needs a factor made with keep_a): up to that
+ * many steps of iterative refinement of the augmented system
+ * [I A~; A~^T 0][r; x] = [b; 0] with FP64 residuals f = b - r - A~ x and
+ * g = -A~^T r and corrections from the stored factor, d = Q^T f,
+ * h = R^{-T} g, dx = R^{-1}(d_1 - h), dr = Q [h; d_2]; the loop stops early
+ * once ||dx||_F <= 2 u ||x||_F.  It recovers FP64 accuracy for a
+ * BLR_MIXED_FP32 factor.  resid_norms: optional device array of nrhs doubles
+ * receiving the squared least-squares residual norm per column
+ * (||(Q^T B)[n:m]||^2, or ||r||^2 of the refined residual).  Requires a complete factor.
+ * Synchronises the stream (the singularity check reads the diagonal of R). */
 blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X,
                            int64_t ldx, int32_t nrhs, int32_t max_refine,
                            double* resid_norms, void* hip_stream);

@@ -38,7 +38,8 @@ class CompressOpts(ctypes.Structure):
 
 
 class FactorOpts(ctypes.Structure):
-    _fields_ = [("variant", c_int32), ("precision", c_int32), ("ib", c_int32), ("stop_after_k", c_int32)]
+    _fields_ = [("variant", c_int32), ("precision", c_int32), ("ib", c_int32), ("stop_after_k", c_int32),
+                ("keep_a", c_int32)]
 
 
 class Info(ctypes.Structure):

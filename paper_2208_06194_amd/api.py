@@ -149,9 +149,9 @@ class BLRMatrix:
 
     # the hot path ----------------------------------------------------------------
     def factor(self, variant: str = "tiled", precision: str = "fp64", stop_after_k: int = -1,
-               ib: int = 0, stream=None):
+               ib: int = 0, keep_a: bool = False, stream=None):
         o = L.FactorOpts(variant=L.VARIANT[variant], precision=L.PRECISION[precision], ib=ib,
-                         stop_after_k=stop_after_k)
+                         stop_after_k=stop_after_k, keep_a=1 if keep_a else 0)
         _check(L.load().blr_qr_factor(self._h, ctypes.byref(o), _stream(stream)))
         return self
 
@@ -175,15 +175,16 @@ class BLRMatrix:
         _check(L.load().blr_apply_qt(self._h, 1 if trans else 0, Bc.data_ptr(), m, nrhs, _stream(stream)))
         return Bc.t()
 
-    def lstsq(self, B: torch.Tensor, with_resid: bool = False, stream=None):
-        """X = argmin ||A X - B||_F for a (m, nrhs) device tensor; returns (n, nrhs)."""
+    def lstsq(self, B: torch.Tensor, with_resid: bool = False, max_refine: int = 0, stream=None):
+        """X = argmin ||A X - B||_F for a (m, nrhs) device tensor; returns (n, nrhs).
+        max_refine > 0 refines with FP64 residuals (the factor must keep A~)."""
         inf = self.info()
         m, n = inf["m"], inf["n"]
         Bc = _colmajor(B.to(torch.float64))
         nrhs = Bc.shape[0]
         Xc = torch.empty((nrhs, n), dtype=torch.float64, device=B.device)
         res = torch.empty(nrhs, dtype=torch.float64, device=B.device) if with_resid else None
-        _check(L.load().blr_lstsq_solve(self._h, Bc.data_ptr(), m, Xc.data_ptr(), n, nrhs, 0,
+        _check(L.load().blr_lstsq_solve(self._h, Bc.data_ptr(), m, Xc.data_ptr(), n, nrhs, max_refine,
                                         None if res is None else res.data_ptr(), _stream(stream)))
         X = Xc.t()
         return (X, torch.sqrt(res)) if with_resid else X

@@ -40,4 +40,11 @@ hipError_t launch_nonfinite(const double* a, int64_t rows, int64_t cols, int64_t
 hipError_t launch_frob2(const Frob2Desc* d, int n, hipStream_t s);
 hipError_t launch_trsm_upper(const double* R, int64_t ldr, int n, double* X, int64_t ldx, int nrhs,
                              hipStream_t s);
+// R^T X = B in place (R upper triangular n x n): forward substitution.
+hipError_t launch_trsm_upper_t(const double* R, int64_t ldr, int n, double* X, int64_t ldx, int nrhs,
+                               hipStream_t s);
+// out = a x + b y + c z (rows x cols, column-major; y and z may be null).
+hipError_t launch_lincomb(double* out, int64_t ldo, const double* x, int64_t ldx, const double* y, int64_t ldy,
+                          const double* z, int64_t ldz, double a, double b, double c, int rows, int cols,
+                          hipStream_t s);
 hipError_t launch_diag_absmin(const DiagDesc* d, int n, int b, double* out, hipStream_t s);

@@ -132,6 +132,41 @@ __global__ __launch_bounds__(256) void k_trsm_upper(const double* __restrict__ R
   for (int t = lane; t < n; t += 64) x[t] = xl[t];
 }
 
+// R^T x = c for upper triangular R (forward substitution), one wave per
+// right-hand side; column r of R is contiguous, so the dot product of step r
+// reads it coalesced.
+__global__ __launch_bounds__(256) void k_trsm_upper_t(const double* __restrict__ R, int64_t ldr, int n,
+                                                      double* X, int64_t ldx, int nrhs) {
+  extern __shared__ double xs[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = blockIdx.x * 4 + wave;
+  if (c >= nrhs) return;
+  double* xl = xs + (size_t)wave * n;
+  double* x = X + (int64_t)c * ldx;
+  for (int r = 0; r < n; ++r) {
+    double s = 0.0;
+    for (int t = lane; t < r; t += 64) s += R[t + (int64_t)r * ldr] * xl[t];
+    s = wave_sum(s);
+    const double xr = (x[r] - s) / R[r + (int64_t)r * ldr];
+    if ((r & 63) == lane) xl[r] = xr;
+    __builtin_amdgcn_wave_barrier();
+  }
+  for (int t = lane; t < n; t += 64) x[t] = xl[t];
+}
+
+// out = a x + b y + c z over a rows x cols column-major block (y, z may be null).
+__global__ void k_lincomb(double* out, int64_t ldo, const double* x, int64_t ldx, const double* y, int64_t ldy,
+                          const double* z, int64_t ldz, double a, double b, double c, int rows, int cols) {
+  const int64_t n = (int64_t)rows * cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e % rows, col = e / rows;
+    double v = a * x[r + col * ldx];
+    if (y) v += b * y[r + col * ldy];
+    if (z) v += c * z[r + col * ldz];
+    out[r + col * ldo] = v;
+  }
+}
+
 __global__ void k_diag_absmin(const DiagDesc* __restrict__ d, int b, double* out) {
   // out[2*i] = min |diag|, out[2*i+1] = ||upper triangle||_F^2 of tile i
   __shared__ double red[16];
@@ -203,6 +238,25 @@ hipError_t launch_trsm_upper(const double* R, int64_t ldr, int n, double* X, int
   if (nrhs <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_trsm_upper, dim3((nrhs + 3) / 4), dim3(256), (size_t)4 * n * sizeof(double), s, R,
                      ldr, n, X, ldx, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_upper_t(const double* R, int64_t ldr, int n, double* X, int64_t ldx, int nrhs,
+                               hipStream_t s) {
+  if (nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_trsm_upper_t, dim3((nrhs + 3) / 4), dim3(256), (size_t)4 * n * sizeof(double), s, R,
+                     ldr, n, X, ldx, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_lincomb(double* out, int64_t ldo, const double* x, int64_t ldx, const double* y, int64_t ldy,
+                          const double* z, int64_t ldz, double a, double b, double c, int rows, int cols,
+                          hipStream_t s) {
+  const int64_t n = (int64_t)rows * cols;
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_lincomb, dim3(blocks), dim3(256), 0, s, out, ldo, x, ldx, y, ldy, z, ldz, a, b, c, rows,
+                     cols);
   return hipGetLastError();
 }
 

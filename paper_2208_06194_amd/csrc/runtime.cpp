@@ -1217,6 +1217,171 @@ void plan_apply(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, int nrhs
   }
 }
 
+// Products with the stored matrix (eq. blr_matrix_def): A~ X, A~^T X (the
+// tiles before the factorization, or the copy a factor with keep_a kept) and
+// R X (eq. qr_fact; the upper triangles of the diagonal tiles and the R_kj
+// tiles).  Dense tiles multiply directly, low-rank ones through the small
+// products V^T X or U^T X; one multi-segment descriptor per block row.
+void plan_matmul(blr_matrix h, Plan& P, int op, const double* X, int64_t ldx, double* Y, int64_t ldy, int nrhs) {
+  const int b = h->b, rc = h->rc, p = h->p, q = h->q;
+  std::vector<Tile>& T = (op == BLR_MATMUL_R || h->state == BLR_STATE_COMPRESSED) ? h->tiles : h->acopy;
+  auto tile = [&](int i, int j) -> Tile& { return T[(size_t)i * q + j]; };
+  const int rows = op == BLR_MATMUL_R ? q : p;
+  std::vector<int> slot((size_t)p * q, -1);
+  int nlr = 0;
+  for (int i = 0; i < rows; ++i)
+    for (int j = (op == BLR_MATMUL_R ? i + 1 : 0); j < q; ++j)
+      if (tile(i, j).fmt == LOWRANK) slot[(size_t)i * q + j] = nlr++;
+  double* S = (double*)h->work.alloc((size_t)std::max(nlr, 1) * rc * nrhs * 8);
+  double* Dg = nullptr;
+  if (op == BLR_MATMUL_R) {
+    Dg = (double*)h->work.alloc((size_t)q * b * b * 8);
+    std::vector<CopyDesc> cp;
+    for (int k = 0; k < q; ++k)
+      cp.push_back(CopyDesc{tile(k, k).D, Dg + (size_t)k * b * b, (int64_t)b, (int64_t)b, b, b, 2, 0});
+    P.copy(cp);
+  }
+  auto Sp = [&](int i, int j) { return S + (size_t)slot[(size_t)i * q + j] * rc * nrhs; };
+  for (int i = 0; i < rows; ++i)
+    for (int j = 0; j < q; ++j) {
+      if (slot[(size_t)i * q + j] < 0) continue;
+      Tile& t = tile(i, j);
+      if (op == BLR_MATMUL_AT)
+        P.gemm(Sp(i, j), rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, t.U, b, X + (int64_t)i * b, ldx, b,
+               SEG_TRANS_A);
+      else
+        P.gemm(Sp(i, j), rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, t.Vt, rc, X + (int64_t)j * b, ldx, b, 0);
+    }
+  P.flush_gemm(0, 0, false);
+  const int outs = op == BLR_MATMUL_A ? p : q;
+  for (int o = 0; o < outs; ++o) {
+    std::vector<GemmSeg> sv;
+    if (op == BLR_MATMUL_AT) {
+      for (int i = 0; i < p; ++i) {
+        Tile& t = tile(i, o);
+        GemmSeg g{};
+        if (t.fmt == DENSE) {
+          g.A = t.D; g.lda = b; g.B = X + (int64_t)i * b; g.ldb = ldx; g.K = b; g.flags = SEG_TRANS_A;
+        } else {
+          g.A = t.Vt; g.lda = rc; g.B = Sp(i, o); g.ldb = rc; g.K = rc; g.flags = SEG_TRANS_A;
+        }
+        sv.push_back(g);
+      }
+    } else {
+      for (int j = (op == BLR_MATMUL_R ? o : 0); j < q; ++j) {
+        Tile& t = tile(o, j);
+        GemmSeg g{};
+        if (op == BLR_MATMUL_R && j == o) {
+          g.A = Dg + (size_t)o * b * b; g.lda = b; g.B = X + (int64_t)j * b; g.ldb = ldx; g.K = b; g.flags = 0;
+        } else if (t.fmt == DENSE) {
+          g.A = t.D; g.lda = b; g.B = X + (int64_t)j * b; g.ldb = ldx; g.K = b; g.flags = 0;
+        } else {
+          g.A = t.U; g.lda = b; g.B = Sp(o, j); g.ldb = rc; g.K = rc; g.flags = 0;
+        }
+        sv.push_back(g);
+      }
+    }
+    P.gemm_multi(Y + (int64_t)o * b, ldy, nullptr, 0, b, nrhs, 1.0, 0.0, sv);
+  }
+  P.flush_gemm(0, 0, false);
+}
+
+// Block back-substitution X <- R^{-1} X (trans = 0) or forward substitution
+// X <- R^{-T} X (trans = 1) through the BLR factor R, in place on the n x nrhs
+// block X: per block row, the off-diagonal tiles' contributions as one
+// multi-segment product (low-rank tiles through V^T X_j or U^T X_j), then a
+// triangular solve with the diagonal tile.  Enqueued on s.
+void run_rsolve(blr_matrix h, double* X, int64_t ldx, int nrhs, int trans, hipStream_t s) {
+  const int b = h->b, q = h->q, rc = h->rc;
+  Plan Q;
+  double* Sx = (double*)h->work.alloc((size_t)q * rc * nrhs * 8);  // rc x nrhs per tile column
+  for (int step = 0; step < q; ++step) {
+    const int k = trans ? step : q - 1 - step;
+    double* Xk = X + (int64_t)k * b;
+    // the already solved blocks: j > k (R X) or j < k (R^T X)
+    const int jb = trans ? 0 : k + 1, je = trans ? k : q;
+    bool any_lr = false;
+    for (int j = jb; j < je; ++j) {
+      Tile& t = trans ? h->t(j, k) : h->t(k, j);
+      if (t.fmt != LOWRANK) continue;
+      if (trans)   // (U V^T)^T X_j = V (U^T X_j)
+        Q.gemm(Sx + (size_t)j * rc * nrhs, rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, t.U, b,
+               X + (int64_t)j * b, ldx, b, SEG_TRANS_A);
+      else
+        Q.gemm(Sx + (size_t)j * rc * nrhs, rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, t.Vt, rc,
+               X + (int64_t)j * b, ldx, b, 0);
+      any_lr = true;
+    }
+    if (any_lr) Q.flush_gemm(0, 0, false);
+    if (je > jb) {
+      std::vector<GemmSeg> sv;
+      for (int j = jb; j < je; ++j) {
+        Tile& t = trans ? h->t(j, k) : h->t(k, j);
+        GemmSeg sg{};
+        if (t.fmt == DENSE) {
+          sg.A = t.D; sg.lda = b; sg.B = X + (int64_t)j * b; sg.ldb = ldx; sg.K = b; sg.flags = trans ? SEG_TRANS_A : 0;
+        } else if (trans) {
+          sg.A = t.Vt; sg.lda = rc; sg.B = Sx + (size_t)j * rc * nrhs; sg.ldb = rc; sg.K = rc; sg.flags = SEG_TRANS_A;
+        } else {
+          sg.A = t.U; sg.lda = b; sg.B = Sx + (size_t)j * rc * nrhs; sg.ldb = rc; sg.K = rc; sg.flags = 0;
+        }
+        sv.push_back(sg);
+      }
+      Q.gemm_multi(Xk, ldx, Xk, ldx, b, nrhs, -1.0, 1.0, sv);
+      Q.flush_gemm(0, 0, false);
+    }
+    Op o;
+    o.kind = Op::TRSM;
+    o.off = k;
+    o.n = trans;
+    Q.ops.push_back(o);
+  }
+  Q.upload(h->work);
+  for (const Op& o : Q.ops) {
+    if (o.kind == Op::TRSM) {
+      const int k = o.off;
+      if (o.n) HIPCHECK(launch_trsm_upper_t(h->t(k, k).D, b, b, X + (int64_t)k * b, ldx, nrhs, s));
+      else HIPCHECK(launch_trsm_upper(h->t(k, k).D, b, b, X + (int64_t)k * b, ldx, nrhs, s));
+    } else {
+      HIPCHECK(launch_gemm(Q.d_descs + o.off, o.n, Q.d_segs, o.ntiles, o.big, 0, s));
+    }
+  }
+}
+
+// Keep a device copy of A~ (all tiles and ranks) for products after the
+// in-place factorization.
+void keep_copy(blr_matrix h, hipStream_t s) {
+  const int b = h->b, rc = h->rc, p = h->p, q = h->q;
+  h->acopy.assign(h->tiles.size(), Tile{});
+  size_t nd = 0, nl = 0;
+  for (auto& t : h->tiles) (t.fmt == DENSE ? nd : nl)++;
+  double* dp = (double*)h->amem.alloc(std::max<size_t>(nd, 1) * b * b * 8);
+  double* lp = (double*)h->amem.alloc(std::max<size_t>(nl, 1) * 2 * (size_t)b * rc * 8);
+  int* rk = (int*)h->amem.alloc((size_t)p * q * sizeof(int));
+  HIPCHECK(hipMemcpyAsync(rk, h->d_rank, (size_t)p * q * sizeof(int), hipMemcpyDeviceToDevice, s));
+  Plan P;
+  std::vector<CopyDesc> cp;
+  size_t id = 0, il = 0;
+  for (size_t a = 0; a < h->tiles.size(); ++a) {
+    Tile& t = h->tiles[a];
+    Tile& c = h->acopy[a];
+    c.fmt = t.fmt;
+    c.rank = rk + a;
+    if (t.fmt == DENSE) {
+      c.D = dp + (id++) * (size_t)b * b;
+      cp.push_back(CopyDesc{t.D, c.D, (int64_t)b, (int64_t)b, b, b, 0, 0});
+    } else {
+      c.U = lp + (il++) * 2 * (size_t)b * rc;
+      c.Vt = c.U + (size_t)b * rc;
+      cp.push_back(CopyDesc{t.U, c.U, (int64_t)b, (int64_t)b, b, rc, 0, 0});
+      cp.push_back(CopyDesc{t.Vt, c.Vt, (int64_t)rc, (int64_t)rc, rc, b, 0, 0});
+    }
+  }
+  P.copy(cp);
+  P.upload(h->work);
+  execute(h, P, s);
+}
+
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
 blr_status run_guarded(const std::function<void()>& f) {
@@ -1620,6 +1785,10 @@ blr_status blr_qr_factor(blr_matrix h, const blr_factor_opts* o, void* stream) {
     const int kend = (o->stop_after_k < 0) ? q : std::min(q, o->stop_after_k);
     h->variant = o->variant;
     h->precision = o->precision;
+    if (o->keep_a) {
+      keep_copy(h, s);
+      HIPCHECK(hipStreamSynchronize(s));
+    }
     const bool bc = o->variant == BLR_BLOCK_COLUMN;
     int bc_pairs = 0;
     // fill-in: simulate formats to find the tiles that need a dense slot
@@ -1716,7 +1885,9 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
   if (h->state != BLR_STATE_FACTORED) return fail(BLR_ERR_STATE, "matrix is not factored");
   if (h->steps_done != h->q) return fail(BLR_ERR_STATE, "factorization is incomplete");
   if (ldb < h->m || ldx < h->n || nrhs < 0) return fail(BLR_ERR_INVALID, "bad B or X shape");
-  if (max_refine != 0) return fail(BLR_ERR_INVALID, "max_refine must be 0");
+  if (max_refine < 0) return fail(BLR_ERR_INVALID, "max_refine must be >= 0");
+  if (max_refine > 0 && h->acopy.empty())
+    return fail(BLR_ERR_STATE, "refinement needs the copy of A~ kept by a factor with keep_a");
   if (nrhs == 0) return BLR_OK;
   hipStream_t s = as_stream(stream);
   return run_guarded([&] {
@@ -1762,85 +1933,73 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
       h->work.release();
     }
     Work w = make_work(h, nrhs);
-    double* C = (double*)h->work.alloc((size_t)m * nrhs * 8);
-    HIPCHECK(hipMemcpy2DAsync(C, m * 8, B, ldb * 8, m * 8, nrhs, hipMemcpyDeviceToDevice, s));
-    Plan P;
-    plan_apply(h, P, w, C, m, nrhs, 0);
-    P.upload(h->work);
-    execute(h, P, s);
-    if (resid_norms) {
+    auto apply = [&](double* C, int trans) {
+      Plan P;
+      plan_apply(h, P, w, C, m, nrhs, trans);
+      P.upload(h->work);
+      execute(h, P, s);
+    };
+    auto frob2 = [&](const double* C, int64_t ld, int64_t rows, double* out) {
       std::vector<Frob2Desc> fr(nrhs);
-      for (int c = 0; c < nrhs; ++c) fr[c] = Frob2Desc{C + n + (int64_t)c * m, m, (int)(m - n), 1, resid_norms + c};
+      for (int c = 0; c < nrhs; ++c) fr[c] = Frob2Desc{C + (int64_t)c * ld, ld, (int)rows, 1, out + c};
       Frob2Desc* dfr = (Frob2Desc*)h->work.alloc(nrhs * sizeof(Frob2Desc));
       HIPCHECK(hipMemcpy(dfr, fr.data(), nrhs * sizeof(Frob2Desc), hipMemcpyHostToDevice));
-      if (m > n) HIPCHECK(launch_frob2(dfr, nrhs, s));
-      else HIPCHECK(hipMemsetAsync(resid_norms, 0, nrhs * 8, s));
-    }
+      if (rows > 0) HIPCHECK(launch_frob2(dfr, nrhs, s));
+      else HIPCHECK(hipMemsetAsync(out, 0, nrhs * 8, s));
+    };
+    // Q^T B, then X = R^{-1} (Q^T B)[0:n]
+    double* C = (double*)h->work.alloc((size_t)m * nrhs * 8);
+    HIPCHECK(hipMemcpy2DAsync(C, m * 8, B, ldb * 8, m * 8, nrhs, hipMemcpyDeviceToDevice, s));
+    apply(C, 0);
+    if (resid_norms && max_refine == 0) frob2(C + n, m, m - n, resid_norms);
     HIPCHECK(hipMemcpy2DAsync(X, ldx * 8, C, m * 8, n * 8, nrhs, hipMemcpyDeviceToDevice, s));
-    // back-substitution through the BLR R
-    Plan Q;
-    double* Sx = (double*)h->work.alloc((size_t)q * rc * nrhs * 8);  // rc x nrhs per j
-    for (int k = q - 1; k >= 0; --k) {
-      double* Xk = X + (int64_t)k * b;
-      bool any_lr = false;
-      for (int j = k + 1; j < q; ++j) {
-        Tile& t = h->t(k, j);
-        if (t.fmt == LOWRANK) {
-          Q.gemm(Sx + (size_t)j * rc * nrhs, rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, t.Vt, rc,
-                 X + (int64_t)j * b, ldx, b, 0);
-          any_lr = true;
+    run_rsolve(h, X, ldx, nrhs, 0, s);
+    if (max_refine > 0) {
+      // iterative refinement of [I A~; A~^T 0][r; x] = [b; 0] with FP64 residuals
+      double* r = (double*)h->work.alloc((size_t)m * nrhs * 8);     // residual b - A~ x
+      double* f = (double*)h->work.alloc((size_t)m * nrhs * 8);
+      double* g = (double*)h->work.alloc((size_t)n * nrhs * 8);
+      double* dr = (double*)h->work.alloc((size_t)m * nrhs * 8);
+      double* nrm = (double*)h->work.alloc((size_t)2 * nrhs * 8);
+      // r = Q [0; (Q^T b)[n:m]]
+      HIPCHECK(launch_lincomb(r, m, C, m, nullptr, 0, nullptr, 0, 0.0, 0.0, 0.0, (int)n, nrhs, s));
+      HIPCHECK(launch_lincomb(r + n, m, C + n, m, nullptr, 0, nullptr, 0, 1.0, 0.0, 0.0, (int)(m - n), nrhs, s));
+      apply(r, 1);
+      const double u = 2.220446049250313e-16;
+      std::vector<double> hn(2 * nrhs);
+      for (int it = 0; it < max_refine; ++it) {
+        {  // f = b - r - A~ x,  g = -A~^T r
+          Plan P;
+          plan_matmul(h, P, BLR_MATMUL_A, X, ldx, f, m, nrhs);
+          plan_matmul(h, P, BLR_MATMUL_AT, r, m, g, n, nrhs);
+          P.upload(h->work);
+          execute(h, P, s);
         }
+        HIPCHECK(launch_lincomb(f, m, B, ldb, r, m, f, m, 1.0, -1.0, -1.0, (int)m, nrhs, s));
+        // d = Q^T f (in f);  h = R^{-T} g with g = -A~^T r (in g)
+        apply(f, 0);
+        HIPCHECK(launch_lincomb(g, n, g, n, nullptr, 0, nullptr, 0, -1.0, 0.0, 0.0, (int)n, nrhs, s));
+        run_rsolve(h, g, n, nrhs, 1, s);
+        // dr = Q [h; d_2]
+        HIPCHECK(launch_lincomb(dr, m, g, n, nullptr, 0, nullptr, 0, 1.0, 0.0, 0.0, (int)n, nrhs, s));
+        HIPCHECK(launch_lincomb(dr + n, m, f + n, m, nullptr, 0, nullptr, 0, 1.0, 0.0, 0.0, (int)(m - n), nrhs, s));
+        apply(dr, 1);
+        // dx = R^{-1} (d_1 - h)  (in f[0:n])
+        HIPCHECK(launch_lincomb(f, m, f, m, g, n, nullptr, 0, 1.0, -1.0, 0.0, (int)n, nrhs, s));
+        run_rsolve(h, f, m, nrhs, 0, s);
+        // x += dx, r += dr
+        HIPCHECK(launch_lincomb(X, ldx, X, ldx, f, m, nullptr, 0, 1.0, 1.0, 0.0, (int)n, nrhs, s));
+        HIPCHECK(launch_lincomb(r, m, r, m, dr, m, nullptr, 0, 1.0, 1.0, 0.0, (int)m, nrhs, s));
+        // stop once every column's correction is at the rounding level of x
+        frob2(f, m, n, nrm);
+        frob2(X, ldx, n, nrm + nrhs);
+        HIPCHECK(hipMemcpyAsync(hn.data(), nrm, 2 * nrhs * 8, hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        bool done = true;
+        for (int c = 0; c < nrhs; ++c) done = done && std::sqrt(hn[c]) <= 2.0 * u * std::sqrt(hn[nrhs + c]);
+        if (done) break;
       }
-      if (any_lr) Q.flush_gemm();
-      if (k + 1 < q) {
-        GemmDesc d{};
-        // multi-segment descriptor: X_k -= sum_j R_kj X_j
-        Q.cur.push_back(d);
-        GemmDesc& dd = Q.cur.back();
-        dd.C = Xk;
-        dd.ldc = ldx;
-        dd.Cin = Xk;
-        dd.ldcin = ldx;
-        dd.M = b;
-        dd.N = nrhs;
-        dd.alpha = -1.0;
-        dd.beta = 1.0;
-        dd.seg_begin = 0;
-        dd.nseg = q - k - 1;
-        for (int j = k + 1; j < q; ++j) {
-          Tile& t = h->t(k, j);
-          GemmSeg sg{};
-          if (t.fmt == DENSE) {
-            sg.A = t.D;
-            sg.lda = b;
-            sg.B = X + (int64_t)j * b;
-            sg.ldb = ldx;
-            sg.K = b;
-          } else {
-            sg.A = t.U;
-            sg.lda = b;
-            sg.B = Sx + (size_t)j * rc * nrhs;
-            sg.ldb = rc;
-            sg.K = rc;
-          }
-          Q.curseg.push_back(sg);
-          Q.curflops += 2.0 * b * nrhs * sg.K;
-        }
-        Q.flush_gemm();
-      }
-      Op o;
-      o.kind = Op::TRSM;
-      o.off = k;
-      Q.ops.push_back(o);
-    }
-    Q.upload(h->work);
-    for (const Op& o : Q.ops) {
-      if (o.kind == Op::TRSM) {
-        const int k = o.off;
-        HIPCHECK(launch_trsm_upper(h->t(k, k).D, b, b, X + (int64_t)k * b, ldx, nrhs, s));
-      } else {
-        HIPCHECK(launch_gemm(Q.d_descs + o.off, o.n, Q.d_segs, o.ntiles, o.big, 0, s));
-      }
+      if (resid_norms) frob2(r, m, m, resid_norms);
     }
     HIPCHECK(hipStreamSynchronize(s));
   });
@@ -1853,8 +2012,8 @@ blr_status blr_matmul(blr_matrix h, int32_t op, const double* X, int64_t ldx, do
   if (op == BLR_MATMUL_R) {
     if (h->state != BLR_STATE_FACTORED) return fail(BLR_ERR_STATE, "matrix is not factored");
     if (h->steps_done != h->q) return fail(BLR_ERR_STATE, "factorization is incomplete");
-  } else if (h->state != BLR_STATE_COMPRESSED) {
-    return fail(BLR_ERR_STATE, "the factorization has overwritten A");
+  } else if (h->state != BLR_STATE_COMPRESSED && h->acopy.empty()) {
+    return fail(BLR_ERR_STATE, "the factorization has overwritten A (factor with keep_a to keep a copy)");
   }
   const int64_t xr = op == BLR_MATMUL_AT ? h->m : h->n;
   const int64_t yr = op == BLR_MATMUL_A ? h->m : h->n;
@@ -1869,69 +2028,10 @@ blr_status blr_matmul(blr_matrix h, int32_t op, const double* X, int64_t ldx, do
   }
   hipStream_t s = as_stream(stream);
   return run_guarded([&] {
-    const int b = h->b, rc = h->rc, p = h->p, q = h->q;
     HIPCHECK(hipDeviceSynchronize());
     h->work.release();
-    // low-rank pre-products S_ij = V_ij^T X_j (A), U_ij^T X_i (A^T) or V_kj^T X_j (R)
-    const int rows = op == BLR_MATMUL_R ? q : p;
-    std::vector<int> slot((size_t)p * q, -1);
-    int nlr = 0;
-    for (int i = 0; i < rows; ++i)
-      for (int j = (op == BLR_MATMUL_R ? i + 1 : 0); j < q; ++j)
-        if (h->t(i, j).fmt == LOWRANK) slot[(size_t)i * q + j] = nlr++;
-    double* S = (double*)h->work.alloc((size_t)std::max(nlr, 1) * rc * nrhs * 8);
-    double* Dg = nullptr;
     Plan P;
-    if (op == BLR_MATMUL_R) {
-      Dg = (double*)h->work.alloc((size_t)q * b * b * 8);
-      std::vector<CopyDesc> cp;
-      for (int k = 0; k < q; ++k)
-        cp.push_back(CopyDesc{h->t(k, k).D, Dg + (size_t)k * b * b, (int64_t)b, (int64_t)b, b, b, 2, 0});
-      P.copy(cp);
-    }
-    auto Sp = [&](int i, int j) { return S + (size_t)slot[(size_t)i * q + j] * rc * nrhs; };
-    for (int i = 0; i < rows; ++i)
-      for (int j = 0; j < q; ++j) {
-        if (slot[(size_t)i * q + j] < 0) continue;
-        Tile& t = h->t(i, j);
-        if (op == BLR_MATMUL_AT)
-          P.gemm(Sp(i, j), rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, t.U, b, X + (int64_t)i * b, ldx, b,
-                 SEG_TRANS_A);
-        else
-          P.gemm(Sp(i, j), rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, t.Vt, rc, X + (int64_t)j * b, ldx, b, 0);
-      }
-    P.flush_gemm();
-    const int outs = op == BLR_MATMUL_A ? p : q;
-    for (int o = 0; o < outs; ++o) {
-      std::vector<GemmSeg> sv;
-      if (op == BLR_MATMUL_AT) {
-        for (int i = 0; i < p; ++i) {
-          Tile& t = h->t(i, o);
-          GemmSeg g{};
-          if (t.fmt == DENSE) {
-            g.A = t.D; g.lda = b; g.B = X + (int64_t)i * b; g.ldb = ldx; g.K = b; g.flags = SEG_TRANS_A;
-          } else {
-            g.A = t.Vt; g.lda = rc; g.B = Sp(i, o); g.ldb = rc; g.K = rc; g.flags = SEG_TRANS_A;
-          }
-          sv.push_back(g);
-        }
-      } else {
-        for (int j = (op == BLR_MATMUL_R ? o : 0); j < q; ++j) {
-          Tile& t = h->t(o, j);
-          GemmSeg g{};
-          if (op == BLR_MATMUL_R && j == o) {
-            g.A = Dg + (size_t)o * b * b; g.lda = b; g.B = X + (int64_t)j * b; g.ldb = ldx; g.K = b; g.flags = 0;
-          } else if (t.fmt == DENSE) {
-            g.A = t.D; g.lda = b; g.B = X + (int64_t)j * b; g.ldb = ldx; g.K = b; g.flags = 0;
-          } else {
-            g.A = t.U; g.lda = b; g.B = Sp(o, j); g.ldb = rc; g.K = rc; g.flags = 0;
-          }
-          sv.push_back(g);
-        }
-      }
-      P.gemm_multi(Y + (int64_t)o * b, ldy, nullptr, 0, b, nrhs, 1.0, 0.0, sv);
-    }
-    P.flush_gemm();
+    plan_matmul(h, P, op, X, ldx, Y, ldy, nrhs);
     P.upload(h->work);
     execute(h, P, s);
   });

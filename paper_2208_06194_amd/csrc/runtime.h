@@ -118,6 +118,8 @@ struct blr_matrix_s {
   int variant = 0, precision = 0, ib = 32;
   int steps_done = 0;
   std::vector<blr::Tile> tiles;          // p*q, i*q + j
+  std::vector<blr::Tile> acopy;          // copy of A~ kept by a factor with keep_a (else empty)
+  blr::Arena amem;                       // storage of acopy
   std::vector<int8_t> yfmt;              // p*q: format of Ytilde_ik after the factor
   std::vector<double*> T;                // p*q: T of tile (tiled) or of column (block column, at (k,k))
   std::vector<double*> tau;              // p*q

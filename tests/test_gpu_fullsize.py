@@ -1,0 +1,79 @@
+"""GPU checks at the benchmark's full sizes, in the launch configuration that
+bench.py times (131072 x 65536 block column, FP64 and mixed; 32768 x 16384
+tiled FP64).  The oracle cannot factor these, so the checks are properties
+that hold at any size:
+  * Res: ||(A~ - Q R) G||_F / ||A~ G||_F for Gaussian probes G (A~ G taken
+    before the in-place factorization) within 10x the compression tolerance;
+  * orthogonality of Q on probes, ||(Q^T Q - I) [G; 0]||;
+  * the first block column: R_00^T R_00 = A~_0^T A~_0 (A~_0 = A~[:, 0:b]),
+    which fixes R_00 up to the signs of its rows;
+  * R has a nonzero diagonal (the kernel matrices have full column rank)."""
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FULL = {
+    "c3": dict(m=131072, n=65536, b=1024, dim=3, kernel="inv_r", rule="dist_gt_diam", tol=1e-8, cap=50),
+    "c2": dict(m=32768, n=16384, b=256, dim=3, kernel="inv_r", rule="dist_gt_diam", tol=1e-8, cap=32),
+}
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2208_06194_amd as P
+    assert torch.cuda.is_available()
+    return P
+
+
+@pytest.mark.parametrize("cfg_id,variant,precision,tol", [
+    ("c3", "block_column", "fp64", 1e-8),
+    ("c3", "block_column", "mixed", 1e-6),
+    ("c2", "tiled", "fp64", 1e-8),
+])
+def test_full_size_factor_properties(P, cfg_id, variant, precision, tol):
+    cfg = FULL[cfg_id]
+    print("case: full size", cfg_id, variant, precision, tol, flush=True)
+    m, n, b = cfg["m"], cfg["n"], cfg["b"]
+    x, y = synth.kernel_points(0, m, n, cfg["dim"])
+    dev = torch.device("cuda")
+    G = P.BLRMatrix.compress_kernel(torch.tensor(x, device=dev), torch.tensor(y, device=dev), cfg["kernel"], b,
+                                    tol, cfg["cap"], admissibility=cfg["rule"], overflow="dense")
+    s = 8
+    probes = torch.tensor(synth.rhs(5, n, s), device=dev)
+    ax = G.matmul(probes, "A")
+    e0 = torch.zeros((n, b), dtype=torch.float64, device=dev)
+    e0[:b] = torch.eye(b, dtype=torch.float64, device=dev)
+    a0 = G.matmul(e0, "A")                       # A~[:, 0:b]
+    gram = (a0.t() @ a0).cpu().numpy()
+    del a0
+    G.factor(variant, precision)
+    torch.cuda.synchronize()
+    print("factored", flush=True)
+    # Res through the library's R and Q
+    rg = G.matmul(probes, "R")
+    pad = torch.zeros((m, s), dtype=torch.float64, device=dev)
+    pad[:n] = rg
+    qr = G.apply_qt(pad, trans=True)
+    res = float(torch.linalg.norm(qr - ax) / torch.linalg.norm(ax))
+    # orthogonality on the probes
+    pad.zero_()
+    pad[:n] = probes
+    back = G.apply_qt(G.apply_qt(pad, trans=True))
+    back[:n] -= probes
+    orth = float(torch.linalg.norm(back) / torch.linalg.norm(probes))
+    # first block column of R
+    r0 = G.matmul(e0, "R")[:b].cpu().numpy()
+    rel0 = np.linalg.norm(r0.T @ r0 - gram) / np.linalg.norm(gram)
+    diag = np.abs(np.diag(r0))
+    info = G.info()
+    print(f"Res {res:.2e}  orth {orth:.2e}  R00 gram {rel0:.2e}  min|R_jj| {diag.min():.2e}  "
+          f"tiles dense {info['n_dense']} lowrank {info['n_lowrank']} fill {info['n_fill_in']}", flush=True)
+    assert res <= 10 * tol
+    assert orth <= 1e-12
+    assert rel0 <= 10 * tol
+    assert np.all(np.triu(r0) == r0)
+    assert diag.min() > 0

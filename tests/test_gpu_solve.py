@@ -210,3 +210,45 @@ def test_matmul_matches_host_products(P, rule, kern, dim):
     assert np.linalg.norm(YR - Rg @ X) <= 1e-13 * np.linalg.norm(Rg) * np.linalg.norm(X)
     with pytest.raises(P.BLRError):
         G.matmul(torch.tensor(X, device="cuda"), "A")      # A~ was overwritten
+
+
+@pytest.mark.parametrize("variant", ["tiled", "block_column"])
+def test_refinement_recovers_fp64_accuracy_from_mixed_factor(P, variant):
+    """Least squares on a mixed-precision factor (FP32 MFMA updates): refining
+    the augmented system with FP64 residuals through the kept copy of A~
+    brings the solution from the FP32 level to the FP64 level of the exact
+    least-squares solution of A~ (LAPACK on the densified A~)."""
+    print("case: refinement", variant, flush=True)
+    m, n, b, eps, cap = 1024, 512, 128, 1e-10, 32
+    A, blr = kernel_blr(12, m, n, b, eps, cap)
+    At = blr.to_dense()
+    Bh = synth.rhs(12, m, 3)
+    Xr = np.linalg.lstsq(At, Bh, rcond=None)[0]
+    kappa = np.linalg.cond(At)
+    G = gpu_import(P, blr, eps, cap)
+    G.factor(variant, precision="mixed", keep_a=True)
+    Bd = torch.tensor(Bh, device="cuda")
+    X0 = G.lstsq(Bd).cpu().numpy()
+    e0 = np.linalg.norm(X0 - Xr) / np.linalg.norm(Xr)
+    X1, res = G.lstsq(Bd, with_resid=True, max_refine=10)
+    X1, res = X1.cpu().numpy(), res.cpu().numpy()
+    e1 = np.linalg.norm(X1 - Xr) / np.linalg.norm(Xr)
+    print(f"kappa {kappa:.2e}  unrefined {e0:.2e}  refined {e1:.2e}", flush=True)
+    assert e1 <= 100 * n * U * kappa
+    assert e1 <= e0 * 1e-3
+    # the reported residual norms are those of the refined solution
+    assert np.allclose(res, np.linalg.norm(Bh - At @ X1, axis=0), rtol=1e-8)
+    # products with A~ still work after the in-place factorization
+    Xp = synth.rhs(13, n, 2)
+    Y = G.matmul(torch.tensor(Xp, device="cuda"), "A").cpu().numpy()
+    assert np.linalg.norm(Y - At @ Xp) <= 1e-13 * np.linalg.norm(At) * np.linalg.norm(Xp)
+
+
+def test_refinement_requires_the_kept_copy(P):
+    m, n, b, eps, cap = 256, 128, 64, 1e-8, 16
+    A, blr = kernel_blr(14, m, n, b, eps, cap)
+    G = gpu_import(P, blr, eps, cap)
+    G.factor("block_column")
+    with pytest.raises(P.BLRError) as e:
+        G.lstsq(torch.tensor(synth.rhs(14, m, 1), device="cuda"), max_refine=2)
+    assert e.value.status == 2      # BLR_ERR_STATE
