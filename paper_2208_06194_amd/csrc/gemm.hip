@@ -202,7 +202,9 @@ typedef __attribute__((address_space(1))) const d2v gd2v;
 template <typename CT, bool TA, bool TB, bool ACC64, int BK>
 __device__ __forceinline__ void gemm_fast_body(const GemmDesc* __restrict__ descs, int ndesc,
                                                const GemmSeg* __restrict__ segs) {
-  constexpr int BM = 128, BN = 128, PAD = 2;
+  // row pad: a 144-element row stride puts the four K rows of one operand
+  // fragment read on disjoint LDS banks (FP64: halves, FP32: quarters)
+  constexpr int BM = 128, BN = 128, PAD = 16;
   constexpr int E = BK / 2;      // elements of each operand one thread moves per K step
   constexpr int NV = E / 2;      // ... as 16-byte vectors
   typedef typename AccT<CT>::T acc_t;

@@ -404,9 +404,18 @@ __global__ __launch_bounds__(256) void k_tall_step(TallArgs a) {
     constexpr int NS = 256 / IB;
     const int e = tid % IB, sl = tid / IB;
     const int per = (G + NS - 1) / NS;
-    double s = 0.0;
-    for (int q = sl * per; q < min(G, (sl + 1) * per); ++q) s += in[(int64_t)q * (2 * IB) + e];
-    acc[sl][e] = s;
+    const int qb = sl * per, qe = min(G, (sl + 1) * per);
+    // eight independent partial sums keep eight loads in flight
+    double s8[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s8[u] = 0.0;
+    int q = qb;
+    for (; q + 8 <= qe; q += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s8[u] += in[(int64_t)(q + u) * (2 * IB) + e];
+    }
+    for (; q < qe; ++q) s8[0] += in[(int64_t)q * (2 * IB) + e];
+    acc[sl][e] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
     __syncthreads();
     if (tid < IB) {
       double t = 0.0;

@@ -738,6 +738,7 @@ void plan_apply_tiled(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, in
 // rounded additions in order i = k, k+1, ...
 
 constexpr int kGramSlices = 16;
+constexpr int kApplySlices = 64;
 
 struct BcSlot {
   double *Ua, *Ub;   // b x rc
@@ -751,6 +752,9 @@ struct BcWork {
   double* Yf[2] = {nullptr, nullptr};  // b x b explicit unit-lower Y_kk (steps alternate)
   double* tallpart = nullptr;   // 2 x (kTallMaxGroups + 1) x 64
   double* gpart = nullptr;      // kGramSlices x b x b split-K Gram partials
+  double* wblk = nullptr;       // 128 x b: W of a block reflector
+  double* wblk2 = nullptr;      // 128 x b: T^T W
+  double* wpart = nullptr;      // kApplySlices x 128 x b split-K partials of W
   double* applypart = nullptr;  // 64 x ceil(b/32) x 32 x 32
   std::vector<BcSlot> slots;
 };
@@ -800,6 +804,9 @@ BcWork make_bc_work(blr_matrix h, int npairs) {
   bw.Yf[1] = (double*)A.alloc((size_t)b * b * 8);
   bw.tallpart = (double*)A.alloc((size_t)2 * (kTallMaxGroups + 1) * 64 * 8);
   bw.gpart = (double*)A.alloc((size_t)kGramSlices * b * b * 8);
+  bw.wblk = (double*)A.alloc((size_t)128 * b * 8);
+  bw.wblk2 = (double*)A.alloc((size_t)128 * b * 8);
+  bw.wpart = (double*)A.alloc((size_t)kApplySlices * 128 * b * 8);
   bw.applypart = (double*)A.alloc((size_t)64 * ((b + 31) / 32) * 32 * 32 * 8);
   const size_t rcwd = rc_work_doubles(b, rc);
   const size_t per = 2 * (size_t)b * rc + (size_t)rc * b + (size_t)rc * rc + rcwd;
@@ -820,85 +827,155 @@ BcWork make_bc_work(blr_matrix h, int npairs) {
 }
 
 // Householder QR of the hs x b stack (ld hs) into T (b x b) and tau.
+// Gram matrix G = Y^T Y (lower triangle valid) of the nw reflectors whose
+// pivot is X (unit lower in the first nw rows, h rows, ld ldx), split over
+// row slices so that tall stacks fill the chip: the first slice (which holds
+// the unit-lower block) on the masked kernel, the others as full products on
+// the fast kernel, summed by one reduction.
+void plan_gram(Plan& P, BcWork& bw, const double* X, int64_t ldx, int h, int nw, double* G, int64_t ldg) {
+  const int S = std::min(kGramSlices, std::max(1, h / 4096));
+  // slice length: a multiple of 16 rounded up, so at most S slices
+  const int ks = std::max(nw, ((h + S - 1) / S + 15) / 16 * 16);
+  int ns = 0;
+  for (int r0 = 0; r0 < h; r0 += ks) {
+    const int kk = std::min(ks, h - r0);
+    double* out = S == 1 ? G : bw.gpart + (size_t)ns * nw * nw;
+    const int64_t ldo = S == 1 ? ldg : nw;
+    if (r0 == 0) {
+      P.gemm(out, ldo, nullptr, 0, nullptr, 0, nw, nw, 1.0, 0.0, X, ldx, X, ldx, kk,
+             SEG_TRANS_A | SEG_A_UNIT_LOWER | SEG_B_UNIT_LOWER, DESC_LOWER_ONLY);
+      P.flush_gemm();
+    } else {
+      P.gemm(out, ldo, nullptr, 0, nullptr, 0, nw, nw, 1.0, 0.0, X + r0, ldx, X + r0, ldx, kk, SEG_TRANS_A);
+    }
+    ++ns;
+  }
+  P.flush_gemm();
+  if (ns > 1) P.copy({CopyDesc{bw.gpart, G, (int64_t)nw, ldg, nw, nw, 0, ns, (int64_t)nw * nw}});
+}
+
+// T of the nw reflectors at X (into T, ld ldt; its ib x ib diagonal blocks
+// already hold the panel kernels' T blocks): Gram matrix and back-substitution.
+void plan_block_t(Plan& P, Work& w, BcWork& bw, const double* X, int64_t ldx, int h, int nw, int ib,
+                  const double* tau, double* T, int64_t ldt) {
+  plan_gram(P, bw, X, ldx, h, nw, w.Wg, nw);
+  TBackArgs t{};
+  t.n = nw;
+  t.ib = ib;
+  t.G = w.Wg;
+  t.ldg = nw;
+  t.tau = tau;
+  t.T = T;
+  t.ldt = ldt;
+  P.tback(t);
+  P.ops.back().flops = (double)nw * nw * nw / 3.0;
+}
+
+// C <- (I - Y T Y^T)^T C for the nw reflectors Y at X (h rows, unit lower
+// in the first nw rows) and the nt columns C (same rows, ld ldx):
+// W = Y^T C split over row slices (masked first slice, fast full products
+// after it, one reduction), W2 = T^T W, C -= Y W2 (the unit-lower top block
+// on the masked kernel, the rows below on the fast kernel).
+void plan_block_apply(Plan& P, BcWork& bw, const double* X, double* C, int64_t ldx, int h, int nw, int nt,
+                      const double* T, int64_t ldt) {
+  const int S = std::min(kApplySlices, std::max(1, h / 2048));
+  const int ks = std::max(nw, ((h + S - 1) / S + 15) / 16 * 16);
+  int ns = 0;
+  for (int r0 = 0; r0 < h; r0 += ks) {
+    const int kk = std::min(ks, h - r0);
+    double* out = S == 1 ? bw.wblk : bw.wpart + (size_t)ns * nw * nt;
+    if (r0 == 0) {
+      P.gemm(out, nw, nullptr, 0, nullptr, 0, nw, nt, 1.0, 0.0, X, ldx, C, ldx, kk, SEG_TRANS_A | SEG_A_UNIT_LOWER);
+      P.flush_gemm();
+    } else {
+      P.gemm(out, nw, nullptr, 0, nullptr, 0, nw, nt, 1.0, 0.0, X + r0, ldx, C + r0, ldx, kk, SEG_TRANS_A);
+    }
+    ++ns;
+  }
+  P.flush_gemm();
+  if (ns > 1) P.copy({CopyDesc{bw.wpart, bw.wblk, (int64_t)nw, (int64_t)nw, nw, nt, 0, ns, (int64_t)nw * nt}});
+  P.gemm(bw.wblk2, nw, nullptr, 0, nullptr, 0, nw, nt, 1.0, 0.0, T, ldt, bw.wblk, nw, nw, SEG_TRANS_A | SEG_A_UPPER);
+  P.flush_gemm();
+  // rows [0, nw): unit-lower Y block; the rows below in a 128-multiple bulk and a ragged rest
+  const int rest = h - nw;
+  const int bulk = rest / 128 * 128;
+  P.gemm(C, ldx, C, ldx, nullptr, 0, nw, nt, -1.0, 1.0, X, ldx, bw.wblk2, nw, nw, SEG_A_UNIT_LOWER);
+  if (rest > bulk)
+    P.gemm(C + nw + bulk, ldx, C + nw + bulk, ldx, nullptr, 0, rest - bulk, nt, -1.0, 1.0, X + nw + bulk, ldx,
+           bw.wblk2, nw, nw, 0);
+  P.flush_gemm();
+  if (bulk > 0) {
+    P.gemm(C + nw, ldx, C + nw, ldx, nullptr, 0, bulk, nt, -1.0, 1.0, X + nw, ldx, bw.wblk2, nw, nw, 0);
+    P.flush_gemm();
+  }
+}
+
+// Householder QR of the hs x b stack (ld hs) into T (b x b) and tau.
+// Stacks of up to 512 (ib 32) or 1024 (ib 16) rows stay in the registers of
+// the one-workgroup panel kernel.  Taller stacks: 32-column sub-panels by
+// the row-split column kernels, each applied within its 128-column block by
+// the split-K sub-panel update; each finished 128-column block is applied to
+// the rest of the stack as a block reflector on the matrix cores.
 void plan_stack_qr(Plan& P, blr_matrix h, Work& w, BcWork& bw, int hs, double* T, double* tau) {
   const int b = h->b;
   double* X = bw.stack;
-  // stacks of up to 512 (ib 32) or 1024 (ib 16) rows stay in the registers
-  // of the one-workgroup panel kernel; taller ones use the row-split kernels
   const bool tall = hs > 1024;
   int ib = (hs > 512 && !tall) ? 16 : 32;
   if (b % ib) ib = 16;
   ib = std::min(ib, b);
-  for (int c0 = 0; c0 < b; c0 += ib) {
-    const int hl = hs - c0;
-    const int nt = b - c0 - ib;
-    PanelArgs a{};
-    a.mode = PANEL_GEQRT;
-    a.ib = ib;
-    a.h = hl;
-    a.X = X + c0 + (int64_t)c0 * hs;
-    a.ldx = hs;
-    a.T = T + c0 + (int64_t)c0 * b;
-    a.ldt = b;
-    a.tau = tau + c0;
-    if (!tall) {
-      P.panel(a);
-      P.ops.back().flops = 2.0 * hl * ib * ib;
-      if (nt > 0) {
-        P.panel_apply(a, nt);
-        P.ops.back().flops = 4.0 * hl * ib * nt;
+  const int OB = (tall && b % 128 == 0) ? 128 : b;   // outer block of the tall path
+  for (int o0 = 0; o0 < b; o0 += OB) {
+    const int oend = std::min(b, o0 + OB);
+    for (int c0 = o0; c0 < oend; c0 += ib) {
+      const int hl = hs - c0;
+      const int nt = (tall ? oend : b) - c0 - ib;
+      PanelArgs a{};
+      a.mode = PANEL_GEQRT;
+      a.ib = ib;
+      a.h = hl;
+      a.X = X + c0 + (int64_t)c0 * hs;
+      a.ldx = hs;
+      a.T = T + c0 + (int64_t)c0 * b;
+      a.ldt = b;
+      a.tau = tau + c0;
+      if (!tall) {
+        P.panel(a);
+        P.ops.back().flops = 2.0 * hl * ib * ib;
+        if (nt > 0) {
+          P.panel_apply(a, nt);
+          P.ops.back().flops = 4.0 * hl * ib * nt;
+        }
+      } else {
+        const int G = std::min(kTallMaxGroups, std::max(1, (hl + 511) / 512));
+        for (int jj = 0; jj < ib; ++jj) {
+          Op o;
+          o.kind = Op::TALL_COL;
+          o.tall = TallArgs{a.X, (int64_t)hs, hl, ib, jj, bw.tallpart, a.T, (int64_t)b, a.tau};
+          o.n = G;
+          o.flops = 4.0 * hl * ib;
+          P.push(o);
+        }
+        if (nt > 0) {
+          Op o;
+          o.kind = Op::TALL_APPLY;
+          o.panel = a;
+          o.ntiles = nt;
+          o.n = std::min(64, std::max(1, hl / 2048));
+          o.buf = bw.applypart;
+          o.flops = 4.0 * hl * ib * nt;
+          P.push(o);
+        }
       }
-    } else {
-      const int G = std::min(kTallMaxGroups, std::max(1, (hl + 511) / 512));
-      for (int jj = 0; jj < ib; ++jj) {
-        Op o;
-        o.kind = Op::TALL_COL;
-        o.tall = TallArgs{a.X, (int64_t)hs, hl, ib, jj, bw.tallpart, a.T, (int64_t)b, a.tau};
-        o.n = G;
-        o.flops = 4.0 * hl * ib;
-        P.push(o);
-      }
-      if (nt > 0) {
-        Op o;
-        o.kind = Op::TALL_APPLY;
-        o.panel = a;
-        o.ntiles = nt;
-        o.n = std::min(64, std::max(1, hl / 2048));
-        o.buf = bw.applypart;
-        o.flops = 4.0 * hl * ib * nt;
-        P.push(o);
-      }
+    }
+    const int ntr = b - oend;
+    if (tall && OB < b && ntr > 0) {
+      const int ho = hs - o0;
+      double* Xo = X + o0 + (int64_t)o0 * hs;
+      plan_block_t(P, w, bw, Xo, hs, ho, OB, ib, tau + o0, T + o0 + (int64_t)o0 * b, b);
+      plan_block_apply(P, bw, Xo, Xo + (int64_t)OB * hs, hs, ho, OB, ntr, T + o0 + (int64_t)o0 * b, b);
     }
   }
-  if (b > ib) {
-    // Gram matrix Y^T Y of the stack's reflectors (lower triangle), split
-    // over row slices so that a tall stack fills the chip; the first slice
-    // holds the unit-lower diagonal block
-    const int S = std::min(kGramSlices, std::max(1, hs / 4096));
-    const int ks = std::max(b, (hs + S - 1) / S);
-    int ns = 0;
-    for (int r0 = 0; r0 < hs; r0 += ks, ++ns) {
-      const int kk = std::min(ks, hs - r0);
-      const int fl = r0 == 0 ? (SEG_TRANS_A | SEG_A_UNIT_LOWER | SEG_B_UNIT_LOWER) : SEG_TRANS_A;
-      P.gemm(S == 1 ? w.Wg : bw.gpart + (size_t)ns * b * b, b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, X + r0, hs,
-             X + r0, hs, kk, fl, DESC_LOWER_ONLY);
-    }
-    P.flush_gemm();
-    if (S > 1) {
-      CopyDesc c{bw.gpart, w.Wg, (int64_t)b, (int64_t)b, b, b, 0, ns, (int64_t)b * b};
-      P.copy({c});
-    }
-    TBackArgs t{};
-    t.n = b;
-    t.ib = ib;
-    t.G = w.Wg;
-    t.ldg = b;
-    t.tau = tau;
-    t.T = T;
-    t.ldt = b;
-    P.tback(t);
-    P.ops.back().flops = (double)b * b * b / 3.0;
-  }
+  if (b > ib) plan_block_t(P, w, bw, X, hs, hs, b, ib, tau, T, b);
 }
 
 // Panel of block-column step k (Section 3.3.1): gather the stack
@@ -947,8 +1024,11 @@ void plan_bc_panel(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k) {
 // (Section 3.3.2): Z_j = sum_i Ytilde_ik^T A_ij, W_j = T_k^T Z_j and
 // A_ij -= Ytilde_ik W_j with the OP1/OP2 rules: Z_j is dense if any term is
 // dense, else the low-rank terms are summed by rounded additions in order
-// i = k, k+1, ...
-void plan_bc_update(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k, int j0, int j1, bool fp32) {
+// i = k, k+1, ...  Z and W are formed for every column first; the updates
+// A_ij -= Ytilde_ik W_j then run for the columns below jsplit, mid() is
+// called (the look-ahead hook), and the remaining columns follow.
+void plan_bc_update(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k, int j0, int j1, bool fp32,
+                    int jsplit, const std::function<void()>& mid) {
   const int b = h->b, rc = h->rc, p = h->p, q = h->q;
   if (j0 >= j1) return;
   std::vector<bool> yd(p, true);
@@ -1054,76 +1134,85 @@ void plan_bc_update(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k, int j0, i
                 SEG_TRANS_A | SEG_A_UPPER);
   }
   P.flush_gemm(fp32, 1);
-  // 6. fill-in: low-rank targets of a dense update become dense (OP1)
-  for (int j = j0; j < j1; ++j)
-    for (int i = k; i < p; ++i) {
-      Tile& A = h->t(i, j);
-      if (zd[j] && yd[i] && A.fmt == LOWRANK) {
-        P.gemm(A.D, b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, A.U, b, A.Vt, rc, rc, 0);
-        A.fmt = DENSE;
-        h->n_fill++;
+  // stages 6-7 for the columns [ja, jb)
+  auto apply_cols = [&](int ja, int jb) {
+    if (ja >= jb) return;
+    // 6. fill-in: low-rank targets of a dense update become dense (OP1)
+    for (int j = ja; j < jb; ++j)
+      for (int i = k; i < p; ++i) {
+        Tile& A = h->t(i, j);
+        if (zd[j] && yd[i] && A.fmt == LOWRANK) {
+          P.gemm(A.D, b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, A.U, b, A.Vt, rc, rc, 0);
+          A.fmt = DENSE;
+          h->n_fill++;
+        }
       }
-    }
-  P.flush_gemm(fp32);
-  // 7. updates A_ij -= Ytilde_ik W_j
-  for (int j = j0; j < j1; ++j)
-    for (int i = k; i < p; ++i)
-      if (yd[i] && zd[j])
-        P.gemm(h->t(i, j).D, b, h->t(i, j).D, b, nullptr, 0, b, b, -1.0, 1.0, Yd(i), b, w.X2[j], b, b, 0);
-  P.flush_gemm(fp32, 1);
-  for (int j = j0; j < j1; ++j)
-    for (int i = k; i < p; ++i) {
-      if (yd[i] && zd[j]) continue;
-      BcSlot& sl = S(i, j);
-      if (!yd[i] && zd[j])
-        P.gemm(sl.Sa, rc, nullptr, 0, nullptr, 0, rc, b, 1.0, 0.0, h->t(i, k).Vt, rc, w.X2[j], b, b, 0);
-      else if (yd[i])
-        P.gemm(sl.Ub, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, Yd(i), b, w.WU[j], b, b, 0);
-      else
-        P.gemm(sl.Sm, rc, nullptr, 0, nullptr, 0, rc, rc, 1.0, 0.0, h->t(i, k).Vt, rc, w.WU[j], b, b, 0);
-    }
-  P.flush_gemm();
-  for (int j = j0; j < j1; ++j)
-    for (int i = k + 1; i < p; ++i)
-      if (!yd[i] && !zd[j]) {
+    P.flush_gemm(fp32);
+    // 7. updates A_ij -= Ytilde_ik W_j
+    for (int j = ja; j < jb; ++j)
+      for (int i = k; i < p; ++i)
+        if (yd[i] && zd[j])
+          P.gemm(h->t(i, j).D, b, h->t(i, j).D, b, nullptr, 0, b, b, -1.0, 1.0, Yd(i), b, w.X2[j], b, b, 0);
+    P.flush_gemm(fp32, 1);
+    for (int j = ja; j < jb; ++j)
+      for (int i = k; i < p; ++i) {
+        if (yd[i] && zd[j]) continue;
         BcSlot& sl = S(i, j);
-        P.gemm(sl.Ub, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, h->t(i, k).U, b, sl.Sm, rc, rc, 0);
+        if (!yd[i] && zd[j])
+          P.gemm(sl.Sa, rc, nullptr, 0, nullptr, 0, rc, b, 1.0, 0.0, h->t(i, k).Vt, rc, w.X2[j], b, b, 0);
+        else if (yd[i])
+          P.gemm(sl.Ub, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, Yd(i), b, w.WU[j], b, b, 0);
+        else
+          P.gemm(sl.Sm, rc, nullptr, 0, nullptr, 0, rc, rc, 1.0, 0.0, h->t(i, k).Vt, rc, w.WU[j], b, b, 0);
       }
-  P.flush_gemm();
-  for (int j = j0; j < j1; ++j)
-    for (int i = k; i < p; ++i) {
-      if (yd[i] && zd[j]) continue;
-      Tile& A = h->t(i, j);
-      BcSlot& sl = S(i, j);
-      // the update as a low-rank product Uu Vu^T
-      const double* Uu;
-      const double* Vu;
-      const int* ru;
-      if (!yd[i] && zd[j]) { Uu = h->t(i, k).U; Vu = sl.Sa; ru = h->t(i, k).rank; }
-      else { Uu = sl.Ub; Vu = zterm[j].Vt; ru = zterm[j].rank_ptr; }
-      if (A.fmt == DENSE) {
-        P.gemm(A.D, b, A.D, b, nullptr, 0, b, b, -1.0, 1.0, Uu, b, Vu, rc, rc, 0);
-      } else {
-        RcDesc d{};
-        d.nterm = 2;
-        d.t[0] = RcTerm{A.U, A.Vt, A.rank, b, rc, 0, 0, 1.0};
-        d.t[1] = RcTerm{Uu, Vu, ru, b, rc, 0, 0, -1.0};
-        d.Uout = A.U;
-        d.Vtout = A.Vt;
-        d.rank_out = A.rank;
-        d.work = sl.rcw;
-        P.rc(d);
+    P.flush_gemm();
+    for (int j = ja; j < jb; ++j)
+      for (int i = k + 1; i < p; ++i)
+        if (!yd[i] && !zd[j]) {
+          BcSlot& sl = S(i, j);
+          P.gemm(sl.Ub, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, h->t(i, k).U, b, sl.Sm, rc, rc, 0);
+        }
+    P.flush_gemm();
+    for (int j = ja; j < jb; ++j)
+      for (int i = k; i < p; ++i) {
+        if (yd[i] && zd[j]) continue;
+        Tile& A = h->t(i, j);
+        BcSlot& sl = S(i, j);
+        // the update as a low-rank product Uu Vu^T
+        const double* Uu;
+        const double* Vu;
+        const int* ru;
+        if (!yd[i] && zd[j]) { Uu = h->t(i, k).U; Vu = sl.Sa; ru = h->t(i, k).rank; }
+        else { Uu = sl.Ub; Vu = zterm[j].Vt; ru = zterm[j].rank_ptr; }
+        if (A.fmt == DENSE) {
+          P.gemm(A.D, b, A.D, b, nullptr, 0, b, b, -1.0, 1.0, Uu, b, Vu, rc, rc, 0);
+        } else {
+          RcDesc d{};
+          d.nterm = 2;
+          d.t[0] = RcTerm{A.U, A.Vt, A.rank, b, rc, 0, 0, 1.0};
+          d.t[1] = RcTerm{Uu, Vu, ru, b, rc, 0, 0, -1.0};
+          d.Uout = A.U;
+          d.Vtout = A.Vt;
+          d.rank_out = A.rank;
+          d.work = sl.rcw;
+          P.rc(d);
+        }
       }
-    }
-  P.flush_gemm(fp32);
-  P.flush_rc();
+    P.flush_gemm(fp32);
+    P.flush_rc();
+  };
+  apply_cols(j0, std::min(jsplit, j1));
+  if (mid) mid();
+  apply_cols(std::max(jsplit, j0), j1);
 }
 
 // Block-column BLR-QR (Alg. 2 with Section 3.3).  Look-ahead: stream 0 runs
-// the trailing updates, stream 1 the panels.  Step k first updates column
-// k + 1 and records E_col(k); the panel of column k + 1 waits for it and runs
-// beside the rest of step k's update; step k + 1 waits for E_panel(k + 1).
-// The two steps' explicit Y_kk copies alternate between two buffers.
+// the trailing updates, stream 1 the panels.  Step k forms Z_j and W_j for
+// every column, updates column k + 1 and records E_col(k); the panel of
+// column k + 1 waits for it and runs beside the rest of step k's update
+// (short-lived workgroups, so the panel's small launches find free compute
+// units); step k + 1 waits for E_panel(k + 1).  The two steps' explicit
+// Y_kk copies alternate between two buffers.
 void plan_blockcol(blr_matrix h, Plan& P, Work& w, BcWork& bw, int kend, bool fp32, bool lookahead) {
   const int q = h->q;
   auto e_panel = [&](int k) { return k; };
@@ -1137,16 +1226,16 @@ void plan_blockcol(blr_matrix h, Plan& P, Work& w, BcWork& bw, int kend, bool fp
     P.cur_stream = 0;
     P.wait(e_panel(k));
     if (k + 1 >= q) continue;
-    plan_bc_update(h, P, w, bw, k, k + 1, k + 2, fp32);
-    if (k + 1 < kend) {
+    auto next_panel = [&]() {
+      if (k + 1 >= kend) return;
       P.record(e_col(k));
       P.cur_stream = ps;
       P.wait(e_col(k));
       plan_bc_panel(h, P, w, bw, k + 1);
       P.record(e_panel(k + 1));
       P.cur_stream = 0;
-    }
-    plan_bc_update(h, P, w, bw, k, k + 2, q, fp32);
+    };
+    plan_bc_update(h, P, w, bw, k, k + 1, q, fp32, k + 2, next_panel);
   }
   P.cur_stream = 0;
 }

@@ -2,8 +2,9 @@
 application (Alg. 3): the HIP path through the C ABI against the oracle's
 block-column factor on the same seeded inputs.  Stacks of up to 512 rows
 take the one-workgroup panel kernel with 32-column panels, up to 1024 rows
-with 16-column panels, taller stacks the row-split kernels: the shapes below
-cover all three and ragged stacks of low-rank row factors."""
+with 16-column panels, taller stacks the row-split kernels (and, for tiles of
+256 or more columns, 128-column blocks applied as block reflectors): the
+shapes below cover all of them and ragged stacks of low-rank row factors."""
 import numpy as np
 import pytest
 
@@ -42,13 +43,15 @@ def kernel_blr(seed, m, n, b, eps, cap, kern="inv_r", dim=3, rule="dist_gt_diam"
     (192, 96, 48),      # b not a multiple of 32
     (2048, 128, 64),    # stacks of 2048 .. 1984 rows: row-split panels
     (1536, 512, 128),   # tall first stacks, register panels for the last
+    (2048, 512, 256),   # tall stacks with b = 256: 128-column blocks applied as block reflectors
 ])
 def test_all_dense_blockcol_matches_oracle(P, m, n, b):
     print("case: blockcol all dense", m, n, b, flush=True)
     A = np.random.default_rng(7 * m + b).standard_normal((m, n))
-    blr = blrmat.compress(A, b, 1e-12, b, np.zeros((m // b, n // b), bool))
-    f = blockcol.factor(blr, 1e-12, b)
-    G = gpu_import(P, blr, 1e-12, b)
+    cap = min(b, 128)
+    blr = blrmat.compress(A, b, 1e-12, cap, np.zeros((m // b, n // b), bool))
+    f = blockcol.factor(blr, 1e-12, cap)
+    G = gpu_import(P, blr, 1e-12, cap)
     G.factor("block_column")
     ex = G.export(with_factor=True)
     kappa = np.linalg.cond(A)
@@ -79,6 +82,7 @@ CASES = [
     (1, 512, 256, 32, 1e-8, 32, "inv_r", 3, "dist_gt_diam"),
     (2, 384, 192, 48, 1e-6, 16, "log2d", 2, "weak"),
     (3, 2048, 512, 64, 1e-8, 32, "inv_r", 3, "dist_gt_diam"),
+    (4, 4096, 1024, 256, 1e-8, 32, "inv_r", 3, "dist_gt_diam"),
 ]
 
 
