@@ -115,8 +115,14 @@ void Plan::gemm_multi(double* C, int64_t ldc, const double* Cin, int64_t ldcin, 
 void Plan::flush_gemm(int fp32, int prof, bool allow_fast) {
   if (cur.empty()) return;
   int mn = 1 << 30;
-  for (auto& d : cur) mn = std::min(mn, std::min(d.M, d.N));
-  int big = mn >= 256 ? GEMM_BIG : GEMM_SMALL;
+  int64_t tiles128 = 0;
+  for (auto& d : cur) {
+    mn = std::min(mn, std::min(d.M, d.N));
+    tiles128 += (int64_t)((d.M + 127) / 128) * ((d.N + 127) / 128);
+  }
+  // 128 x 128 tiles when every product has at least one full tile and the
+  // batch has enough of them to fill the chip; 64 x 64 tiles otherwise
+  int big = (mn >= 256 || (mn >= 128 && tiles128 >= 128)) ? GEMM_BIG : GEMM_SMALL;
   if (big == GEMM_BIG && allow_fast) {
     // fast path: full tiles, single uniform segment, aligned, no masks
     bool ok = true;
