@@ -210,15 +210,16 @@ void blr_destroy(blr_matrix h);
 const char* blr_status_string(blr_status s);
 const char* blr_last_error(void);
 
-/* Kernel-level timing of the next blr_qr_factor on this handle: when enabled,
- * HIP events bracket every launch of the dominant kernel, the untransposed
- * 128 x 128 matrix-core product of the trailing updates (k_gemm_fast with
- * FP64 operands, or FP32 operands under BLR_MIXED_FP32), on the stream it is
- * launched on.  After the factor,
- * blr_profile_read returns the number of such launches, their total device
- * time in milliseconds and their total algorithmic flops.  Synchronises. */
+/* Kernel-level timing of the dominant kernel, the untransposed 128 x 128
+ * matrix-core product (k_gemm_fast<double|float, false, false>: trailing
+ * updates and block-reflector applications).  While enabled, HIP events
+ * bracket every launch of it on this handle, on the stream it runs on
+ * (blr_qr_factor clears the record first).  blr_profile_read returns, for
+ * kernel 0 (FP64 operands) or 1 (FP32 operands), the number of launches,
+ * their total device time in milliseconds and their total algorithmic flops.
+ * Synchronises. */
 blr_status blr_profile_enable(blr_matrix h, int32_t on);
-blr_status blr_profile_read(blr_matrix h, int64_t* launches, double* total_ms,
+blr_status blr_profile_read(blr_matrix h, int32_t kernel, int64_t* launches, double* total_ms,
                             double* total_flops);
 
 #ifdef __cplusplus

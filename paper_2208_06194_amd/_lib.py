@@ -85,7 +85,7 @@ def load() -> ctypes.CDLL:
     lib.blr_last_error.argtypes = []
     lib.blr_last_error.restype = ctypes.c_char_p
     lib.blr_profile_enable.argtypes = [c_void_p, c_int32]
-    lib.blr_profile_read.argtypes = [c_void_p, P(c_int64), P(c_double), P(c_double)]
+    lib.blr_profile_read.argtypes = [c_void_p, c_int32, P(c_int64), P(c_double), P(c_double)]
     lib.blr_selftest_gemm.argtypes = [c_int32, c_int32, c_int32, c_int32, c_double, c_void_p, c_int64,
                                       c_void_p, c_int64, c_double, c_void_p, c_int64, c_int32, c_void_p]
     lib.blr_selftest_gemm.restype = c_int32

@@ -192,7 +192,10 @@ class BLRMatrix:
     def profile(self, on: bool = True):
         _check(L.load().blr_profile_enable(self._h, 1 if on else 0))
 
-    def profile_read(self):
+    def profile_read(self, kernel: str = "fp64"):
+        """(launches, total ms, total flops) of the dominant kernel with FP64
+        ("fp64") or FP32 ("fp32") operands in the last profiled factor."""
         n, ms, fl = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
-        _check(L.load().blr_profile_read(self._h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)))
+        _check(L.load().blr_profile_read(self._h, 0 if kernel == "fp64" else 1, ctypes.byref(n),
+                                         ctypes.byref(ms), ctypes.byref(fl)))
         return n.value, ms.value, fl.value

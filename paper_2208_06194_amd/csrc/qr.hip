@@ -355,7 +355,7 @@ __device__ __forceinline__ void tall_rows(int h, int G, int g, int* rs, int* re)
   *re = min(h, *rs + chunk);
 }
 
-template <int IB>
+template <int IB, int NT>
 __device__ __forceinline__ void tall_store_partials(double (&part)[IB], double (*red)[IB], double* out, int g) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
 #pragma unroll
@@ -364,12 +364,18 @@ __device__ __forceinline__ void tall_store_partials(double (&part)[IB], double (
     if (lane == 0) red[w][t] = s;
   }
   __syncthreads();
-  if (tid < IB) out[(int64_t)g * (2 * IB) + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+  if (tid < IB) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < NT / 64; ++q) s += red[q][tid];
+    out[(int64_t)g * (2 * IB) + tid] = s;
+  }
 }
 
 template <int IB>
-__global__ __launch_bounds__(256) void k_tall_first(TallArgs a) {
-  __shared__ double red[4][IB];
+__global__ __launch_bounds__(kTallThreads) void k_tall_first(TallArgs a) {
+  constexpr int NT = kTallThreads;
+  __shared__ double red[NT / 64][IB];
   const int tid = threadIdx.x, G = gridDim.x, g = blockIdx.x;
   const int64_t ld = a.ldx;
   int rs, re;
@@ -378,21 +384,22 @@ __global__ __launch_bounds__(256) void k_tall_first(TallArgs a) {
   double part[IB];
 #pragma unroll
   for (int t = 0; t < IB; ++t) part[t] = 0.0;
-  for (int r = max(rs, 1) + tid; r < re; r += 256) {
+  for (int r = max(rs, 1) + tid; r < re; r += NT) {
     const double v = a.X[r];
 #pragma unroll
     for (int t = 0; t < IB; ++t) part[t] += (t == 0) ? v * v : v * a.X[r + (int64_t)t * ld];
   }
-  tall_store_partials<IB>(part, red, out, g);
+  tall_store_partials<IB, NT>(part, red, out, g);
   if (rs == 0 && re > 0 && tid < IB) out[(int64_t)G * (2 * IB) + tid] = a.X[(int64_t)tid * ld];
 }
 
 template <int IB>
-__global__ __launch_bounds__(256) void k_tall_step(TallArgs a) {
-  __shared__ double acc[256 / IB][2 * IB];
+__global__ __launch_bounds__(kTallThreads) void k_tall_step(TallArgs a) {
+  constexpr int NT = kTallThreads;
+  __shared__ double acc[NT / IB][2 * IB];
   __shared__ double sv[2 * IB];   // [0, IB): dots of column jj (its tail sum of squares at jj); [IB, 2 IB): pivot row
   __shared__ double wv[IB];
-  __shared__ double red[4][IB];
+  __shared__ double red[NT / 64][IB];
   const int tid = threadIdx.x, G = gridDim.x, g = blockIdx.x;
   const int jj = a.jj;
   const int64_t ld = a.ldx;
@@ -401,7 +408,7 @@ __global__ __launch_bounds__(256) void k_tall_step(TallArgs a) {
   double* out = a.part + ((jj + 1) & 1) * bufsz;
   // 1. sum the partials of column jj (fixed order: slice of groups per thread, then slices)
   {
-    constexpr int NS = 256 / IB;
+    constexpr int NS = NT / IB;
     const int e = tid % IB, sl = tid / IB;
     const int per = (G + NS - 1) / NS;
     const int qb = sl * per, qe = min(G, (sl + 1) * per);
@@ -437,7 +444,7 @@ __global__ __launch_bounds__(256) void k_tall_step(TallArgs a) {
 #pragma unroll
   for (int t = 0; t < IB; ++t) part[t] = 0.0;
   // 2. reflector column jj and rank-one update of the later columns on this group's rows
-  for (int r = max(rs, jj + 1) + tid; r < re; r += 256) {
+  for (int r = max(rs, jj + 1) + tid; r < re; r += NT) {
     // (register arrays are indexed by unrolled constants only: selects, no dynamic indexing)
     double x[IB];
 #pragma unroll
@@ -484,7 +491,7 @@ __global__ __launch_bounds__(256) void k_tall_step(TallArgs a) {
     }
   }
   // 4. partials of the next column
-  if (more) tall_store_partials<IB>(part, red, out, g);
+  if (more) tall_store_partials<IB, NT>(part, red, out, g);
 }
 
 // Split-K trailing update of a tall panel (V unit lower, h rows, IB columns)
@@ -645,11 +652,11 @@ __global__ void k_copy_blocks(const CopyDesc* __restrict__ d) {
 hipError_t launch_tall_column(const TallArgs& a, int groups, hipStream_t stream) {
   if (groups < 1 || groups > kTallMaxGroups) return hipErrorInvalidValue;
   if (a.ib == 32) {
-    if (a.jj == 0) hipLaunchKernelGGL(k_tall_first<32>, dim3(groups), dim3(256), 0, stream, a);
-    hipLaunchKernelGGL(k_tall_step<32>, dim3(groups), dim3(256), 0, stream, a);
+    if (a.jj == 0) hipLaunchKernelGGL(k_tall_first<32>, dim3(groups), dim3(kTallThreads), 0, stream, a);
+    hipLaunchKernelGGL(k_tall_step<32>, dim3(groups), dim3(kTallThreads), 0, stream, a);
   } else if (a.ib == 16) {
-    if (a.jj == 0) hipLaunchKernelGGL(k_tall_first<16>, dim3(groups), dim3(256), 0, stream, a);
-    hipLaunchKernelGGL(k_tall_step<16>, dim3(groups), dim3(256), 0, stream, a);
+    if (a.jj == 0) hipLaunchKernelGGL(k_tall_first<16>, dim3(groups), dim3(kTallThreads), 0, stream, a);
+    hipLaunchKernelGGL(k_tall_step<16>, dim3(groups), dim3(kTallThreads), 0, stream, a);
   } else {
     return hipErrorInvalidValue;
   }

@@ -266,8 +266,9 @@ void execute(blr_matrix h, Plan& P, hipStream_t s) {
     switch (o.kind) {
       case Op::GEMM: {
         // the dominant kernel: k_gemm_fast<CT, false, false> (untransposed
-        // 128x128 products: the trailing updates) in the factor's precision
-        const bool rec = h->prof_on && o.big == GEMM_FAST_NN && o.fp32 == (h->precision == BLR_MIXED_FP32 ? 1 : 0);
+        // 128x128 products), FP64 operands (fp32 == 0) or FP32 (fp32 == 1)
+        const bool rec = h->prof_on && o.big == GEMM_FAST_NN && (o.fp32 == 0 || o.fp32 == 1);
+        const int pk = o.fp32;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (rec) {
           HIPCHECK(hipEventCreate(&e0));
@@ -277,10 +278,10 @@ void execute(blr_matrix h, Plan& P, hipStream_t s) {
         HIPCHECK(launch_gemm(P.d_descs + o.off, o.n, P.d_segs, o.ntiles, o.big, o.fp32, q));
         if (rec) {
           HIPCHECK(hipEventRecord(e1, q));
-          h->prof_ev.push_back(e0);
-          h->prof_ev.push_back(e1);
-          h->prof_flops += o.flops;
-          h->prof_launches += 1;
+          h->prof_ev[pk].push_back(e0);
+          h->prof_ev[pk].push_back(e1);
+          h->prof_flops[pk] += o.flops;
+          h->prof_launches[pk] += 1;
         }
         h->launches += 1;
         break;
@@ -927,6 +928,7 @@ void plan_stack_qr(Plan& P, blr_matrix h, Work& w, BcWork& bw, int hs, double* T
   double* X = bw.stack;
   const bool tall = hs > 1024;
   int ib = (hs > 512 && !tall) ? 16 : 32;
+  if (tall) ib = 16;   // 16-column sub-panels: the column kernel's rows stay in registers at 512 threads
   if (b % ib) ib = 16;
   ib = std::min(ib, b);
   const int OB = (tall && b % 128 == 0) ? 128 : b;   // outer block of the tall path
@@ -1945,10 +1947,12 @@ blr_status blr_qr_factor(blr_matrix h, const blr_factor_opts* o, void* stream) {
     P.upload(h->work);
     h->flops = 0.0;
     for (auto& op : P.ops) h->flops += op.flops;
-    for (auto e : h->prof_ev) (void)hipEventDestroy(e);
-    h->prof_ev.clear();
-    h->prof_flops = 0.0;
-    h->prof_launches = 0;
+    for (int k = 0; k < 2; ++k) {
+      for (auto e : h->prof_ev[k]) (void)hipEventDestroy(e);
+      h->prof_ev[k].clear();
+      h->prof_flops[k] = 0.0;
+      h->prof_launches[k] = 0;
+    }
     h->launches = 0;
     HIPCHECK(hipMemsetAsync(h->d_counters, 0, 4 * sizeof(unsigned long long), s));
     execute(h, P, s);
@@ -2166,7 +2170,8 @@ blr_status blr_query(blr_matrix h, blr_info* info) {
 void blr_destroy(blr_matrix h) {
   if (!h) return;
   (void)hipDeviceSynchronize();
-  for (auto e : h->prof_ev) (void)hipEventDestroy(e);
+  for (int k = 0; k < 2; ++k)
+    for (auto e : h->prof_ev[k]) (void)hipEventDestroy(e);
   for (auto st : h->streams) (void)hipStreamDestroy(st);
   delete h;
 }
@@ -2177,19 +2182,22 @@ blr_status blr_profile_enable(blr_matrix h, int32_t on) {
   return BLR_OK;
 }
 
-blr_status blr_profile_read(blr_matrix h, int64_t* launches, double* total_ms, double* total_flops) {
+blr_status blr_profile_read(blr_matrix h, int32_t kernel, int64_t* launches, double* total_ms,
+                            double* total_flops) {
   if (!h || !launches || !total_ms || !total_flops) return fail(BLR_ERR_INVALID, "NULL argument");
+  if (kernel != 0 && kernel != 1) return fail(BLR_ERR_INVALID, "kernel must be 0 (FP64) or 1 (FP32)");
   return run_guarded([&] {
     HIPCHECK(hipDeviceSynchronize());
     double ms = 0.0;
-    for (size_t a = 0; a + 1 < h->prof_ev.size(); a += 2) {
+    const auto& ev = h->prof_ev[kernel];
+    for (size_t a = 0; a + 1 < ev.size(); a += 2) {
       float t = 0.f;
-      HIPCHECK(hipEventElapsedTime(&t, h->prof_ev[a], h->prof_ev[a + 1]));
+      HIPCHECK(hipEventElapsedTime(&t, ev[a], ev[a + 1]));
       ms += t;
     }
-    *launches = h->prof_launches;
+    *launches = h->prof_launches[kernel];
     *total_ms = ms;
-    *total_flops = h->prof_flops;
+    *total_flops = h->prof_flops[kernel];
   });
 }
 

@@ -132,10 +132,10 @@ struct blr_matrix_s {
   double flops = 0.0;
   int64_t launches = 0;
   bool prof_on = false;
-  std::vector<hipEvent_t> prof_ev;
+  std::vector<hipEvent_t> prof_ev[2];     // [0] FP64, [1] FP32 fast untransposed products
   std::vector<hipStream_t> streams;      // look-ahead streams (created on first use)
-  double prof_flops = 0.0;
-  int64_t prof_launches = 0;
+  double prof_flops[2] = {0.0, 0.0};
+  int64_t prof_launches[2] = {0, 0};
 
   blr::Tile& t(int i, int j) { return tiles[(size_t)i * q + j]; }
 };
