@@ -759,6 +759,7 @@ struct BcWork {
   double* Yf[2] = {nullptr, nullptr};  // b x b explicit unit-lower Y_kk (steps alternate)
   double* tallpart = nullptr;   // 2 x (kTallMaxGroups + 1) x 64
   double* gpart = nullptr;      // kGramSlices x b x b split-K Gram partials
+  int64_t gpart_doubles = 0;
   double* wblk = nullptr;       // 128 x b: W of a block reflector
   double* wblk2 = nullptr;      // 128 x b: T^T W
   double* wpart = nullptr;      // kApplySlices x 128 x b split-K partials of W
@@ -810,7 +811,8 @@ BcWork make_bc_work(blr_matrix h, int npairs) {
   bw.Yf[0] = (double*)A.alloc((size_t)b * b * 8);
   bw.Yf[1] = (double*)A.alloc((size_t)b * b * 8);
   bw.tallpart = (double*)A.alloc((size_t)2 * (kTallMaxGroups + 1) * 64 * 8);
-  bw.gpart = (double*)A.alloc((size_t)kGramSlices * b * b * 8);
+  bw.gpart_doubles = (int64_t)kGramSlices * b * b;
+  bw.gpart = (double*)A.alloc((size_t)bw.gpart_doubles * 8);
   bw.wblk = (double*)A.alloc((size_t)128 * b * 8);
   bw.wblk2 = (double*)A.alloc((size_t)128 * b * 8);
   bw.wpart = (double*)A.alloc((size_t)kApplySlices * 128 * b * 8);
@@ -835,30 +837,29 @@ BcWork make_bc_work(blr_matrix h, int npairs) {
 
 // Householder QR of the hs x b stack (ld hs) into T (b x b) and tau.
 // Gram matrix G = Y^T Y (lower triangle valid) of the nw reflectors whose
-// pivot is X (unit lower in the first nw rows, h rows, ld ldx), split over
-// row slices so that tall stacks fill the chip: the first slice (which holds
-// the unit-lower block) on the masked kernel, the others as full products on
-// the fast kernel, summed by one reduction.
+// pivot is X (unit lower in the first nw rows, h rows, ld ldx).  The unit-
+// lower top block goes to the masked kernel; the rows below it are split
+// into slices of full products on the fast kernel so that tall stacks fill
+// the chip; one reduction sums the parts.
 void plan_gram(Plan& P, BcWork& bw, const double* X, int64_t ldx, int h, int nw, double* G, int64_t ldg) {
-  const int S = std::min(kGramSlices, std::max(1, h / 4096));
-  // slice length: a multiple of 16 rounded up, so at most S slices
-  const int ks = std::max(nw, ((h + S - 1) / S + 15) / 16 * 16);
-  int ns = 0;
-  for (int r0 = 0; r0 < h; r0 += ks) {
+  const int rest = h - nw;
+  // narrow blocks take more, shorter slices (the partial buffer holds
+  // kGramSlices full-width Gram matrices)
+  const int cap = (int)std::min<int64_t>(nw <= 256 ? 64 : kGramSlices, bw.gpart_doubles / ((int64_t)nw * nw));
+  const int S = rest > 0 ? std::min(cap - 1, std::max(1, rest / (nw <= 256 ? 2048 : 4096))) : 0;
+  const int ks = S > 0 ? ((rest + S - 1) / S + 15) / 16 * 16 : 0;
+  const bool direct = S == 0;
+  P.gemm(direct ? G : bw.gpart, direct ? ldg : nw, nullptr, 0, nullptr, 0, nw, nw, 1.0, 0.0, X, ldx, X, ldx, nw,
+         SEG_TRANS_A | SEG_A_UNIT_LOWER | SEG_B_UNIT_LOWER, DESC_LOWER_ONLY);
+  P.flush_gemm();
+  int ns = 1;
+  for (int r0 = nw; r0 < h; r0 += ks, ++ns) {
     const int kk = std::min(ks, h - r0);
-    double* out = S == 1 ? G : bw.gpart + (size_t)ns * nw * nw;
-    const int64_t ldo = S == 1 ? ldg : nw;
-    if (r0 == 0) {
-      P.gemm(out, ldo, nullptr, 0, nullptr, 0, nw, nw, 1.0, 0.0, X, ldx, X, ldx, kk,
-             SEG_TRANS_A | SEG_A_UNIT_LOWER | SEG_B_UNIT_LOWER, DESC_LOWER_ONLY);
-      P.flush_gemm();
-    } else {
-      P.gemm(out, ldo, nullptr, 0, nullptr, 0, nw, nw, 1.0, 0.0, X + r0, ldx, X + r0, ldx, kk, SEG_TRANS_A);
-    }
-    ++ns;
+    P.gemm(bw.gpart + (size_t)ns * nw * nw, nw, nullptr, 0, nullptr, 0, nw, nw, 1.0, 0.0, X + r0, ldx, X + r0, ldx,
+           kk, SEG_TRANS_A);
   }
   P.flush_gemm();
-  if (ns > 1) P.copy({CopyDesc{bw.gpart, G, (int64_t)nw, ldg, nw, nw, 0, ns, (int64_t)nw * nw}});
+  if (!direct) P.copy({CopyDesc{bw.gpart, G, (int64_t)nw, ldg, nw, nw, 0, ns, (int64_t)nw * nw}});
 }
 
 // T of the nw reflectors at X (into T, ld ldt; its ib x ib diagonal blocks
@@ -885,26 +886,26 @@ void plan_block_t(Plan& P, Work& w, BcWork& bw, const double* X, int64_t ldx, in
 // on the masked kernel, the rows below on the fast kernel).
 void plan_block_apply(Plan& P, BcWork& bw, const double* X, double* C, int64_t ldx, int h, int nw, int nt,
                       const double* T, int64_t ldt) {
-  const int S = std::min(kApplySlices, std::max(1, h / 2048));
-  const int ks = std::max(nw, ((h + S - 1) / S + 15) / 16 * 16);
-  int ns = 0;
-  for (int r0 = 0; r0 < h; r0 += ks) {
+  // W = Y^T C: the unit-lower top block on the masked kernel, the rows below
+  // in slices on the fast kernel, one reduction
+  const int rest = h - nw;
+  const int S = rest > 0 ? std::min(kApplySlices - 1, std::max(1, rest / 2048)) : 0;
+  const int ks = S > 0 ? ((rest + S - 1) / S + 15) / 16 * 16 : 0;
+  const bool direct = S == 0;
+  P.gemm(direct ? bw.wblk : bw.wpart, nw, nullptr, 0, nullptr, 0, nw, nt, 1.0, 0.0, X, ldx, C, ldx, nw,
+         SEG_TRANS_A | SEG_A_UNIT_LOWER);
+  P.flush_gemm();
+  int ns = 1;
+  for (int r0 = nw; r0 < h; r0 += ks, ++ns) {
     const int kk = std::min(ks, h - r0);
-    double* out = S == 1 ? bw.wblk : bw.wpart + (size_t)ns * nw * nt;
-    if (r0 == 0) {
-      P.gemm(out, nw, nullptr, 0, nullptr, 0, nw, nt, 1.0, 0.0, X, ldx, C, ldx, kk, SEG_TRANS_A | SEG_A_UNIT_LOWER);
-      P.flush_gemm();
-    } else {
-      P.gemm(out, nw, nullptr, 0, nullptr, 0, nw, nt, 1.0, 0.0, X + r0, ldx, C + r0, ldx, kk, SEG_TRANS_A);
-    }
-    ++ns;
+    P.gemm(bw.wpart + (size_t)ns * nw * nt, nw, nullptr, 0, nullptr, 0, nw, nt, 1.0, 0.0, X + r0, ldx, C + r0, ldx,
+           kk, SEG_TRANS_A);
   }
   P.flush_gemm();
-  if (ns > 1) P.copy({CopyDesc{bw.wpart, bw.wblk, (int64_t)nw, (int64_t)nw, nw, nt, 0, ns, (int64_t)nw * nt}});
+  if (!direct) P.copy({CopyDesc{bw.wpart, bw.wblk, (int64_t)nw, (int64_t)nw, nw, nt, 0, ns, (int64_t)nw * nt}});
   P.gemm(bw.wblk2, nw, nullptr, 0, nullptr, 0, nw, nt, 1.0, 0.0, T, ldt, bw.wblk, nw, nw, SEG_TRANS_A | SEG_A_UPPER);
   P.flush_gemm();
   // rows [0, nw): unit-lower Y block; the rows below in a 128-multiple bulk and a ragged rest
-  const int rest = h - nw;
   const int bulk = rest / 128 * 128;
   P.gemm(C, ldx, C, ldx, nullptr, 0, nw, nt, -1.0, 1.0, X, ldx, bw.wblk2, nw, nw, SEG_A_UNIT_LOWER);
   if (rest > bulk)
