@@ -443,35 +443,42 @@ __global__ __launch_bounds__(kTallThreads) void k_tall_step(TallArgs a) {
   double part[IB];
 #pragma unroll
   for (int t = 0; t < IB; ++t) part[t] = 0.0;
-  // 2. reflector column jj and rank-one update of the later columns on this group's rows
+  // 2. reflector column jj and rank-one update of the later columns on this
+  // group's rows, streamed column by column so that only the partial sums
+  // of the next column stay live across a row
   for (int r = max(rs, jj + 1) + tid; r < re; r += NT) {
-    // (register arrays are indexed by unrolled constants only: selects, no dynamic indexing)
-    double x[IB];
-#pragma unroll
-    for (int t = 0; t < IB; ++t) x[t] = (t >= jj || more) ? a.X[r + (int64_t)t * ld] : 0.0;
-    double xj = 0.0;
-#pragma unroll
-    for (int t = 0; t < IB; ++t) xj = (t == jj) ? x[t] : xj;
-    const double v = xj * scal;
+    const double v = a.X[r + (int64_t)jj * ld] * scal;
     a.X[r + (int64_t)jj * ld] = v;
+    if (more && r == nx) {
+      // the next pivot row: snapshot it after this update
+#pragma unroll
+      for (int t = 0; t < IB; ++t) {
+        double x = t == jj ? v : a.X[r + (int64_t)t * ld];
+        if (t > jj) {
+          x -= tau * wv[t] * v;
+          a.X[r + (int64_t)t * ld] = x;
+        }
+        out[(int64_t)G * (2 * IB) + t] = x;
+      }
+      continue;
+    }
+    double xn = 0.0;
+    if (more) {
+      xn = a.X[r + (int64_t)nx * ld] - tau * wv[nx] * v;
+      a.X[r + (int64_t)nx * ld] = xn;
+    }
 #pragma unroll
     for (int t = 0; t < IB; ++t) {
-      if (t == jj) x[t] = v;
-      if (t > jj) {
-        x[t] -= tau * wv[t] * v;
-        a.X[r + (int64_t)t * ld] = x[t];
-      }
-    }
-    if (more) {
-      if (r > nx) {
-        double xn = 0.0;
-#pragma unroll
-        for (int t = 0; t < IB; ++t) xn = (t == nx) ? x[t] : xn;
-#pragma unroll
-        for (int t = 0; t < IB; ++t) part[t] += (t == nx) ? xn * xn : xn * x[t];
-      } else {   // r == nx: the next pivot row
-#pragma unroll
-        for (int t = 0; t < IB; ++t) out[(int64_t)G * (2 * IB) + t] = x[t];
+      if (t > nx) {
+        double x = a.X[r + (int64_t)t * ld] - tau * wv[t] * v;
+        a.X[r + (int64_t)t * ld] = x;
+        part[t] += xn * x;
+      } else if (t == nx) {
+        part[t] += xn * xn;
+      } else if (t == jj) {
+        part[t] += xn * v;
+      } else if (more) {   // t < jj: final reflector entries
+        part[t] += xn * a.X[r + (int64_t)t * ld];
       }
     }
   }
