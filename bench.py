@@ -40,8 +40,8 @@ PEAK = {"fp64": 78.6e12, "mixed": 157.3e12}   # MI355X dense matrix-core peaks (
 # the counters were taken on (sha256 of csrc/gemm.hip); otherwise null.
 TRAFFIC = {
     ("c3", "fp64", "block_column"): {
-        "gemm_sha256": "399ef48a14ecb46fb614f6668a757847afdbb79ad37f068c785162e1642f2ee9",
-        "bytes_per_launch": 196428776417,
+        "gemm_sha256": "9fedc7d4aee4c765779141ecf9856288cadaa07864e9735fb10f565961d7a503",
+        "bytes_per_launch": 9746686466,
     },
 }
 
