@@ -130,7 +130,7 @@ def run(args, cfg, precision, tol, xd, yd, dev):
     import synth
     import paper_2208_06194_amd as P
     times, comp_times = [], []
-    prof, info, acc = {"fp64": (0, 0.0, 0.0), "fp32": (0, 0.0, 0.0)}, None, None
+    prof, info, acc, solve = {"fp64": (0, 0.0, 0.0), "fp32": (0, 0.0, 0.0)}, None, None, None
     stream = torch.cuda.current_stream()
     probes = torch.tensor(synth.rhs(args.seed + 17, cfg["n"], args.probes), device=dev)
     for step in range(args.warmup + args.steps):
@@ -163,10 +163,25 @@ def run(args, cfg, precision, tol, xd, yd, dev):
         if ax is not None and args.stop_after_k < 0:
             acc = accuracy_probes(G, probes, ax)
             print(f"[bench] {precision}: Res~ {acc[0]:.2e} Orth {acc[1]:.2e}", file=sys.stderr, flush=True)
+            # Q^T B and the least-squares solve with 16 right-hand sides (untimed by the metric)
+            rhs = torch.tensor(synth.rhs(args.seed + 23, cfg["m"], 16), device=dev)
+            f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            f0.record(stream)
+            G.apply_qt(rhs)
+            f1.record(stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            G.lstsq(rhs)
+            torch.cuda.synchronize()
+            solve = {"nrhs": 16, "apply_qt_s": f0.elapsed_time(f1) / 1e3, "lstsq_s": time.perf_counter() - t0}
+            print(f"[bench] {precision}: apply Q^T {solve['apply_qt_s']:.3f}s lstsq {solve['lstsq_s']:.3f}s "
+                  f"(16 right-hand sides)", file=sys.stderr, flush=True)
         del G
     value = float(np.median(times))
     return {"value": value, "compress_s": float(np.median(comp_times)), "info": info, "tol": tol,
-            "res_est": acc[0] if acc else None, "orth_est": acc[1] if acc else None, "prof": prof}
+            "res_est": acc[0] if acc else None, "orth_est": acc[1] if acc else None, "prof": prof,
+            "solve": solve}
 
 
 def roofline(prof, kernel, args, timed_s):
@@ -250,6 +265,7 @@ def main():
         "orth_est": r["orth_est"],
         "accuracy_note": f"Gaussian-probe estimates ({args.probes} probes) of ||A~-QR||_F/||A~||_F and "
                          "||Q1^T Q1 - I||_F/sqrt(n); A~ is the compressed matrix (||A~-A|| <= eps ||A|| per tile)",
+        "solve_16rhs": r["solve"],
         "ledger_flops": info["flops_factor"],
         "gflops": info["flops_factor"] / value / 1e9,
         "dense_equiv_tflops": dense_equiv_flops(cfg["m"], cfg["n"]) / value / 1e12,
@@ -277,7 +293,7 @@ def main():
         rfm = roofline(mx["prof"]["fp32"], "fp32", args, mx["value"] * args.steps)
         out["mixed"] = {
             "value": mx["value"], "unit": "s", "tol": mx["tol"], "res_est": mx["res_est"],
-            "orth_est": mx["orth_est"], "speedup_vs_fp64": value / mx["value"],
+            "orth_est": mx["orth_est"], "speedup_vs_fp64": value / mx["value"], "solve_16rhs": mx["solve"],
             "tiles": {"dense": mx["info"]["n_dense"], "lowrank": mx["info"]["n_lowrank"],
                       "fill_in": mx["info"]["n_fill_in"], "factor_overflow": mx["info"]["factor_overflow"]},
             **({"roofline": rfm} if rfm else {}),

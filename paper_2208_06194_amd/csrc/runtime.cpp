@@ -1254,6 +1254,7 @@ void plan_blockcol(blr_matrix h, Plan& P, Work& w, BcWork& bw, int kend, bool fp
 void plan_apply_blockcol(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, int nrhs, int trans,
                          double* Sbuf) {
   const int b = h->b, rc = h->rc, p = h->p, q = h->q;
+  double* Wpart = (double*)h->work.alloc((size_t)kApplySlices * b * std::max(nrhs, 1) * 8);
   const int K = h->steps_done;
   auto step = [&](int k) {
     double* Tk = h->T[(size_t)k * q + k];
@@ -1276,8 +1277,23 @@ void plan_apply_blockcol(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb,
       }
       sv.push_back(g);
     }
-    P.gemm_multi(w.Wx, b, nullptr, 0, b, nrhs, 1.0, 0.0, sv);
-    P.flush_gemm();
+    // the sum over the block column's tiles in up to kApplySlices groups
+    // (one partial product each, then one reduction), so that a few
+    // right-hand sides still fill the chip
+    const int ng = std::min<int>((int)sv.size(), kApplySlices);
+    if (ng <= 1) {
+      P.gemm_multi(w.Wx, b, nullptr, 0, b, nrhs, 1.0, 0.0, sv);
+      P.flush_gemm();
+    } else {
+      const int per = ((int)sv.size() + ng - 1) / ng;
+      int nd = 0;
+      for (int g0 = 0; g0 < (int)sv.size(); g0 += per, ++nd) {
+        std::vector<GemmSeg> part(sv.begin() + g0, sv.begin() + std::min<int>((int)sv.size(), g0 + per));
+        P.gemm_multi(Wpart + (size_t)nd * b * nrhs, b, nullptr, 0, b, nrhs, 1.0, 0.0, part);
+      }
+      P.flush_gemm();
+      P.copy({CopyDesc{Wpart, w.Wx, (int64_t)b, (int64_t)b, b, nrhs, 0, nd, (int64_t)b * nrhs}});
+    }
     P.gemm(w.Wx2, b, nullptr, 0, nullptr, 0, b, nrhs, 1.0, 0.0, Tk, b, w.Wx, b, b,
            (trans ? 0 : SEG_TRANS_A) | SEG_A_UPPER);
     P.flush_gemm();
@@ -1393,6 +1409,7 @@ void run_rsolve(blr_matrix h, double* X, int64_t ldx, int nrhs, int trans, hipSt
   const int b = h->b, q = h->q, rc = h->rc;
   Plan Q;
   double* Sx = (double*)h->work.alloc((size_t)q * rc * nrhs * 8);  // rc x nrhs per tile column
+  double* Wp = (double*)h->work.alloc((size_t)kApplySlices * b * std::min(nrhs, 64) * 8);
   for (int step = 0; step < q; ++step) {
     const int k = trans ? step : q - 1 - step;
     double* Xk = X + (int64_t)k * b;
@@ -1425,8 +1442,23 @@ void run_rsolve(blr_matrix h, double* X, int64_t ldx, int nrhs, int trans, hipSt
         }
         sv.push_back(sg);
       }
-      Q.gemm_multi(Xk, ldx, Xk, ldx, b, nrhs, -1.0, 1.0, sv);
-      Q.flush_gemm(0, 0, false);
+      // X_k -= sum_j (...): split over up to kApplySlices groups of tiles
+      // (partial products, then X_k and the partials summed in one pass)
+      const int ng = std::min<int>((int)sv.size(), kApplySlices - 1);
+      if (ng <= 1 || nrhs > 64) {
+        Q.gemm_multi(Xk, ldx, Xk, ldx, b, nrhs, -1.0, 1.0, sv);
+        Q.flush_gemm(0, 0, false);
+      } else {
+        const int per = ((int)sv.size() + ng - 1) / ng;
+        Q.copy({CopyDesc{Xk, Wp, ldx, (int64_t)b, b, nrhs, 0, 0}});
+        int nd = 1;
+        for (int g0 = 0; g0 < (int)sv.size(); g0 += per, ++nd) {
+          std::vector<GemmSeg> part(sv.begin() + g0, sv.begin() + std::min<int>((int)sv.size(), g0 + per));
+          Q.gemm_multi(Wp + (size_t)nd * b * nrhs, b, nullptr, 0, b, nrhs, -1.0, 0.0, part);
+        }
+        Q.flush_gemm(0, 0, false);
+        Q.copy({CopyDesc{Wp, Xk, (int64_t)b, ldx, b, nrhs, 0, nd, (int64_t)b * nrhs}});
+      }
     }
     Op o;
     o.kind = Op::TRSM;
@@ -1440,6 +1472,8 @@ void run_rsolve(blr_matrix h, double* X, int64_t ldx, int nrhs, int trans, hipSt
       const int k = o.off;
       if (o.n) HIPCHECK(launch_trsm_upper_t(h->t(k, k).D, b, b, X + (int64_t)k * b, ldx, nrhs, s));
       else HIPCHECK(launch_trsm_upper(h->t(k, k).D, b, b, X + (int64_t)k * b, ldx, nrhs, s));
+    } else if (o.kind == Op::COPY) {
+      HIPCHECK(launch_copy_blocks(Q.d_copies + o.off, o.n, o.maxel, s));
     } else {
       HIPCHECK(launch_gemm(Q.d_descs + o.off, o.n, Q.d_segs, o.ntiles, o.big, 0, s));
     }
