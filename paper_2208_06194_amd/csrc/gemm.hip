@@ -270,7 +270,13 @@ __device__ __forceinline__ void gemm_fast_body(const GemmDesc* __restrict__ desc
         for (int v = 0; v < 4; ++v) acc64[i][j][v] = 0.0;
   }
 
-  d2v ra[NV], rb[NV];
+  // PF2 (FP64 operands): two register sets, the global loads run two K steps
+  // ahead and the LDS writes of the next step are issued after the first
+  // quarter of a step's matrix-core work, so both overlap the rest of it.
+  // FP32 operands keep one set (their occupancy depends on the registers).
+  constexpr bool PF2 = sizeof(CT) == 8;
+  d2v ra0[NV], rb0[NV];
+  d2v ra1[PF2 ? NV : 1], rb1[PF2 ? NV : 1];
   for (int sgi = 0; sgi < d.nseg; ++sgi) {
     const GemmSeg sg = segs[d.seg_begin + sgi];
     int kbeg = 0, kend = sg.K;
@@ -284,7 +290,7 @@ __device__ __forceinline__ void gemm_fast_body(const GemmDesc* __restrict__ desc
                           : sg.B + (int64_t)(n0 + b_nk) * sg.ldb + kbeg + b_8;
     const int64_t astep = TA ? BK : (int64_t)BK * sg.lda;
     const int64_t bstep = TB ? (int64_t)BK * sg.ldb : BK;
-    auto gload = [&](int step) {
+    auto gload = [&](d2v (&ra)[NV], d2v (&rb)[NV], int step) {
       const gd2v* pa = (const gd2v*)(ap + step * astep);
       const gd2v* pb = (const gd2v*)(bp + step * bstep);
 #pragma unroll
@@ -293,7 +299,7 @@ __device__ __forceinline__ void gemm_fast_body(const GemmDesc* __restrict__ desc
         rb[q] = pb[q];
       }
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](const d2v (&ra)[NV], const d2v (&rb)[NV], int buf) {
 #pragma unroll
       for (int q = 0; q < NV; ++q)
 #pragma unroll
@@ -304,31 +310,57 @@ __device__ __forceinline__ void gemm_fast_body(const GemmDesc* __restrict__ desc
           else Bs[buf][b_8 + 2 * q + e][b_nk] = (CT)rb[q][e];
         }
     };
-    const int nsteps = (kend - kbeg) / BK;
-    if (nsteps <= 0) continue;
-    gload(0);
-    __syncthreads();  // previous segment's last reads of buffer 0 are done
-    lstore(0);
-    __syncthreads();
-    for (int st = 0; st < nsteps; ++st) {
-      const int buf = st & 1;
-      const bool more = st + 1 < nsteps;
-      if (more) gload(st + 1);
+    auto kstep = [&](int buf, int kk) {
+      CT af[4], bf[4];
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        CT af[4], bf[4];
+      for (int i = 0; i < 4; ++i) af[i] = As[buf][kk + (lane >> 4)][wm * 64 + i * 16 + (lane & 15)];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) af[i] = As[buf][kk + (lane >> 4)][wm * 64 + i * 16 + (lane & 15)];
+      for (int j = 0; j < 4; ++j) bf[j] = Bs[buf][kk + (lane >> 4)][wn * 64 + j * 16 + (lane & 15)];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bf[j] = Bs[buf][kk + (lane >> 4)][wn * 64 + j * 16 + (lane & 15)];
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma_op(af[i], bf[j], acc[i][j]);
+    };
+    // one K step from LDS buffer buf; the register set (na, nb) holds the
+    // next step's tiles and goes to the other buffer
+    auto step = [&](int st, int buf, const d2v (&na)[NV], const d2v (&nb)[NV], bool has_next) {
+      kstep(buf, 0);
+      if (has_next) lstore(na, nb, buf ^ 1);
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = mfma_op(af[i], bf[j], acc[i][j]);
-      }
-      if (more) lstore(buf ^ 1);
+      for (int kk = 4; kk < BK; kk += 4) kstep(buf, kk);
       __syncthreads();
       if (ACC64 && (st + 1) % kFlushSteps == 0) flush();
+    };
+    const int nsteps = (kend - kbeg) / BK;
+    if (nsteps <= 0) continue;
+    gload(ra0, rb0, 0);
+    __syncthreads();  // previous segment's last reads of buffer 0 are done
+    lstore(ra0, rb0, 0);
+    if constexpr (PF2) {
+      if (nsteps > 1) gload(ra1, rb1, 1);
+      __syncthreads();
+      for (int st = 0; st < nsteps; st += 2) {
+        // even step: buffer 0; set 1 holds step st + 1, set 0 takes step st + 2
+        if (st + 2 < nsteps) gload(ra0, rb0, st + 2);
+        step(st, 0, ra1, rb1, st + 1 < nsteps);
+        if (st + 1 >= nsteps) break;
+        // odd step: buffer 1; set 0 holds step st + 2, set 1 takes step st + 3
+        if (st + 3 < nsteps) gload(ra1, rb1, st + 3);
+        step(st + 1, 1, ra0, rb0, st + 2 < nsteps);
+      }
+    } else {
+      // one register set: loads one step ahead, LDS writes after the step
+      __syncthreads();
+      for (int st = 0; st < nsteps; ++st) {
+        const int buf = st & 1;
+        const bool more = st + 1 < nsteps;
+        if (more) gload(ra0, rb0, st + 1);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) kstep(buf, kk);
+        if (more) lstore(ra0, rb0, buf ^ 1);
+        __syncthreads();
+        if (ACC64 && (st + 1) % kFlushSteps == 0) flush();
+      }
     }
     if (ACC64 && nsteps % kFlushSteps != 0) flush();
   }
