@@ -746,6 +746,7 @@ void plan_apply_tiled(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, in
 
 constexpr int kGramSlices = 16;
 constexpr int kApplySlices = 64;
+constexpr int kZSlices = 16;
 
 struct BcSlot {
   double *Ua, *Ub;   // b x rc
@@ -763,6 +764,7 @@ struct BcWork {
   double* wblk = nullptr;       // 128 x b: W of a block reflector
   double* wblk2 = nullptr;      // 128 x b: T^T W
   double* wpart = nullptr;      // kApplySlices x 128 x b split-K partials of W
+  double* zpart = nullptr;      // kZSlices x b x b partial sums of the look-ahead column's Z
   double* applypart = nullptr;  // 64 x ceil(b/32) x 32 x 32
   std::vector<BcSlot> slots;
 };
@@ -816,6 +818,7 @@ BcWork make_bc_work(blr_matrix h, int npairs) {
   bw.wblk = (double*)A.alloc((size_t)128 * b * 8);
   bw.wblk2 = (double*)A.alloc((size_t)128 * b * 8);
   bw.wpart = (double*)A.alloc((size_t)kApplySlices * 128 * b * 8);
+  bw.zpart = (double*)A.alloc((size_t)kZSlices * b * b * 8);
   bw.applypart = (double*)A.alloc((size_t)64 * ((b + 31) / 32) * 32 * 32 * 8);
   const size_t rcwd = rc_work_doubles(b, rc);
   const size_t per = 2 * (size_t)b * rc + (size_t)rc * b + (size_t)rc * rc + rcwd;
@@ -1098,6 +1101,7 @@ void plan_bc_update(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k, int j0, i
     }
   }
   P.flush_gemm();
+  std::vector<CopyDesc> zred;
   for (int j = j0; j < j1; ++j) {
     if (!zd[j]) continue;
     std::vector<GemmSeg> sv;
@@ -1108,9 +1112,28 @@ void plan_bc_update(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k, int j0, i
       g.A = Yd(i); g.lda = b; g.B = A.D; g.ldb = b; g.K = b; g.flags = SEG_TRANS_A;
       sv.push_back(g);
     }
-    P.gemm_multi(w.X[j], b, zlr[j] ? w.X[j] : nullptr, b, b, b, 1.0, zlr[j] ? 1.0 : 0.0, sv);
+    // a single column (the look-ahead column) is on the panels' critical
+    // path: its sum over the stack is split into partial products so that it
+    // finishes in a fraction of one long K sweep
+    const int ng = (j1 - j0 == 1) ? std::min<int>((int)sv.size(), kZSlices - 1) : 1;
+    if (ng <= 1) {
+      P.gemm_multi(w.X[j], b, zlr[j] ? w.X[j] : nullptr, b, b, b, 1.0, zlr[j] ? 1.0 : 0.0, sv);
+      continue;
+    }
+    const int per = ((int)sv.size() + ng - 1) / ng;
+    int nd = 0;
+    if (zlr[j]) {   // the low-rank contributions already in X_j join the reduction as slice 0
+      P.copy({CopyDesc{w.X[j], bw.zpart, (int64_t)b, (int64_t)b, b, b, 0, 0}});
+      nd = 1;
+    }
+    for (int g0 = 0; g0 < (int)sv.size(); g0 += per, ++nd) {
+      std::vector<GemmSeg> part(sv.begin() + g0, sv.begin() + std::min<int>((int)sv.size(), g0 + per));
+      P.gemm_multi(bw.zpart + (size_t)nd * b * b, b, nullptr, 0, b, b, 1.0, 0.0, part);
+    }
+    zred.push_back(CopyDesc{bw.zpart, w.X[j], (int64_t)b, (int64_t)b, b, b, 0, nd, (int64_t)b * b});
   }
   P.flush_gemm(fp32, 1);
+  if (!zred.empty()) P.copy(zred);
   // 4c. low-rank Z_j: rounded additions of the terms in order i = k, k+1, ...
   std::vector<RcTerm> zterm(q);
   auto term = [&](int i, int j) -> RcTerm {
@@ -1244,7 +1267,8 @@ void plan_blockcol(blr_matrix h, Plan& P, Work& w, BcWork& bw, int kend, bool fp
       P.record(e_panel(k + 1));
       P.cur_stream = 0;
     };
-    plan_bc_update(h, P, w, bw, k, k + 1, q, fp32, k + 2, next_panel);
+    plan_bc_update(h, P, w, bw, k, k + 1, k + 2, fp32, k + 2, next_panel);
+    plan_bc_update(h, P, w, bw, k, k + 2, q, fp32, q, nullptr);
   }
   P.cur_stream = 0;
 }
