@@ -57,7 +57,9 @@ hipError_t launch_panel(const PanelArgs& a, hipStream_t stream);
 constexpr int kTallMaxGroups = 512;
 constexpr int kTallThreads = 512;   // threads per row group (one row each for 512-row groups)
 hipError_t launch_tall_column(const TallArgs& a, int groups, hipStream_t stream);
-// Split-K trailing update of a tall panel; part: slices * ceil(nt/32) * ib * 32 doubles.
+// Split-K trailing update of a tall panel over 1 .. kTallApplySlices row
+// slices; part: slices * ceil(nt/32) * ib * 32 doubles.
+constexpr int kTallApplySlices = 256;
 hipError_t launch_tall_apply(const PanelArgs& a, int nt, int slices, double* part, hipStream_t stream);
 hipError_t launch_copy_blocks(const CopyDesc* d, int n, int64_t max_elems, hipStream_t stream);
 hipError_t launch_t_backsolve(const TBackArgs& a, hipStream_t stream);

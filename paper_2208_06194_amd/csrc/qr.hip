@@ -590,9 +590,17 @@ __global__ __launch_bounds__(256) void k_tall_apply_upd(PanelArgs a, int nt, con
   double* B = a.X + (int64_t)(IB + c0) * a.ldx;
   const int64_t ld = a.ldx;
   for (int e = tid; e < IB * NC; e += 256) {
-    double s = 0.0;
-    for (int q = 0; q < S; ++q) s += part[((int64_t)q * NB + cb) * IB * NC + e];
-    W[e % IB][e / IB] = s;
+    // eight independent partial sums keep eight loads in flight
+    double s8[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s8[u] = 0.0;
+    int q = 0;
+    for (; q + 8 <= S; q += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s8[u] += part[((int64_t)(q + u) * NB + cb) * IB * NC + e];
+    }
+    for (; q < S; ++q) s8[0] += part[((int64_t)q * NB + cb) * IB * NC + e];
+    W[e % IB][e / IB] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
   }
   __syncthreads();
   for (int e = tid; e < IB * NC; e += 256) {
@@ -672,6 +680,7 @@ hipError_t launch_tall_column(const TallArgs& a, int groups, hipStream_t stream)
 
 hipError_t launch_tall_apply(const PanelArgs& a, int nt, int slices, double* part, hipStream_t stream) {
   if (nt <= 0) return hipSuccess;
+  if (slices < 1 || slices > kTallApplySlices) return hipErrorInvalidValue;
   dim3 grid((nt + 31) / 32, slices), block(256);
   if (a.ib == 32) {
     hipLaunchKernelGGL((k_tall_apply_part<32>), grid, block, 0, stream, a, nt, part);

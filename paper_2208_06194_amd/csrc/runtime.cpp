@@ -765,7 +765,7 @@ struct BcWork {
   double* wblk2 = nullptr;      // 128 x b: T^T W
   double* wpart = nullptr;      // kApplySlices x 128 x b split-K partials of W
   double* zpart = nullptr;      // kZSlices x b x b partial sums of the look-ahead column's Z
-  double* applypart = nullptr;  // 64 x ceil(b/32) x 32 x 32
+  double* applypart = nullptr;  // kTallApplySlices x ceil(b/32) x 32 x 32
   std::vector<BcSlot> slots;
 };
 
@@ -819,7 +819,7 @@ BcWork make_bc_work(blr_matrix h, int npairs) {
   bw.wblk2 = (double*)A.alloc((size_t)128 * b * 8);
   bw.wpart = (double*)A.alloc((size_t)kApplySlices * 128 * b * 8);
   bw.zpart = (double*)A.alloc((size_t)kZSlices * b * b * 8);
-  bw.applypart = (double*)A.alloc((size_t)64 * ((b + 31) / 32) * 32 * 32 * 8);
+  bw.applypart = (double*)A.alloc((size_t)kTallApplySlices * ((b + 31) / 32) * 32 * 32 * 8);
   const size_t rcwd = rc_work_doubles(b, rc);
   const size_t per = 2 * (size_t)b * rc + (size_t)rc * b + (size_t)rc * rc + rcwd;
   if (npairs > 0) {
@@ -972,7 +972,7 @@ void plan_stack_qr(Plan& P, blr_matrix h, Work& w, BcWork& bw, int hs, double* T
           o.kind = Op::TALL_APPLY;
           o.panel = a;
           o.ntiles = nt;
-          o.n = std::min(64, std::max(1, hl / 2048));
+          o.n = std::min(kTallApplySlices, std::max(1, hl / 512));
           o.buf = bw.applypart;
           o.flops = 4.0 * hl * ib * nt;
           P.push(o);
