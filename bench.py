@@ -30,6 +30,9 @@ CONFIGS = {
     "c1": dict(m=2048, n=1024, b=128, dim=2, kernel="log2d", rule="adjacent", tol=1e-8, cap=16),
     "c2": dict(m=32768, n=16384, b=256, dim=3, kernel="inv_r", rule="dist_gt_diam", tol=1e-8, cap=32),
     "c3": dict(m=131072, n=65536, b=1024, dim=3, kernel="inv_r", rule="dist_gt_diam", tol=1e-8, cap=50),
+    # the paper's random-BLR workload at scale (low-rank heavy): N(0,1) dense
+    # diagonal tiles, every other tile a rank-16 product, weak admissibility
+    "wr": dict(m=32768, n=16384, b=256, kind="random_blr", rank=16, rule="weak", tol=1e-10, cap=64),
 }
 PEAK = {"fp64": 78.6e12, "mixed": 157.3e12}   # MI355X dense matrix-core peaks (FP64, FP32)
 
@@ -71,13 +74,19 @@ def cpu_baseline(cfg, seed, variant):
     from oracle import blockcol, blrmat, tiled
     fac = tiled.factor if variant == "tiled" else blockcol.factor
     b = cfg["b"]
-    x, y = synth.kernel_points(seed, cfg["m"], cfg["n"], cfg["dim"])
+    rblr = cfg.get("kind") == "random_blr"
+    if not rblr:
+        x, y = synth.kernel_points(seed, cfg["m"], cfg["n"], cfg["dim"])
     ms, ns = min(4 * b, cfg["m"]), min(2 * b, cfg["n"])
     spent = 0.0
     while True:
-        xs, ys = x[:ms], y[:ns]
-        A = blrmat.kernel_matrix(xs, ys, cfg["kernel"])
-        mask = blrmat.lowrank_mask(xs, ys, b, cfg["rule"], ms // b, ns // b)
+        if rblr:
+            A = synth.random_blr_dense(seed, ms, ns, b, cfg["rank"])
+            mask = np.ones((ms // b, ns // b), bool)
+        else:
+            xs, ys = x[:ms], y[:ns]
+            A = blrmat.kernel_matrix(xs, ys, cfg["kernel"])
+            mask = blrmat.lowrank_mask(xs, ys, b, cfg["rule"], ms // b, ns // b)
         blr = blrmat.compress(A, b, cfg["tol"], cfg["cap"], mask)
         t0 = time.perf_counter()
         fac(blr, cfg["tol"], cfg["cap"], copy=False)
@@ -96,7 +105,8 @@ def cpu_baseline(cfg, seed, variant):
     return {
         "value": dense_equiv_flops(cfg["m"], cfg["n"]) / rate, "unit": "s",
         "cores": cores, "kind": "oracle",
-        "sample": f"oracle {variant} factor of the leading {ms}x{ns} block (b={b}) of the same matrix took "
+        "sample": f"oracle {variant} factor of " + (f"a {ms}x{ns} random BLR matrix of the same tile size, rank and "
+                  f"tolerance" if rblr else f"the leading {ms}x{ns} block (b={b}) of the same matrix") + " took "
                   f"{el:.2f} s ({rate / 1e9:.2f} GFLOP/s dense-equivalent); value extrapolated to "
                   f"{cfg['m']}x{cfg['n']} by dense-equivalent flops",
     }
@@ -136,8 +146,12 @@ def run(args, cfg, precision, tol, xd, yd, dev):
     for step in range(args.warmup + args.steps):
         torch.cuda.synchronize()
         tc = time.perf_counter()
-        G = P.BLRMatrix.compress_kernel(xd, yd, cfg["kernel"], cfg["b"], tol, cfg["cap"],
-                                        admissibility=cfg["rule"], overflow="dense", seed=args.seed)
+        if cfg.get("kind") == "random_blr":
+            G = P.BLRMatrix.compress_dense(xd, cfg["b"], tol, cfg["cap"], admissibility="weak",
+                                           overflow="dense", seed=args.seed)
+        else:
+            G = P.BLRMatrix.compress_kernel(xd, yd, cfg["kernel"], cfg["b"], tol, cfg["cap"],
+                                            admissibility=cfg["rule"], overflow="dense", seed=args.seed)
         torch.cuda.synchronize()
         comp_times.append(time.perf_counter() - tc)
         timed = step >= args.warmup
@@ -233,9 +247,27 @@ def main():
     cfg = CONFIGS[args.config]
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
-    x, y = synth.kernel_points(args.seed, cfg["m"], cfg["n"], cfg["dim"])
-    xd, yd = torch.tensor(x, device=dev), torch.tensor(y, device=dev)
-    print(f"[bench] {args.config}: points ready in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    if cfg.get("kind") == "random_blr":
+        # the dense random-BLR matrix on the device, from its seeded tile factors
+        m, n, b, r = cfg["m"], cfg["n"], cfg["b"], cfg["rank"]
+        p, q = m // b, n // b
+        D, X, Y = synth.random_blr_tiles(args.seed, m, n, b, r)
+        Xd = torch.tensor(X.reshape(p * q, b, r), device=dev)
+        Yt = torch.tensor(Y.reshape(p * q, b, r), device=dev).transpose(1, 2).contiguous()
+        tiles = torch.bmm(Xd, Yt)
+        del Xd, Yt
+        for k in range(q):
+            tiles[k * q + k] = torch.tensor(D[k], device=dev)
+        xd = tiles.reshape(p, q, b, b).permute(0, 2, 1, 3).reshape(m, n).contiguous()
+        yd = None
+        del tiles
+        print(f"[bench] {args.config}: random BLR matrix ready in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
+              flush=True)
+    else:
+        x, y = synth.kernel_points(args.seed, cfg["m"], cfg["n"], cfg["dim"])
+        xd, yd = torch.tensor(x, device=dev), torch.tensor(y, device=dev)
+        print(f"[bench] {args.config}: points ready in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
+              flush=True)
 
     main_prec = "mixed" if args.precision == "mixed" else "fp64"
     r = run(args, cfg, main_prec, cfg["tol"] if main_prec == "fp64" else args.mixed_tol, xd, yd, dev)
@@ -255,7 +287,9 @@ def main():
         "dtype": "f64" if main_prec == "fp64" else "f32-mfma+f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{cfg['m']}x{cfg['n']} {cfg['dim']}D {cfg['kernel']} kernel matrix, b={cfg['b']}, "
+            "workload": (f"{cfg['m']}x{cfg['n']} random BLR (rank-{cfg['rank']} off-diagonal tiles), b={cfg['b']}, "
+                         if cfg.get("kind") == "random_blr" else
+                         f"{cfg['m']}x{cfg['n']} {cfg['dim']}D {cfg['kernel']} kernel matrix, b={cfg['b']}, ") +
                         f"{cfg['rule']}, eps={r['tol']:g}, cap={cfg['cap']}, {args.variant} {main_prec}",
             "m": cfg["m"], "n": cfg["n"], "tile": cfg["b"], "tol": r["tol"], "max_rank": cfg["cap"],
             "variant": args.variant, "precision": main_prec, "config_id": args.config,

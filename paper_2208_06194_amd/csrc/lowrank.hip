@@ -19,10 +19,13 @@ namespace {
 
 constexpr double JACOBI_TOL = 1e-15;
 constexpr int JACOBI_MAX_SWEEPS = 40;
-constexpr int LDS_DIM = 64;
+constexpr int LDS_DIM = 64;      // Jacobi matrices of the compression SVD held in LDS up to this order
+constexpr int RC_LDS_DIM = 96;   // the rounded addition's core and rotations in LDS up to this order
 
 // Householder QR of rows x cols column-major X (global memory), in place:
 // R in the upper triangle, reflector tails below, tau[0 .. min(rows,cols)).
+// Each wave updates four trailing columns at a time (independent loads and
+// reductions in flight).
 __device__ void wg_hqr(double* X, int64_t ld, int rows, int cols, double* tau, double* red) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kmax = min(rows, cols);
@@ -44,31 +47,62 @@ __device__ void wg_hqr(double* X, int64_t ld, int rows, int cols, double* tau, d
     }
     __syncthreads();
     if (t != 0.0) {
-      for (int cc = c + 1 + wave; cc < cols; cc += 4) {
-        double s = 0.0;
-        for (int i = c + 1 + lane; i < rows; i += 64) s += X[i + c * ld] * X[i + cc * ld];
-        s = wave_sum(s) + X[c + cc * ld];
-        for (int i = c + 1 + lane; i < rows; i += 64) X[i + cc * ld] -= t * s * X[i + c * ld];
-        if (lane == 0) X[c + cc * ld] -= t * s;
+      for (int c0 = c + 1 + 4 * wave; c0 < cols; c0 += 16) {
+        double sv[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int i = c + 1 + lane; i < rows; i += 64) {
+          const double v = X[i + c * ld];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (c0 + u < cols) sv[u] += v * X[i + (c0 + u) * ld];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) sv[u] = wave_sum(sv[u]) + ((c0 + u < cols) ? X[c + (c0 + u) * ld] : 0.0);
+        for (int i = c + 1 + lane; i < rows; i += 64) {
+          const double v = X[i + c * ld];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (c0 + u < cols) X[i + (c0 + u) * ld] -= t * sv[u] * v;
+        }
+        if (lane == 0) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (c0 + u < cols) X[c + (c0 + u) * ld] -= t * sv[u];
+        }
       }
     }
     __syncthreads();
   }
 }
 
-// C <- Q C with Q = H_0 ... H_{k-1} stored as reflectors in X (rows x k).
+// C <- Q C with Q = H_0 ... H_{k-1} stored as reflectors in X (rows x k);
+// four columns of C per wave at a time.
 __device__ void wg_apply_q(const double* X, int64_t ld, int rows, int k, const double* tau,
                            double* C, int64_t ldc, int nc) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int c = k - 1; c >= 0; --c) {
     const double t = tau[c];
     if (t != 0.0) {
-      for (int j = wave; j < nc; j += 4) {
-        double s = 0.0;
-        for (int i = c + 1 + lane; i < rows; i += 64) s += X[i + c * ld] * C[i + j * ldc];
-        s = wave_sum(s) + C[c + j * ldc];
-        for (int i = c + 1 + lane; i < rows; i += 64) C[i + j * ldc] -= t * s * X[i + c * ld];
-        if (lane == 0) C[c + j * ldc] -= t * s;
+      for (int j0 = 4 * wave; j0 < nc; j0 += 16) {
+        double sv[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int i = c + 1 + lane; i < rows; i += 64) {
+          const double v = X[i + c * ld];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (j0 + u < nc) sv[u] += v * C[i + (j0 + u) * ldc];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) sv[u] = wave_sum(sv[u]) + ((j0 + u < nc) ? C[c + (j0 + u) * ldc] : 0.0);
+        for (int i = c + 1 + lane; i < rows; i += 64) {
+          const double v = X[i + c * ld];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (j0 + u < nc) C[i + (j0 + u) * ldc] -= t * sv[u] * v;
+        }
+        if (lane == 0) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (j0 + u < nc) C[c + (j0 + u) * ldc] -= t * sv[u];
+        }
       }
     }
     __syncthreads();
@@ -96,36 +130,40 @@ __device__ void wg_jacobi(double* Z, int64_t ldz, int nr, int nc, double* J, int
     return;
   }
   const int n2 = nc + (nc & 1);
-  const int g = tid >> 4, gl = tid & 15;
+  // lanes per column pair: every pair of a round in one batch once there
+  // are at least 16 pairs (64 groups of 4 lanes), else groups of 16 lanes
+  const int GW = (n2 / 2 >= 16) ? 4 : 16;
+  const int NG = 256 / GW;
+  const int g = tid / GW, gl = tid % GW;
   for (int sweep = 0; sweep < JACOBI_MAX_SWEEPS; ++sweep) {
     if (tid == 0) *flag = 0;
     __syncthreads();
     for (int round = 0; round < n2 - 1; ++round) {
-      for (int pi = g; pi < n2 / 2; pi += 16) {
+      for (int pi = g; pi < n2 / 2; pi += NG) {
         int a, bq;
         rr_pair(pi, round, n2, &a, &bq);
         if (a >= nc || bq >= nc) continue;
         const int p = min(a, bq), q = max(a, bq);
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = gl; i < nr; i += 16) {
+        for (int i = gl; i < nr; i += GW) {
           const double zp = Z[i + p * ldz], zq = Z[i + q * ldz];
           al += zp * zp;
           be += zq * zq;
           ga += zp * zq;
         }
-        al = group_sum(al, 16);
-        be = group_sum(be, 16);
-        ga = group_sum(ga, 16);
+        al = group_sum(al, GW);
+        be = group_sum(be, GW);
+        ga = group_sum(ga, GW);
         if (ga != 0.0 && fabs(ga) > JACOBI_TOL * sqrt(al * be)) {
           const double zeta = (be - al) / (2.0 * ga);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-          for (int i = gl; i < nr; i += 16) {
+          for (int i = gl; i < nr; i += GW) {
             const double zp = Z[i + p * ldz], zq = Z[i + q * ldz];
             Z[i + p * ldz] = cs * zp - sn * zq;
             Z[i + q * ldz] = sn * zp + cs * zq;
           }
-          for (int i = gl; i < nc; i += 16) {
+          for (int i = gl; i < nc; i += GW) {
             const double jp = J[i + p * ldj], jq = J[i + q * ldj];
             J[i + p * ldj] = cs * jp - sn * jq;
             J[i + q * ldj] = sn * jp + cs * jq;
@@ -171,8 +209,8 @@ __device__ void record_overflow(const RcParams& P, double dropped_rel) {
 
 __global__ __launch_bounds__(256) void k_recompress(const RcDesc* __restrict__ descs, RcParams P) {
   __shared__ double red[16];
-  __shared__ double zl[LDS_DIM * LDS_DIM];
-  __shared__ double jl[LDS_DIM * LDS_DIM];
+  __shared__ double zl[RC_LDS_DIM * RC_LDS_DIM];
+  __shared__ double jl[RC_LDS_DIM * RC_LDS_DIM];
   __shared__ double sig[384];
   __shared__ int perm[384];
   __shared__ int ranks[3];
@@ -223,16 +261,45 @@ __global__ __launch_bounds__(256) void k_recompress(const RcDesc* __restrict__ d
   wg_hqr(WU, b, b, s, tauU, red);
   wg_hqr(WV, b, b, s, tauV, red);
   const int k = min(b, s);
-  const bool lds = k <= LDS_DIM;
+  const bool lds = k <= RC_LDS_DIM && s <= RC_LDS_DIM;
   double* Z = lds ? zl : Zg;
   double* J = lds ? jl : Jg;
   const int64_t ldz = k, ldj = k;
   // Z = R_V R_U^T  (k x k)
-  for (int e = tid; e < k * k; e += 256) {
-    const int i = e % k, j = e / k;
-    double acc = 0.0;
-    for (int l = max(i, j); l < s; ++l) acc += WV[i + (size_t)l * b] * WU[j + (size_t)l * b];
-    Z[i + j * ldz] = acc;
+  if (lds) {
+    // R_V and R_U (k x s upper triangles) staged in LDS; the products are
+    // held in registers until both stagings are no longer read
+    for (int e = tid; e < k * s; e += 256) {
+      const int i = e % k, l = e / k;
+      zl[e] = (l >= i) ? WV[i + (size_t)l * b] : 0.0;
+      jl[e] = (l >= i) ? WU[i + (size_t)l * b] : 0.0;
+    }
+    __syncthreads();
+    constexpr int ZPT = (RC_LDS_DIM * RC_LDS_DIM + 255) / 256;
+    double zr[ZPT];
+#pragma unroll
+    for (int u = 0; u < ZPT; ++u) {
+      const int e = tid + 256 * u;
+      double acc = 0.0;
+      if (e < k * k) {
+        const int i = e % k, j = e / k;
+        for (int l = max(i, j); l < s; ++l) acc += zl[i + l * k] * jl[j + l * k];
+      }
+      zr[u] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < ZPT; ++u) {
+      const int e = tid + 256 * u;
+      if (e < k * k) zl[e] = zr[u];
+    }
+  } else {
+    for (int e = tid; e < k * k; e += 256) {
+      const int i = e % k, j = e / k;
+      double acc = 0.0;
+      for (int l = max(i, j); l < s; ++l) acc += WV[i + (size_t)l * b] * WU[j + (size_t)l * b];
+      Z[i + j * ldz] = acc;
+    }
   }
   __syncthreads();
   wg_jacobi(Z, ldz, k, k, J, ldj, &flag);

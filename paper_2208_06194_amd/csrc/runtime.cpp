@@ -1267,8 +1267,17 @@ void plan_blockcol(blr_matrix h, Plan& P, Work& w, BcWork& bw, int kend, bool fp
       P.record(e_panel(k + 1));
       P.cur_stream = 0;
     };
-    plan_bc_update(h, P, w, bw, k, k + 1, k + 2, fp32, k + 2, next_panel);
-    plan_bc_update(h, P, w, bw, k, k + 2, q, fp32, q, nullptr);
+    // the look-ahead column gets a pass of its own when its Z is dense (a
+    // short split product); a low-rank Z would add a second sequential chain
+    // of rounded additions, so then one pass covers every column
+    std::vector<int8_t> f((size_t)h->p * q);
+    for (size_t t = 0; t < f.size(); ++t) f[t] = h->tiles[t].fmt;
+    if (bc_zdense(h, f, k, k + 1)) {
+      plan_bc_update(h, P, w, bw, k, k + 1, k + 2, fp32, k + 2, next_panel);
+      plan_bc_update(h, P, w, bw, k, k + 2, q, fp32, q, nullptr);
+    } else {
+      plan_bc_update(h, P, w, bw, k, k + 1, q, fp32, k + 2, next_panel);
+    }
   }
   P.cur_stream = 0;
 }

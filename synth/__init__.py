@@ -100,6 +100,28 @@ def rhs(seed: int, m: int, nrhs: int) -> np.ndarray:
     return normal(seed, STREAM_RHS, m * nrhs).reshape(nrhs, m).T.copy()
 
 
+def random_blr_tiles(seed: int, m: int, n: int, b: int, rank: int):
+    """The draws of random_blr_dense as tile factors, without forming the
+    dense matrix: D[k] (b x b) for the diagonal tiles (k,k), k < n/b, and
+    X[i,j], Y[i,j] (b x rank) for every other tile, so that tile (i,j) of
+    random_blr_dense is X[i,j] @ Y[i,j].T.  X and Y of diagonal tiles are zero."""
+    p, q = m // b, n // b
+    per = b * max(b, 2 * rank)
+    D = np.empty((q, b, b))
+    X = np.zeros((p, q, b, rank))
+    Y = np.zeros((p, q, b, rank))
+    for i in range(p):
+        for j in range(q):
+            off = (i * q + j) * per
+            if i == j:
+                D[i] = normal(seed, STREAM_TILES, b * b, off).reshape(b, b)
+            else:
+                g = normal(seed, STREAM_TILES, 2 * b * rank, off)
+                X[i, j] = g[: b * rank].reshape(b, rank)
+                Y[i, j] = g[b * rank:].reshape(b, rank)
+    return D, X, Y
+
+
 def random_blr_dense(seed: int, m: int, n: int, b: int, rank: int) -> np.ndarray:
     """Random BLR test matrix (the random-BLR workload of the paper's first
     experiment): diagonal tiles (k,k), k < n/b, are N(0,1) dense; every other

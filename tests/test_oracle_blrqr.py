@@ -241,3 +241,17 @@ def test_planted_mistakes_fail_the_dense_pin(monkeypatch, slip):
     A = np.random.default_rng(9).standard_normal((48, 24))
     f = tiled.factor(all_dense(A, 8), 1e-12, 8)
     assert metrics.r_rel_diff(f.r_dense(), np.linalg.qr(A, mode="r")) > 1e-6
+
+
+def test_random_blr_tiles_are_the_dense_generator_draws():
+    """The tile-factor form of the random-BLR workload (used at benchmark
+    size) draws exactly the values of the dense generator."""
+    m, n, b, r = 96, 64, 16, 3
+    A = synth.random_blr_dense(4, m, n, b, r)
+    D, X, Y = synth.random_blr_tiles(4, m, n, b, r)
+    for i in range(m // b):
+        for j in range(n // b):
+            blk = A[i * b:(i + 1) * b, j * b:(j + 1) * b]
+            ref = D[i] if i == j else X[i, j] @ Y[i, j].T
+            assert np.array_equal(blk, ref)
+
