@@ -238,7 +238,7 @@ def main():
                     help="exploration only: factor the first K block columns (not a valid metric)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "runs on one GPU only (the factorization is single-device); --gpus must be 1"}))
         sys.exit(2)
 
     import torch

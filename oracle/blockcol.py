@@ -10,7 +10,10 @@ Step k:
      A_ij -= Ytilde_ik W_j (eq. blr_bch_apply_bc_reflector).  Reading of the
      accumulation: if any term is dense the sum is dense (OP1) and all terms
      are added exactly; otherwise the low-rank terms are accumulated by
-     rounded addition in the order i = k, k+1, ... (OP2, Alg. 6).
+     rounded additions of two terms at a time (OP2, Alg. 6) in a pairwise
+     tree: the terms in order i = k, k+1, ... are the leaves, each level adds
+     neighbouring pairs (the left one first in the stack), an odd one out
+     passes to the next level unchanged.
 """
 from __future__ import annotations
 
@@ -19,6 +22,19 @@ import numpy as np
 from . import blrops, dense
 from .blrmat import BLR, DENSE, LOWRANK
 from .factor import Factor
+
+
+def pairwise_sum(terms, add):
+    """Sum terms[0] + terms[1] + ... two at a time in a pairwise tree: at
+    stride s = 1, 2, 4, ... term x (x a multiple of 2s) absorbs term x + s."""
+    terms = list(terms)
+    n = len(terms)
+    s = 1
+    while s < n:
+        for x in range(0, n - s, 2 * s):
+            terms[x] = add(terms[x], terms[x + s])
+        s *= 2
+    return terms[0]
 
 
 class BlockColumnFactor(Factor):
@@ -60,9 +76,7 @@ class BlockColumnFactor(Factor):
         if any(t[0] == "D" for t in terms):
             Z = ("D", sum(blrops.dense_of(t) for t in terms))
         else:
-            Z = terms[0]
-            for t in terms[1:]:
-                Z = blrops.add(Z, t, 1.0, e, c, st)
+            Z = pairwise_sum(terms, lambda a, t: blrops.add(a, t, 1.0, e, c, st))
         W = blrops.t_times(self.Tk[k], Z, True)
         for i in range(k, self.p):
             upd = blrops.y_times(self.yrep(i, k), W)

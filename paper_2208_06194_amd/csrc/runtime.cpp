@@ -742,7 +742,7 @@ void plan_apply_tiled(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, in
 // the tiles, then for every j > k form Z_j = sum_i Ytilde_ik^T A_ij,
 // W_j = T_k^T Z_j and apply A_ij -= Ytilde_ik W_j with the OP1/OP2 rules:
 // Z_j is dense if any term is dense, else the low-rank terms are summed by
-// rounded additions in order i = k, k+1, ...
+// rounded additions of two terms at a time in a pairwise tree.
 
 constexpr int kGramSlices = 16;
 constexpr int kApplySlices = 64;
@@ -753,6 +753,7 @@ struct BcSlot {
   double *Sa;        // rc x b
   double *Sm;        // rc x rc
   double *rcw;       // recompression workspace
+  int* rank;         // rank of a partial sum of Z_j kept in (Ub, Sa)
 };
 
 struct BcWork {
@@ -824,6 +825,7 @@ BcWork make_bc_work(blr_matrix h, int npairs) {
   const size_t per = 2 * (size_t)b * rc + (size_t)rc * b + (size_t)rc * rc + rcwd;
   if (npairs > 0) {
     double* base = (double*)A.alloc((size_t)npairs * per * 8);
+    int* ranks = (int*)A.alloc((size_t)npairs * sizeof(int));
     for (int a = 0; a < npairs; ++a) {
       double* x = base + (size_t)a * per;
       BcSlot sl;
@@ -832,6 +834,7 @@ BcWork make_bc_work(blr_matrix h, int npairs) {
       sl.Sa = x + 2 * (size_t)b * rc;
       sl.Sm = sl.Sa + (size_t)rc * b;
       sl.rcw = sl.Sm + (size_t)rc * rc;
+      sl.rank = ranks + a;
       bw.slots.push_back(sl);
     }
   }
@@ -1035,10 +1038,11 @@ void plan_bc_panel(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k) {
 // Trailing update of the columns j in [j0, j1) by the reflectors of step k
 // (Section 3.3.2): Z_j = sum_i Ytilde_ik^T A_ij, W_j = T_k^T Z_j and
 // A_ij -= Ytilde_ik W_j with the OP1/OP2 rules: Z_j is dense if any term is
-// dense, else the low-rank terms are summed by rounded additions in order
-// i = k, k+1, ...  Z and W are formed for every column first; the updates
-// A_ij -= Ytilde_ik W_j then run for the columns below jsplit, mid() is
-// called (the look-ahead hook), and the remaining columns follow.
+// dense, else the low-rank terms are summed by rounded additions of two terms
+// at a time in a pairwise tree over the order i = k, k+1, ...  Z and W are
+// formed for every column first; the updates A_ij -= Ytilde_ik W_j then run
+// for the columns below jsplit, mid() is called (the look-ahead hook), and
+// the remaining columns follow.
 void plan_bc_update(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k, int j0, int j1, bool fp32,
                     int jsplit, const std::function<void()>& mid) {
   const int b = h->b, rc = h->rc, p = h->p, q = h->q;
@@ -1134,31 +1138,45 @@ void plan_bc_update(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k, int j0, i
   }
   P.flush_gemm(fp32, 1);
   if (!zred.empty()) P.copy(zred);
-  // 4c. low-rank Z_j: rounded additions of the terms in order i = k, k+1, ...
-  std::vector<RcTerm> zterm(q);
-  auto term = [&](int i, int j) -> RcTerm {
-    Tile& A = h->t(i, j);
-    if (A.fmt == LOWRANK) return RcTerm{S(i, j).Ua, A.Vt, A.rank, b, rc, 0, 0, 1.0};
-    return RcTerm{h->t(i, k).Vt, S(i, j).Sa, h->t(i, k).rank, rc, rc, 0, 1, 1.0};
-  };
-  for (int j = j0; j < j1; ++j)
-    if (!zd[j]) zterm[j] = term(k, j);
-  for (int i = k + 1; i < p; ++i) {
+  // 4c. low-rank Z_j: rounded additions of two terms at a time in a pairwise
+  // tree whose leaves are the terms in order i = k, k+1, ...: at stride
+  // s = 1, 2, 4, ... term x absorbs term x + s (x a multiple of 2s).  The sum
+  // goes to the slot of the left term (U into Ub, V^T into Sa, in place from
+  // the second level on; the recompression reads its inputs before it writes),
+  // so every level is one batch of independent problems.
+  const int nt = p - k;
+  std::vector<std::vector<RcTerm>> tv(q);
+  for (int j = j0; j < j1; ++j) {
+    if (zd[j]) continue;
+    tv[j].resize(nt);
+    for (int x = 0; x < nt; ++x) {
+      Tile& A = h->t(k + x, j);
+      tv[j][x] = A.fmt == LOWRANK ? RcTerm{S(k + x, j).Ua, A.Vt, A.rank, b, rc, 0, 0, 1.0}
+                                  : RcTerm{h->t(k + x, k).Vt, S(k + x, j).Sa, h->t(k + x, k).rank, rc, rc, 0, 1, 1.0};
+    }
+  }
+  for (int st = 1; st < nt; st *= 2) {
     for (int j = j0; j < j1; ++j) {
       if (zd[j]) continue;
-      RcDesc d{};
-      d.nterm = 2;
-      d.t[0] = zterm[j];
-      d.t[1] = term(i, j);
-      d.Uout = w.Uw[j];
-      d.Vtout = w.Vtw[j];
-      d.rank_out = w.rankw[j];
-      d.work = w.rcw[2 * j];
-      P.rc(d);
-      zterm[j] = RcTerm{w.Uw[j], w.Vtw[j], w.rankw[j], b, rc, 0, 0, 1.0};
+      for (int x = 0; x + st < nt; x += 2 * st) {
+        BcSlot& sl = S(k + x, j);
+        RcDesc d{};
+        d.nterm = 2;
+        d.t[0] = tv[j][x];
+        d.t[1] = tv[j][x + st];
+        d.Uout = sl.Ub;
+        d.Vtout = sl.Sa;
+        d.rank_out = sl.rank;
+        d.work = sl.rcw;
+        P.rc(d);
+        tv[j][x] = RcTerm{sl.Ub, sl.Sa, sl.rank, b, rc, 0, 0, 1.0};
+      }
     }
     P.flush_rc();
   }
+  std::vector<RcTerm> zterm(q);
+  for (int j = j0; j < j1; ++j)
+    if (!zd[j]) zterm[j] = tv[j][0];
   // 5. W_j = T_k^T Z_j
   for (int j = j0; j < j1; ++j) {
     if (zd[j]) P.gemm(w.X2[j], b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, Tk, b, w.X[j], b, b, SEG_TRANS_A | SEG_A_UPPER);

@@ -255,3 +255,13 @@ def test_random_blr_tiles_are_the_dense_generator_draws():
             ref = D[i] if i == j else X[i, j] @ Y[i, j].T
             assert np.array_equal(blk, ref)
 
+
+def test_pairwise_sum_order():
+    """The block-column accumulation order: a pairwise tree over the terms
+    in index order (checked on strings, where the order is visible)."""
+    from oracle.blockcol import pairwise_sum
+    cat = lambda a, b: "(" + a + "+" + b + ")"
+    assert pairwise_sum(["a"], cat) == "a"
+    assert pairwise_sum(["a", "b", "c"], cat) == "((a+b)+c)"
+    assert pairwise_sum(list("abcde"), cat) == "(((a+b)+(c+d))+e)"
+    assert pairwise_sum(list("abcdefgh"), cat) == "(((a+b)+(c+d))+((e+f)+(g+h)))"
