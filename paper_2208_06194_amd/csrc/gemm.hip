@@ -270,11 +270,14 @@ __device__ __forceinline__ void gemm_fast_body(const GemmDesc* __restrict__ desc
         for (int v = 0; v < 4; ++v) acc64[i][j][v] = 0.0;
   }
 
-  // PF2 (FP64 operands): two register sets, the global loads run two K steps
-  // ahead and the LDS writes of the next step are issued after the first
-  // quarter of a step's matrix-core work, so both overlap the rest of it.
+  // PF2 (FP64 operands, A transposed): two register sets, the global loads
+  // run two K steps ahead and the LDS writes of the next step are issued
+  // after the first quarter of a step's matrix-core work, so both overlap the
+  // rest of it.  The untransposed FP64 form (the trailing updates, which run
+  // beside the panel kernels) keeps one set: at 216 registers two of its waves
+  // leave room on each SIMD for one wave of the tall-panel column kernel.
   // FP32 operands keep one set (their occupancy depends on the registers).
-  constexpr bool PF2 = sizeof(CT) == 8;
+  constexpr bool PF2 = sizeof(CT) == 8 && TA;
   d2v ra0[NV], rb0[NV];
   d2v ra1[PF2 ? NV : 1], rb1[PF2 ? NV : 1];
   for (int sgi = 0; sgi < d.nseg; ++sgi) {

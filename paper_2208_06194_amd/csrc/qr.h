@@ -55,7 +55,7 @@ hipError_t launch_panel(const PanelArgs& a, hipStream_t stream);
 // One launch per column of a tall panel (two for its first column), over
 // groups row groups (1 .. kTallMaxGroups); ib must be 16 or 32.
 constexpr int kTallMaxGroups = 512;
-constexpr int kTallThreads = 512;   // threads per row group (one row each for 512-row groups)
+constexpr int kTallThreads = 256;   // threads per row group (two rows each for 512-row groups)
 hipError_t launch_tall_column(const TallArgs& a, int groups, hipStream_t stream);
 // Split-K trailing update of a tall panel over 1 .. kTallApplySlices row
 // slices; part: slices * ceil(nt/32) * ib * 32 doubles.

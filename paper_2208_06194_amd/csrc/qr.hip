@@ -399,7 +399,6 @@ __global__ __launch_bounds__(kTallThreads) void k_tall_step(TallArgs a) {
   __shared__ double acc[NT / IB][2 * IB];
   __shared__ double sv[2 * IB];   // [0, IB): dots of column jj (its tail sum of squares at jj); [IB, 2 IB): pivot row
   __shared__ double wv[IB];
-  __shared__ double red[NT / 64][IB];
   const int tid = threadIdx.x, G = gridDim.x, g = blockIdx.x;
   const int jj = a.jj;
   const int64_t ld = a.ldx;
@@ -440,46 +439,53 @@ __global__ __launch_bounds__(kTallThreads) void k_tall_step(TallArgs a) {
   tall_rows(a.h, G, g, &rs, &re);
   const int nx = jj + 1;   // next column
   const bool more = nx < IB;
-  double part[IB];
-#pragma unroll
-  for (int t = 0; t < IB; ++t) part[t] = 0.0;
   // 2. reflector column jj and rank-one update of the later columns on this
-  // group's rows, streamed column by column so that only the partial sums
-  // of the next column stay live across a row
-  for (int r = max(rs, jj + 1) + tid; r < re; r += NT) {
-    const double v = a.X[r + (int64_t)jj * ld] * scal;
-    a.X[r + (int64_t)jj * ld] = v;
-    if (more && r == nx) {
-      // the next pivot row: snapshot it after this update
+  // group's rows.  Lanes take consecutive rows, wave w the columns
+  // t = w, w + NW, ...: each thread keeps one partial sum per column it owns
+  // and recomputes v and the updated next column for its row (the other
+  // waves' loads of those two columns hit the cache), so the kernel needs few
+  // registers and shares compute units with long-running GEMM workgroups.
+  // The trip count of the row loop is the same for every thread (it holds a
+  // barrier).
+  constexpr int NW = NT / 64, CPW = IB / NW;
+  static_assert(IB % NW == 0, "columns per wave");
+  const int lane = tid & 63, w = tid >> 6;
+  double part[CPW];
 #pragma unroll
-      for (int t = 0; t < IB; ++t) {
-        double x = t == jj ? v : a.X[r + (int64_t)t * ld];
-        if (t > jj) {
-          x -= tau * wv[t] * v;
-          a.X[r + (int64_t)t * ld] = x;
-        }
-        out[(int64_t)G * (2 * IB) + t] = x;
-      }
-      continue;
+  for (int u = 0; u < CPW; ++u) part[u] = 0.0;
+  const double twn = more ? tau * wv[nx] : 0.0;
+  for (int r0 = rs; r0 < re; r0 += 64) {
+    const int r = r0 + lane;
+    const bool act = r < re && r > jj;
+    double vr = 0.0, xr = 0.0;
+    if (act) {
+      vr = a.X[r + (int64_t)jj * ld];
+      if (more) xr = a.X[r + (int64_t)nx * ld];
     }
-    double xn = 0.0;
-    if (more) {
-      xn = a.X[r + (int64_t)nx * ld] - tau * wv[nx] * v;
-      a.X[r + (int64_t)nx * ld] = xn;
-    }
+    // every wave has read columns jj and nx of these rows before the waves
+    // owning them write them back
+    __syncthreads();
+    if (!act) continue;
+    const double v = vr * scal;
+    const double xn = more ? xr - twn * v : 0.0;
+    const bool pivot = more && r == nx;   // the next pivot row: snapshot it after this update
 #pragma unroll
-    for (int t = 0; t < IB; ++t) {
-      if (t > nx) {
-        double x = a.X[r + (int64_t)t * ld] - tau * wv[t] * v;
+    for (int u = 0; u < CPW; ++u) {
+      const int t = w + NW * u;
+      double x;
+      if (t == jj) {
+        x = v;
+        a.X[r + (int64_t)t * ld] = v;
+      } else if (t > jj) {
+        if (!more) continue;
+        x = a.X[r + (int64_t)t * ld] - tau * wv[t] * v;
         a.X[r + (int64_t)t * ld] = x;
-        part[t] += xn * x;
-      } else if (t == nx) {
-        part[t] += xn * xn;
-      } else if (t == jj) {
-        part[t] += xn * v;
-      } else if (more) {   // t < jj: final reflector entries
-        part[t] += xn * a.X[r + (int64_t)t * ld];
+      } else {   // t < jj: final reflector entries
+        if (!more) continue;
+        x = a.X[r + (int64_t)t * ld];
       }
+      if (pivot) out[(int64_t)G * (2 * IB) + t] = x;
+      else part[u] += xn * x;
     }
   }
   // 3. the group holding row jj: pivot row, tau, column jj of T
@@ -497,8 +503,15 @@ __global__ __launch_bounds__(kTallThreads) void k_tall_step(TallArgs a) {
       a.T[tid + (int64_t)jj * a.ldt] = -tau * s;
     }
   }
-  // 4. partials of the next column
-  if (more) tall_store_partials<IB, NT>(part, red, out, g);
+  // 4. partials of the next column: each column's sum over this group's rows
+  // lives in one wave
+  if (more) {
+#pragma unroll
+    for (int u = 0; u < CPW; ++u) {
+      const double s = wave_sum(part[u]);
+      if (lane == 0) out[(int64_t)g * (2 * IB) + w + NW * u] = s;
+    }
+  }
 }
 
 // Split-K trailing update of a tall panel (V unit lower, h rows, IB columns)
