@@ -340,16 +340,24 @@ __device__ __forceinline__ void gemm_fast_body(const GemmDesc* __restrict__ desc
     __syncthreads();  // previous segment's last reads of buffer 0 are done
     lstore(ra0, rb0, 0);
     if constexpr (PF2) {
-      if (nsteps > 1) gload(ra1, rb1, 1);
+      // pairs of steps with no branch inside: the loads past the end repeat
+      // the last step and their LDS copies go to the buffer nobody reads, so
+      // every pass has the same loads in flight and the wait before an LDS
+      // write covers only the register set it writes
+      const int last = nsteps - 1;
+      gload(ra1, rb1, min(1, last));
       __syncthreads();
-      for (int st = 0; st < nsteps; st += 2) {
+      for (int st = 0; st + 1 < nsteps; st += 2) {
         // even step: buffer 0; set 1 holds step st + 1, set 0 takes step st + 2
-        if (st + 2 < nsteps) gload(ra0, rb0, st + 2);
-        step(st, 0, ra1, rb1, st + 1 < nsteps);
-        if (st + 1 >= nsteps) break;
+        gload(ra0, rb0, min(st + 2, last));
+        step(st, 0, ra1, rb1, true);
         // odd step: buffer 1; set 0 holds step st + 2, set 1 takes step st + 3
-        if (st + 3 < nsteps) gload(ra1, rb1, st + 3);
-        step(st + 1, 1, ra0, rb0, st + 2 < nsteps);
+        gload(ra1, rb1, min(st + 3, last));
+        step(st + 1, 1, ra0, rb0, true);
+      }
+      if (nsteps & 1) {   // the last step, already in buffer 0
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) kstep(0, kk);
       }
     } else {
       // one register set: loads one step ahead, LDS writes after the step
