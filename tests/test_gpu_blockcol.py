@@ -188,3 +188,53 @@ def test_blockcol_mixed_precision(P):
     res = np.linalg.norm(QR - At) / np.linalg.norm(At)
     print("mixed Res", res, flush=True)
     assert res <= 1e-5
+
+
+def random_blr(seed, m, n, b, rank, eps, cap):
+    """The random-BLR matrix of the paper's first experiment: dense N(0,1)
+    diagonal tiles, rank-`rank` outer products elsewhere (weak admissibility)."""
+    D, X, Y = synth.random_blr_tiles(seed, m, n, b, rank)
+    p, q = m // b, n // b
+    A = np.empty((m, n))
+    for i in range(p):
+        for j in range(q):
+            A[i * b:(i + 1) * b, j * b:(j + 1) * b] = D[j] if i == j else X[i, j] @ Y[i, j].T
+    mask = np.ones((p, q), bool)
+    mask[np.arange(q), np.arange(q)] = False
+    return A, blrmat.compress(A, b, eps, cap, mask)
+
+
+@pytest.mark.parametrize("cap", [64, 32])
+def test_blockcol_random_blr_matches_oracle(P, cap):
+    """Every off-diagonal tile low-rank: Z_j of each step is a pairwise tree of
+    up to 16 rounded additions.  cap = b never truncates (the ranks reach 44);
+    cap 32 truncates (the oracle: 83 times, Res 1.7e-3) in both
+    factorizations, whose residuals then agree to six digits."""
+    m, n, b, eps = 1024, 512, 64, 1e-10
+    print("case: blockcol random BLR", m, n, b, cap, flush=True)
+    A, blr = random_blr(9, m, n, b, 2, eps, cap)
+    At = blr.to_dense()
+    f = blockcol.factor(blr, eps, cap)
+    G = gpu_import(P, blr, eps, cap)
+    G.factor("block_column")
+    ex = G.export(with_factor=True)
+    assert np.array_equal(ex["fmt"], f.A.fmt)
+    Rg = export_r(ex)
+    RR = np.zeros((m, n))
+    RR[:n] = Rg
+    QR = G.apply_qt(torch.tensor(RR, device="cuda"), trans=True).cpu().numpy()
+    res = np.linalg.norm(QR - At) / np.linalg.norm(At)
+    res_o = metrics.res(f, At)
+    info = G.info()
+    print("Res GPU", res, "oracle", res_o, "truncations GPU", info["factor_overflow"], "oracle", f.stats.overflow,
+          flush=True)
+    if cap == b:
+        assert info["factor_overflow"] == 0 and f.stats.overflow == 0
+        assert res <= 10 * eps and res_o <= 10 * eps
+        Ro = f.r_dense()
+        kappa = np.linalg.cond(At)
+        assert np.linalg.norm(metrics.sign_fix(Rg, Ro) - Ro) / np.linalg.norm(Ro) <= 10 * kappa * eps
+    else:
+        # the same truncations (up to ties at the threshold), the same residual
+        assert f.stats.overflow > 0 and abs(info["factor_overflow"] - f.stats.overflow) <= 2
+        assert abs(res - res_o) <= 1e-6 * res_o
