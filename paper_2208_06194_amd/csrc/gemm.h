@@ -53,10 +53,12 @@ constexpr int kFastKStep32 = 16;
 enum GemmMode {
   GEMM_SMALL = 0, GEMM_BIG = 1,
   GEMM_FAST_NN = 2, GEMM_FAST_TN = 3, GEMM_FAST_NT = 4, GEMM_FAST_TT = 5,
+  GEMM_SKINNY_N = 6, GEMM_SKINNY_T = 7,   // FP64, N <= 16, B not transposed: 64-row tiles
 };
 
 // Launch host wrapper: descs / segs are device arrays; ntiles = total WG tiles
-// (tiles of 64 for GEMM_SMALL, 128 otherwise).  fp32 = 1 computes in FP32 on
+// (tiles of 64 x 64 for GEMM_SMALL, 64 x 16 for the skinny modes, 128 x 128
+// otherwise).  fp32 = 1 computes in FP32 on
 // the matrix cores (operands rounded to FP32, FP32 accumulation); fp32 = 2
 // (fast modes) also rounds operands to FP32 but adds the FP32 partial sums
 // into FP64 accumulators every 1024 of K and at every segment end.

@@ -191,6 +191,106 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   }
 }
 
+// Skinny products (N <= 16, FP64): the applications of Q^T / Q and the
+// back-substitution sums with a few right-hand sides.  These read each tile of
+// A once and do 2 * N flops per element, so they are bound by HBM; the
+// 64 x 64 MFMA tile would compute four times the useful work.  A workgroup
+// owns 64 rows of C and all (<= 16) columns; its four waves take interleaved
+// 16-deep K blocks and sum their 64 x 16 partials through LDS in a fixed
+// order.  Operands go straight from global memory into the MFMA registers:
+// for A transposed a lane reads four consecutive k of one column (lane group
+// g takes k = 4g .. 4g + 3 of each block and steps through them), otherwise
+// sixteen lanes read sixteen consecutive rows of one k column.
+template <bool TA>
+__global__ __launch_bounds__(256) void k_gemm_skinny(const GemmDesc* __restrict__ descs, int ndesc,
+                                                     const GemmSeg* __restrict__ segs) {
+  constexpr int BM = 64, BKS = 16;
+  __shared__ double red[3][BM / 16][4][64];
+  const int wg = blockIdx.x;
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].tile_begin <= wg) lo = mid;
+    else hi = mid - 1;
+  }
+  const GemmDesc d = descs[lo];
+  const int m0 = (wg - d.tile_begin) * BM;
+  const int M = d.M, N = d.N;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lm = lane & 15, lg = lane >> 4;
+  v4d acc[BM / 16];
+#pragma unroll
+  for (int i = 0; i < BM / 16; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int s = 0; s < d.nseg; ++s) {
+    const GemmSeg sg = segs[d.seg_begin + s];
+    const bool aul = sg.flags & SEG_A_UNIT_LOWER;
+    int kbeg = 0, kend = sg.K;
+    if (aul) {
+      if (TA) kbeg = max(kbeg, m0);
+      else kend = min(kend, m0 + BM);
+    }
+    kbeg = (kbeg / BKS) * BKS;
+    const double* __restrict__ Ap = sg.A;
+    const double* __restrict__ Bp = sg.B;
+    const int64_t lda = sg.lda, ldb = sg.ldb;
+    for (int k0 = kbeg + wave * BKS; k0 < kend; k0 += 4 * BKS) {
+      // B: lane (n = lm, group lg) holds k = k0 + 4 lg + u, u = 0..3
+      double bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + 4 * lg + u;
+        bv[u] = (lm < N && k < kend) ? Bp[k + (int64_t)lm * ldb] : 0.0;
+      }
+      double av[BM / 16][4];
+#pragma unroll
+      for (int i = 0; i < BM / 16; ++i) {
+        const int m = m0 + 16 * i + lm;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + 4 * lg + u;
+          double x = 0.0;
+          if (m < M && k < kend) {
+            const int64_t row = TA ? k : m, col = TA ? m : k;
+            x = Ap[row + col * lda];
+            if (aul) x = unit_lower_mask(x, row, col);
+          }
+          av[i][u] = x;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int i = 0; i < BM / 16; ++i) acc[i] = mfma_op(av[i][u], bv[u], acc[i]);
+    }
+  }
+  // waves 1..3 hand their partials to wave 0, which adds them in wave order
+  if (wave > 0) {
+#pragma unroll
+    for (int i = 0; i < BM / 16; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[wave - 1][i][v][lane] = acc[i][v];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+  const int col = lm;
+  if (col >= N) return;
+#pragma unroll
+  for (int i = 0; i < BM / 16; ++i) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = m0 + 16 * i + 4 * v + lg;   // FP64 16x16x4 layout: row 4 v + lane / 16
+      if (row >= M) continue;
+      const double raw = ((acc[i][v] + red[0][i][v][lane]) + red[1][i][v][lane]) + red[2][i][v][lane];
+      if (d.C) {
+        double c = d.alpha * raw;
+        if (d.Cin) c += d.beta * d.Cin[row + (int64_t)col * d.ldcin];
+        d.C[row + (int64_t)col * d.ldc] = c;
+      }
+      if (d.D2) d.D2[row + (int64_t)col * d.ldd2] = raw;
+    }
+  }
+}
+
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) const d2v gd2v;
 
@@ -447,6 +547,14 @@ hipError_t launch_gemm(const GemmDesc* d_descs, int ndesc, const GemmSeg* d_segs
       break;
     case GEMM_FAST_TT:
       if (fp32) BLR_FAST(float, true, true); else BLR_FAST(double, true, true);
+      break;
+    case GEMM_SKINNY_N:
+      if (fp32) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_gemm_skinny<false>), grid, block, 0, stream, d_descs, ndesc, d_segs);
+      break;
+    case GEMM_SKINNY_T:
+      if (fp32) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_gemm_skinny<true>), grid, block, 0, stream, d_descs, ndesc, d_segs);
       break;
     default:
       return hipErrorInvalidValue;

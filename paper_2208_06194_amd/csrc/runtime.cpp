@@ -146,7 +146,26 @@ void Plan::flush_gemm(int fp32, int prof, bool allow_fast) {
       big = ta ? (tb ? GEMM_FAST_TT : GEMM_FAST_TN) : (tb ? GEMM_FAST_NT : GEMM_FAST_NN);
     }
   }
-  const int BM = big == GEMM_SMALL ? 64 : 128;
+  // FP64 products with at most 16 columns (Q^T B, Q B, the back-substitution
+  // sums, basis products with a few right-hand sides) take the skinny kernel
+  if (!fp32) {
+    bool sk = true;
+    int ta = -1;
+    for (auto& d : cur) {
+      if (d.N > 16 || (d.flags & DESC_LOWER_ONLY)) { sk = false; break; }
+      for (int si = 0; si < d.nseg && sk; ++si) {
+        const int f = curseg[d.seg_begin + si].flags;
+        const int t = (f & SEG_TRANS_A) ? 1 : 0;
+        if ((f & (SEG_TRANS_B | SEG_B_UNIT_LOWER)) || (ta >= 0 && t != ta)) sk = false;
+        ta = t;
+      }
+      if (!sk) break;
+    }
+    if (sk && ta >= 0) big = ta ? GEMM_SKINNY_T : GEMM_SKINNY_N;
+  }
+  const bool skinny = big == GEMM_SKINNY_N || big == GEMM_SKINNY_T;
+  const int BM = (big == GEMM_SMALL || skinny) ? 64 : 128;
+  const int BN = skinny ? 16 : BM;
   // FP32 products with long K sums accumulate in FP64 between K chunks
   if (fp32 && big >= GEMM_FAST_NN) {
     int64_t kmax = 0;
@@ -170,7 +189,7 @@ void Plan::flush_gemm(int fp32, int prof, bool allow_fast) {
   for (auto& d : cur) {
     d.tilesM = (d.M + BM - 1) / BM;
     d.tile_begin = tiles;
-    tiles += d.tilesM * ((d.N + BM - 1) / BM);
+    tiles += d.tilesM * ((d.N + BN - 1) / BN);
     d.seg_begin += segbase;
     descs.push_back(d);
   }

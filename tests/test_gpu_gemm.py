@@ -41,7 +41,8 @@ def lib():
 
 
 SHAPES = [(16, 16, 4), (64, 64, 64), (50, 70, 33), (300, 260, 130), (256, 512, 256), (1024, 128, 1024),
-          (256, 256, 272), (512, 384, 1056)]  # K % 32 == 16: FP64 leaves the 32-deep fast path
+          (256, 256, 272), (512, 384, 1056),  # K % 32 == 16: FP64 leaves the 32-deep fast path
+          (1000, 16, 3000), (4096, 5, 1024), (130, 1, 77)]  # N <= 16: the skinny kernel (B not transposed)
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -53,7 +54,7 @@ def test_gemm_fp64(lib, shape, flags):
 
 
 @pytest.mark.parametrize("flags", [1 | 4, 4, 1 | 8, 8, 1 | 4 | 16, 2 | 16])
-@pytest.mark.parametrize("shape", [(192, 160, 192), (256, 384, 256)])
+@pytest.mark.parametrize("shape", [(192, 160, 192), (256, 384, 256), (320, 16, 320)])
 def test_gemm_triangular_modes(lib, flags, shape):
     # 256 x 384 runs the fast full-tile kernel for the upper-triangular A modes
     print("case: gemm triangular", flags, shape, flush=True)
