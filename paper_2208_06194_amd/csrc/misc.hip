@@ -111,47 +111,122 @@ __global__ void k_frob2(const Frob2Desc* __restrict__ d) {
   if (threadIdx.x == 0) *D.out = s;
 }
 
-// X <- R^{-1} X for upper-triangular R (n x n, ld ldr), X n x nrhs.  One
-// wave per right-hand side; lane l keeps the solution entries t = l mod 64
-// in LDS, so every lane only ever reads what it wrote itself.
-__global__ __launch_bounds__(256) void k_trsm_upper(const double* __restrict__ R, int64_t ldr, int n,
-                                                    double* X, int64_t ldx, int nrhs) {
-  extern __shared__ double xs[];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int c = blockIdx.x * 4 + wave;
-  if (c >= nrhs) return;
-  double* xl = xs + (size_t)wave * n;
-  double* x = X + (int64_t)c * ldx;
-  for (int r = n - 1; r >= 0; --r) {
-    double s = 0.0;
-    for (int t = r + 1 + ((lane - (r + 1)) & 63); t < n; t += 64) s += R[r + (int64_t)t * ldr] * xl[t];
-    s = wave_sum(s);
-    const double xr = (x[r] - s) / R[r + (int64_t)r * ldr];
-    if ((r & 63) == lane) xl[r] = xr;
-  }
-  for (int t = lane; t < n; t += 64) x[t] = xl[t];
+// Blocked triangular solves with the upper triangular R (n x n, ld ldr):
+// TRANS = false solves R X = C (back substitution, 64-row blocks from the
+// bottom), TRANS = true solves R^T X = C (forward substitution, blocks from
+// the top).  One workgroup of 8 waves per group of up to 16 right-hand
+// sides, X overwritten in place.  Each diagonal block is staged in LDS with
+// the reciprocals of its diagonal and solved by four waves, four right-hand
+// sides each (lanes on rows; the solved value of each step read from its
+// lane with readlane).  Then all waves subtract the block's contribution from
+// the rows still to be solved (right-looking) as a matrix-core product:
+// op(R)(rows, block), 16-row tiles loaded from global memory eight K steps at
+// a time, times the block's solution from LDS.
+constexpr int kTrsmB = 64, kTrsmR = 16, kTrsmThreads = 512;
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-
-// R^T x = c for upper triangular R (forward substitution), one wave per
-// right-hand side; column r of R is contiguous, so the dot product of step r
-// reads it coalesced.
-__global__ __launch_bounds__(256) void k_trsm_upper_t(const double* __restrict__ R, int64_t ldr, int n,
-                                                      double* X, int64_t ldx, int nrhs) {
-  extern __shared__ double xs[];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int c = blockIdx.x * 4 + wave;
-  if (c >= nrhs) return;
-  double* xl = xs + (size_t)wave * n;
-  double* x = X + (int64_t)c * ldx;
-  for (int r = 0; r < n; ++r) {
-    double s = 0.0;
-    for (int t = lane; t < r; t += 64) s += R[t + (int64_t)r * ldr] * xl[t];
-    s = wave_sum(s);
-    const double xr = (x[r] - s) / R[r + (int64_t)r * ldr];
-    if ((r & 63) == lane) xl[r] = xr;
-    __builtin_amdgcn_wave_barrier();
+template <bool TRANS>
+__global__ __launch_bounds__(kTrsmThreads) void k_trsm_blk(const double* __restrict__ R, int64_t ldr, int n,
+                                                           double* X, int64_t ldx, int nrhs) {
+  constexpr int NW = kTrsmThreads / 64;
+  __shared__ double Rs[kTrsmB][kTrsmB + 1];   // op(R) of the diagonal block: Rs[row][col]
+  __shared__ double dinv[kTrsmB];
+  __shared__ double xs[kTrsmB][kTrsmR];       // the block's solution (zero past the block and nrhs)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lm = lane & 15, lg = lane >> 4;
+  const int c0 = blockIdx.x * kTrsmR;
+  const int nr = min(kTrsmR, nrhs - c0);
+  double* Xc = X + (int64_t)c0 * ldx;
+  const int nb = (n + kTrsmB - 1) / kTrsmB;
+  for (int bi = 0; bi < nb; ++bi) {
+    const int blk = TRANS ? bi : nb - 1 - bi;
+    const int r0 = blk * kTrsmB, r1 = min(n, r0 + kTrsmB), bs = r1 - r0;
+    for (int e = tid; e < kTrsmB * kTrsmB; e += kTrsmThreads) {
+      const int i = e % kTrsmB, j = e / kTrsmB;
+      double v = 0.0;
+      if (i < bs && j < bs)
+        v = TRANS ? R[(r0 + j) + (int64_t)(r0 + i) * ldr] : R[(r0 + i) + (int64_t)(r0 + j) * ldr];
+      Rs[i][j] = v;
+    }
+    if (tid < kTrsmB) {
+      const double d = tid < bs ? (TRANS ? R[(r0 + tid) + (int64_t)(r0 + tid) * ldr]
+                                         : R[(r0 + tid) + (int64_t)(r0 + tid) * ldr])
+                                : 1.0;
+      dinv[tid] = 1.0 / d;
+    }
+    __syncthreads();
+    if (wave < kTrsmR / 4) {
+      // wave w solves right-hand sides 4w .. 4w + 3 of the group
+      const int r = r0 + lane;
+      double c[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int cu = 4 * wave + u;
+        c[u] = (lane < bs && cu < nr) ? Xc[r + (int64_t)cu * ldx] : 0.0;
+      }
+      for (int st = 0; st < bs; ++st) {
+        const int i = TRANS ? st : bs - 1 - st;
+        const double rinv = dinv[i];
+        const double a = Rs[lane][i];
+        const bool upd = TRANS ? (lane > i) : (lane < i);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double xi = readlane_f64(c[u], i) * rinv;
+          if (upd) c[u] -= a * xi;
+          if (lane == i) c[u] = xi;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int cu = 4 * wave + u;
+        xs[lane][cu] = c[u];
+        if (lane < bs && cu < nr) Xc[r + (int64_t)cu * ldx] = c[u];
+      }
+    }
+    __syncthreads();
+    // rows [ua, ub) still to solve: C(rows) -= op(R)(rows, r0:r1) x_block
+    const int ua = TRANS ? r1 : 0, ub = TRANS ? n : r0;
+    const int ntile = (ub - ua + 15) / 16;
+    for (int t0 = wave * 4; t0 < ntile; t0 += 4 * NW) {
+      v4d acc[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+      for (int half = 0; half < 2; ++half) {
+        double av[4][8];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int kk = 0; kk < 8; ++kk) {
+            const int k = 4 * (8 * half + kk) + lg;
+            const int row = ua + 16 * (t0 + q) + lm;
+            double v = 0.0;
+            if (t0 + q < ntile && row < ub && k < bs)
+              v = TRANS ? R[(r0 + k) + (int64_t)row * ldr] : R[row + (int64_t)(r0 + k) * ldr];
+            av[q][kk] = v;
+          }
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+          const double bv = xs[4 * (8 * half + kk) + lg][lm];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q][kk], bv, acc[q], 0, 0, 0);
+        }
+      }
+      // FP64 16x16x4 layout: lane holds column lane % 16, accumulator v row 4 v + lane / 16
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = ua + 16 * (t0 + q) + 4 * v + lg;
+          if (t0 + q < ntile && row < ub && lm < nr) Xc[row + (int64_t)lm * ldx] -= acc[q][v];
+        }
+    }
+    __syncthreads();
   }
-  for (int t = lane; t < n; t += 64) x[t] = xl[t];
 }
 
 // out = a x + b y + c z over a rows x cols column-major block (y, z may be null).
@@ -235,17 +310,17 @@ hipError_t launch_frob2(const Frob2Desc* d, int n, hipStream_t s) {
 
 hipError_t launch_trsm_upper(const double* R, int64_t ldr, int n, double* X, int64_t ldx, int nrhs,
                              hipStream_t s) {
-  if (nrhs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_trsm_upper, dim3((nrhs + 3) / 4), dim3(256), (size_t)4 * n * sizeof(double), s, R,
-                     ldr, n, X, ldx, nrhs);
+  if (nrhs <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_trsm_blk<false>, dim3((nrhs + kTrsmR - 1) / kTrsmR), dim3(kTrsmThreads), 0, s, R, ldr, n,
+                     X, ldx, nrhs);
   return hipGetLastError();
 }
 
 hipError_t launch_trsm_upper_t(const double* R, int64_t ldr, int n, double* X, int64_t ldx, int nrhs,
                                hipStream_t s) {
-  if (nrhs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_trsm_upper_t, dim3((nrhs + 3) / 4), dim3(256), (size_t)4 * n * sizeof(double), s, R,
-                     ldr, n, X, ldx, nrhs);
+  if (nrhs <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_trsm_blk<true>, dim3((nrhs + kTrsmR - 1) / kTrsmR), dim3(kTrsmThreads), 0, s, R, ldr, n,
+                     X, ldx, nrhs);
   return hipGetLastError();
 }
 

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import blrmat, metrics, tiled
+from oracle import blockcol, blrmat, metrics, tiled
 from oracle.blrmat import LOWRANK
 from oracle.factor import SingularR
 from tests.blr_helpers import blr_to_host, export_r
@@ -51,6 +51,26 @@ def test_lstsq_matches_oracle(P, rule, kern, dim):
     r_true = np.linalg.norm(Bh - f.q_times_r() @ X, axis=0)
     assert np.allclose(res, r_true, rtol=1e-6)
     # normal-equation optimality for the factored matrix
+    assert np.all(metrics.eta_ne(f.q_times_r(), X, Bh) <= 1e3 * n * U)
+
+
+@pytest.mark.parametrize("variant", ["tiled", "block_column"])
+def test_lstsq_many_rhs_ragged_blocks(P, variant):
+    """20 right-hand sides (two groups of the triangular solve: 16 and 4) and
+    b = 96 (a full and a ragged 64-row block per diagonal tile)."""
+    print("case: lstsq 20 rhs b 96", variant, flush=True)
+    m, n, b, eps, cap = 768, 384, 96, 1e-8, 32
+    A, blr = kernel_blr(21, m, n, b, eps, cap)
+    At = blr.to_dense()
+    mod = tiled if variant == "tiled" else blockcol
+    f = mod.factor(blr, eps, cap)
+    Bh = synth.rhs(21, m, 20)
+    Xo = f.lstsq(Bh)
+    G = gpu_import(P, blr, eps, cap)
+    G.factor(variant)
+    X = G.lstsq(torch.tensor(Bh, device="cuda")).cpu().numpy()
+    kappa = np.linalg.cond(At)
+    assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) <= 10 * kappa * eps
     assert np.all(metrics.eta_ne(f.q_times_r(), X, Bh) <= 1e3 * n * U)
 
 
