@@ -35,6 +35,7 @@ CONFIGS = {
     "wr": dict(m=8192, n=4096, b=128, kind="random_blr", rank=1, rule="weak", tol=1e-10, cap=128),
 }
 PEAK = {"fp64": 78.6e12, "mixed": 157.3e12}   # MI355X dense matrix-core peaks (FP64, FP32)
+HBM_PEAK_TBS = 8.0                                # MI355X HBM3E bandwidth, TB/s
 
 # HBM traffic per launch of the dominant kernel, from two rocprofv3 --pmc passes
 # (FETCH_SIZE, WRITE_SIZE) over the factor's launches, scaled by what the same
@@ -189,6 +190,13 @@ def run(args, cfg, precision, tol, xd, yd, dev):
             G.lstsq(rhs)
             torch.cuda.synchronize()
             solve = {"nrhs": 16, "apply_qt_s": f0.elapsed_time(f1) / 1e3, "lstsq_s": time.perf_counter() - t0}
+            # HBM roofline of Q^T B: the reflectors are read twice (Y^T B, then
+            # B -= Y W), counted as if every tile were dense
+            b, m, q = cfg["b"], cfg["m"], cfg["n"] // cfg["b"]
+            ybytes = sum((m - k * b) * b * 8 for k in range(q))
+            solve["apply_qt_bytes_dense_equiv"] = 2 * ybytes
+            solve["apply_qt_gbs"] = 2 * ybytes / solve["apply_qt_s"] / 1e9
+            solve["apply_qt_hbm_frac"] = solve["apply_qt_gbs"] / (HBM_PEAK_TBS * 1e3)
             print(f"[bench] {precision}: apply Q^T {solve['apply_qt_s']:.3f}s lstsq {solve['lstsq_s']:.3f}s "
                   f"(16 right-hand sides)", file=sys.stderr, flush=True)
         del G
