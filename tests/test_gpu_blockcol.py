@@ -238,3 +238,34 @@ def test_blockcol_random_blr_matches_oracle(P, cap):
         # the same truncations (up to ties at the threshold), the same residual
         assert f.stats.overflow > 0 and abs(info["factor_overflow"] - f.stats.overflow) <= 2
         assert abs(res - res_o) <= 1e-6 * res_o
+
+
+@pytest.mark.parametrize("cap", [64, 32])
+def test_tiled_random_blr_matches_oracle(P, cap):
+    """The tiled factor (Alg. 4) of the same random BLR matrices: every TPMQRT
+    with a low-rank tile runs its recompressions.  cap = b never truncates;
+    cap 32 truncates (the oracle: 112 times, Res 9.1e-4) in both."""
+    m, n, b, eps = 1024, 512, 64, 1e-10
+    print("case: tiled random BLR", m, n, b, cap, flush=True)
+    A, blr = random_blr(9, m, n, b, 2, eps, cap)
+    At = blr.to_dense()
+    f = tiled.factor(blr, eps, cap)
+    G = gpu_import(P, blr, eps, cap)
+    G.factor("tiled")
+    ex = G.export()
+    assert np.array_equal(ex["fmt"], f.A.fmt)
+    Rg = export_r(ex)
+    RR = np.zeros((m, n))
+    RR[:n] = Rg
+    QR = G.apply_qt(torch.tensor(RR, device="cuda"), trans=True).cpu().numpy()
+    res = np.linalg.norm(QR - At) / np.linalg.norm(At)
+    res_o = metrics.res(f, At)
+    info = G.info()
+    print("Res GPU", res, "oracle", res_o, "truncations GPU", info["factor_overflow"], "oracle", f.stats.overflow,
+          flush=True)
+    if cap == b:
+        assert info["factor_overflow"] == 0 and f.stats.overflow == 0
+        assert res <= 10 * eps and res_o <= 10 * eps
+    else:
+        assert f.stats.overflow > 0 and abs(info["factor_overflow"] - f.stats.overflow) <= 2
+        assert abs(res - res_o) <= 1e-6 * res_o
