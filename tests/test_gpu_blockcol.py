@@ -204,13 +204,14 @@ def random_blr(seed, m, n, b, rank, eps, cap):
     return A, blrmat.compress(A, b, eps, cap, mask)
 
 
-@pytest.mark.parametrize("cap", [64, 32])
-def test_blockcol_random_blr_matches_oracle(P, cap):
+@pytest.mark.parametrize("b,cap", [(64, 64), (64, 32), (128, 128)])
+def test_blockcol_random_blr_matches_oracle(P, b, cap):
     """Every off-diagonal tile low-rank: Z_j of each step is a pairwise tree of
-    up to 16 rounded additions.  cap = b never truncates (the ranks reach 44);
-    cap 32 truncates (the oracle: 83 times, Res 1.7e-3) in both
-    factorizations, whose residuals then agree to six digits."""
-    m, n, b, eps = 1024, 512, 64, 1e-10
+    up to 16 rounded additions.  cap = b never truncates (the ranks reach 44
+    at b = 64); cap 32 truncates (the oracle: 83 times, Res 1.7e-3) in both
+    factorizations, whose residuals then agree to six digits.  At b = 128
+    the rank capacity is 128, and the cores grow past the LDS-staged size."""
+    m, n, eps = 1024, 512, 1e-10
     print("case: blockcol random BLR", m, n, b, cap, flush=True)
     A, blr = random_blr(9, m, n, b, 2, eps, cap)
     At = blr.to_dense()
@@ -240,12 +241,12 @@ def test_blockcol_random_blr_matches_oracle(P, cap):
         assert abs(res - res_o) <= 1e-6 * res_o
 
 
-@pytest.mark.parametrize("cap", [64, 32])
-def test_tiled_random_blr_matches_oracle(P, cap):
+@pytest.mark.parametrize("b,cap", [(64, 64), (64, 32), (128, 128)])
+def test_tiled_random_blr_matches_oracle(P, b, cap):
     """The tiled factor (Alg. 4) of the same random BLR matrices: every TPMQRT
     with a low-rank tile runs its recompressions.  cap = b never truncates;
     cap 32 truncates (the oracle: 112 times, Res 9.1e-4) in both."""
-    m, n, b, eps = 1024, 512, 64, 1e-10
+    m, n, eps = 1024, 512, 1e-10
     print("case: tiled random BLR", m, n, b, cap, flush=True)
     A, blr = random_blr(9, m, n, b, 2, eps, cap)
     At = blr.to_dense()
