@@ -44,8 +44,8 @@ HBM_PEAK_TBS = 8.0                                # MI355X HBM3E bandwidth, TB/s
 # the counters were taken on (sha256 of csrc/gemm.hip); otherwise null.
 TRAFFIC = {
     ("c3", "fp64", "block_column"): {
-        "gemm_sha256": "364d155cdedbcf7e2b25b21821e65a5c1bacfe226e9adcaa437009134ff95b3e",
-        "bytes_per_launch": 9709683113,
+        "gemm_sha256": "44b99667909767a3c5dccc9e2959ecb03f79b3cbd70f075dca30acf38ef68d67",
+        "bytes_per_launch": 9709666765,
     },
 }
 
