@@ -140,6 +140,21 @@ typedef struct blr_tiles_host {
   double* T;
 } blr_tiles_host;
 
+/* Morton (Z-order) ordering of n points (dim 1..3, row-major FP64, device
+ * pointer pts), the input preparation of a kernel-matrix workload: tiles of
+ * consecutive points in this order are spatially compact, so the
+ * admissibility test of Section 3.1 finds far-field tiles.  Each coordinate
+ * is quantised to 2^21 levels (floor(x * 2^21), clamped to [0, 2^21 - 1];
+ * coordinates are expected in [0, 1)), the bits are interleaved most
+ * significant first in coordinate order, and the points are sorted by key,
+ * ties by original index.  perm (device, n int64, required) receives the
+ * original index of the r-th point in that order; sorted (device, n x dim
+ * row-major, may be NULL) receives the points in that order.  Allocates
+ * temporary device memory and synchronises the stream.  Errors:
+ * BLR_ERR_INVALID for NULL pts/perm, n < 0 or dim outside 1..3. */
+blr_status blr_morton_sort(const double* pts, int64_t n, int32_t dim, int64_t* perm, double* sorted,
+                           void* hip_stream);
+
 /* Compress a kernel or dense matrix into a new BLR handle (Section 3.1:
  * admissibility, then a truncated SVD of each admissible tile to the
  * smallest rank meeting the tolerance; U orthonormal, V = W Sigma).

@@ -12,7 +12,7 @@ c_int32, c_int64, c_double, c_void_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_
 EXPORTED = [
     "blr_compress", "blr_import", "blr_export", "blr_qr_factor", "blr_apply_qt",
     "blr_lstsq_solve", "blr_query", "blr_destroy", "blr_status_string", "blr_last_error",
-    "blr_profile_enable", "blr_profile_read", "blr_matmul",
+    "blr_profile_enable", "blr_profile_read", "blr_matmul", "blr_morton_sort",
 ]
 SELFTEST = ["blr_selftest_gemm"]
 MATMUL = {"A": 0, "AT": 1, "R": 2}
@@ -77,6 +77,7 @@ def load() -> ctypes.CDLL:
     lib.blr_lstsq_solve.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int32, c_int32,
                                     c_void_p, c_void_p]
     lib.blr_matmul.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_void_p, c_int64, c_int32, c_void_p]
+    lib.blr_morton_sort.argtypes = [c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p]
     lib.blr_query.argtypes = [c_void_p, P(Info)]
     lib.blr_destroy.argtypes = [c_void_p]
     lib.blr_destroy.restype = None

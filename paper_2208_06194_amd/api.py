@@ -45,6 +45,18 @@ def _ptr(a: np.ndarray | None):
     return None if a is None else a.ctypes.data
 
 
+def morton_sort(pts: torch.Tensor, stream=None):
+    """Morton (Z-order) ordering of (n, dim) device points with coordinates in
+    [0, 1): returns (the points in that order, the permutation as int64)."""
+    lib = L.load()
+    pts = pts.contiguous().to(torch.float64)
+    n, dim = pts.shape
+    perm = torch.empty(n, dtype=torch.int64, device=pts.device)
+    out = torch.empty_like(pts)
+    _check(lib.blr_morton_sort(pts.data_ptr(), n, dim, perm.data_ptr(), out.data_ptr(), _stream(stream)))
+    return out, perm
+
+
 class BLRMatrix:
     """A BLR matrix owned by the library (one handle)."""
 

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libblrqr.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["gemm.hip", "qr.hip", "lowrank.hip", "misc.hip", "runtime.cpp"]
+SOURCES = ["gemm.hip", "qr.hip", "lowrank.hip", "misc.hip", "morton.hip", "runtime.cpp"]
 ARCH = os.environ.get("BLRQR_ARCH", "gfx950")
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -2209,6 +2209,13 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
   });
 }
 
+blr_status blr_morton_sort(const double* pts, int64_t n, int32_t dim, int64_t* perm, double* sorted,
+                           void* stream) {
+  if (!pts || !perm) return fail(BLR_ERR_INVALID, "NULL argument");
+  if (n < 0 || dim < 1 || dim > 3) return fail(BLR_ERR_INVALID, "n must be >= 0 and dim in 1..3");
+  return run_guarded([&] { HIPCHECK(morton_sort(pts, n, dim, perm, sorted, as_stream(stream))); });
+}
+
 blr_status blr_matmul(blr_matrix h, int32_t op, const double* X, int64_t ldx, double* Y, int64_t ldy,
                       int32_t nrhs, void* stream) {
   if (!h || !X || !Y) return fail(BLR_ERR_INVALID, "NULL argument");

@@ -11,6 +11,7 @@
 #include "gemm.h"
 #include "lowrank.h"
 #include "misc.h"
+#include "morton.h"
 #include "qr.h"
 
 namespace blr {

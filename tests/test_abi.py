@@ -49,3 +49,14 @@ def test_invalid_arguments_are_rejected_without_a_device():
         assert lib.blr_compress(ctypes.byref(src), ctypes.byref(o), None, ctypes.byref(h)) == L.BLR_ERR_INVALID
     assert lib.blr_qr_factor(None, None, None) == L.BLR_ERR_INVALID
     assert lib.blr_last_error() != b""
+
+
+def test_morton_sort_rejects_bad_arguments_without_a_device():
+    from paper_2208_06194_amd import _lib as L
+    lib = L.load()
+    p = ctypes.c_void_p(8)
+    assert lib.blr_morton_sort(None, 4, 2, p, None, None) == L.BLR_ERR_INVALID
+    assert lib.blr_morton_sort(p, 4, 2, None, None, None) == L.BLR_ERR_INVALID
+    assert lib.blr_morton_sort(p, -1, 2, p, None, None) == L.BLR_ERR_INVALID
+    assert lib.blr_morton_sort(p, 4, 4, p, None, None) == L.BLR_ERR_INVALID
+    assert lib.blr_morton_sort(p, 4, 0, p, None, None) == L.BLR_ERR_INVALID

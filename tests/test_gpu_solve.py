@@ -272,3 +272,26 @@ def test_refinement_requires_the_kept_copy(P):
     with pytest.raises(P.BLRError) as e:
         G.lstsq(torch.tensor(synth.rhs(14, m, 1), device="cuda"), max_refine=2)
     assert e.value.status == 2      # BLR_ERR_STATE
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_morton_sort_matches_host_order(P, dim):
+    """blr_morton_sort against the host Morton order (synth.morton_keys with a
+    stable sort): bit-exact permutation, including duplicated points (ties
+    keep the original order) and coordinates outside [0, 1) (clamped)."""
+    print("case: morton sort", dim, flush=True)
+    rng = np.random.default_rng(40 + dim)
+    pts = rng.random((100003, dim))
+    pts[7] = pts[3]
+    pts[11] = pts[3]
+    pts[20] = -0.25
+    pts[21] = 1.0
+    pts[22] = 1.75
+    out, perm = P.morton_sort(torch.tensor(pts, device="cuda"))
+    ref = np.argsort(synth.morton_keys(pts), kind="stable")
+    assert np.array_equal(perm.cpu().numpy(), ref)
+    assert np.array_equal(out.cpu().numpy(), pts[ref])
+    # the workload generator's points come out unchanged (already in order)
+    x, _ = synth.kernel_points(3, 4096, 2048, max(dim, 2))
+    _, perm2 = P.morton_sort(torch.tensor(x, device="cuda"))
+    assert np.array_equal(perm2.cpu().numpy(), np.arange(4096))
