@@ -10,7 +10,7 @@ never imports the library.  The two share no code: the only common module is
 Source: Apriansyah & Yokota, "Parallel QR Factorization of Block Low-Rank
 Matrices" (arXiv 2208.06194).  Each function cites the section, equation or
 algorithm it follows.  Where the paper is silent or garbled the reading taken
-is stated in the function and listed in the design doc.
+is stated in the function.
 
 Everything is float64 numpy.  Library primitives used as single steps: matrix
 products, ``numpy.linalg.qr`` (QR of the stacked bases in Alg. 6) and

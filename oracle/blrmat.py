@@ -2,7 +2,7 @@
 admissibility discussion after it).
 
 A BLR matrix has p x q tiles of size b x b; tile (i,j) is dense (fmt 0) or
-U V^T (fmt 1) with U orthonormal.  Readings (see DESIGN.md):
+U V^T (fmt 1) with U orthonormal.  Readings:
 * diagonal tiles (k,k), k < q, are always dense;
 * a cluster box is the tight axis-aligned box of the b consecutive points of a
   tile row/column (points are Morton sorted by the caller);

@@ -1,6 +1,6 @@
 """Dense Householder tile operations (paper Section 2.2-2.3, eq. compact WY).
 
-Conventions (readings, see DESIGN.md):
+Conventions (readings):
 * reflector generation follows LAPACK's larfg: for pivot alpha and tail x,
   beta = -sign(alpha) * ||(alpha, x)||, sign(0) = +1, tau = (beta - alpha)/beta,
   v = x / (alpha - beta) with an implicit leading 1; if ||x|| = 0 then tau = 0,

@@ -2,7 +2,7 @@
 rounded low-rank addition (paper Section 3.1, Alg. 6 "Rounded Low-Rank
 Addition", and the compression rule stated with eq. blr_matrix_def).
 
-Readings (see DESIGN.md):
+Readings:
 * Truncation rank r_eps is the smallest r with
       sqrt(sum_{l >= r} sigma_l^2) <= eps * sqrt(sum_l sigma_l^2),
   i.e. relative to the Frobenius norm of the matrix being (re)compressed

@@ -1,7 +1,7 @@
 """Accuracy metrics of Section 5 (Res and Orth) plus the least-squares
 normal-equation residual and a sign-insensitive comparison of R factors.
 
-Readings (see DESIGN.md): Res is reported against both the original matrix A
+Readings: Res is reported against both the original matrix A
 and the compressed matrix A~; Orth uses the thin factor Q1 = Q[:, :n] of the
 rectangular matrix, normalised by sqrt(n)."""
 from __future__ import annotations
