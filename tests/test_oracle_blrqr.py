@@ -265,3 +265,54 @@ def test_pairwise_sum_order():
     assert pairwise_sum(["a", "b", "c"], cat) == "((a+b)+c)"
     assert pairwise_sum(list("abcde"), cat) == "(((a+b)+(c+d))+e)"
     assert pairwise_sum(list("abcdefgh"), cat) == "(((a+b)+(c+d))+((e+f)+(g+h)))"
+
+
+def test_lstsq_adjoint_matches_finite_differences():
+    """The adjoint of x = argmin ||A x - b|| against central differences of
+    the exact least-squares map, for b, a dense entry of A and, through a
+    low-rank tile A_ij = U V^T, entries of U and V.  L = <Xbar, X>."""
+    from oracle import adjoint, blrmat
+    rng = np.random.default_rng(17)
+    m, n, b, nrhs = 48, 24, 8, 2
+    A0 = rng.standard_normal((m, n))
+    blr = blrmat.compress(A0, b, 1e-14, b, np.zeros((m // b, n // b), bool))
+    # one low-rank tile with rank 3 factors (U orthonormal), the rest dense
+    Uq, _ = np.linalg.qr(rng.standard_normal((b, 3)))
+    blr.fmt[4, 1] = 1
+    blr.U[(4, 1)], blr.V[(4, 1)] = Uq, rng.standard_normal((b, 3))
+    blr.D.pop((4, 1), None)
+    A = blr.to_dense()
+    B = rng.standard_normal((m, nrhs))
+    Xbar = rng.standard_normal((n, nrhs))
+    X, Bbar, Abar = adjoint.lstsq_adjoint(A, B, Xbar)
+    g = adjoint.tile_gradients(blr, Abar)
+    loss = lambda A_, B_: float(np.sum(Xbar * np.linalg.lstsq(A_, B_, rcond=None)[0]))
+    h = 1e-6
+    E = np.zeros_like(B); E[5, 1] = h
+    assert np.isclose((loss(A, B + E) - loss(A, B - E)) / (2 * h), Bbar[5, 1], rtol=1e-6, atol=1e-9)
+    E = np.zeros_like(A); E[10, 3] = h      # tile (1, 0), dense
+    assert blr.fmt[1, 0] == 0
+    assert np.isclose((loss(A + E, B) - loss(A - E, B)) / (2 * h), g[(1, 0)][1][10 - 8, 3], rtol=1e-6, atol=1e-9)
+    for which, (r, c) in (("U", (2, 1)), ("V", (6, 2))):
+        def dense_with(d):
+            U, V = blr.U[(4, 1)].copy(), blr.V[(4, 1)].copy()
+            (U if which == "U" else V)[r, c] += d
+            A_ = A.copy()
+            A_[32:40, 8:16] = U @ V.T
+            return A_
+        fd = (loss(dense_with(h), B) - loss(dense_with(-h), B)) / (2 * h)
+        an = g[(4, 1)][1 if which == "U" else 2][r, c]
+        assert np.isclose(fd, an, rtol=1e-6, atol=1e-9), (which, fd, an)
+
+
+def test_lstsq_adjoint_closed_form_square():
+    """Square nonsingular A: x = A^{-1} b, so bbar = A^{-T} xbar and
+    Abar = -bbar x^T (the residual is zero)."""
+    from oracle import adjoint
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((12, 12)) + 12 * np.eye(12)
+    B = rng.standard_normal((12, 2))
+    Xbar = rng.standard_normal((12, 2))
+    X, Bbar, Abar = adjoint.lstsq_adjoint(A, B, Xbar)
+    assert np.allclose(Bbar, np.linalg.solve(A.T, Xbar))
+    assert np.allclose(Abar, -Bbar @ X.T)
