@@ -140,6 +140,32 @@ typedef struct blr_tiles_host {
   double* T;
 } blr_tiles_host;
 
+/* X <- R^{-1} X (trans = 0) or X <- R^{-T} X (trans = 1) with the R factor of
+ * a factored handle (Section 3.3 / 3.4: R has the tile structure of A~), for
+ * X n x nrhs, column-major, device, ld ldx >= n, overwritten.  The blocked
+ * back- or forward substitution of the least-squares solve.  Synchronises
+ * the stream.  Errors: BLR_ERR_STATE if not (fully) factored. */
+blr_status blr_rsolve(blr_matrix h, int32_t trans, double* X, int64_t ldx, int32_t nrhs, void* hip_stream);
+
+/* Adjoint of the least-squares solve X = argmin ||A~ X - B||_F (full column
+ * rank; the use of the QR factorization that motivates the paper).  Given B
+ * (m x nrhs), the solution X (n x nrhs) and Xbar = dL/dX (n x nrhs) for a
+ * scalar loss L, computes Z = R^{-1} R^{-T} Xbar, the residual Rs = B - A~ X,
+ *   Bbar = dL/dB = A~ Z                                (m x nrhs, ld ldbb)
+ * and dL/dA~ = Rs Z^T - Bbar X^T restricted to the stored tiles of A~ (the
+ * matrix as compressed, kept by a factor made with keep_a):
+ *   dD: dense tile (i,j) gets its b x b block, column-major at offset
+ *       (i*q + j)*b*b;
+ *   dU, dV: low-rank tile U V^T (U, V b x rc as in blr_tiles_host) gets
+ *       dU = dA_ij V and dV = dA_ij^T U, b x rc column-major at offset
+ *       (i*q + j)*b*rc (columns past the rank are zero).
+ * All pointers are device memory; dD, dU and dV may be NULL to skip, and
+ * only the slots of tiles of the matching format are written.  Synchronises
+ * the stream.  Errors: BLR_ERR_STATE if not factored or A~ was not kept. */
+blr_status blr_lstsq_adjoint(blr_matrix h, const double* B, int64_t ldb, const double* X, int64_t ldx,
+                             const double* Xbar, int64_t ldxb, int32_t nrhs, double* Bbar, int64_t ldbb,
+                             double* dD, double* dU, double* dV, void* hip_stream);
+
 /* Morton (Z-order) ordering of n points (dim 1..3, row-major FP64, device
  * pointer pts), the input preparation of a kernel-matrix workload: tiles of
  * consecutive points in this order are spatially compact, so the

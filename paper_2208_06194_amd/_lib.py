@@ -12,7 +12,8 @@ c_int32, c_int64, c_double, c_void_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_
 EXPORTED = [
     "blr_compress", "blr_import", "blr_export", "blr_qr_factor", "blr_apply_qt",
     "blr_lstsq_solve", "blr_query", "blr_destroy", "blr_status_string", "blr_last_error",
-    "blr_profile_enable", "blr_profile_read", "blr_matmul", "blr_morton_sort",
+    "blr_profile_enable", "blr_profile_read", "blr_matmul", "blr_morton_sort", "blr_rsolve",
+    "blr_lstsq_adjoint",
 ]
 SELFTEST = ["blr_selftest_gemm"]
 MATMUL = {"A": 0, "AT": 1, "R": 2}
@@ -78,6 +79,9 @@ def load() -> ctypes.CDLL:
                                     c_void_p, c_void_p]
     lib.blr_matmul.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_void_p, c_int64, c_int32, c_void_p]
     lib.blr_morton_sort.argtypes = [c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p]
+    lib.blr_rsolve.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_int32, c_void_p]
+    lib.blr_lstsq_adjoint.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_int32,
+                                      c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.blr_query.argtypes = [c_void_p, P(Info)]
     lib.blr_destroy.argtypes = [c_void_p]
     lib.blr_destroy.restype = None

@@ -34,15 +34,44 @@ def _stream(stream=None) -> int:
     return stream.cuda_stream
 
 
-def _colmajor(t: torch.Tensor) -> torch.Tensor:
-    """(m, k) tensor -> contiguous (k, m) tensor holding its column-major image."""
+def _colmajor(t: torch.Tensor, copy: bool = False) -> torch.Tensor:
+    """(m, k) tensor -> contiguous (k, m) tensor holding its column-major image
+    (a new tensor when copy is set; otherwise it may share t's storage, which
+    is fine for arguments the library only reads)."""
     if t.dim() == 1:
         t = t[:, None]
-    return t.t().contiguous()
+    t = t.t()
+    return t.clone(memory_format=torch.contiguous_format) if copy else t.contiguous()
 
 
 def _ptr(a: np.ndarray | None):
     return None if a is None else a.ctypes.data
+
+
+class LstsqFunction(torch.autograd.Function):
+    """X = argmin ||A~ X - B|| as an autograd function.  G is a handle factored
+    with keep_a; D, U, V are the tensors the stored tiles of G were built from
+    ((p, q, b, b) dense blocks, (p, q, b, rc) low-rank factors): their values
+    are not read again, they receive the gradients of the stored tiles.  The
+    backward pass is the library's adjoint (blr_lstsq_adjoint)."""
+
+    @staticmethod
+    def forward(ctx, B, D, U, V, G):
+        X = G.lstsq(B)
+        ctx.G = G
+        ctx.save_for_backward(B, X)
+        return X
+
+    @staticmethod
+    def backward(ctx, Xbar):
+        B, X = ctx.saved_tensors
+        Bbar, dD, dU, dV = ctx.G.lstsq_adjoint(B, X, Xbar.contiguous())
+        return Bbar, dD, dU, dV, None
+
+
+def lstsq(G, B, D, U, V):
+    """Differentiable least-squares solve with the factored handle G (see LstsqFunction)."""
+    return LstsqFunction.apply(B, D, U, V, G)
 
 
 def morton_sort(pts: torch.Tensor, stream=None):
@@ -182,7 +211,7 @@ class BLRMatrix:
 
     def apply_qt(self, B: torch.Tensor, trans: bool = False, stream=None) -> torch.Tensor:
         """Return Q^T B (trans=False) or Q B (trans=True) for a (m, nrhs) device tensor."""
-        Bc = _colmajor(B.to(torch.float64))
+        Bc = _colmajor(B.to(torch.float64), copy=True)   # overwritten in place by the library
         nrhs, m = Bc.shape
         _check(L.load().blr_apply_qt(self._h, 1 if trans else 0, Bc.data_ptr(), m, nrhs, _stream(stream)))
         return Bc.t()
@@ -200,6 +229,33 @@ class BLRMatrix:
                                         None if res is None else res.data_ptr(), _stream(stream)))
         X = Xc.t()
         return (X, torch.sqrt(res)) if with_resid else X
+
+    def rsolve(self, X: torch.Tensor, trans: bool = False, stream=None) -> torch.Tensor:
+        """R^{-1} X (trans=False) or R^{-T} X (trans=True) for an (n, nrhs) device tensor."""
+        Xc = _colmajor(X.to(torch.float64), copy=True)   # overwritten in place by the library
+        nrhs, n = Xc.shape
+        _check(L.load().blr_rsolve(self._h, 1 if trans else 0, Xc.data_ptr(), n, nrhs, _stream(stream)))
+        return Xc.t()
+
+    def lstsq_adjoint(self, B: torch.Tensor, X: torch.Tensor, Xbar: torch.Tensor, stream=None):
+        """Gradients of a loss L(X) through X = argmin ||A~ X - B|| (the factor
+        must keep A~): returns (dL/dB, dL/dD, dL/dU, dL/dV).  dL/dD is (p, q, b, b)
+        with tile (i, j) holding dL/dA~ restricted to that tile (dense tiles
+        only; zero elsewhere); dL/dU and dL/dV are (p, q, b, rc) for the factors
+        U, V (b x rc) of the low-rank tiles (zero elsewhere)."""
+        inf = self.info()
+        m, n, p, q, b, rc = inf["m"], inf["n"], inf["p"], inf["q"], inf["tile"], inf["rank_capacity"]
+        Bc, Xc, Xbc = _colmajor(B.to(torch.float64)), _colmajor(X.to(torch.float64)), _colmajor(Xbar.to(torch.float64))
+        nrhs = Bc.shape[0]
+        dev = Bc.device
+        Bbar = torch.empty((nrhs, m), dtype=torch.float64, device=dev)
+        dD = torch.zeros((p, q, b, b), dtype=torch.float64, device=dev)     # per tile column-major: [i, j, col, row]
+        dU = torch.zeros((p, q, rc, b), dtype=torch.float64, device=dev)
+        dV = torch.zeros((p, q, rc, b), dtype=torch.float64, device=dev)
+        _check(L.load().blr_lstsq_adjoint(self._h, Bc.data_ptr(), m, Xc.data_ptr(), n, Xbc.data_ptr(), n, nrhs,
+                                          Bbar.data_ptr(), m, dD.data_ptr(), dU.data_ptr(), dV.data_ptr(),
+                                          _stream(stream)))
+        return Bbar.t(), dD.transpose(-1, -2), dU.transpose(-1, -2), dV.transpose(-1, -2)
 
     def profile(self, on: bool = True):
         _check(L.load().blr_profile_enable(self._h, 1 if on else 0))

@@ -2209,6 +2209,143 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
   });
 }
 
+blr_status blr_rsolve(blr_matrix h, int32_t trans, double* X, int64_t ldx, int32_t nrhs, void* stream) {
+  if (!h || !X) return fail(BLR_ERR_INVALID, "NULL argument");
+  if (trans != 0 && trans != 1) return fail(BLR_ERR_INVALID, "trans must be 0 or 1");
+  if (h->state != BLR_STATE_FACTORED) return fail(BLR_ERR_STATE, "matrix is not factored");
+  if (h->steps_done != h->q) return fail(BLR_ERR_STATE, "factorization is incomplete");
+  if (ldx < h->n || nrhs < 0) return fail(BLR_ERR_INVALID, "bad X shape");
+  if (nrhs == 0) return BLR_OK;
+  hipStream_t s = as_stream(stream);
+  return run_guarded([&] {
+    HIPCHECK(hipDeviceSynchronize());
+    h->work.release();
+    run_rsolve(h, X, ldx, nrhs, trans, s);
+    HIPCHECK(hipStreamSynchronize(s));
+  });
+}
+
+// Adjoint of X = argmin ||A~ X - B|| (full column rank): Z = R^{-1} R^{-T} Xbar,
+// Rs = B - A~ X, Bbar = A~ Z, and dL/dA~ = Rs Z^T - Bbar X^T restricted to the
+// stored tiles of A~ (dense: the b x b block; low-rank U V^T: dU = dA V and
+// dV = dA^T U, formed from small products with the factors).
+blr_status blr_lstsq_adjoint(blr_matrix h, const double* B, int64_t ldb, const double* X, int64_t ldx,
+                             const double* Xbar, int64_t ldxb, int32_t nrhs, double* Bbar, int64_t ldbb,
+                             double* dD, double* dU, double* dV, void* stream) {
+  if (!h || !B || !X || !Xbar || !Bbar) return fail(BLR_ERR_INVALID, "NULL argument");
+  if (h->state != BLR_STATE_FACTORED) return fail(BLR_ERR_STATE, "matrix is not factored");
+  if (h->steps_done != h->q) return fail(BLR_ERR_STATE, "factorization is incomplete");
+  if (h->acopy.empty()) return fail(BLR_ERR_STATE, "the adjoint needs the copy of A~ kept by a factor with keep_a");
+  if (ldb < h->m || ldx < h->n || ldxb < h->n || ldbb < h->m || nrhs < 0)
+    return fail(BLR_ERR_INVALID, "bad B, X, Xbar or Bbar shape");
+  if (nrhs == 0) return BLR_OK;
+  hipStream_t s = as_stream(stream);
+  return run_guarded([&] {
+    const int b = h->b, rc = h->rc, p = h->p, q = h->q;
+    const int64_t m = h->m, n = h->n;
+    HIPCHECK(hipDeviceSynchronize());
+    h->work.release();
+    double* Z = (double*)h->work.alloc((size_t)n * nrhs * 8);
+    double* Rs = (double*)h->work.alloc((size_t)m * nrhs * 8);
+    // Z = R^{-1} R^{-T} Xbar
+    HIPCHECK(hipMemcpy2DAsync(Z, n * 8, Xbar, ldxb * 8, n * 8, nrhs, hipMemcpyDeviceToDevice, s));
+    run_rsolve(h, Z, n, nrhs, 1, s);
+    run_rsolve(h, Z, n, nrhs, 0, s);
+    // Rs = B - A~ X, Bbar = A~ Z
+    {
+      Plan P;
+      plan_matmul(h, P, BLR_MATMUL_A, X, ldx, Rs, m, nrhs);
+      plan_matmul(h, P, BLR_MATMUL_A, Z, n, Bbar, ldbb, nrhs);
+      P.upload(h->work);
+      execute(h, P, s);
+    }
+    HIPCHECK(launch_lincomb(Rs, m, B, ldb, Rs, m, nullptr, 0, 1.0, -1.0, 0.0, (int)m, nrhs, s));
+    // tile gradients
+    std::vector<Tile>& T = h->acopy;
+    int nlr = 0;
+    for (auto& t : T) nlr += t.fmt == LOWRANK;
+    double* S = (double*)h->work.alloc((size_t)std::max(nlr, 1) * 4 * rc * nrhs * 8);
+    Plan P;
+    int l = 0;
+    for (int i = 0; i < p; ++i)
+      for (int j = 0; j < q; ++j) {
+        Tile& t = T[(size_t)i * q + j];
+        const double* Rsi = Rs + (int64_t)i * b;
+        const double* Bbi = Bbar + (int64_t)i * b;
+        const double* Zj = Z + (int64_t)j * b;
+        const double* Xj = X + (int64_t)j * b;
+        const size_t tix = (size_t)i * q + j;
+        if (t.fmt == DENSE) {
+          if (dD) P.gemm(dD + tix * b * b, b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, Rsi, m, Zj, n, nrhs,
+                         SEG_TRANS_B);
+        } else if (dU || dV) {
+          double* S1 = S + (size_t)l * 4 * rc * nrhs;   // V^T Z_j, V^T X_j, U^T Rs_i, U^T Bbar_i (rc x nrhs each)
+          P.gemm(S1, rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, t.Vt, rc, Zj, n, b, 0);
+          P.gemm(S1 + (size_t)rc * nrhs, rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, t.Vt, rc, Xj, ldx, b, 0);
+          P.gemm(S1 + (size_t)2 * rc * nrhs, rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, t.U, b, Rsi, m, b,
+                 SEG_TRANS_A);
+          P.gemm(S1 + (size_t)3 * rc * nrhs, rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, t.U, b, Bbi, ldbb, b,
+                 SEG_TRANS_A);
+          ++l;
+        }
+      }
+    P.flush_gemm(0, 0, false);
+    l = 0;
+    for (int i = 0; i < p; ++i)
+      for (int j = 0; j < q; ++j) {
+        Tile& t = T[(size_t)i * q + j];
+        const double* Rsi = Rs + (int64_t)i * b;
+        const double* Bbi = Bbar + (int64_t)i * b;
+        const double* Zj = Z + (int64_t)j * b;
+        const double* Xj = X + (int64_t)j * b;
+        const size_t tix = (size_t)i * q + j;
+        if (t.fmt == DENSE) {
+          if (dD) {
+            double* C = dD + tix * b * b;
+            P.gemm(C, b, C, b, nullptr, 0, b, b, -1.0, 1.0, Bbi, ldbb, Xj, ldx, nrhs, SEG_TRANS_B);
+          }
+        } else if (dU || dV) {
+          const double* S1 = S + (size_t)l * 4 * rc * nrhs;
+          if (dU) {   // dU = Rs_i (V^T Z_j)^T - Bbar_i (V^T X_j)^T
+            double* C = dU + tix * b * rc;
+            P.gemm(C, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, Rsi, m, S1, rc, nrhs, SEG_TRANS_B);
+          }
+          if (dV) {   // dV = Z_j (U^T Rs_i)^T - X_j (U^T Bbar_i)^T
+            double* C = dV + tix * b * rc;
+            P.gemm(C, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, Zj, n, S1 + (size_t)2 * rc * nrhs, rc, nrhs,
+                   SEG_TRANS_B);
+          }
+          ++l;
+        }
+      }
+    P.flush_gemm(0, 0, false);
+    l = 0;
+    for (int i = 0; i < p; ++i)
+      for (int j = 0; j < q; ++j) {
+        Tile& t = T[(size_t)i * q + j];
+        if (t.fmt == DENSE || !(dU || dV)) continue;
+        const double* Bbi = Bbar + (int64_t)i * b;
+        const double* Xj = X + (int64_t)j * b;
+        const size_t tix = (size_t)i * q + j;
+        const double* S1 = S + (size_t)l * 4 * rc * nrhs;
+        if (dU) {
+          double* C = dU + tix * b * rc;
+          P.gemm(C, b, C, b, nullptr, 0, b, rc, -1.0, 1.0, Bbi, ldbb, S1 + (size_t)rc * nrhs, rc, nrhs, SEG_TRANS_B);
+        }
+        if (dV) {
+          double* C = dV + tix * b * rc;
+          P.gemm(C, b, C, b, nullptr, 0, b, rc, -1.0, 1.0, Xj, ldx, S1 + (size_t)3 * rc * nrhs, rc, nrhs,
+                 SEG_TRANS_B);
+        }
+        ++l;
+      }
+    P.flush_gemm(0, 0, false);
+    P.upload(h->work);
+    execute(h, P, s);
+    HIPCHECK(hipStreamSynchronize(s));
+  });
+}
+
 blr_status blr_morton_sort(const double* pts, int64_t n, int32_t dim, int64_t* perm, double* sorted,
                            void* stream) {
   if (!pts || !perm) return fail(BLR_ERR_INVALID, "NULL argument");
