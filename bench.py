@@ -30,8 +30,10 @@ CONFIGS = {
     "c1": dict(m=2048, n=1024, b=128, dim=2, kernel="log2d", rule="adjacent", tol=1e-8, cap=16),
     "c2": dict(m=32768, n=16384, b=256, dim=3, kernel="inv_r", rule="dist_gt_diam", tol=1e-8, cap=32),
     "c3": dict(m=131072, n=65536, b=1024, dim=3, kernel="inv_r", rule="dist_gt_diam", tol=1e-8, cap=50),
-    # the paper's random-BLR workload at scale (low-rank heavy): N(0,1) dense
-    # diagonal tiles, every other tile a rank-16 product, weak admissibility
+    # the differentiated least-squares workload: 65536x32768, b = 512, 32 right-hand sides
+    "c5": dict(m=65536, n=32768, b=512, dim=3, kernel="inv_r", rule="dist_gt_diam", tol=1e-8, cap=32),
+    # the paper's random-BLR accuracy workload (8192x4096 row): N(0,1) dense
+    # diagonal tiles, every other tile a rank-1 product, weak admissibility
     "wr": dict(m=8192, n=4096, b=128, kind="random_blr", rank=1, rule="weak", tol=1e-10, cap=128),
 }
 PEAK = {"fp64": 78.6e12, "mixed": 157.3e12}   # MI355X dense matrix-core peaks (FP64, FP32)
@@ -163,7 +165,7 @@ def run(args, cfg, precision, tol, xd, yd, dev):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(stream)
-        G.factor(args.variant, precision, stop_after_k=args.stop_after_k)
+        G.factor(args.variant, precision, stop_after_k=args.stop_after_k, keep_a=args.adjoint)
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
@@ -197,6 +199,20 @@ def run(args, cfg, precision, tol, xd, yd, dev):
             solve["apply_qt_bytes_dense_equiv"] = 2 * ybytes
             solve["apply_qt_gbs"] = 2 * ybytes / solve["apply_qt_s"] / 1e9
             solve["apply_qt_hbm_frac"] = solve["apply_qt_gbs"] / (HBM_PEAK_TBS * 1e3)
+            if args.adjoint:
+                # backward pass of the least-squares solve: dL/dB and dL/dtiles
+                nr = args.adjoint_rhs
+                Bq = torch.tensor(synth.rhs(args.seed + 29, cfg["m"], nr), device=dev)
+                Xq = G.lstsq(Bq)
+                Xbar = torch.tensor(synth.rhs(args.seed + 31, cfg["n"], nr), device=dev)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                grads = G.lstsq_adjoint(Bq, Xq, Xbar)
+                torch.cuda.synchronize()
+                solve["adjoint"] = {"nrhs": nr, "adjoint_s": time.perf_counter() - t0}
+                del grads
+                print(f"[bench] {precision}: least-squares adjoint {solve['adjoint']['adjoint_s']:.3f}s "
+                      f"({nr} right-hand sides)", file=sys.stderr, flush=True)
             print(f"[bench] {precision}: apply Q^T {solve['apply_qt_s']:.3f}s lstsq {solve['lstsq_s']:.3f}s "
                   f"(16 right-hand sides)", file=sys.stderr, flush=True)
         del G
@@ -242,6 +258,9 @@ def main():
     ap.add_argument("--probes", type=int, default=8, help="Gaussian probes for the Res / Orth estimates")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--adjoint", action="store_true",
+                    help="also time the least-squares adjoint (the factor keeps a copy of A~)")
+    ap.add_argument("--adjoint-rhs", type=int, default=32)
     ap.add_argument("--stop-after-k", type=int, default=-1,
                     help="exploration only: factor the first K block columns (not a valid metric)")
     args = ap.parse_args()
