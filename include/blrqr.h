@@ -140,6 +140,17 @@ typedef struct blr_tiles_host {
   double* T;
 } blr_tiles_host;
 
+/* The explicit orthogonal factor Q~ of a factored handle as a new BLR handle
+ * (Section 3.3: Q~ is a BLR matrix with the structure of A~, its admissible
+ * blocks approximated at the same threshold).  The thin Q [I_n; 0] (m x n)
+ * is formed on the device, a block of 1024 columns at a time, then
+ * compressed with the tile formats A~ had when the factor started as the
+ * mask, tolerance and rank cap of A~ (a block whose rank exceeds the cap is
+ * stored dense).  Needs m*n*8 bytes of temporary device memory.  *q_out is a
+ * new handle in state COMPRESSED (its products and export work as for A~).
+ * Synchronises the stream.  Errors: BLR_ERR_STATE if not (fully) factored. */
+blr_status blr_form_q(blr_matrix h, void* hip_stream, blr_matrix* q_out);
+
 /* X <- R^{-1} X (trans = 0) or X <- R^{-T} X (trans = 1) with the R factor of
  * a factored handle (Section 3.3 / 3.4: R has the tile structure of A~), for
  * X n x nrhs, column-major, device, ld ldx >= n, overwritten.  The blocked

@@ -13,7 +13,7 @@ EXPORTED = [
     "blr_compress", "blr_import", "blr_export", "blr_qr_factor", "blr_apply_qt",
     "blr_lstsq_solve", "blr_query", "blr_destroy", "blr_status_string", "blr_last_error",
     "blr_profile_enable", "blr_profile_read", "blr_matmul", "blr_morton_sort", "blr_rsolve",
-    "blr_lstsq_adjoint",
+    "blr_lstsq_adjoint", "blr_form_q",
 ]
 SELFTEST = ["blr_selftest_gemm"]
 MATMUL = {"A": 0, "AT": 1, "R": 2}
@@ -80,6 +80,7 @@ def load() -> ctypes.CDLL:
     lib.blr_matmul.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_void_p, c_int64, c_int32, c_void_p]
     lib.blr_morton_sort.argtypes = [c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p]
     lib.blr_rsolve.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_int32, c_void_p]
+    lib.blr_form_q.argtypes = [c_void_p, c_void_p, P(c_void_p)]
     lib.blr_lstsq_adjoint.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_int32,
                                       c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.blr_query.argtypes = [c_void_p, P(Info)]

@@ -230,6 +230,13 @@ class BLRMatrix:
         X = Xc.t()
         return (X, torch.sqrt(res)) if with_resid else X
 
+    def form_q(self, stream=None) -> "BLRMatrix":
+        """The explicit orthogonal factor Q~ (m x n) as a new BLR matrix with the
+        structure, tolerance and rank cap of A~."""
+        h = ctypes.c_void_p()
+        _check(L.load().blr_form_q(self._h, _stream(stream), ctypes.byref(h)))
+        return BLRMatrix(h.value)
+
     def rsolve(self, X: torch.Tensor, trans: bool = False, stream=None) -> torch.Tensor:
         """R^{-1} X (trans=False) or R^{-T} X (trans=True) for an (n, nrhs) device tensor."""
         Xc = _colmajor(X.to(torch.float64), copy=True)   # overwritten in place by the library

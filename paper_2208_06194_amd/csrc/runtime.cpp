@@ -1987,6 +1987,8 @@ blr_status blr_qr_factor(blr_matrix h, const blr_factor_opts* o, void* stream) {
     const int kend = (o->stop_after_k < 0) ? q : std::min(q, o->stop_after_k);
     h->variant = o->variant;
     h->precision = o->precision;
+    h->fmt0.resize((size_t)p * q);
+    for (size_t t = 0; t < h->fmt0.size(); ++t) h->fmt0[t] = h->tiles[t].fmt;
     if (o->keep_a) {
       keep_copy(h, s);
       HIPCHECK(hipStreamSynchronize(s));
@@ -2344,6 +2346,69 @@ blr_status blr_lstsq_adjoint(blr_matrix h, const double* B, int64_t ldb, const d
     execute(h, P, s);
     HIPCHECK(hipStreamSynchronize(s));
   });
+}
+
+// Explicit Q~ (Section 3.3: Q~ is a BLR matrix with the structure of A~ and
+// the same threshold): the thin Q [I; 0] is formed densely, a block of
+// columns at a time, and compressed with A~'s tile formats as the mask.
+blr_status blr_form_q(blr_matrix h, void* stream, blr_matrix* q_out) {
+  if (!h || !q_out) return fail(BLR_ERR_INVALID, "NULL argument");
+  *q_out = nullptr;
+  if (h->state != BLR_STATE_FACTORED) return fail(BLR_ERR_STATE, "matrix is not factored");
+  if (h->steps_done != h->q) return fail(BLR_ERR_STATE, "factorization is incomplete");
+  hipStream_t s = as_stream(stream);
+  blr_status inner = BLR_OK;
+  blr_status st = run_guarded([&] {
+    const int b = h->b, p = h->p, q = h->q;
+    const int64_t m = h->m, n = h->n;
+    struct DevBuf {
+      double* p = nullptr;
+      ~DevBuf() {
+        if (p) (void)hipFree(p);
+      }
+    } E;
+    HIPCHECK(hipDeviceSynchronize());
+    h->work.release();
+    HIPCHECK(hipMalloc(&E.p, (size_t)m * n * 8));
+    HIPCHECK(hipMemsetAsync(E.p, 0, (size_t)m * n * 8, s));
+    {
+      Plan P;   // the identity in the top n x n block (unit-lower copy of zeros, in place)
+      P.copy({CopyDesc{E.p, E.p, m, m, (int)n, (int)n, 1, 0}});
+      P.upload(h->work);
+      execute(h, P, s);
+      HIPCHECK(hipStreamSynchronize(s));
+    }
+    const int64_t nc = std::min<int64_t>(n, 1024);
+    for (int64_t c0 = 0; c0 < n; c0 += nc) {
+      const int cols = (int)std::min<int64_t>(nc, n - c0);
+      h->work.release();
+      Work w = make_work(h, cols);
+      Plan P;
+      plan_apply(h, P, w, E.p + c0 * m, m, cols, 1);
+      P.upload(h->work);
+      execute(h, P, s);
+      HIPCHECK(hipStreamSynchronize(s));
+    }
+    h->work.release();
+    std::vector<int8_t> mask((size_t)p * q);
+    for (size_t t = 0; t < mask.size(); ++t) mask[t] = h->fmt0[t] == LOWRANK ? 1 : 0;
+    blr_source src{};
+    src.kind = BLR_SRC_DENSE;
+    src.A = E.p;
+    src.lda = m;
+    src.admissibility = BLR_ADM_MASK;
+    src.mask = mask.data();
+    blr_compress_opts co{};
+    co.m = m;
+    co.n = n;
+    co.tile = b;
+    co.tol = h->tol;
+    co.max_rank = h->cap;
+    co.overflow = BLR_OVERFLOW_DENSE;
+    inner = blr_compress(&src, &co, stream, q_out);
+    if (inner != BLR_OK) throw Error(inner, blr_last_error());
+  });
+  return st;
 }
 
 blr_status blr_morton_sort(const double* pts, int64_t n, int32_t dim, int64_t* perm, double* sorted,

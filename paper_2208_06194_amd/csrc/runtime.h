@@ -122,6 +122,7 @@ struct blr_matrix_s {
   std::vector<blr::Tile> acopy;          // copy of A~ kept by a factor with keep_a (else empty)
   blr::Arena amem;                       // storage of acopy
   std::vector<int8_t> yfmt;              // p*q: format of Ytilde_ik after the factor
+  std::vector<int8_t> fmt0;              // p*q: tile formats of A~ when the factor started
   std::vector<double*> T;                // p*q: T of tile (tiled) or of column (block column, at (k,k))
   std::vector<double*> tau;              // p*q
   int* d_rank = nullptr;

@@ -100,3 +100,42 @@ def test_autograd_function_returns_the_adjoint(P):
     Bbar, dD, dU, dV = G.lstsq_adjoint(B.detach(), X.detach(), Xbar)
     assert torch.equal(B.grad, Bbar)
     assert torch.equal(D.grad, dD) and torch.equal(U.grad, dU) and torch.equal(V.grad, dV)
+
+
+@pytest.mark.parametrize("variant", ["tiled", "block_column"])
+def test_explicit_q_matches_oracle(P, variant):
+    """blr_form_q: Q~ = Q [I; 0] compressed with the structure and threshold
+    of A~ (Section 3.3), against the oracle's thin Q compressed the same way;
+    the paper's Orth and Res computed with the explicit Q~."""
+    from oracle import blockcol, tiled, metrics
+    from tests.blr_helpers import export_dense, export_r
+    print("case: explicit Q", variant, flush=True)
+    m, n, b, eps, cap = 512, 256, 64, 1e-8, 32
+    x, y = synth.kernel_points(4, m, n, 2)
+    A = blrmat.kernel_matrix(x, y, "log2d")
+    mask = blrmat.lowrank_mask(x, y, b, "adjacent", m // b, n // b)
+    blr = blrmat.compress(A, b, eps, cap, mask)
+    At = blr.to_dense()
+    fmt0 = blr.fmt.copy()
+    assert (fmt0 == 1).any()
+    f = (tiled if variant == "tiled" else blockcol).factor(blr, eps, cap)   # works on a copy
+    Qo = blrmat.compress(f.thin_q(), b, eps, cap, fmt0 == 1)
+    G = P.BLRMatrix.import_tiles(m, n, b, eps, cap, *blr_to_host(blr, cap))
+    G.factor(variant)
+    Q = G.form_q()
+    exq = Q.export()
+    # Q~ keeps A~'s structure: low-rank only where A~ is (a block whose rank
+    # exceeds the cap is stored dense, which near the cap may differ by a tile)
+    assert np.all(exq["fmt"][fmt0 == 0] == 0) and (exq["fmt"] == 1).sum() >= 1
+    assert abs(int((exq["fmt"] == 1).sum()) - int((Qo.fmt == 1).sum())) <= 2
+    Qg = export_dense(exq)
+    Rg = export_r(G.export())
+    s = np.sign(np.diag(Rg)) * np.sign(np.diag(f.r_dense()))
+    Qdiff = np.linalg.norm(Qg * s[None, :] - Qo.to_dense()) / np.sqrt(n)
+    orth = np.linalg.norm(Qg.T @ Qg - np.eye(n)) / np.sqrt(n)
+    res = np.linalg.norm(Qg @ Rg - At) / np.linalg.norm(At)
+    orth_o = np.linalg.norm(Qo.to_dense().T @ Qo.to_dense() - np.eye(n)) / np.sqrt(n)
+    print("Q~ diff", Qdiff, "Orth", orth, "oracle", orth_o, "Res", res, flush=True)
+    kappa = np.linalg.cond(At)
+    assert Qdiff <= 10 * kappa * eps
+    assert orth <= 10 * eps and res <= 10 * eps
