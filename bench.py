@@ -199,6 +199,24 @@ def run(args, cfg, precision, tol, xd, yd, dev):
             solve["apply_qt_bytes_dense_equiv"] = 2 * ybytes
             solve["apply_qt_gbs"] = 2 * ybytes / solve["apply_qt_s"] / 1e9
             solve["apply_qt_hbm_frac"] = solve["apply_qt_gbs"] / (HBM_PEAK_TBS * 1e3)
+            if args.explicit_q:
+                # the explicit BLR Q~ and the paper's Orth / Res measured on it
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                Qt = G.form_q()
+                torch.cuda.synchronize()
+                tq = time.perf_counter() - t0
+                g = probes[:, :min(8, probes.shape[1])]
+                qg = Qt.matmul(g, "A")
+                orth_q = float(torch.linalg.norm(Qt.matmul(qg, "AT") - g) / torch.linalg.norm(g))
+                res_q = float(torch.linalg.norm(Qt.matmul(G.matmul(g, "R"), "A") - ax[:, :g.shape[1]])
+                              / torch.linalg.norm(ax[:, :g.shape[1]]))
+                qi = Qt.info()
+                solve["explicit_q"] = {"form_q_s": tq, "orth_est": orth_q, "res_est": res_q,
+                                       "tiles_dense": qi["n_dense"], "tiles_lowrank": qi["n_lowrank"]}
+                del Qt
+                print(f"[bench] {precision}: explicit Q~ {tq:.3f}s, Orth~ {orth_q:.2e}, Res~ {res_q:.2e}",
+                      file=sys.stderr, flush=True)
             if args.adjoint:
                 # backward pass of the least-squares solve: dL/dB and dL/dtiles
                 nr = args.adjoint_rhs
@@ -261,6 +279,8 @@ def main():
     ap.add_argument("--adjoint", action="store_true",
                     help="also time the least-squares adjoint (the factor keeps a copy of A~)")
     ap.add_argument("--adjoint-rhs", type=int, default=32)
+    ap.add_argument("--explicit-q", action="store_true",
+                    help="also form the explicit BLR Q~ and estimate the paper's Orth and Res on it")
     ap.add_argument("--stop-after-k", type=int, default=-1,
                     help="exploration only: factor the first K block columns (not a valid metric)")
     args = ap.parse_args()

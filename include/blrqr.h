@@ -143,7 +143,7 @@ typedef struct blr_tiles_host {
 /* The explicit orthogonal factor Q~ of a factored handle as a new BLR handle
  * (Section 3.3: Q~ is a BLR matrix with the structure of A~, its admissible
  * blocks approximated at the same threshold).  The thin Q [I_n; 0] (m x n)
- * is formed on the device, a block of 1024 columns at a time, then
+ * is formed on the device, a block of 4096 columns at a time, then
  * compressed with the tile formats A~ had when the factor started as the
  * mask, tolerance and rank cap of A~ (a block whose rank exceeds the cap is
  * stored dense).  Needs m*n*8 bytes of temporary device memory.  *q_out is a

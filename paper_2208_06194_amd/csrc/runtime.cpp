@@ -2378,7 +2378,7 @@ blr_status blr_form_q(blr_matrix h, void* stream, blr_matrix* q_out) {
       execute(h, P, s);
       HIPCHECK(hipStreamSynchronize(s));
     }
-    const int64_t nc = std::min<int64_t>(n, 1024);
+    const int64_t nc = std::min<int64_t>(n, 4096);
     for (int64_t c0 = 0; c0 < n; c0 += nc) {
       const int cols = (int)std::min<int64_t>(nc, n - c0);
       h->work.release();
