@@ -2037,17 +2037,13 @@ blr_status blr_qr_factor(blr_matrix h, const blr_factor_opts* o, void* stream) {
     }
     h->work.release();
     std::vector<Work> works;
-    int nstreams = bc ? 1 : kStreams;
-    if (const char* e = std::getenv("BLRQR_STREAMS"); e && !bc)
-      nstreams = std::max(1, std::min(kStreams, std::atoi(e)));
+    const int nstreams = bc ? 1 : kStreams;
     for (int a = 0; a < nstreams; ++a) works.push_back(make_work(h, 0));
     Plan P;
     h->n_fill = 0;
     if (bc) {
       BcWork bw = make_bc_work(h, bc_pairs);
-      bool la = true;
-      if (const char* e = std::getenv("BLRQR_LOOKAHEAD")) la = std::atoi(e) != 0;
-      plan_blockcol(h, P, works[0], bw, kend, o->precision == BLR_MIXED_FP32, la);
+      plan_blockcol(h, P, works[0], bw, kend, o->precision == BLR_MIXED_FP32, true);
     } else {
       plan_tiled(h, P, works, kend, o->precision == BLR_MIXED_FP32);
     }
