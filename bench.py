@@ -70,9 +70,10 @@ def dense_equiv_flops(m, n):
 
 def cpu_baseline(cfg, seed, variant):
     """The oracle (numpy FP64, untuned) timed on a bounded sample of the same
-    workload: the leading (4b x 2b) block of the same kernel matrix with the
-    same tile size, rule and tolerance, factored by the same variant.  Scaled
-    to the full matrix by dense-equivalent flops (2mn^2 - 2n^3/3)."""
+    workload: a leading block (from 4b x 2b, grown until one factor takes
+    about 10 s) of the same kernel matrix with the same tile size, rule and
+    tolerance, factored by the same variant.  Scaled to the full matrix by
+    dense-equivalent flops (2mn^2 - 2n^3/3)."""
     import synth
     from oracle import blockcol, blrmat, tiled
     fac = tiled.factor if variant == "tiled" else blockcol.factor
@@ -95,10 +96,12 @@ def cpu_baseline(cfg, seed, variant):
         fac(blr, cfg["tol"], cfg["cap"], copy=False)
         el = time.perf_counter() - t0
         spent += el
-        # grow the sample until it holds a few seconds of work (or is the whole matrix)
-        if el >= 4.0 or spent >= 15.0 or (ms == cfg["m"] and ns == cfg["n"]):
+        # grow the sample by 1.5x per side (whole tiles) until one factor holds
+        # about 10 s of work, 30 s are spent, or it is the whole matrix
+        if el >= 10.0 or spent >= 30.0 or (ms == cfg["m"] and ns == cfg["n"]):
             break
-        ms, ns = min(2 * ms, cfg["m"]), min(2 * ns, cfg["n"])
+        grow = lambda v, cap: min(cap, -(-(3 * v // 2) // b) * b)
+        ms, ns = grow(ms, cfg["m"]), grow(ns, cfg["n"])
     rate = dense_equiv_flops(ms, ns) / el
     try:
         from threadpoolctl import threadpool_info
