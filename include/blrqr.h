@@ -216,6 +216,25 @@ blr_status blr_export(blr_matrix h, blr_tiles_host* tiles);
  * BLR_ERR_STATE.  Enqueued on hip_stream (asynchronous). */
 blr_status blr_qr_factor(blr_matrix h, const blr_factor_opts* opts, void* hip_stream);
 
+/* Householder QR of count independent BLR matrices of any sizes, as one
+ * batch (the block-column algorithm, Alg. 2 with Section 3.3, on each; the
+ * task graph of Section 4.3 taken over the batch).  hs (host array) holds
+ * count distinct handles in state COMPRESSED that share tile size, rank cap
+ * and tolerance; opts->variant must be BLR_BLOCK_COLUMN, and precision,
+ * keep_a and stop_after_k apply to every matrix.  The steps of all matrices
+ * are merged so that one kernel launch serves the same step of many
+ * matrices; each matrix ends exactly as blr_qr_factor with the same opts
+ * leaves it (bit-identical factors, FACTORED state, own overflow counters;
+ * blr_query reports the batch's launch count).  Enqueued on hip_stream
+ * (asynchronous); the merged launch list lives in hs[0]'s workspace until
+ * its next factorization or destruction.  Errors: BLR_ERR_INVALID for NULL
+ * arguments, count < 1, a repeated or NULL handle, unequal tile size, cap or
+ * tolerance, or another variant; BLR_ERR_STATE if a handle is not
+ * COMPRESSED.  If the call fails after validation, the handles stay
+ * COMPRESSED but may hold fill-in slots and workspace. */
+blr_status blr_qr_factor_batch(blr_matrix* hs, int32_t count, const blr_factor_opts* opts,
+                               void* hip_stream);
+
 /* B <- Q^T B (trans = 0) or B <- Q B (trans = 1), replaying the stored
  * reflectors (Alg. 3 / Alg. 5).  B: device, column-major m x nrhs, ldb >= m,
  * overwritten.  Requires FACTORED.  Asynchronous. */

@@ -86,6 +86,19 @@ def morton_sort(pts: torch.Tensor, stream=None):
     return out, perm
 
 
+def factor_batch(mats, precision: str = "fp64", stop_after_k: int = -1, keep_a: bool = False,
+                 stream=None):
+    """Block-column QR of several independent BLR matrices as one batch
+    (blr_qr_factor_batch): the same result per matrix as mats[i].factor(
+    "block_column", precision, ...), with the launches shared."""
+    mats = list(mats)
+    o = L.FactorOpts(variant=L.VARIANT["block_column"], precision=L.PRECISION[precision], ib=0,
+                     stop_after_k=stop_after_k, keep_a=1 if keep_a else 0)
+    arr = (ctypes.c_void_p * len(mats))(*[m._h.value for m in mats])
+    _check(L.load().blr_qr_factor_batch(arr, len(mats), ctypes.byref(o), _stream(stream)))
+    return mats
+
+
 class BLRMatrix:
     """A BLR matrix owned by the library (one handle)."""
 

@@ -25,6 +25,7 @@ struct RcDesc {
   double* Vtout;         // rc x b (ld rc); rows >= rank are zeroed
   int* rank_out;
   double* work;          // per-problem workspace (rc_work_doubles)
+  unsigned long long* counters;  // own [overflow count, max dropped bits], or nullptr: the launch's
 };
 
 struct RcParams {

@@ -202,9 +202,11 @@ __device__ void wg_sort_sigma(const double* Z, int64_t ldz, int nr, int nc, doub
   __syncthreads();
 }
 
-__device__ void record_overflow(const RcParams& P, double dropped_rel) {
-  atomicAdd(P.overflow_count, 1ull);
-  atomicMax(P.max_dropped_bits, (unsigned long long)__double_as_longlong(dropped_rel));
+__device__ void record_overflow(const RcParams& P, unsigned long long* own, double dropped_rel) {
+  unsigned long long* c = own ? own : P.overflow_count;
+  unsigned long long* m = own ? own + 1 : P.max_dropped_bits;
+  atomicAdd(c, 1ull);
+  atomicMax(m, (unsigned long long)__double_as_longlong(dropped_rel));
 }
 
 __global__ __launch_bounds__(256) void k_recompress(const RcDesc* __restrict__ descs, RcParams P) {
@@ -322,7 +324,7 @@ __global__ __launch_bounds__(256) void k_recompress(const RcDesc* __restrict__ d
       if (r > P.cap) {
         double drop2 = 0.0;
         for (int l = P.cap; l < k; ++l) drop2 += sig[perm[l]] * sig[perm[l]];
-        record_overflow(P, sqrt(drop2 / total2));
+        record_overflow(P, D.counters, sqrt(drop2 / total2));
         r = P.cap;
       }
     }

@@ -66,3 +66,26 @@ hipError_t launch_t_backsolve(const TBackArgs& a, hipStream_t stream);
 // Fused trailing update of the nt columns right of panel a (same PanelArgs:
 // X points at the panel's first column / first row, T at its diagonal block).
 hipError_t launch_panel_apply(const PanelArgs& a, int nt, hipStream_t stream);
+
+// One job of a batched launch of the kernels above (one per independent
+// matrix of a batched factorization): the single-problem arguments and the
+// job's own extent.  Each job is computed exactly as by its single-problem
+// launch.  Job arrays are device memory.
+struct PanelJob {
+  PanelArgs a;     // panel, panel update, tall update
+  TallArgs t;      // tall column
+  TBackArgs tb;    // T back-substitution (order tb.n > tb.ib)
+  int nt;          // panel update / tall update: trailing columns (> 0)
+  int groups;      // tall column: row groups; tall update: row slices
+  double* part;    // tall update: partial sums
+};
+// max_rows selects the register-tile template: every job's h must fall in
+// the same bucket as max_rows (1, 2, 4, 8, 16 chunks of 64 rows).
+hipError_t launch_panel_batch(const PanelJob* d, int n, int ib, int max_rows, hipStream_t stream);
+hipError_t launch_panel_apply_batch(const PanelJob* d, int n, int ib, int max_nt, hipStream_t stream);
+hipError_t launch_t_backsolve_batch(const PanelJob* d, int n, int max_n, hipStream_t stream);
+// first = 1: the jobs are the first column of their panels (jj = 0)
+hipError_t launch_tall_column_batch(const PanelJob* d, int n, int ib, int first, int max_groups,
+                                    hipStream_t stream);
+hipError_t launch_tall_apply_batch(const PanelJob* d, int n, int ib, int max_nt, int max_slices,
+                                   hipStream_t stream);

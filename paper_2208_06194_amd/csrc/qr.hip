@@ -32,7 +32,7 @@ namespace {
 // with its own columns by one wavefront reduction per column and applies the
 // rank-one update in registers.
 template <int RS, int CPW>
-__global__ __launch_bounds__(1024) void k_panel(PanelArgs a) {
+__device__ __forceinline__ void panel_body(const PanelArgs& a) {
   constexpr int IB = 16 * CPW;
   __shared__ double vbuf[64 * RS];
   __shared__ double top[IB][IB + 1];
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(1024) void k_panel(PanelArgs a) {
 // chunk's rows over the 4 waves (partial sums reduced in LDS), V W2 gives
 // each wave 16 rows of the chunk.
 template <int IB>
-__global__ __launch_bounds__(256) void k_panel_apply(PanelArgs a, int nt) {
+__device__ __forceinline__ void panel_apply_body(const PanelArgs& a, int nt, int cb) {
   constexpr int NC = 32, CH = 64, MT = IB / 16;
   __shared__ double Vs[CH][IB + 1];
   __shared__ double Bs[CH][NC + 1];
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void k_panel_apply(PanelArgs a, int nt) {
   __shared__ double Tt[IB][IB + 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const bool tp = a.mode == PANEL_TPQRT;
-  const int c0 = blockIdx.x * NC;
+  const int c0 = cb * NC;
   const int nc = min(NC, nt - c0);
   const int h = a.h;
   const double* V = a.X;
@@ -289,10 +289,10 @@ __global__ __launch_bounds__(256) void k_panel_apply(PanelArgs a, int nt) {
 // the already known part of the column are formed together (their loads and
 // reductions overlap), then the 8 x 8 triangle is solved redundantly by every
 // lane.  Lane l owns x[t] for t = l (mod 64) in LDS.
-__global__ __launch_bounds__(256) void k_t_backsolve(TBackArgs a) {
+__device__ __forceinline__ void t_backsolve_body(const TBackArgs& a, int cb) {
   extern __shared__ double xs[];  // 4 waves x n
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int c = blockIdx.x * 4 + wave;
+  const int c = cb * 4 + wave;
   if (c >= a.n) return;
   double* x = xs + (size_t)wave * a.n;
   const int bs = (c / a.ib) * a.ib;
@@ -373,10 +373,10 @@ __device__ __forceinline__ void tall_store_partials(double (&part)[IB], double (
 }
 
 template <int IB>
-__global__ __launch_bounds__(kTallThreads) void k_tall_first(TallArgs a) {
+__device__ __forceinline__ void tall_first_body(const TallArgs& a, int G, int g) {
   constexpr int NT = kTallThreads;
   __shared__ double red[NT / 64][IB];
-  const int tid = threadIdx.x, G = gridDim.x, g = blockIdx.x;
+  const int tid = threadIdx.x;
   const int64_t ld = a.ldx;
   int rs, re;
   tall_rows(a.h, G, g, &rs, &re);
@@ -394,12 +394,12 @@ __global__ __launch_bounds__(kTallThreads) void k_tall_first(TallArgs a) {
 }
 
 template <int IB>
-__global__ __launch_bounds__(kTallThreads) void k_tall_step(TallArgs a) {
+__device__ __forceinline__ void tall_step_body(const TallArgs& a, int G, int g) {
   constexpr int NT = kTallThreads;
   __shared__ double acc[NT / IB][2 * IB];
   __shared__ double sv[2 * IB];   // [0, IB): dots of column jj (its tail sum of squares at jj); [IB, 2 IB): pivot row
   __shared__ double wv[IB];
-  const int tid = threadIdx.x, G = gridDim.x, g = blockIdx.x;
+  const int tid = threadIdx.x;
   const int jj = a.jj;
   const int64_t ld = a.ldx;
   const int64_t bufsz = (int64_t)(G + 1) * (2 * IB);
@@ -520,13 +520,13 @@ __global__ __launch_bounds__(kTallThreads) void k_tall_step(TallArgs a) {
 // k_tall_apply_upd sums the slices, forms W2 = T^T W and updates its slice:
 // C -= V W2.
 template <int IB>
-__global__ __launch_bounds__(256) void k_tall_apply_part(PanelArgs a, int nt, double* part) {
+__device__ __forceinline__ void tall_apply_part_body(const PanelArgs& a, int nt, double* part, int cb, int sl,
+                                                     int NB, int S) {
   constexpr int NC = 32, CH = 64, MT = IB / 16;
   __shared__ double Vs[CH][IB + 1];
   __shared__ double Bs[CH][NC + 1];
   __shared__ double Wp[4][IB][NC + 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int cb = blockIdx.x, sl = blockIdx.y, S = gridDim.y;
   const int c0 = cb * NC, nc = min(NC, nt - c0);
   const int h = a.h;
   const int slice = ((h + S - 1) / S + CH - 1) / CH * CH;
@@ -579,7 +579,7 @@ __global__ __launch_bounds__(256) void k_tall_apply_part(PanelArgs a, int nt, do
 #pragma unroll
       for (int v = 0; v < 4; ++v) Wp[w][mt * 16 + 4 * v + (lane >> 4)][j * 16 + (lane & 15)] = acc[mt][j][v];
   __syncthreads();
-  double* out = part + ((int64_t)sl * gridDim.x + cb) * IB * NC;
+  double* out = part + ((int64_t)sl * NB + cb) * IB * NC;
   for (int e = tid; e < IB * NC; e += 256) {
     const int l = e % IB, c = e / IB;
     out[e] = Wp[0][l][c] + Wp[1][l][c] + Wp[2][l][c] + Wp[3][l][c];
@@ -587,14 +587,14 @@ __global__ __launch_bounds__(256) void k_tall_apply_part(PanelArgs a, int nt, do
 }
 
 template <int IB>
-__global__ __launch_bounds__(256) void k_tall_apply_upd(PanelArgs a, int nt, const double* part) {
+__device__ __forceinline__ void tall_apply_upd_body(const PanelArgs& a, int nt, const double* part, int cb, int sl,
+                                                    int NB, int S) {
   constexpr int NC = 32, CH = 64;
   __shared__ double Vs[CH][IB + 1];
   __shared__ double Ps[CH][NC + 1];
   __shared__ double W[IB][NC + 1];
   __shared__ double W2[IB][NC + 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int cb = blockIdx.x, sl = blockIdx.y, S = gridDim.y, NB = gridDim.x;
   const int c0 = cb * NC, nc = min(NC, nt - c0);
   const int h = a.h;
   const int slice = ((h + S - 1) / S + CH - 1) / CH * CH;
@@ -675,6 +675,83 @@ __global__ void k_copy_blocks(const CopyDesc* __restrict__ d) {
   }
 }
 
+// Single-problem kernels: the grid covers one problem.
+template <int RS, int CPW>
+__global__ __launch_bounds__(1024) void k_panel(PanelArgs a) { panel_body<RS, CPW>(a); }
+template <int IB>
+__global__ __launch_bounds__(256) void k_panel_apply(PanelArgs a, int nt) { panel_apply_body<IB>(a, nt, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_t_backsolve(TBackArgs a) { t_backsolve_body(a, blockIdx.x); }
+template <int IB>
+__global__ __launch_bounds__(kTallThreads) void k_tall_first(TallArgs a) {
+  tall_first_body<IB>(a, gridDim.x, blockIdx.x);
+}
+template <int IB>
+__global__ __launch_bounds__(kTallThreads) void k_tall_step(TallArgs a) {
+  tall_step_body<IB>(a, gridDim.x, blockIdx.x);
+}
+template <int IB>
+__global__ __launch_bounds__(256) void k_tall_apply_part(PanelArgs a, int nt, double* part) {
+  tall_apply_part_body<IB>(a, nt, part, blockIdx.x, blockIdx.y, gridDim.x, gridDim.y);
+}
+template <int IB>
+__global__ __launch_bounds__(256) void k_tall_apply_upd(PanelArgs a, int nt, const double* part) {
+  tall_apply_upd_body<IB>(a, nt, part, blockIdx.x, blockIdx.y, gridDim.x, gridDim.y);
+}
+
+// Batched kernels: the last grid dimension indexes the job; the others span
+// the largest job, and workgroups beyond a job's own extent exit at once
+// (before any barrier).  Each job gets exactly the workgroups, and therefore
+// the partitioning and summation order, of its single-problem launch.
+template <int RS, int CPW>
+__global__ __launch_bounds__(1024) void k_panel_batch(const PanelJob* __restrict__ jobs) {
+  const PanelArgs a = jobs[blockIdx.x].a;
+  panel_body<RS, CPW>(a);
+}
+template <int IB>
+__global__ __launch_bounds__(256) void k_panel_apply_batch(const PanelJob* __restrict__ jobs) {
+  const PanelArgs a = jobs[blockIdx.y].a;
+  const int nt = jobs[blockIdx.y].nt;
+  if ((int)blockIdx.x >= (nt + 31) / 32) return;
+  panel_apply_body<IB>(a, nt, blockIdx.x);
+}
+__global__ __launch_bounds__(256) void k_t_backsolve_batch(const PanelJob* __restrict__ jobs) {
+  const TBackArgs a = jobs[blockIdx.y].tb;
+  if ((int)blockIdx.x >= (a.n + 3) / 4) return;
+  t_backsolve_body(a, blockIdx.x);
+}
+template <int IB>
+__global__ __launch_bounds__(kTallThreads) void k_tall_first_batch(const PanelJob* __restrict__ jobs) {
+  const TallArgs a = jobs[blockIdx.y].t;
+  const int G = jobs[blockIdx.y].groups;
+  if ((int)blockIdx.x >= G) return;
+  tall_first_body<IB>(a, G, blockIdx.x);
+}
+template <int IB>
+__global__ __launch_bounds__(kTallThreads) void k_tall_step_batch(const PanelJob* __restrict__ jobs) {
+  const TallArgs a = jobs[blockIdx.y].t;
+  const int G = jobs[blockIdx.y].groups;
+  if ((int)blockIdx.x >= G) return;
+  tall_step_body<IB>(a, G, blockIdx.x);
+}
+template <int IB>
+__global__ __launch_bounds__(256) void k_tall_apply_part_batch(const PanelJob* __restrict__ jobs) {
+  const PanelJob& J = jobs[blockIdx.z];
+  const PanelArgs a = J.a;
+  const int nt = J.nt, S = J.groups, NB = (nt + 31) / 32;
+  double* part = J.part;
+  if ((int)blockIdx.x >= NB || (int)blockIdx.y >= S) return;
+  tall_apply_part_body<IB>(a, nt, part, blockIdx.x, blockIdx.y, NB, S);
+}
+template <int IB>
+__global__ __launch_bounds__(256) void k_tall_apply_upd_batch(const PanelJob* __restrict__ jobs) {
+  const PanelJob& J = jobs[blockIdx.z];
+  const PanelArgs a = J.a;
+  const int nt = J.nt, S = J.groups, NB = (nt + 31) / 32;
+  const double* part = J.part;
+  if ((int)blockIdx.x >= NB || (int)blockIdx.y >= S) return;
+  tall_apply_upd_body<IB>(a, nt, part, blockIdx.x, blockIdx.y, NB, S);
+}
+
 }  // namespace
 
 hipError_t launch_tall_column(const TallArgs& a, int groups, hipStream_t stream) {
@@ -751,5 +828,80 @@ hipError_t launch_t_backsolve(const TBackArgs& a, hipStream_t stream) {
   if (a.n <= a.ib) return hipSuccess;
   dim3 grid((a.n + 3) / 4), block(256);
   hipLaunchKernelGGL(k_t_backsolve, grid, block, (size_t)4 * a.n * sizeof(double), stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_panel_batch(const PanelJob* d, int n, int ib, int max_rows, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const int rs = (max_rows + 63) / 64;
+  dim3 grid(n), block(1024);
+#define BLR_PANEL(RSV, CPWV) hipLaunchKernelGGL((k_panel_batch<RSV, CPWV>), grid, block, 0, stream, d)
+  if (ib == 32) {
+    if (rs <= 1) BLR_PANEL(1, 2);
+    else if (rs <= 2) BLR_PANEL(2, 2);
+    else if (rs <= 4) BLR_PANEL(4, 2);
+    else if (rs <= 8) BLR_PANEL(8, 2);
+    else return hipErrorInvalidValue;
+  } else if (ib == 16) {
+    if (rs <= 1) BLR_PANEL(1, 1);
+    else if (rs <= 2) BLR_PANEL(2, 1);
+    else if (rs <= 4) BLR_PANEL(4, 1);
+    else if (rs <= 8) BLR_PANEL(8, 1);
+    else if (rs <= 16) BLR_PANEL(16, 1);
+    else return hipErrorInvalidValue;
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef BLR_PANEL
+  return hipGetLastError();
+}
+
+hipError_t launch_panel_apply_batch(const PanelJob* d, int n, int ib, int max_nt, hipStream_t stream) {
+  if (n <= 0 || max_nt <= 0) return hipSuccess;
+  dim3 grid((max_nt + 31) / 32, n), block(256);
+  if (ib == 32) hipLaunchKernelGGL((k_panel_apply_batch<32>), grid, block, 0, stream, d);
+  else if (ib == 16) hipLaunchKernelGGL((k_panel_apply_batch<16>), grid, block, 0, stream, d);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_t_backsolve_batch(const PanelJob* d, int n, int max_n, hipStream_t stream) {
+  if (n <= 0 || max_n <= 0) return hipSuccess;
+  dim3 grid((max_n + 3) / 4, n), block(256);
+  hipLaunchKernelGGL(k_t_backsolve_batch, grid, block, (size_t)4 * max_n * sizeof(double), stream, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_tall_column_batch(const PanelJob* d, int n, int ib, int first, int max_groups,
+                                    hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  if (max_groups < 1 || max_groups > kTallMaxGroups) return hipErrorInvalidValue;
+  dim3 grid(max_groups, n), block(kTallThreads);
+  if (ib == 32) {
+    if (first) hipLaunchKernelGGL(k_tall_first_batch<32>, grid, block, 0, stream, d);
+    hipLaunchKernelGGL(k_tall_step_batch<32>, grid, block, 0, stream, d);
+  } else if (ib == 16) {
+    if (first) hipLaunchKernelGGL(k_tall_first_batch<16>, grid, block, 0, stream, d);
+    hipLaunchKernelGGL(k_tall_step_batch<16>, grid, block, 0, stream, d);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_tall_apply_batch(const PanelJob* d, int n, int ib, int max_nt, int max_slices,
+                                   hipStream_t stream) {
+  if (n <= 0 || max_nt <= 0) return hipSuccess;
+  if (max_slices < 1 || max_slices > kTallApplySlices) return hipErrorInvalidValue;
+  dim3 grid((max_nt + 31) / 32, max_slices, n), block(256);
+  if (ib == 32) {
+    hipLaunchKernelGGL((k_tall_apply_part_batch<32>), grid, block, 0, stream, d);
+    hipLaunchKernelGGL((k_tall_apply_upd_batch<32>), grid, block, 0, stream, d);
+  } else if (ib == 16) {
+    hipLaunchKernelGGL((k_tall_apply_part_batch<16>), grid, block, 0, stream, d);
+    hipLaunchKernelGGL((k_tall_apply_upd_batch<16>), grid, block, 0, stream, d);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }

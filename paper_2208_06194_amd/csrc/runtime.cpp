@@ -231,6 +231,10 @@ void Plan::upload(Arena& arena) {
     d_rcs = (RcDesc*)arena.alloc(rcs.size() * sizeof(RcDesc));
     HIPCHECK(hipMemcpy(d_rcs, rcs.data(), rcs.size() * sizeof(RcDesc), hipMemcpyHostToDevice));
   }
+  if (!jobs.empty()) {
+    d_jobs = (PanelJob*)arena.alloc(jobs.size() * sizeof(PanelJob));
+    HIPCHECK(hipMemcpy(d_jobs, jobs.data(), jobs.size() * sizeof(PanelJob), hipMemcpyHostToDevice));
+  }
 }
 
 void Plan::clear() { *this = Plan(); }
@@ -332,6 +336,26 @@ void execute(blr_matrix h, Plan& P, hipStream_t s) {
       case Op::COPY:
         HIPCHECK(launch_copy_blocks(P.d_copies + o.off, o.n, o.maxel, q));
         h->launches += 1;
+        break;
+      case Op::PANEL_B:
+        HIPCHECK(launch_panel_batch(P.d_jobs + o.off, o.n, o.ib, o.ext, q));
+        h->launches += 1;
+        break;
+      case Op::PANEL_APPLY_B:
+        HIPCHECK(launch_panel_apply_batch(P.d_jobs + o.off, o.n, o.ib, o.ext, q));
+        h->launches += 1;
+        break;
+      case Op::TBACK_B:
+        HIPCHECK(launch_t_backsolve_batch(P.d_jobs + o.off, o.n, o.ext, q));
+        h->launches += 1;
+        break;
+      case Op::TALL_COL_B:
+        HIPCHECK(launch_tall_column_batch(P.d_jobs + o.off, o.n, o.ib, o.first, o.ext, q));
+        h->launches += o.first ? 2 : 1;
+        break;
+      case Op::TALL_APPLY_B:
+        HIPCHECK(launch_tall_apply_batch(P.d_jobs + o.off, o.n, o.ib, o.ext, o.ext2, q));
+        h->launches += 2;
         break;
       case Op::WAIT:
         if (nstreams > 1) HIPCHECK(hipStreamWaitEvent(q, ev[o.event], 0));
@@ -1319,6 +1343,224 @@ void plan_blockcol(blr_matrix h, Plan& P, Work& w, BcWork& bw, int kend, bool fp
   P.cur_stream = 0;
 }
 
+// ---------------------------------------------------------------------------
+// Batched factorization of independent matrices (the task graph of Section
+// 4.3 taken over many BLR matrices of uneven sizes).  Every matrix gets its
+// own single-stream block-column plan; the plans are then merged into one
+// launch list.  Each round launches, as one batched kernel, the next op of
+// every matrix whose next op runs the same kernel with the same compile-time
+// shape; the round takes the kernel whose matrices have the most ops left in
+// total, so long factorizations keep moving while short ones ride along.  A
+// matrix's ops keep their order and the batch runs on one stream, so every
+// dependency of the single-matrix plan holds, and each job is computed
+// exactly as by its own launch (bit-identical factors).
+
+struct OpSig {
+  int kind = -1, a = 0, b = 0, c = 0;
+  bool operator==(const OpSig& o) const { return kind == o.kind && a == o.a && b == o.b && c == o.c; }
+};
+
+// register-tile template of the panel kernel: chunks of 64 rows, rounded up to 1, 2, 4, 8, 16
+int panel_bucket(int h) {
+  const int rs = (h + 63) / 64;
+  int bk = 1;
+  while (bk < rs) bk *= 2;
+  return bk;
+}
+
+// false for ops that launch nothing (the waits and records of a one-stream plan)
+bool op_launches(const Op& o) {
+  switch (o.kind) {
+    case Op::GEMM:
+    case Op::RC: return o.n > 0;
+    case Op::COPY: return o.n > 0 && o.maxel > 0;
+    case Op::PANEL:
+    case Op::TALL_COL: return true;
+    case Op::PANEL_APPLY: return o.n > 0;
+    case Op::TBACK: return o.tback.n > o.tback.ib;
+    case Op::TALL_APPLY: return o.ntiles > 0;
+    case Op::WAIT:
+    case Op::RECORD: return false;
+    default: throw Error(BLR_ERR_INVALID, "op kind cannot be batched");
+  }
+}
+
+OpSig op_sig(const Op& o) {
+  OpSig g;
+  g.kind = (int)o.kind;
+  switch (o.kind) {
+    case Op::GEMM: g.a = o.big; g.b = o.fp32; g.c = o.prof; break;
+    case Op::PANEL: g.a = o.panel.ib; g.b = panel_bucket(o.panel.h); break;
+    case Op::PANEL_APPLY:
+    case Op::TALL_APPLY: g.a = o.panel.ib; break;
+    case Op::TALL_COL: g.a = o.tall.ib; g.b = o.tall.jj == 0; break;
+    default: break;
+  }
+  return g;
+}
+
+// One merged op from the ops src[a] = (plan, op index), all of one signature.
+void emit_merged(Plan& M, const std::vector<Plan>& plans, const std::vector<blr_matrix>& hs,
+                 const std::vector<std::pair<int, int>>& src) {
+  const Op& o0 = plans[src[0].first].ops[src[0].second];
+  Op m;
+  m.kind = o0.kind;
+  m.stream = 0;
+  const bool single = src.size() == 1;
+  auto job = [&](PanelJob j) { M.jobs.push_back(j); };
+  switch (o0.kind) {
+    case Op::GEMM:
+      m.big = o0.big;
+      m.fp32 = o0.fp32;
+      m.prof = o0.prof;
+      m.off = (int)M.descs.size();
+      for (auto& sp : src) {
+        const Plan& S = plans[sp.first];
+        const Op& o = S.ops[sp.second];
+        for (int d = o.off; d < o.off + o.n; ++d) {
+          GemmDesc e = S.descs[d];
+          const int sb = e.seg_begin;
+          e.seg_begin = (int)M.segs.size();
+          M.segs.insert(M.segs.end(), S.segs.begin() + sb, S.segs.begin() + sb + e.nseg);
+          e.tile_begin += m.ntiles;
+          M.descs.push_back(e);
+        }
+        m.n += o.n;
+        m.ntiles += o.ntiles;
+        m.flops += o.flops;
+      }
+      break;
+    case Op::RC:
+      m.off = (int)M.rcs.size();
+      for (auto& sp : src) {
+        const Plan& S = plans[sp.first];
+        const Op& o = S.ops[sp.second];
+        for (int d = o.off; d < o.off + o.n; ++d) {
+          RcDesc e = S.rcs[d];
+          e.counters = hs[sp.first]->d_counters;
+          M.rcs.push_back(e);
+        }
+        m.n += o.n;
+        m.flops += o.flops;
+      }
+      break;
+    case Op::COPY:
+      m.off = (int)M.copies.size();
+      for (auto& sp : src) {
+        const Plan& S = plans[sp.first];
+        const Op& o = S.ops[sp.second];
+        M.copies.insert(M.copies.end(), S.copies.begin() + o.off, S.copies.begin() + o.off + o.n);
+        m.n += o.n;
+        m.maxel = std::max(m.maxel, o.maxel);
+      }
+      break;
+    default: {
+      if (single) {   // one job: the single-problem kernel
+        m = o0;
+        m.stream = 0;
+        break;
+      }
+      m.off = (int)M.jobs.size();
+      for (auto& sp : src) {
+        const Op& o = plans[sp.first].ops[sp.second];
+        PanelJob j{};
+        switch (o.kind) {
+          case Op::PANEL:
+            m.kind = Op::PANEL_B;
+            j.a = o.panel;
+            m.ib = o.panel.ib;
+            m.ext = std::max(m.ext, o.panel.h);
+            break;
+          case Op::PANEL_APPLY:
+            m.kind = Op::PANEL_APPLY_B;
+            j.a = o.panel;
+            j.nt = o.n;
+            m.ib = o.panel.ib;
+            m.ext = std::max(m.ext, o.n);
+            break;
+          case Op::TBACK:
+            m.kind = Op::TBACK_B;
+            j.tb = o.tback;
+            m.ext = std::max(m.ext, o.tback.n);
+            break;
+          case Op::TALL_COL:
+            m.kind = Op::TALL_COL_B;
+            j.t = o.tall;
+            j.groups = o.n;
+            m.ib = o.tall.ib;
+            m.first = o.tall.jj == 0;
+            m.ext = std::max(m.ext, o.n);
+            break;
+          case Op::TALL_APPLY:
+            m.kind = Op::TALL_APPLY_B;
+            j.a = o.panel;
+            j.nt = o.ntiles;
+            j.groups = o.n;
+            j.part = o.buf;
+            m.ib = o.panel.ib;
+            m.ext = std::max(m.ext, o.ntiles);
+            m.ext2 = std::max(m.ext2, o.n);
+            break;
+          default:
+            throw Error(BLR_ERR_INVALID, "op kind cannot be batched");
+        }
+        job(j);
+        m.n += 1;
+        m.flops += o.flops;
+      }
+      break;
+    }
+  }
+  M.ops.push_back(m);
+}
+
+Plan merge_plans(const std::vector<Plan>& plans, const std::vector<blr_matrix>& hs) {
+  const int nb = (int)plans.size();
+  std::vector<std::vector<int>> chain(nb);
+  for (int i = 0; i < nb; ++i)
+    for (int x = 0; x < (int)plans[i].ops.size(); ++x) {
+      const Op& o = plans[i].ops[x];
+      if (o.stream != 0) throw Error(BLR_ERR_INVALID, "batched plans run on one stream");
+      if (op_launches(o)) chain[i].push_back(x);
+    }
+  std::vector<size_t> head(nb, 0);
+  std::vector<OpSig> hsig(nb);
+  for (int i = 0; i < nb; ++i)
+    if (!chain[i].empty()) hsig[i] = op_sig(plans[i].ops[chain[i][0]]);
+  Plan M;
+  std::vector<std::pair<OpSig, int64_t>> score;
+  std::vector<std::pair<int, int>> src;
+  for (;;) {
+    score.clear();
+    for (int i = 0; i < nb; ++i) {
+      if (head[i] >= chain[i].size()) continue;
+      const int64_t left = (int64_t)(chain[i].size() - head[i]);
+      bool found = false;
+      for (auto& e : score)
+        if (e.first == hsig[i]) {
+          e.second += left;
+          found = true;
+          break;
+        }
+      if (!found) score.push_back({hsig[i], left});
+    }
+    if (score.empty()) break;
+    size_t best = 0;
+    for (size_t e = 1; e < score.size(); ++e)
+      if (score[e].second > score[best].second) best = e;
+    const OpSig g = score[best].first;
+    src.clear();
+    for (int i = 0; i < nb; ++i)
+      if (head[i] < chain[i].size() && hsig[i] == g) src.push_back({i, chain[i][head[i]]});
+    emit_merged(M, plans, hs, src);
+    for (auto& sp : src) {
+      const int i = sp.first;
+      if (++head[i] < chain[i].size()) hsig[i] = op_sig(plans[i].ops[chain[i][head[i]]]);
+    }
+  }
+  return M;
+}
+
 // B <- Q^T B or Q B for the block-column factor (Alg. 3): per step k,
 // W = sum_i Ytilde_ik^T B_i, W = T_k^T W (or T_k W), B_i -= Ytilde_ik W.
 void plan_apply_blockcol(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, int nrhs, int trans,
@@ -1648,6 +1890,86 @@ blr_status validate_opts(const blr_compress_opts* o) {
     return fail(BLR_ERR_INVALID, "bad overflow policy");
   if (o->m / o->tile > 1 << 15 || o->n / o->tile > 1 << 15) return fail(BLR_ERR_INVALID, "too many tiles");
   return BLR_OK;
+}
+
+// Set-up and launch plan of one factorization (Alg. 2 or Alg. 4): fill-in
+// slots from the simulated formats, T and tau storage, workspaces, plan.
+// Returns the number of steps planned.
+int prepare_factor(blr_matrix h, const blr_factor_opts* o, hipStream_t s, Plan& P, bool lookahead) {
+  const int b = h->b, p = h->p, q = h->q;
+  const int kend = (o->stop_after_k < 0) ? q : std::min(q, o->stop_after_k);
+
+  h->variant = o->variant;
+  h->precision = o->precision;
+  h->fmt0.resize((size_t)p * q);
+  for (size_t t = 0; t < h->fmt0.size(); ++t) h->fmt0[t] = h->tiles[t].fmt;
+  if (o->keep_a) {
+    keep_copy(h, s);
+    HIPCHECK(hipStreamSynchronize(s));
+  }
+  const bool bc = o->variant == BLR_BLOCK_COLUMN;
+  int bc_pairs = 0;
+  // fill-in: simulate formats to find the tiles that need a dense slot
+  if (bc) {
+    alloc_dense(h, bc_simulate(h, kend, &bc_pairs));
+  } else {
+    std::vector<int8_t> f((size_t)p * q);
+    for (size_t t = 0; t < f.size(); ++t) f[t] = h->tiles[t].fmt;
+    std::vector<int> need;
+    for (int k = 0; k < kend; ++k)
+      for (int i = k + 1; i < p; ++i) {
+        const bool yd = f[(size_t)i * q + k] == DENSE;
+        if (!yd) continue;
+        for (int j = k + 1; j < q; ++j) {
+          int8_t& R = f[(size_t)k * q + j];
+          int8_t& A = f[(size_t)i * q + j];
+          if (R == LOWRANK && A == DENSE) {
+            R = DENSE;
+            need.push_back(k * q + j);
+          }
+          if (R == DENSE && A == LOWRANK) {
+            A = DENSE;
+            need.push_back(i * q + j);
+          }
+        }
+      }
+    alloc_dense(h, need);
+  }
+  // T and tau storage for every (i,k), i >= k, k < kend
+  {
+    std::vector<int> idx;
+    for (int k = 0; k < kend; ++k)
+      for (int i = k; i < (bc ? k + 1 : p); ++i) idx.push_back(i * q + k);
+    double* tp = (double*)h->mem.alloc(idx.size() * (size_t)b * b * 8);
+    HIPCHECK(hipMemset(tp, 0, idx.size() * (size_t)b * b * 8));
+    double* tu = (double*)h->mem.alloc(idx.size() * (size_t)b * 8);
+    HIPCHECK(hipMemset(tu, 0, idx.size() * (size_t)b * 8));
+    for (size_t a = 0; a < idx.size(); ++a) {
+      h->T[idx[a]] = tp + a * (size_t)b * b;
+      h->tau[idx[a]] = tu + a * (size_t)b;
+    }
+  }
+  h->work.release();
+  std::vector<Work> works;
+  const int nstreams = bc ? 1 : kStreams;
+  for (int a = 0; a < nstreams; ++a) works.push_back(make_work(h, 0));
+  h->n_fill = 0;
+  if (bc) {
+    BcWork bw = make_bc_work(h, bc_pairs);
+    plan_blockcol(h, P, works[0], bw, kend, o->precision == BLR_MIXED_FP32, lookahead);
+  } else {
+    plan_tiled(h, P, works, kend, o->precision == BLR_MIXED_FP32);
+  }
+  h->flops = 0.0;
+  for (auto& op : P.ops) h->flops += op.flops;
+  for (int k = 0; k < 2; ++k) {
+    for (auto e : h->prof_ev[k]) (void)hipEventDestroy(e);
+    h->prof_ev[k].clear();
+    h->prof_flops[k] = 0.0;
+    h->prof_launches[k] = 0;
+  }
+  h->launches = 0;
+  return kend;
 }
 
 blr_matrix new_handle(const blr_compress_opts* o) {
@@ -1983,84 +2305,45 @@ blr_status blr_qr_factor(blr_matrix h, const blr_factor_opts* o, void* stream) {
   if (o->precision != BLR_FP64 && o->precision != BLR_MIXED_FP32) return fail(BLR_ERR_INVALID, "bad precision");
   hipStream_t s = as_stream(stream);
   return run_guarded([&] {
-    const int b = h->b, p = h->p, q = h->q;
-    const int kend = (o->stop_after_k < 0) ? q : std::min(q, o->stop_after_k);
-    h->variant = o->variant;
-    h->precision = o->precision;
-    h->fmt0.resize((size_t)p * q);
-    for (size_t t = 0; t < h->fmt0.size(); ++t) h->fmt0[t] = h->tiles[t].fmt;
-    if (o->keep_a) {
-      keep_copy(h, s);
-      HIPCHECK(hipStreamSynchronize(s));
-    }
-    const bool bc = o->variant == BLR_BLOCK_COLUMN;
-    int bc_pairs = 0;
-    // fill-in: simulate formats to find the tiles that need a dense slot
-    if (bc) {
-      alloc_dense(h, bc_simulate(h, kend, &bc_pairs));
-    } else {
-      std::vector<int8_t> f((size_t)p * q);
-      for (size_t t = 0; t < f.size(); ++t) f[t] = h->tiles[t].fmt;
-      std::vector<int> need;
-      for (int k = 0; k < kend; ++k)
-        for (int i = k + 1; i < p; ++i) {
-          const bool yd = f[(size_t)i * q + k] == DENSE;
-          if (!yd) continue;
-          for (int j = k + 1; j < q; ++j) {
-            int8_t& R = f[(size_t)k * q + j];
-            int8_t& A = f[(size_t)i * q + j];
-            if (R == LOWRANK && A == DENSE) {
-              R = DENSE;
-              need.push_back(k * q + j);
-            }
-            if (R == DENSE && A == LOWRANK) {
-              A = DENSE;
-              need.push_back(i * q + j);
-            }
-          }
-        }
-      alloc_dense(h, need);
-    }
-    // T and tau storage for every (i,k), i >= k, k < kend
-    {
-      std::vector<int> idx;
-      for (int k = 0; k < kend; ++k)
-        for (int i = k; i < (bc ? k + 1 : p); ++i) idx.push_back(i * q + k);
-      double* tp = (double*)h->mem.alloc(idx.size() * (size_t)b * b * 8);
-      HIPCHECK(hipMemset(tp, 0, idx.size() * (size_t)b * b * 8));
-      double* tu = (double*)h->mem.alloc(idx.size() * (size_t)b * 8);
-      HIPCHECK(hipMemset(tu, 0, idx.size() * (size_t)b * 8));
-      for (size_t a = 0; a < idx.size(); ++a) {
-        h->T[idx[a]] = tp + a * (size_t)b * b;
-        h->tau[idx[a]] = tu + a * (size_t)b;
-      }
-    }
-    h->work.release();
-    std::vector<Work> works;
-    const int nstreams = bc ? 1 : kStreams;
-    for (int a = 0; a < nstreams; ++a) works.push_back(make_work(h, 0));
     Plan P;
-    h->n_fill = 0;
-    if (bc) {
-      BcWork bw = make_bc_work(h, bc_pairs);
-      plan_blockcol(h, P, works[0], bw, kend, o->precision == BLR_MIXED_FP32, true);
-    } else {
-      plan_tiled(h, P, works, kend, o->precision == BLR_MIXED_FP32);
-    }
+    const int kend = prepare_factor(h, o, s, P, true);
     P.upload(h->work);
-    h->flops = 0.0;
-    for (auto& op : P.ops) h->flops += op.flops;
-    for (int k = 0; k < 2; ++k) {
-      for (auto e : h->prof_ev[k]) (void)hipEventDestroy(e);
-      h->prof_ev[k].clear();
-      h->prof_flops[k] = 0.0;
-      h->prof_launches[k] = 0;
-    }
-    h->launches = 0;
     HIPCHECK(hipMemsetAsync(h->d_counters, 0, 4 * sizeof(unsigned long long), s));
     execute(h, P, s);
     h->steps_done = kend;
     h->state = BLR_STATE_FACTORED;
+  });
+}
+
+blr_status blr_qr_factor_batch(blr_matrix* hs, int32_t count, const blr_factor_opts* o, void* stream) {
+  if (!hs || !o || count < 1) return fail(BLR_ERR_INVALID, "NULL argument or count < 1");
+  if (o->variant != BLR_BLOCK_COLUMN) return fail(BLR_ERR_INVALID, "the batched factor runs the block-column variant");
+  if (o->precision != BLR_FP64 && o->precision != BLR_MIXED_FP32) return fail(BLR_ERR_INVALID, "bad precision");
+  std::vector<blr_matrix> v(hs, hs + count);
+  for (int i = 0; i < count; ++i) {
+    if (!v[i]) return fail(BLR_ERR_INVALID, "NULL handle in the batch");
+    if (v[i]->state != BLR_STATE_COMPRESSED) return fail(BLR_ERR_STATE, "a matrix of the batch is already factored");
+    for (int j = 0; j < i; ++j)
+      if (v[j] == v[i]) return fail(BLR_ERR_INVALID, "a handle appears twice in the batch");
+    if (v[i]->b != v[0]->b || v[i]->rc != v[0]->rc || v[i]->cap != v[0]->cap || v[i]->tol != v[0]->tol)
+      return fail(BLR_ERR_INVALID, "the matrices of a batch share tile size, rank cap and tolerance");
+  }
+  hipStream_t s = as_stream(stream);
+  return run_guarded([&] {
+    std::vector<Plan> plans(count);
+    std::vector<int> kend(count);
+    for (int i = 0; i < count; ++i) kend[i] = prepare_factor(v[i], o, s, plans[i], false);
+    Plan M = merge_plans(plans, v);
+    plans.clear();
+    M.upload(v[0]->work);
+    for (int i = 0; i < count; ++i)
+      HIPCHECK(hipMemsetAsync(v[i]->d_counters, 0, 4 * sizeof(unsigned long long), s));
+    execute(v[0], M, s);
+    for (int i = 0; i < count; ++i) {
+      v[i]->launches = v[0]->launches;
+      v[i]->steps_done = kend[i];
+      v[i]->state = BLR_STATE_FACTORED;
+    }
   });
 }
 

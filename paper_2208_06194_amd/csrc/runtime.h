@@ -45,8 +45,13 @@ struct Arena {
 
 // One enqueued operation of a plan.
 struct Op {
-  enum Kind { GEMM, PANEL, PANEL_APPLY, TBACK, RC, TRSM, WAIT, RECORD, TALL_COL, TALL_APPLY, COPY } kind;
+  enum Kind {
+    GEMM, PANEL, PANEL_APPLY, TBACK, RC, TRSM, WAIT, RECORD, TALL_COL, TALL_APPLY, COPY,
+    // batched forms of the panel kernels (jobs [off, off + n) of the plan)
+    PANEL_B, PANEL_APPLY_B, TBACK_B, TALL_COL_B, TALL_APPLY_B
+  } kind;
   int off = 0, n = 0, ntiles = 0, big = 0, fp32 = 0, prof = 0;
+  int ib = 0, ext = 0, ext2 = 0, first = 0;   // batched panel ops: width, largest extents, first column
   int stream = 0;   // index into the plan's streams
   int event = -1;   // WAIT / RECORD: event index
   double flops = 0.0;
@@ -64,7 +69,9 @@ struct Plan {
   std::vector<GemmSeg> segs;
   std::vector<RcDesc> rcs;
   std::vector<CopyDesc> copies;
+  std::vector<PanelJob> jobs;
   CopyDesc* d_copies = nullptr;
+  PanelJob* d_jobs = nullptr;
   GemmDesc* d_descs = nullptr;
   GemmSeg* d_segs = nullptr;
   RcDesc* d_rcs = nullptr;

@@ -60,3 +60,20 @@ def test_morton_sort_rejects_bad_arguments_without_a_device():
     assert lib.blr_morton_sort(p, -1, 2, p, None, None) == L.BLR_ERR_INVALID
     assert lib.blr_morton_sort(p, 4, 4, p, None, None) == L.BLR_ERR_INVALID
     assert lib.blr_morton_sort(p, 4, 0, p, None, None) == L.BLR_ERR_INVALID
+
+
+def test_batched_factor_rejects_bad_arguments_without_a_device():
+    from paper_2208_06194_amd import _lib as L
+    lib = L.load()
+    bc = L.FactorOpts(variant=L.VARIANT["block_column"], precision=L.PRECISION["fp64"], ib=0,
+                      stop_after_k=-1, keep_a=0)
+    tiled = L.FactorOpts(variant=L.VARIANT["tiled"], precision=L.PRECISION["fp64"], ib=0,
+                         stop_after_k=-1, keep_a=0)
+    none2 = (ctypes.c_void_p * 2)(None, None)
+    assert lib.blr_qr_factor_batch(None, 1, ctypes.byref(bc), None) == L.BLR_ERR_INVALID
+    assert lib.blr_qr_factor_batch(none2, 0, ctypes.byref(bc), None) == L.BLR_ERR_INVALID
+    assert lib.blr_qr_factor_batch(none2, 2, None, None) == L.BLR_ERR_INVALID
+    assert lib.blr_qr_factor_batch(none2, 2, ctypes.byref(tiled), None) == L.BLR_ERR_INVALID
+    assert b"block-column" in lib.blr_last_error()
+    assert lib.blr_qr_factor_batch(none2, 2, ctypes.byref(bc), None) == L.BLR_ERR_INVALID
+    assert b"NULL handle" in lib.blr_last_error()
