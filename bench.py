@@ -12,6 +12,10 @@ Morton sorted, kernel evaluated on the device):
   c1  2048 x 1024,     2D -log(r+1e-3),  b = 128,  adjacent boxes dense, eps 1e-8, cap 16
   c2  32768 x 16384,   3D 1/(r+1e-3),    b = 256,  gap > diameter low-rank, eps 1e-8, cap 32
   c3  131072 x 65536,  3D 1/(r+1e-3),    b = 1024, gap > diameter low-rank, eps 1e-8, cap 50
+  c4  64 matrices, m log-uniform in [4096, 32768], n = m/2, 3D 1/(r+1e-3), b = 256, eps 1e-8,
+      cap 64, each with a 16-RHS least-squares solve: the plain form (one factorization after
+      the other) against the batched form (blr_qr_factor_batch), in FP64 and in the mixed form
+      with FP64 iterative refinement of the solve
 """
 from __future__ import annotations
 
@@ -32,6 +36,10 @@ CONFIGS = {
     "c3": dict(m=131072, n=65536, b=1024, dim=3, kernel="inv_r", rule="dist_gt_diam", tol=1e-8, cap=50),
     # the differentiated least-squares workload: 65536x32768, b = 512, 32 right-hand sides
     "c5": dict(m=65536, n=32768, b=512, dim=3, kernel="inv_r", rule="dist_gt_diam", tol=1e-8, cap=32),
+    # batched forms: 64 independent matrices, rows log-uniform in [4096, 32768]
+    # (multiples of 512), n = m/2, each followed by a 16-RHS least-squares solve
+    "c4": dict(kind="batch", count=64, m_lo=4096, m_hi=32768, b=256, dim=3, kernel="inv_r",
+               rule="dist_gt_diam", tol=1e-8, cap=64, nrhs=16),
     # the paper's random-BLR accuracy workload (8192x4096 row): N(0,1) dense
     # diagonal tiles, every other tile a rank-1 product, weak admissibility
     "wr": dict(m=8192, n=4096, b=128, kind="random_blr", rank=1, rule="weak", tol=1e-10, cap=128),
@@ -243,6 +251,97 @@ def run(args, cfg, precision, tol, xd, yd, dev):
             "solve": solve}
 
 
+def run_batch(args, cfg):
+    """The batched-forms workload: every member compressed (untimed), then
+    factored one after the other (plain) or as one batch, and each solved for
+    16 right-hand sides; FP64 and mixed (FP32 MFMA updates, the solve refined
+    with FP64 residuals against the kept A~)."""
+    import torch
+    import synth
+    import paper_2208_06194_amd as P
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    rows = synth.batch_rows(args.seed, cfg["count"], cfg["m_lo"], cfg["m_hi"], 2 * cfg["b"])
+    seeds = [1000 * (args.seed + 1) + i for i in range(cfg["count"])]
+    pts = []
+    for sd, m in zip(seeds, rows):
+        x, y = synth.kernel_points(sd, int(m), int(m) // 2, cfg["dim"])
+        pts.append((torch.tensor(x, device=dev), torch.tensor(y, device=dev)))
+    rhs = [torch.tensor(synth.rhs(sd + 7, int(m), cfg["nrhs"]), device=dev) for sd, m in zip(seeds, rows)]
+    print(f"[bench] c4: {cfg['count']} members, rows {int(rows.min())}..{int(rows.max())}", file=sys.stderr,
+          flush=True)
+
+    def compress_all():
+        t0 = time.perf_counter()
+        Gs = [P.BLRMatrix.compress_kernel(x, y, cfg["kernel"], cfg["b"], cfg["tol"], cfg["cap"],
+                                          admissibility=cfg["rule"], overflow="dense", seed=args.seed)
+              for (x, y) in pts]
+        torch.cuda.synchronize()
+        return Gs, time.perf_counter() - t0
+
+    out = {}
+    x_ref = None
+    precs = ("fp64", "mixed") if args.precision == "both" else (args.precision,)
+    forms = ("plain", "batched") if args.batch_form == "both" else (args.batch_form,)
+    for prec in precs:
+        refine = 5 if prec == "mixed" else 0
+        res_prec = {}
+        for form in forms:
+            Gs, tc = compress_all()
+            probes, ax = None, None
+            if form == "batched":
+                probes = [torch.tensor(synth.rhs(args.seed + 17, G.info()["n"], 4), device=dev) for G in Gs]
+                ax = [G.matmul(pr, "A") for G, pr in zip(Gs, probes)]
+                Gs[0].profile(True)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            if form == "plain":
+                for G in Gs:
+                    G.factor("block_column", prec, keep_a=refine > 0)
+            else:
+                P.factor_batch(Gs, precision=prec, keep_a=refine > 0)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            tf = e0.elapsed_time(e1) / 1e3
+            t0 = time.perf_counter()
+            X = [G.lstsq(B, max_refine=refine) for G, B in zip(Gs, rhs)]
+            torch.cuda.synchronize()
+            ts = time.perf_counter() - t0
+            inf = [G.info() for G in Gs]
+            r = {"factor_s": tf, "lstsq_s": ts, "total_s": tf + ts, "compress_s": tc,
+                 "kernel_launches": (sum(i["kernel_launches"] for i in inf) if form == "plain"
+                                     else inf[0]["kernel_launches"]),
+                 "factor_overflow": sum(i["factor_overflow"] for i in inf)}
+            if form == "batched":
+                acc = [accuracy_probes(G, pr, a) for G, pr, a in zip(Gs, probes, ax)]
+                r["res_est_max"] = max(a[0] for a in acc)
+                r["orth_est_max"] = max(a[1] for a in acc)
+                n_g, ms_g, fl_g = Gs[0].profile_read("fp64" if prec == "fp64" else "fp32")
+                if n_g > 0:
+                    r["dominant_gemm"] = {"launches": n_g, "avg_launch_ms": ms_g / n_g,
+                                          "tflops": fl_g / (ms_g / 1e3) / 1e12}
+                r["ledger_flops"] = sum(i["flops_factor"] for i in inf)
+                r["tiles"] = {"dense": sum(i["n_dense"] for i in inf), "lowrank": sum(i["n_lowrank"] for i in inf)}
+                xs = [t.cpu().numpy() for t in X]
+                if prec == "fp64":
+                    x_ref = xs
+                elif x_ref is not None:
+                    r["lstsq_rel_err_vs_fp64_max"] = max(
+                        float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(xs, x_ref))
+            res_prec[form] = r
+            print(f"[bench] c4 {prec} {form}: factor {tf:.3f}s lstsq {ts:.3f}s "
+                  f"(launches {r['kernel_launches']})", file=sys.stderr, flush=True)
+            del Gs, X
+            torch.cuda.synchronize()
+        if len(forms) == 2:
+            res_prec["batched_speedup_factor"] = res_prec["plain"]["factor_s"] / res_prec["batched"]["factor_s"]
+            res_prec["batched_speedup_total"] = res_prec["plain"]["total_s"] / res_prec["batched"]["total_s"]
+        out[prec] = res_prec
+    dense_fl = float(sum(dense_equiv_flops(int(a), int(a) // 2) for a in rows))
+    return out, rows, dense_fl
+
+
 def roofline(prof, kernel, args, timed_s):
     """Roofline object of the dominant kernel from its HIP-event record:
     average algorithmic flops per launch / average launch duration."""
@@ -284,6 +383,8 @@ def main():
     ap.add_argument("--adjoint-rhs", type=int, default=32)
     ap.add_argument("--explicit-q", action="store_true",
                     help="also form the explicit BLR Q~ and estimate the paper's Orth and Res on it")
+    ap.add_argument("--batch-form", default="both", choices=["plain", "batched", "both"],
+                    help="c4: the forms to run (both: one factorization after the other, then the batch)")
     ap.add_argument("--stop-after-k", type=int, default=-1,
                     help="exploration only: factor the first K block columns (not a valid metric)")
     args = ap.parse_args()
@@ -296,6 +397,27 @@ def main():
 
     cfg = CONFIGS[args.config]
     dev = torch.device("cuda:0")
+    if cfg.get("kind") == "batch":
+        res, rows, dense_fl = run_batch(args, cfg)
+        p0 = "fp64" if "fp64" in res else "mixed"
+        f0 = "batched" if "batched" in res[p0] else "plain"
+        value = res[p0][f0]["total_s"]
+        out = {
+            "metric": f"batch of 64 BLR matrices: factor + 16-RHS least-squares time (s), {f0} form",
+            "value": value, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": value * 1e3,
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if p0 == "fp64" else "f32-mfma+f64",
+            "data": "synthetic",
+            "config": {"workload": f"{cfg['count']} {cfg['dim']}D {cfg['kernel']} kernel matrices, m log-uniform in "
+                                   f"[{cfg['m_lo']}, {cfg['m_hi']}] (multiples of {2 * cfg['b']}), n=m/2, "
+                                   f"b={cfg['b']}, {cfg['rule']}, eps={cfg['tol']:g}, cap={cfg['cap']}, "
+                                   f"{cfg['nrhs']} RHS each", "config_id": args.config,
+                       "rows": [int(a) for a in rows]},
+            "dense_equiv_tflops": dense_fl / res[p0][f0]["factor_s"] / 1e12,
+            **res,
+        }
+        print(json.dumps(out), flush=True)
+        return
     t0 = time.perf_counter()
     if cfg.get("kind") == "random_blr":
         # the dense random-BLR matrix on the device, from its seeded tile factors

@@ -14,7 +14,7 @@ Generator (splitmix64, Steele, Lea & Flood 2014):
              g_i = sqrt(-2 ln u1) * cos(2 pi u2)
 
 Streams: 0 = row points x, 1 = column points y, 2 = right-hand sides,
-3 = random-BLR tile entries.
+3 = random-BLR tile entries, 4 = sizes of a batch of matrices.
 """
 from __future__ import annotations
 
@@ -25,7 +25,7 @@ _GAMMA2 = np.uint64(0xD1B54A32D192ED03)
 _M1 = np.uint64(0xBF58476D1CE4E5B9)
 _M2 = np.uint64(0x94D049BB133111EB)
 
-STREAM_X, STREAM_Y, STREAM_RHS, STREAM_TILES = 0, 1, 2, 3
+STREAM_X, STREAM_Y, STREAM_RHS, STREAM_TILES, STREAM_BATCH = 0, 1, 2, 3, 4
 
 
 def _mix(z: np.ndarray) -> np.ndarray:
@@ -93,6 +93,16 @@ def points(seed: int, stream: int, count: int, dim: int) -> np.ndarray:
 def kernel_points(seed: int, m: int, n: int, dim: int):
     """Row points x (m) and column points y (n) of a kernel-matrix workload."""
     return points(seed, STREAM_X, m, dim), points(seed, STREAM_Y, n, dim)
+
+
+def batch_rows(seed: int, count: int, lo: int, hi: int, mult: int) -> np.ndarray:
+    """Row counts of a batch of matrices, log-uniform in [lo, hi]: member i
+    has exp(ln lo + u_i (ln hi - ln lo)) rounded to the nearest multiple of
+    mult and clamped to [lo, hi], with u_i uniform word i of stream 4."""
+    u = uniform(seed, STREAM_BATCH, count)
+    m = np.exp(np.log(lo) + u * (np.log(hi) - np.log(lo)))
+    m = np.rint(m / mult).astype(np.int64) * mult
+    return np.clip(m, lo, hi)
 
 
 def rhs(seed: int, m: int, nrhs: int) -> np.ndarray:
