@@ -253,9 +253,10 @@ def run(args, cfg, precision, tol, xd, yd, dev):
 
 def run_batch(args, cfg):
     """The batched-forms workload: every member compressed (untimed), then
-    factored one after the other (plain) or as one batch, and each solved for
-    16 right-hand sides; FP64 and mixed (FP32 MFMA updates, the solve refined
-    with FP64 residuals against the kept A~)."""
+    factored and solved for 16 right-hand sides one matrix after the other
+    (plain), or as one batch (blr_qr_factor_batch, blr_lstsq_solve_batch);
+    FP64 and mixed (FP32 MFMA updates, the solve refined with FP64 residuals
+    against the kept A~)."""
     import torch
     import synth
     import paper_2208_06194_amd as P
@@ -286,6 +287,7 @@ def run_batch(args, cfg):
     for prec in precs:
         refine = 5 if prec == "mixed" else 0
         res_prec = {}
+        x_plain = None
         for form in forms:
             Gs, tc = compress_all()
             probes, ax = None, None
@@ -305,7 +307,10 @@ def run_batch(args, cfg):
             torch.cuda.synchronize()
             tf = e0.elapsed_time(e1) / 1e3
             t0 = time.perf_counter()
-            X = [G.lstsq(B, max_refine=refine) for G, B in zip(Gs, rhs)]
+            if form == "plain":
+                X = [G.lstsq(B, max_refine=refine) for G, B in zip(Gs, rhs)]
+            else:
+                X = P.lstsq_batch(Gs, rhs, max_refine=refine)
             torch.cuda.synchronize()
             ts = time.perf_counter() - t0
             inf = [G.info() for G in Gs]
@@ -324,11 +329,15 @@ def run_batch(args, cfg):
                 r["ledger_flops"] = sum(i["flops_factor"] for i in inf)
                 r["tiles"] = {"dense": sum(i["n_dense"] for i in inf), "lowrank": sum(i["n_lowrank"] for i in inf)}
                 xs = [t.cpu().numpy() for t in X]
+                if x_plain is not None:
+                    r["identical_to_plain"] = all(np.array_equal(a, b) for a, b in zip(xs, x_plain))
                 if prec == "fp64":
                     x_ref = xs
                 elif x_ref is not None:
                     r["lstsq_rel_err_vs_fp64_max"] = max(
                         float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(xs, x_ref))
+            if form == "plain":
+                x_plain = [t.cpu().numpy() for t in X]
             res_prec[form] = r
             print(f"[bench] c4 {prec} {form}: factor {tf:.3f}s lstsq {ts:.3f}s "
                   f"(launches {r['kernel_launches']})", file=sys.stderr, flush=True)

@@ -272,6 +272,23 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
                            int64_t ldx, int32_t nrhs, int32_t max_refine,
                            double* resid_norms, void* hip_stream);
 
+/* Least squares for count independent factored matrices as one batch: for
+ * each i, X[i] = argmin ||A~_i X - B[i]||_F exactly as blr_lstsq_solve(hs[i],
+ * B[i], ldb[i], X[i], ldx[i], nrhs, max_refine, NULL, stream) computes it
+ * (bit-identical results), with the launches of all members merged as in
+ * blr_qr_factor_batch.  hs, B, ldb, X, ldx are host arrays of count entries;
+ * B[i] (device, m_i x nrhs, ldb[i] >= m_i) is not modified, X[i] (device,
+ * n_i x nrhs, ldx[i] >= n_i) is overwritten.  Members may differ in size,
+ * tile size and variant.  max_refine > 0 needs every factor made with keep_a;
+ * each member stops refining when its own test is met.  No residual norms.
+ * Synchronises the stream.  Errors: BLR_ERR_INVALID (NULL pointers, count <
+ * 1, a repeated handle, bad shapes), BLR_ERR_STATE (a member not fully
+ * factored, or refinement without keep_a), BLR_ERR_SINGULAR (the message
+ * names the first singular member; no X is written then). */
+blr_status blr_lstsq_solve_batch(blr_matrix* hs, int32_t count, const double* const* B, const int64_t* ldb,
+                                 double* const* X, const int64_t* ldx, int32_t nrhs, int32_t max_refine,
+                                 void* hip_stream);
+
 /* Shape, formats, state, memory and counters of a handle.  Synchronises. */
 blr_status blr_query(blr_matrix h, blr_info* info);
 

@@ -6,6 +6,6 @@ on first use and every entry point raises if it has not been built: there is
 no fallback path.
 """
 from ._lib import load
-from .api import BLRError, BLRMatrix, LstsqFunction, factor_batch, lstsq, morton_sort
+from .api import BLRError, BLRMatrix, LstsqFunction, factor_batch, lstsq, lstsq_batch, morton_sort
 
-__all__ = ["BLRMatrix", "BLRError", "LstsqFunction", "factor_batch", "load", "lstsq", "morton_sort"]
+__all__ = ["BLRMatrix", "BLRError", "LstsqFunction", "factor_batch", "load", "lstsq", "lstsq_batch", "morton_sort"]

@@ -13,7 +13,7 @@ EXPORTED = [
     "blr_compress", "blr_import", "blr_export", "blr_qr_factor", "blr_apply_qt",
     "blr_lstsq_solve", "blr_query", "blr_destroy", "blr_status_string", "blr_last_error",
     "blr_profile_enable", "blr_profile_read", "blr_matmul", "blr_morton_sort", "blr_rsolve",
-    "blr_lstsq_adjoint", "blr_form_q", "blr_qr_factor_batch",
+    "blr_lstsq_adjoint", "blr_form_q", "blr_qr_factor_batch", "blr_lstsq_solve_batch",
 ]
 SELFTEST = ["blr_selftest_gemm"]
 MATMUL = {"A": 0, "AT": 1, "R": 2}
@@ -75,6 +75,8 @@ def load() -> ctypes.CDLL:
     lib.blr_export.argtypes = [c_void_p, P(TilesHost)]
     lib.blr_qr_factor.argtypes = [c_void_p, P(FactorOpts), c_void_p]
     lib.blr_qr_factor_batch.argtypes = [P(c_void_p), c_int32, P(FactorOpts), c_void_p]
+    lib.blr_lstsq_solve_batch.argtypes = [P(c_void_p), c_int32, P(c_void_p), P(c_int64), P(c_void_p),
+                                          P(c_int64), c_int32, c_int32, c_void_p]
     lib.blr_apply_qt.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_int32, c_void_p]
     lib.blr_lstsq_solve.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int32, c_int32,
                                     c_void_p, c_void_p]

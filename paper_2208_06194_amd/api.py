@@ -99,6 +99,32 @@ def factor_batch(mats, precision: str = "fp64", stop_after_k: int = -1, keep_a: 
     return mats
 
 
+def lstsq_batch(mats, Bs, max_refine: int = 0, stream=None):
+    """X_i = argmin ||A~_i X - B_i|| for factored matrices mats[i] and (m_i,
+    nrhs) device tensors Bs[i], as one batch (blr_lstsq_solve_batch); the
+    same result per member as mats[i].lstsq(Bs[i], max_refine=max_refine)."""
+    mats, Bs = list(mats), list(Bs)
+    if len(mats) != len(Bs):
+        raise ValueError("one right-hand side block per matrix")
+    nrhs = Bs[0].shape[1] if Bs[0].dim() == 2 else 1
+    Bc, Xc = [], []
+    for G, B in zip(mats, Bs):
+        inf = G.info()
+        b = _colmajor(B.to(torch.float64))
+        if b.shape != (nrhs, inf["m"]):
+            raise ValueError("every B must be (m_i, nrhs) with the same nrhs")
+        Bc.append(b)
+        Xc.append(torch.empty((nrhs, inf["n"]), dtype=torch.float64, device=B.device))
+    k = len(mats)
+    hs = (ctypes.c_void_p * k)(*[G._h.value for G in mats])
+    bp = (ctypes.c_void_p * k)(*[b.data_ptr() for b in Bc])
+    xp = (ctypes.c_void_p * k)(*[x.data_ptr() for x in Xc])
+    lb = (ctypes.c_int64 * k)(*[G.info()["m"] for G in mats])
+    lx = (ctypes.c_int64 * k)(*[G.info()["n"] for G in mats])
+    _check(L.load().blr_lstsq_solve_batch(hs, k, bp, lb, xp, lx, nrhs, max_refine, _stream(stream)))
+    return [x.t() for x in Xc]
+
+
 class BLRMatrix:
     """A BLR matrix owned by the library (one handle)."""
 

@@ -48,3 +48,28 @@ hipError_t launch_lincomb(double* out, int64_t ldo, const double* x, int64_t ldx
                           const double* z, int64_t ldz, double a, double b, double c, int rows, int cols,
                           hipStream_t s);
 hipError_t launch_diag_absmin(const DiagDesc* d, int n, int b, double* out, hipStream_t s);
+
+// One triangular solve of a batched launch (op(R) X = C in place, R upper
+// triangular n x n): the arguments of launch_trsm_upper(_t).  Device array.
+struct TrsmJob {
+  const double* R;
+  int64_t ldr;
+  double* X;
+  int64_t ldx;
+  int32_t n, nrhs;
+};
+hipError_t launch_trsm_batch(const TrsmJob* d, int count, int trans, int max_nrhs, hipStream_t s);
+// out = a x + b y + c z for each descriptor (device array; y, z may be null).
+struct LincombDesc {
+  double* out;
+  int64_t ldo;
+  const double* x;
+  int64_t ldx;
+  const double* y;
+  int64_t ldy;
+  const double* z;
+  int64_t ldz;
+  double a, b, c;
+  int32_t rows, cols;
+};
+hipError_t launch_lincomb_batch(const LincombDesc* d, int count, int64_t max_elems, hipStream_t s);

@@ -130,15 +130,15 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 template <bool TRANS>
-__global__ __launch_bounds__(kTrsmThreads) void k_trsm_blk(const double* __restrict__ R, int64_t ldr, int n,
-                                                           double* X, int64_t ldx, int nrhs) {
+__device__ __forceinline__ void trsm_body(const double* __restrict__ R, int64_t ldr, int n, double* X, int64_t ldx,
+                                          int nrhs, int cb) {
   constexpr int NW = kTrsmThreads / 64;
   __shared__ double Rs[kTrsmB][kTrsmB + 1];   // op(R) of the diagonal block: Rs[row][col]
   __shared__ double dinv[kTrsmB];
   __shared__ double xs[kTrsmB][kTrsmR];       // the block's solution (zero past the block and nrhs)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lm = lane & 15, lg = lane >> 4;
-  const int c0 = blockIdx.x * kTrsmR;
+  const int c0 = cb * kTrsmR;
   const int nr = min(kTrsmR, nrhs - c0);
   double* Xc = X + (int64_t)c0 * ldx;
   const int nb = (n + kTrsmB - 1) / kTrsmB;
@@ -229,17 +229,41 @@ __global__ __launch_bounds__(kTrsmThreads) void k_trsm_blk(const double* __restr
   }
 }
 
+template <bool TRANS>
+__global__ __launch_bounds__(kTrsmThreads) void k_trsm_blk(const double* __restrict__ R, int64_t ldr, int n,
+                                                           double* X, int64_t ldx, int nrhs) {
+  trsm_body<TRANS>(R, ldr, n, X, ldx, nrhs, blockIdx.x);
+}
+
+// Batched form: job blockIdx.y; workgroups past the job's right-hand sides exit.
+template <bool TRANS>
+__global__ __launch_bounds__(kTrsmThreads) void k_trsm_blk_batch(const TrsmJob* __restrict__ jobs) {
+  const TrsmJob J = jobs[blockIdx.y];
+  if ((int)blockIdx.x * kTrsmR >= J.nrhs) return;
+  trsm_body<TRANS>(J.R, J.ldr, J.n, J.X, J.ldx, J.nrhs, blockIdx.x);
+}
+
 // out = a x + b y + c z over a rows x cols column-major block (y, z may be null).
+__device__ __forceinline__ void lincomb_one(const LincombDesc& D, int64_t e0, int64_t stride) {
+  const int64_t n = (int64_t)D.rows * D.cols;
+  for (int64_t e = e0; e < n; e += stride) {
+    const int64_t r = e % D.rows, col = e / D.rows;
+    double v = D.a * D.x[r + col * D.ldx];
+    if (D.y) v += D.b * D.y[r + col * D.ldy];
+    if (D.z) v += D.c * D.z[r + col * D.ldz];
+    D.out[r + col * D.ldo] = v;
+  }
+}
+
+__global__ void k_lincomb_batch(const LincombDesc* __restrict__ d) {
+  const LincombDesc D = d[blockIdx.y];
+  lincomb_one(D, blockIdx.x * (int64_t)blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
+}
+
 __global__ void k_lincomb(double* out, int64_t ldo, const double* x, int64_t ldx, const double* y, int64_t ldy,
                           const double* z, int64_t ldz, double a, double b, double c, int rows, int cols) {
-  const int64_t n = (int64_t)rows * cols;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = e % rows, col = e / rows;
-    double v = a * x[r + col * ldx];
-    if (y) v += b * y[r + col * ldy];
-    if (z) v += c * z[r + col * ldz];
-    out[r + col * ldo] = v;
-  }
+  const LincombDesc D{out, ldo, x, ldx, y, ldy, z, ldz, a, b, c, rows, cols};
+  lincomb_one(D, blockIdx.x * (int64_t)blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
 }
 
 __global__ void k_diag_absmin(const DiagDesc* __restrict__ d, int b, double* out) {
@@ -332,6 +356,21 @@ hipError_t launch_lincomb(double* out, int64_t ldo, const double* x, int64_t ldx
   const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
   hipLaunchKernelGGL(k_lincomb, dim3(blocks), dim3(256), 0, s, out, ldo, x, ldx, y, ldy, z, ldz, a, b, c, rows,
                      cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_batch(const TrsmJob* d, int count, int trans, int max_nrhs, hipStream_t s) {
+  if (count <= 0 || max_nrhs <= 0) return hipSuccess;
+  dim3 grid((max_nrhs + kTrsmR - 1) / kTrsmR, count), block(kTrsmThreads);
+  if (trans) hipLaunchKernelGGL(k_trsm_blk_batch<true>, grid, block, 0, s, d);
+  else hipLaunchKernelGGL(k_trsm_blk_batch<false>, grid, block, 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_lincomb_batch(const LincombDesc* d, int count, int64_t max_elems, hipStream_t s) {
+  if (count <= 0 || max_elems <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>((max_elems + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_lincomb_batch, dim3(blocks, count), dim3(256), 0, s, d);
   return hipGetLastError();
 }
 

@@ -235,6 +235,18 @@ void Plan::upload(Arena& arena) {
     d_jobs = (PanelJob*)arena.alloc(jobs.size() * sizeof(PanelJob));
     HIPCHECK(hipMemcpy(d_jobs, jobs.data(), jobs.size() * sizeof(PanelJob), hipMemcpyHostToDevice));
   }
+  if (!tjobs.empty()) {
+    d_tjobs = (TrsmJob*)arena.alloc(tjobs.size() * sizeof(TrsmJob));
+    HIPCHECK(hipMemcpy(d_tjobs, tjobs.data(), tjobs.size() * sizeof(TrsmJob), hipMemcpyHostToDevice));
+  }
+  if (!lincs.empty()) {
+    d_lincs = (LincombDesc*)arena.alloc(lincs.size() * sizeof(LincombDesc));
+    HIPCHECK(hipMemcpy(d_lincs, lincs.data(), lincs.size() * sizeof(LincombDesc), hipMemcpyHostToDevice));
+  }
+  if (!frobs.empty()) {
+    d_frobs = (Frob2Desc*)arena.alloc(frobs.size() * sizeof(Frob2Desc));
+    HIPCHECK(hipMemcpy(d_frobs, frobs.data(), frobs.size() * sizeof(Frob2Desc), hipMemcpyHostToDevice));
+  }
 }
 
 void Plan::clear() { *this = Plan(); }
@@ -356,6 +368,25 @@ void execute(blr_matrix h, Plan& P, hipStream_t s) {
       case Op::TALL_APPLY_B:
         HIPCHECK(launch_tall_apply_batch(P.d_jobs + o.off, o.n, o.ib, o.ext, o.ext2, q));
         h->launches += 2;
+        break;
+      case Op::TRSM: {
+        const TrsmJob& J = o.trsm;
+        if (o.n) HIPCHECK(launch_trsm_upper_t(J.R, J.ldr, J.n, J.X, J.ldx, J.nrhs, q));
+        else HIPCHECK(launch_trsm_upper(J.R, J.ldr, J.n, J.X, J.ldx, J.nrhs, q));
+        h->launches += 1;
+        break;
+      }
+      case Op::TRSM_B:
+        HIPCHECK(launch_trsm_batch(P.d_tjobs + o.off, o.n, o.first, o.ext, q));
+        h->launches += 1;
+        break;
+      case Op::LINCOMB:
+        HIPCHECK(launch_lincomb_batch(P.d_lincs + o.off, o.n, o.maxel, q));
+        h->launches += 1;
+        break;
+      case Op::FROB2:
+        HIPCHECK(launch_frob2(P.d_frobs + o.off, o.n, q));
+        h->launches += 1;
         break;
       case Op::WAIT:
         if (nstreams > 1) HIPCHECK(hipStreamWaitEvent(q, ev[o.event], 0));
@@ -1379,6 +1410,9 @@ bool op_launches(const Op& o) {
     case Op::PANEL_APPLY: return o.n > 0;
     case Op::TBACK: return o.tback.n > o.tback.ib;
     case Op::TALL_APPLY: return o.ntiles > 0;
+    case Op::TRSM: return o.trsm.n > 0 && o.trsm.nrhs > 0;
+    case Op::LINCOMB: return o.n > 0 && o.maxel > 0;
+    case Op::FROB2: return o.n > 0;
     case Op::WAIT:
     case Op::RECORD: return false;
     default: throw Error(BLR_ERR_INVALID, "op kind cannot be batched");
@@ -1394,6 +1428,7 @@ OpSig op_sig(const Op& o) {
     case Op::PANEL_APPLY:
     case Op::TALL_APPLY: g.a = o.panel.ib; break;
     case Op::TALL_COL: g.a = o.tall.ib; g.b = o.tall.jj == 0; break;
+    case Op::TRSM: g.a = o.n; break;
     default: break;
   }
   return g;
@@ -1452,6 +1487,41 @@ void emit_merged(Plan& M, const std::vector<Plan>& plans, const std::vector<blr_
         M.copies.insert(M.copies.end(), S.copies.begin() + o.off, S.copies.begin() + o.off + o.n);
         m.n += o.n;
         m.maxel = std::max(m.maxel, o.maxel);
+      }
+      break;
+    case Op::LINCOMB:
+      m.off = (int)M.lincs.size();
+      for (auto& sp : src) {
+        const Plan& S = plans[sp.first];
+        const Op& o = S.ops[sp.second];
+        M.lincs.insert(M.lincs.end(), S.lincs.begin() + o.off, S.lincs.begin() + o.off + o.n);
+        m.n += o.n;
+        m.maxel = std::max(m.maxel, o.maxel);
+      }
+      break;
+    case Op::FROB2:
+      m.off = (int)M.frobs.size();
+      for (auto& sp : src) {
+        const Plan& S = plans[sp.first];
+        const Op& o = S.ops[sp.second];
+        M.frobs.insert(M.frobs.end(), S.frobs.begin() + o.off, S.frobs.begin() + o.off + o.n);
+        m.n += o.n;
+      }
+      break;
+    case Op::TRSM:
+      if (single) {
+        m = o0;
+        m.stream = 0;
+        break;
+      }
+      m.kind = Op::TRSM_B;
+      m.first = o0.n;   // transposed solves
+      m.off = (int)M.tjobs.size();
+      for (auto& sp : src) {
+        const Op& o = plans[sp.first].ops[sp.second];
+        M.tjobs.push_back(o.trsm);
+        m.n += 1;
+        m.ext = std::max(m.ext, o.trsm.nrhs);
       }
       break;
     default: {
@@ -1717,11 +1787,21 @@ void plan_matmul(blr_matrix h, Plan& P, int op, const double* X, int64_t ldx, do
 // block X: per block row, the off-diagonal tiles' contributions as one
 // multi-segment product (low-rank tiles through V^T X_j or U^T X_j), then a
 // triangular solve with the diagonal tile.  Enqueued on s.
-void run_rsolve(blr_matrix h, double* X, int64_t ldx, int nrhs, int trans, hipStream_t s) {
+// Workspace of plan_rsolve: Sx (rc x nrhs per tile column) and Wp (split partial sums).
+struct RsolveWork {
+  double *Sx, *Wp;
+};
+RsolveWork make_rsolve_work(blr_matrix h, int nrhs) {
+  RsolveWork r;
+  r.Sx = (double*)h->work.alloc((size_t)h->q * h->rc * nrhs * 8);
+  r.Wp = (double*)h->work.alloc((size_t)kApplySlices * h->b * std::min(nrhs, 64) * 8);
+  return r;
+}
+
+void plan_rsolve(blr_matrix h, Plan& Q, const RsolveWork& rw, double* X, int64_t ldx, int nrhs, int trans) {
   const int b = h->b, q = h->q, rc = h->rc;
-  Plan Q;
-  double* Sx = (double*)h->work.alloc((size_t)q * rc * nrhs * 8);  // rc x nrhs per tile column
-  double* Wp = (double*)h->work.alloc((size_t)kApplySlices * b * std::min(nrhs, 64) * 8);
+  double* Sx = rw.Sx;
+  double* Wp = rw.Wp;
   for (int step = 0; step < q; ++step) {
     const int k = trans ? step : q - 1 - step;
     double* Xk = X + (int64_t)k * b;
@@ -1774,22 +1854,63 @@ void run_rsolve(blr_matrix h, double* X, int64_t ldx, int nrhs, int trans, hipSt
     }
     Op o;
     o.kind = Op::TRSM;
-    o.off = k;
     o.n = trans;
-    Q.ops.push_back(o);
+    o.trsm = TrsmJob{h->t(k, k).D, (int64_t)b, Xk, ldx, b, nrhs};
+    Q.push(o);
   }
+}
+
+void run_rsolve(blr_matrix h, double* X, int64_t ldx, int nrhs, int trans, hipStream_t s) {
+  Plan Q;
+  plan_rsolve(h, Q, make_rsolve_work(h, nrhs), X, ldx, nrhs, trans);
   Q.upload(h->work);
-  for (const Op& o : Q.ops) {
-    if (o.kind == Op::TRSM) {
-      const int k = o.off;
-      if (o.n) HIPCHECK(launch_trsm_upper_t(h->t(k, k).D, b, b, X + (int64_t)k * b, ldx, nrhs, s));
-      else HIPCHECK(launch_trsm_upper(h->t(k, k).D, b, b, X + (int64_t)k * b, ldx, nrhs, s));
-    } else if (o.kind == Op::COPY) {
-      HIPCHECK(launch_copy_blocks(Q.d_copies + o.off, o.n, o.maxel, s));
-    } else {
-      HIPCHECK(launch_gemm(Q.d_descs + o.off, o.n, Q.d_segs, o.ntiles, o.big, 0, s));
+  execute(h, Q, s);
+}
+
+// Singularity check of a complete factor: min |R_jj| against n u ||R||_F.
+// sing_launch enqueues the reductions and their copies to the host; after
+// the stream is synchronised, sing_ok evaluates them.
+struct SingCheck {
+  std::vector<double> ho, hf;
+};
+SingCheck sing_launch(blr_matrix h, hipStream_t s) {
+  const int b = h->b, q = h->q, rc = h->rc;
+  SingCheck c;
+  std::vector<DiagDesc> dd(q);
+  for (int k = 0; k < q; ++k) dd[k].R = h->t(k, k).D;
+  DiagDesc* ddd = (DiagDesc*)h->work.alloc(q * sizeof(DiagDesc));
+  double* out = (double*)h->work.alloc((size_t)2 * q * 8);
+  HIPCHECK(hipMemcpy(ddd, dd.data(), q * sizeof(DiagDesc), hipMemcpyHostToDevice));
+  HIPCHECK(launch_diag_absmin(ddd, q, b, out, s));
+  std::vector<Frob2Desc> fr;
+  double* fo = (double*)h->work.alloc((size_t)q * q * 8 + 8);
+  for (int k = 0; k < q; ++k)
+    for (int j = k + 1; j < q; ++j) {
+      Tile& t = h->t(k, j);
+      double* o = fo + fr.size();
+      if (t.fmt == DENSE) fr.push_back(Frob2Desc{t.D, b, b, b, o});
+      else fr.push_back(Frob2Desc{t.Vt, rc, rc, b, o});
     }
+  if (!fr.empty()) {
+    Frob2Desc* dfr = (Frob2Desc*)h->work.alloc(fr.size() * sizeof(Frob2Desc));
+    HIPCHECK(hipMemcpy(dfr, fr.data(), fr.size() * sizeof(Frob2Desc), hipMemcpyHostToDevice));
+    HIPCHECK(launch_frob2(dfr, (int)fr.size(), s));
   }
+  c.ho.resize(2 * q);
+  c.hf.resize(fr.size());
+  HIPCHECK(hipMemcpyAsync(c.ho.data(), out, 2 * q * 8, hipMemcpyDeviceToHost, s));
+  if (!fr.empty()) HIPCHECK(hipMemcpyAsync(c.hf.data(), fo, fr.size() * 8, hipMemcpyDeviceToHost, s));
+  return c;
+}
+bool sing_ok(blr_matrix h, const SingCheck& c) {
+  double r2 = 0.0, mn = 1e300;
+  for (int k = 0; k < h->q; ++k) {
+    mn = std::min(mn, c.ho[2 * k]);
+    r2 += c.ho[2 * k + 1];
+  }
+  for (double v : c.hf) r2 += v;
+  const double thr = (double)h->n * 2.220446049250313e-16 * std::sqrt(r2);
+  return mn > thr;
 }
 
 // Keep a device copy of A~ (all tiles and ranks) for products after the
@@ -2380,41 +2501,10 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
     const int64_t m = h->m, n = h->n;
     HIPCHECK(hipDeviceSynchronize());
     h->work.release();
-    // singularity check: min |R_jj| against n u ||R||_F
     {
-      Plan P0;
-      std::vector<DiagDesc> dd(q);
-      for (int k = 0; k < q; ++k) dd[k].R = h->t(k, k).D;
-      DiagDesc* ddd = (DiagDesc*)h->work.alloc(q * sizeof(DiagDesc));
-      double* out = (double*)h->work.alloc((size_t)2 * q * 8);
-      HIPCHECK(hipMemcpy(ddd, dd.data(), q * sizeof(DiagDesc), hipMemcpyHostToDevice));
-      HIPCHECK(launch_diag_absmin(ddd, q, b, out, s));
-      std::vector<Frob2Desc> fr;
-      double* fo = (double*)h->work.alloc((size_t)q * q * 8 + 8);
-      for (int k = 0; k < q; ++k)
-        for (int j = k + 1; j < q; ++j) {
-          Tile& t = h->t(k, j);
-          double* o = fo + fr.size();
-          if (t.fmt == DENSE) fr.push_back(Frob2Desc{t.D, b, b, b, o});
-          else fr.push_back(Frob2Desc{t.Vt, rc, rc, b, o});
-        }
-      if (!fr.empty()) {
-        Frob2Desc* dfr = (Frob2Desc*)h->work.alloc(fr.size() * sizeof(Frob2Desc));
-        HIPCHECK(hipMemcpy(dfr, fr.data(), fr.size() * sizeof(Frob2Desc), hipMemcpyHostToDevice));
-        HIPCHECK(launch_frob2(dfr, (int)fr.size(), s));
-      }
-      std::vector<double> ho(2 * q), hf(fr.size());
-      HIPCHECK(hipMemcpyAsync(ho.data(), out, 2 * q * 8, hipMemcpyDeviceToHost, s));
-      if (!fr.empty()) HIPCHECK(hipMemcpyAsync(hf.data(), fo, fr.size() * 8, hipMemcpyDeviceToHost, s));
+      SingCheck sc = sing_launch(h, s);
       HIPCHECK(hipStreamSynchronize(s));
-      double r2 = 0.0, mn = 1e300;
-      for (int k = 0; k < q; ++k) {
-        mn = std::min(mn, ho[2 * k]);
-        r2 += ho[2 * k + 1];
-      }
-      for (double v : hf) r2 += v;
-      const double thr = (double)n * 2.220446049250313e-16 * std::sqrt(r2);
-      if (!(mn > thr)) throw Error(BLR_ERR_SINGULAR, "R is numerically singular");
+      if (!sing_ok(h, sc)) throw Error(BLR_ERR_SINGULAR, "R is numerically singular");
       h->work.release();
     }
     Work w = make_work(h, nrhs);
@@ -2485,6 +2575,141 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
         if (done) break;
       }
       if (resid_norms) frob2(r, m, m, resid_norms);
+    }
+    HIPCHECK(hipStreamSynchronize(s));
+  });
+}
+
+blr_status blr_lstsq_solve_batch(blr_matrix* hs, int32_t count, const double* const* B, const int64_t* ldb,
+                                 double* const* X, const int64_t* ldx, int32_t nrhs, int32_t max_refine,
+                                 void* stream) {
+  if (!hs || !B || !ldb || !X || !ldx || count < 1) return fail(BLR_ERR_INVALID, "NULL argument or count < 1");
+  if (nrhs < 0 || max_refine < 0) return fail(BLR_ERR_INVALID, "nrhs and max_refine must be >= 0");
+  std::vector<blr_matrix> v(hs, hs + count);
+  for (int i = 0; i < count; ++i) {
+    blr_matrix h = v[i];
+    if (!h || !B[i] || !X[i]) return fail(BLR_ERR_INVALID, "NULL handle or pointer in the batch");
+    for (int j = 0; j < i; ++j)
+      if (v[j] == h) return fail(BLR_ERR_INVALID, "a handle appears twice in the batch");
+    if (h->state != BLR_STATE_FACTORED || h->steps_done != h->q)
+      return fail(BLR_ERR_STATE, "a matrix of the batch is not (fully) factored");
+    if (ldb[i] < h->m || ldx[i] < h->n) return fail(BLR_ERR_INVALID, "bad B or X shape");
+    if (max_refine > 0 && h->acopy.empty())
+      return fail(BLR_ERR_STATE, "refinement needs the copy of A~ kept by a factor with keep_a");
+  }
+  if (nrhs == 0) return BLR_OK;
+  hipStream_t s = as_stream(stream);
+  return run_guarded([&] {
+    HIPCHECK(hipDeviceSynchronize());
+    std::vector<SingCheck> sc(count);
+    for (int i = 0; i < count; ++i) {
+      v[i]->work.release();
+      sc[i] = sing_launch(v[i], s);
+    }
+    HIPCHECK(hipStreamSynchronize(s));
+    for (int i = 0; i < count; ++i) {
+      if (!sing_ok(v[i], sc[i]))
+        throw Error(BLR_ERR_SINGULAR, "R of batch member " + std::to_string(i) + " is numerically singular");
+      v[i]->work.release();
+    }
+    struct Member {
+      Work w;
+      RsolveWork rw;
+      double *C = nullptr, *r = nullptr, *f = nullptr, *g = nullptr, *dr = nullptr, *nrm = nullptr;
+      std::vector<double> hn;
+      bool active = true;
+    };
+    std::vector<Member> mb(count);
+    auto run = [&](std::vector<Plan>& plans) {
+      std::vector<Plan> live;
+      std::vector<blr_matrix> hv;
+      for (int i = 0; i < count; ++i)
+        if (!plans[i].ops.empty()) {
+          live.push_back(std::move(plans[i]));
+          hv.push_back(v[i]);
+        }
+      if (live.empty()) return;
+      Plan M = merge_plans(live, hv);
+      M.upload(v[0]->work);
+      execute(v[0], M, s);
+    };
+    auto lc = [](double* out, int64_t ldo, const double* x, int64_t lx, const double* y, int64_t ly,
+                 const double* z, int64_t lz, double a, double b, double c, int64_t rows, int cols) {
+      return LincombDesc{out, ldo, x, lx, y, ly, z, lz, a, b, c, (int32_t)rows, cols};
+    };
+    // Q^T B, then X = R^{-1} (Q^T B)[0:n]; with refinement also r = Q [0; (Q^T b)[n:m]]
+    std::vector<Plan> plans(count);
+    for (int i = 0; i < count; ++i) {
+      blr_matrix h = v[i];
+      const int64_t m = h->m, n = h->n;
+      Member& e = mb[i];
+      Plan& P = plans[i];
+      e.w = make_work(h, nrhs);
+      e.rw = make_rsolve_work(h, nrhs);
+      e.C = (double*)h->work.alloc((size_t)m * nrhs * 8);
+      P.copy({CopyDesc{B[i], e.C, ldb[i], m, (int32_t)m, nrhs, 0, 0, 0}});
+      plan_apply(h, P, e.w, e.C, m, nrhs, 0);
+      P.copy({CopyDesc{e.C, X[i], m, ldx[i], (int32_t)n, nrhs, 0, 0, 0}});
+      plan_rsolve(h, P, e.rw, X[i], ldx[i], nrhs, 0);
+      if (max_refine > 0) {
+        e.r = (double*)h->work.alloc((size_t)m * nrhs * 8);
+        e.f = (double*)h->work.alloc((size_t)m * nrhs * 8);
+        e.g = (double*)h->work.alloc((size_t)n * nrhs * 8);
+        e.dr = (double*)h->work.alloc((size_t)m * nrhs * 8);
+        e.nrm = (double*)h->work.alloc((size_t)2 * nrhs * 8);
+        e.hn.resize(2 * nrhs);
+        P.lincomb(lc(e.r, m, e.C, m, nullptr, 0, nullptr, 0, 0.0, 0.0, 0.0, n, nrhs));
+        P.lincomb(lc(e.r + n, m, e.C + n, m, nullptr, 0, nullptr, 0, 1.0, 0.0, 0.0, m - n, nrhs));
+        plan_apply(h, P, e.w, e.r, m, nrhs, 1);
+      }
+    }
+    run(plans);
+    // refinement of [I A~; A~^T 0][r; x] = [b; 0] with FP64 residuals, the
+    // steps of blr_lstsq_solve for every member still refining
+    const double u = 2.220446049250313e-16;
+    for (int it = 0; it < max_refine; ++it) {
+      plans.assign(count, Plan());
+      bool any = false;
+      for (int i = 0; i < count; ++i) {
+        Member& e = mb[i];
+        if (!e.active) continue;
+        any = true;
+        blr_matrix h = v[i];
+        const int64_t m = h->m, n = h->n;
+        Plan& P = plans[i];
+        plan_matmul(h, P, BLR_MATMUL_A, X[i], ldx[i], e.f, m, nrhs);
+        plan_matmul(h, P, BLR_MATMUL_AT, e.r, m, e.g, n, nrhs);
+        P.lincomb(lc(e.f, m, B[i], ldb[i], e.r, m, e.f, m, 1.0, -1.0, -1.0, m, nrhs));
+        plan_apply(h, P, e.w, e.f, m, nrhs, 0);
+        P.lincomb(lc(e.g, n, e.g, n, nullptr, 0, nullptr, 0, -1.0, 0.0, 0.0, n, nrhs));
+        plan_rsolve(h, P, e.rw, e.g, n, nrhs, 1);
+        P.lincomb(lc(e.dr, m, e.g, n, nullptr, 0, nullptr, 0, 1.0, 0.0, 0.0, n, nrhs));
+        P.lincomb(lc(e.dr + n, m, e.f + n, m, nullptr, 0, nullptr, 0, 1.0, 0.0, 0.0, m - n, nrhs));
+        plan_apply(h, P, e.w, e.dr, m, nrhs, 1);
+        P.lincomb(lc(e.f, m, e.f, m, e.g, n, nullptr, 0, 1.0, -1.0, 0.0, n, nrhs));
+        plan_rsolve(h, P, e.rw, e.f, m, nrhs, 0);
+        P.lincomb(lc(X[i], ldx[i], X[i], ldx[i], e.f, m, nullptr, 0, 1.0, 1.0, 0.0, n, nrhs));
+        P.lincomb(lc(e.r, m, e.r, m, e.dr, m, nullptr, 0, 1.0, 1.0, 0.0, m, nrhs));
+        std::vector<Frob2Desc> fr(2 * nrhs);
+        for (int c = 0; c < nrhs; ++c) {
+          fr[c] = Frob2Desc{e.f + (int64_t)c * m, m, (int32_t)n, 1, e.nrm + c};
+          fr[nrhs + c] = Frob2Desc{X[i] + (int64_t)c * ldx[i], ldx[i], (int32_t)n, 1, e.nrm + nrhs + c};
+        }
+        P.frob2(fr);
+      }
+      if (!any) break;
+      run(plans);
+      for (int i = 0; i < count; ++i)
+        if (mb[i].active)
+          HIPCHECK(hipMemcpyAsync(mb[i].hn.data(), mb[i].nrm, 2 * nrhs * 8, hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      for (int i = 0; i < count; ++i) {
+        Member& e = mb[i];
+        if (!e.active) continue;
+        bool done = true;
+        for (int c = 0; c < nrhs; ++c) done = done && std::sqrt(e.hn[c]) <= 2.0 * u * std::sqrt(e.hn[nrhs + c]);
+        if (done) e.active = false;
+      }
     }
     HIPCHECK(hipStreamSynchronize(s));
   });

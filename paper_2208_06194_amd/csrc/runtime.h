@@ -48,7 +48,9 @@ struct Op {
   enum Kind {
     GEMM, PANEL, PANEL_APPLY, TBACK, RC, TRSM, WAIT, RECORD, TALL_COL, TALL_APPLY, COPY,
     // batched forms of the panel kernels (jobs [off, off + n) of the plan)
-    PANEL_B, PANEL_APPLY_B, TBACK_B, TALL_COL_B, TALL_APPLY_B
+    PANEL_B, PANEL_APPLY_B, TBACK_B, TALL_COL_B, TALL_APPLY_B,
+    // solve steps: batched triangular solves, linear combinations, squared norms
+    TRSM_B, LINCOMB, FROB2
   } kind;
   int off = 0, n = 0, ntiles = 0, big = 0, fp32 = 0, prof = 0;
   int ib = 0, ext = 0, ext2 = 0, first = 0;   // batched panel ops: width, largest extents, first column
@@ -58,6 +60,7 @@ struct Op {
   PanelArgs panel{};
   TBackArgs tback{};
   TallArgs tall{};
+  TrsmJob trsm{};         // TRSM: the solve (n: 1 = with R^T)
   double* buf = nullptr;   // TALL_APPLY: partial sums
   int64_t maxel = 0;       // COPY: largest block
 };
@@ -70,8 +73,14 @@ struct Plan {
   std::vector<RcDesc> rcs;
   std::vector<CopyDesc> copies;
   std::vector<PanelJob> jobs;
+  std::vector<TrsmJob> tjobs;
+  std::vector<LincombDesc> lincs;
+  std::vector<Frob2Desc> frobs;
   CopyDesc* d_copies = nullptr;
   PanelJob* d_jobs = nullptr;
+  TrsmJob* d_tjobs = nullptr;
+  LincombDesc* d_lincs = nullptr;
+  Frob2Desc* d_frobs = nullptr;
   GemmDesc* d_descs = nullptr;
   GemmSeg* d_segs = nullptr;
   RcDesc* d_rcs = nullptr;
@@ -107,6 +116,26 @@ struct Plan {
     o.n = (int)v.size();
     for (auto& c : v) o.maxel = std::max<int64_t>(o.maxel, (int64_t)c.rows * c.cols);
     copies.insert(copies.end(), v.begin(), v.end());
+    push(o);
+  }
+  // out = a x + b y + c z on a rows x cols block (one launch)
+  void lincomb(const LincombDesc& d) {
+    if ((int64_t)d.rows * d.cols <= 0) return;
+    Op o;
+    o.kind = Op::LINCOMB;
+    o.off = (int)lincs.size();
+    o.n = 1;
+    o.maxel = (int64_t)d.rows * d.cols;
+    lincs.push_back(d);
+    push(o);
+  }
+  void frob2(const std::vector<Frob2Desc>& v) {
+    if (v.empty()) return;
+    Op o;
+    o.kind = Op::FROB2;
+    o.off = (int)frobs.size();
+    o.n = (int)v.size();
+    frobs.insert(frobs.end(), v.begin(), v.end());
     push(o);
   }
   void wait(int e) { Op o; o.kind = Op::WAIT; o.event = e; push(o); n_events = std::max(n_events, e + 1); }

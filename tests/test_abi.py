@@ -77,3 +77,15 @@ def test_batched_factor_rejects_bad_arguments_without_a_device():
     assert b"block-column" in lib.blr_last_error()
     assert lib.blr_qr_factor_batch(none2, 2, ctypes.byref(bc), None) == L.BLR_ERR_INVALID
     assert b"NULL handle" in lib.blr_last_error()
+
+
+def test_batched_solve_rejects_bad_arguments_without_a_device():
+    from paper_2208_06194_amd import _lib as L
+    lib = L.load()
+    none1 = (ctypes.c_void_p * 1)(None)
+    ld = (ctypes.c_int64 * 1)(8)
+    assert lib.blr_lstsq_solve_batch(None, 1, none1, ld, none1, ld, 1, 0, None) == L.BLR_ERR_INVALID
+    assert lib.blr_lstsq_solve_batch(none1, 0, none1, ld, none1, ld, 1, 0, None) == L.BLR_ERR_INVALID
+    assert lib.blr_lstsq_solve_batch(none1, 1, none1, ld, none1, ld, -1, 0, None) == L.BLR_ERR_INVALID
+    assert lib.blr_lstsq_solve_batch(none1, 1, none1, ld, none1, ld, 1, 0, None) == L.BLR_ERR_INVALID
+    assert b"NULL" in lib.blr_last_error()

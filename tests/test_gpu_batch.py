@@ -158,3 +158,49 @@ def test_batch_rejects_mixed_shapes_and_states(P):
     # the failed calls left the compressed member untouched and usable
     P.factor_batch([Gd])
     assert same_export(Ga.export(with_factor=True), Gd.export(with_factor=True))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_solve_is_bitwise_equal_to_single_solves(P, precision):
+    """blr_lstsq_solve_batch gives each member exactly blr_lstsq_solve's
+    result: FP64 factors without refinement, mixed factors (kept A~) with
+    FP64 iterative refinement; one member factored by the tiled variant."""
+    members, b, eps, cap = BATCHES["b64"]
+    print("case: batched solve", precision, flush=True)
+    refine = 5 if precision == "mixed" else 0
+    blrs = [member_blr(s, m, n, b, eps, cap, k, d, r) for (s, m, n, k, d, r) in members]
+    Gs = [gpu_import(P, blr, eps, cap) for blr in blrs]
+    Gs[0].factor("tiled", precision=precision, keep_a=refine > 0)
+    P.factor_batch(Gs[1:], precision=precision, keep_a=refine > 0)
+    Bs = [torch.tensor(synth.rhs(200 + i, blr.m, 5), device="cuda") for i, blr in enumerate(blrs)]
+    singles = [G.lstsq(B, max_refine=refine) for G, B in zip(Gs, Bs)]
+    batched = P.lstsq_batch(Gs, Bs, max_refine=refine)
+    for mem, blr, xs, xb, B in zip(members, blrs, singles, batched, Bs):
+        assert torch.equal(xs, xb), mem
+        if precision == "mixed":
+            # refinement recovers the FP64 solution of A~
+            At = blr.to_dense()
+            Xo = np.linalg.lstsq(At, B.cpu().numpy(), rcond=None)[0]
+            kappa = np.linalg.cond(At)
+            err = np.linalg.norm(xb.cpu().numpy() - Xo) / np.linalg.norm(Xo)
+            print(mem, "refined mixed solve vs dense FP64 lstsq", err, "kappa", kappa, flush=True)
+            assert err <= 10 * kappa * eps
+
+
+def test_batched_solve_rejects_bad_batches(P):
+    print("case: batched solve errors", flush=True)
+    a = member_blr(0, 256, 128, 64, 1e-8, 16, "log2d", 2, "adjacent")
+    G = gpu_import(P, a, 1e-8, 16)
+    B = torch.tensor(synth.rhs(1, 256, 2), device="cuda")
+    with pytest.raises(P.BLRError) as e:
+        P.lstsq_batch([G], [B])
+    assert e.value.status == 2      # not factored
+    G.factor("block_column")
+    with pytest.raises(P.BLRError) as e:
+        P.lstsq_batch([G], [B], max_refine=2)
+    assert e.value.status == 2      # refinement without keep_a
+    with pytest.raises(P.BLRError) as e:
+        P.lstsq_batch([G, G], [B, B])
+    assert e.value.status == 1
+    X = P.lstsq_batch([G], [B])[0]
+    assert torch.equal(X, G.lstsq(B))
