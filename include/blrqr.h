@@ -263,7 +263,8 @@ blr_status blr_matmul(blr_matrix h, int32_t op, const double* X, int64_t ldx, do
  * [I A~; A~^T 0][r; x] = [b; 0] with FP64 residuals f = b - r - A~ x and
  * g = -A~^T r and corrections from the stored factor, d = Q^T f,
  * h = R^{-T} g, dx = R^{-1}(d_1 - h), dr = Q [h; d_2]; the loop stops early
- * once ||dx||_F <= 2 u ||x||_F.  It recovers FP64 accuracy for a
+ * once every column's correction satisfies ||dx|| <= 2 u ||x|| or is more
+ * than half the previous step's (it has reached the rounding noise).  It recovers FP64 accuracy for a
  * BLR_MIXED_FP32 factor.  resid_norms: optional device array of nrhs doubles
  * receiving the squared least-squares residual norm per column
  * (||(Q^T B)[n:m]||^2, or ||r||^2 of the refined residual).  Requires a complete factor.

@@ -1913,6 +1913,21 @@ bool sing_ok(blr_matrix h, const SingCheck& c) {
   return mn > thr;
 }
 
+// Convergence test of one refinement step from the squared norms hn[c] =
+// ||dx_c||^2 and hn[nrhs + c] = ||x_c||^2: a column has converged once its
+// correction is at the rounding level of x (||dx|| <= 2u ||x||) or no longer
+// at most half the previous one (the correction has reached the rounding
+// noise of the residuals); prev keeps the previous ||dx|| per column.
+bool refine_converged(const std::vector<double>& hn, std::vector<double>& prev, int nrhs, double u) {
+  bool done = true;
+  for (int c = 0; c < nrhs; ++c) {
+    const double dx = std::sqrt(hn[c]);
+    done = done && (dx <= 2.0 * u * std::sqrt(hn[nrhs + c]) || dx > 0.5 * prev[c]);
+    prev[c] = dx;
+  }
+  return done;
+}
+
 // Keep a device copy of A~ (all tiles and ranks) for products after the
 // in-place factorization.
 void keep_copy(blr_matrix h, hipStream_t s) {
@@ -2541,7 +2556,7 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
       HIPCHECK(launch_lincomb(r + n, m, C + n, m, nullptr, 0, nullptr, 0, 1.0, 0.0, 0.0, (int)(m - n), nrhs, s));
       apply(r, 1);
       const double u = 2.220446049250313e-16;
-      std::vector<double> hn(2 * nrhs);
+      std::vector<double> hn(2 * nrhs), prev(nrhs, HUGE_VAL);
       for (int it = 0; it < max_refine; ++it) {
         {  // f = b - r - A~ x,  g = -A~^T r
           Plan P;
@@ -2565,14 +2580,12 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
         // x += dx, r += dr
         HIPCHECK(launch_lincomb(X, ldx, X, ldx, f, m, nullptr, 0, 1.0, 1.0, 0.0, (int)n, nrhs, s));
         HIPCHECK(launch_lincomb(r, m, r, m, dr, m, nullptr, 0, 1.0, 1.0, 0.0, (int)m, nrhs, s));
-        // stop once every column's correction is at the rounding level of x
+        // stop once every column has converged
         frob2(f, m, n, nrm);
         frob2(X, ldx, n, nrm + nrhs);
         HIPCHECK(hipMemcpyAsync(hn.data(), nrm, 2 * nrhs * 8, hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
-        bool done = true;
-        for (int c = 0; c < nrhs; ++c) done = done && std::sqrt(hn[c]) <= 2.0 * u * std::sqrt(hn[nrhs + c]);
-        if (done) break;
+        if (refine_converged(hn, prev, nrhs, u)) break;
       }
       if (resid_norms) frob2(r, m, m, resid_norms);
     }
@@ -2616,7 +2629,7 @@ blr_status blr_lstsq_solve_batch(blr_matrix* hs, int32_t count, const double* co
       Work w;
       RsolveWork rw;
       double *C = nullptr, *r = nullptr, *f = nullptr, *g = nullptr, *dr = nullptr, *nrm = nullptr;
-      std::vector<double> hn;
+      std::vector<double> hn, prev;
       bool active = true;
     };
     std::vector<Member> mb(count);
@@ -2658,6 +2671,7 @@ blr_status blr_lstsq_solve_batch(blr_matrix* hs, int32_t count, const double* co
         e.dr = (double*)h->work.alloc((size_t)m * nrhs * 8);
         e.nrm = (double*)h->work.alloc((size_t)2 * nrhs * 8);
         e.hn.resize(2 * nrhs);
+        e.prev.assign(nrhs, HUGE_VAL);
         P.lincomb(lc(e.r, m, e.C, m, nullptr, 0, nullptr, 0, 0.0, 0.0, 0.0, n, nrhs));
         P.lincomb(lc(e.r + n, m, e.C + n, m, nullptr, 0, nullptr, 0, 1.0, 0.0, 0.0, m - n, nrhs));
         plan_apply(h, P, e.w, e.r, m, nrhs, 1);
@@ -2705,10 +2719,7 @@ blr_status blr_lstsq_solve_batch(blr_matrix* hs, int32_t count, const double* co
       HIPCHECK(hipStreamSynchronize(s));
       for (int i = 0; i < count; ++i) {
         Member& e = mb[i];
-        if (!e.active) continue;
-        bool done = true;
-        for (int c = 0; c < nrhs; ++c) done = done && std::sqrt(e.hn[c]) <= 2.0 * u * std::sqrt(e.hn[nrhs + c]);
-        if (done) e.active = false;
+        if (e.active && refine_converged(e.hn, e.prev, nrhs, u)) e.active = false;
       }
     }
     HIPCHECK(hipStreamSynchronize(s));
