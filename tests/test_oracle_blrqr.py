@@ -256,6 +256,20 @@ def test_random_blr_tiles_are_the_dense_generator_draws():
             assert np.array_equal(blk, ref)
 
 
+def test_batch_rows_are_log_uniform_multiples():
+    """Row counts of the batched workload: multiples of 2b inside [lo, hi],
+    deterministic in the seed, and log-uniform (the logarithms of many draws
+    spread evenly over [ln lo, ln hi])."""
+    m = synth.batch_rows(0, 64, 4096, 32768, 512)
+    assert np.array_equal(m, synth.batch_rows(0, 64, 4096, 32768, 512))
+    assert not np.array_equal(m, synth.batch_rows(1, 64, 4096, 32768, 512))
+    assert m.min() >= 4096 and m.max() <= 32768 and np.all(m % 512 == 0)
+    big = synth.batch_rows(3, 20000, 4096, 32768, 1)
+    z = (np.log(big) - np.log(4096)) / (np.log(32768) - np.log(4096))
+    hist = np.histogram(z, bins=8, range=(0, 1))[0] / len(z)
+    assert np.all(np.abs(hist - 1 / 8) < 0.01)
+
+
 def test_pairwise_sum_order():
     """The block-column accumulation order: a pairwise tree over the terms
     in index order (checked on strings, where the order is visible)."""
