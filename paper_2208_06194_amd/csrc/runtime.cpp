@@ -282,22 +282,9 @@ void ensure_streams(blr_matrix h) {
 
 // Enqueue a plan.  Ops name one of the handle's look-ahead streams; the
 // caller's stream s is joined before the first op and after the last one.
-void execute(blr_matrix h, Plan& P, hipStream_t s) {
-  int nstreams = 1;
-  for (const Op& o : P.ops) nstreams = std::max(nstreams, o.stream + 1);
-  std::vector<hipStream_t> st(nstreams, s);
-  std::vector<hipEvent_t> ev(P.n_events, nullptr);
-  hipEvent_t join = nullptr;
-  if (nstreams > 1) {
-    ensure_streams(h);
-    for (int a = 0; a < nstreams; ++a) st[a] = h->streams[a];
-    HIPCHECK(hipEventCreateWithFlags(&join, hipEventDisableTiming));
-    HIPCHECK(hipEventRecord(join, s));
-    for (int a = 0; a < nstreams; ++a) HIPCHECK(hipStreamWaitEvent(st[a], join, 0));
-    for (auto& e : ev) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  }
-  for (const Op& o : P.ops) {
-    hipStream_t q = st[o.stream];
+// Enqueue one op on stream q (launches counted on h).  ev: the plan's events
+// (used only by a plan on several streams).
+void enqueue(blr_matrix h, const Plan& P, const Op& o, hipStream_t q, bool multi, std::vector<hipEvent_t>& ev) {
     switch (o.kind) {
       case Op::GEMM: {
         // the dominant kernel: k_gemm_fast<CT, false, false> (untransposed
@@ -389,15 +376,31 @@ void execute(blr_matrix h, Plan& P, hipStream_t s) {
         h->launches += 1;
         break;
       case Op::WAIT:
-        if (nstreams > 1) HIPCHECK(hipStreamWaitEvent(q, ev[o.event], 0));
+        if (multi) HIPCHECK(hipStreamWaitEvent(q, ev[o.event], 0));
         break;
       case Op::RECORD:
-        if (nstreams > 1) HIPCHECK(hipEventRecord(ev[o.event], q));
+        if (multi) HIPCHECK(hipEventRecord(ev[o.event], q));
         break;
       default:
         break;
     }
+}
+
+void execute(blr_matrix h, Plan& P, hipStream_t s) {
+  int nstreams = 1;
+  for (const Op& o : P.ops) nstreams = std::max(nstreams, o.stream + 1);
+  std::vector<hipStream_t> st(nstreams, s);
+  std::vector<hipEvent_t> ev(P.n_events, nullptr);
+  hipEvent_t join = nullptr;
+  if (nstreams > 1) {
+    ensure_streams(h);
+    for (int a = 0; a < nstreams; ++a) st[a] = h->streams[a];
+    HIPCHECK(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+    HIPCHECK(hipEventRecord(join, s));
+    for (int a = 0; a < nstreams; ++a) HIPCHECK(hipStreamWaitEvent(st[a], join, 0));
+    for (auto& e : ev) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
+  for (const Op& o : P.ops) enqueue(h, P, o, st[o.stream], nstreams > 1, ev);
   if (nstreams > 1) {
     for (int a = 0; a < nstreams; ++a) {
       hipEvent_t e;
@@ -1631,6 +1634,75 @@ Plan merge_plans(const std::vector<Plan>& plans, const std::vector<blr_matrix>& 
   return M;
 }
 
+// Run the one-stream plans of independent matrices as a batch.  The members
+// are split into two groups of about equal work (largest first, each to the
+// lighter group; an op counts as its flops plus 2e8 for its launch latency);
+// each group's plans are merged and the two launch lists are enqueued
+// interleaved on two streams of hv[0], joined to s before and after, so that
+// one group's panel and solve kernels overlap the other group's products.
+// Launches are counted on hv[0].
+void run_batch_plans(std::vector<Plan>& plans, const std::vector<blr_matrix>& hv, hipStream_t s) {
+  const int nb = (int)plans.size();
+  if (nb == 0) return;
+  const int ng = nb >= 2 ? 2 : 1;
+  std::vector<std::pair<double, int>> wt(nb);
+  for (int i = 0; i < nb; ++i) {
+    double w = 0.0;
+    for (const Op& o : plans[i].ops) w += o.flops + 2e8;
+    wt[i] = {w, i};
+  }
+  std::sort(wt.begin(), wt.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+    return a.first > b.first || (a.first == b.first && a.second < b.second);
+  });
+  std::vector<std::vector<int>> grp(ng);
+  std::vector<double> load(ng, 0.0);
+  for (auto& e : wt) {
+    const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    grp[g].push_back(e.second);
+    load[g] += e.first;
+  }
+  std::vector<Plan> M(ng);
+  for (int g = 0; g < ng; ++g) {
+    std::sort(grp[g].begin(), grp[g].end());
+    std::vector<Plan> gp;
+    std::vector<blr_matrix> gh;
+    for (int i : grp[g]) {
+      gp.push_back(std::move(plans[i]));
+      gh.push_back(hv[i]);
+    }
+    M[g] = merge_plans(gp, gh);
+    M[g].upload(gh[0]->work);
+  }
+  blr_matrix h0 = hv[0];
+  std::vector<hipEvent_t> none;
+  if (ng == 1) {
+    for (const Op& o : M[0].ops) enqueue(h0, M[0], o, s, false, none);
+    return;
+  }
+  ensure_streams(h0);
+  hipStream_t st[2] = {h0->streams[0], h0->streams[1]};
+  hipEvent_t join;
+  HIPCHECK(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+  HIPCHECK(hipEventRecord(join, s));
+  for (int g = 0; g < 2; ++g) HIPCHECK(hipStreamWaitEvent(st[g], join, 0));
+  HIPCHECK(hipEventDestroy(join));
+  // interleave in proportion to the two lists' lengths
+  const size_t n0 = M[0].ops.size(), n1 = M[1].ops.size();
+  size_t a = 0, b = 0;
+  while (a < n0 || b < n1) {
+    const bool take0 = b >= n1 || (a < n0 && (double)a * (double)n1 <= (double)b * (double)n0);
+    if (take0) enqueue(h0, M[0], M[0].ops[a++], st[0], false, none);
+    else enqueue(h0, M[1], M[1].ops[b++], st[1], false, none);
+  }
+  for (int g = 0; g < 2; ++g) {
+    hipEvent_t e;
+    HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIPCHECK(hipEventRecord(e, st[g]));
+    HIPCHECK(hipStreamWaitEvent(s, e, 0));
+    HIPCHECK(hipEventDestroy(e));
+  }
+}
+
 // B <- Q^T B or Q B for the block-column factor (Alg. 3): per step k,
 // W = sum_i Ytilde_ik^T B_i, W = T_k^T W (or T_k W), B_i -= Ytilde_ik W.
 void plan_apply_blockcol(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, int nrhs, int trans,
@@ -2469,12 +2541,10 @@ blr_status blr_qr_factor_batch(blr_matrix* hs, int32_t count, const blr_factor_o
     std::vector<Plan> plans(count);
     std::vector<int> kend(count);
     for (int i = 0; i < count; ++i) kend[i] = prepare_factor(v[i], o, s, plans[i], false);
-    Plan M = merge_plans(plans, v);
-    plans.clear();
-    M.upload(v[0]->work);
     for (int i = 0; i < count; ++i)
       HIPCHECK(hipMemsetAsync(v[i]->d_counters, 0, 4 * sizeof(unsigned long long), s));
-    execute(v[0], M, s);
+    run_batch_plans(plans, v, s);
+    plans.clear();
     for (int i = 0; i < count; ++i) {
       v[i]->launches = v[0]->launches;
       v[i]->steps_done = kend[i];
@@ -2641,10 +2711,7 @@ blr_status blr_lstsq_solve_batch(blr_matrix* hs, int32_t count, const double* co
           live.push_back(std::move(plans[i]));
           hv.push_back(v[i]);
         }
-      if (live.empty()) return;
-      Plan M = merge_plans(live, hv);
-      M.upload(v[0]->work);
-      execute(v[0], M, s);
+      run_batch_plans(live, hv, s);
     };
     auto lc = [](double* out, int64_t ldo, const double* x, int64_t lx, const double* y, int64_t ly,
                  const double* z, int64_t lz, double a, double b, double c, int64_t rows, int cols) {
