@@ -2582,7 +2582,6 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
   if (nrhs == 0) return BLR_OK;
   hipStream_t s = as_stream(stream);
   return run_guarded([&] {
-    const int b = h->b, q = h->q, rc = h->rc;
     const int64_t m = h->m, n = h->n;
     HIPCHECK(hipDeviceSynchronize());
     h->work.release();
