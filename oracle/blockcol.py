@@ -48,16 +48,17 @@ class BlockColumnFactor(Factor):
         return self.ytilde(i, k)
 
     def panel(self, k):
-        A, b = self.A, self.b
+        A = self.A
         parts = [A.D[(k, k)]]
         for i in range(k + 1, self.p):
             parts.append(A.D[(i, k)] if A.fmt[i, k] == DENSE else A.V[(i, k)].T)
         F, tau, T = dense.householder_qr(np.concatenate(parts, axis=0))
         Y = dense.unit_lower(F)
-        A.D[(k, k)] = F[:b].copy()
-        self.Ykk[k] = Y[:b].copy()
+        h0 = parts[0].shape[0]
+        A.D[(k, k)] = F[:h0].copy()
+        self.Ykk[k] = Y[:h0].copy()
         self.Tk[k] = T
-        off = b
+        off = h0
         for i in range(k + 1, self.p):
             h = parts[i - k].shape[0]
             Yi = Y[off:off + h].copy()
@@ -93,7 +94,7 @@ class BlockColumnFactor(Factor):
 
     def _apply(self, B, k, transpose):
         b = self.b
-        W = np.zeros((b, B.shape[1]))
+        W = np.zeros((self.Tk[k].shape[0], B.shape[1]))
         for i in range(k, self.p):
             Yr = self.yrep(i, k)
             Bi = B[i * b:(i + 1) * b]

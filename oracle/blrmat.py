@@ -2,7 +2,9 @@
 admissibility discussion after it).
 
 A BLR matrix has p x q tiles of size b x b; tile (i,j) is dense (fmt 0) or
-U V^T (fmt 1) with U orthonormal.  Readings:
+U V^T (fmt 1) with U orthonormal.  When b does not divide m or n, the last
+tile row or column is narrower (the rectangular blocks the paper notes the
+method extends to, Section 3.1).  Readings:
 * diagonal tiles (k,k), k < q, are always dense;
 * a cluster box is the tight axis-aligned box of the b consecutive points of a
   tile row/column (points are Morton sorted by the caller);
@@ -31,9 +33,10 @@ def kernel_matrix(x: np.ndarray, y: np.ndarray, kernel: str, reg: float = 1e-3):
 
 
 def cluster_boxes(pts: np.ndarray, b: int):
-    c = pts.shape[0] // b
-    P = pts[: c * b].reshape(c, b, -1)
-    return P.min(axis=1), P.max(axis=1)
+    """Tight boxes of the clusters of b consecutive points (the last cluster
+    holds the remaining points when b does not divide their number)."""
+    starts = np.arange(0, pts.shape[0], b)
+    return np.minimum.reduceat(pts, starts, axis=0), np.maximum.reduceat(pts, starts, axis=0)
 
 
 def lowrank_mask(x, y, b, rule: str, p: int, q: int) -> np.ndarray:
@@ -63,9 +66,9 @@ class BLR:
     """Tile storage: fmt[i,j], D[(i,j)] for dense, U/V[(i,j)] for low-rank."""
 
     def __init__(self, m: int, n: int, b: int):
-        assert m % b == 0 and n % b == 0 and m >= n
+        assert m >= n >= 1 and b >= 1
         self.m, self.n, self.b = m, n, b
-        self.p, self.q = m // b, n // b
+        self.p, self.q = -(-m // b), -(-n // b)
         self.fmt = np.zeros((self.p, self.q), dtype=np.int8)
         self.D = {}
         self.U = {}

@@ -57,11 +57,14 @@ class Factor:
         return self.val(k, j)
 
     def r_dense(self) -> np.ndarray:
-        b, q = self.b, self.q
-        R = np.zeros((q * b, q * b))
+        """The n x n factor R; block row k holds the first (width of block
+        column k) rows of the tiles R_kj."""
+        b, q, n = self.b, self.q, self.A.n
+        R = np.zeros((n, n))
         for k in range(q):
+            rk = min(b, n - k * b)
             for j in range(k, q):
-                R[k * b:(k + 1) * b, j * b:(j + 1) * b] = blrops.dense_of(self.r_val(k, j))
+                R[k * b:k * b + rk, j * b:(j + 1) * b] = blrops.dense_of(self.r_val(k, j))[:rk]
         return R
 
     def r_frob(self) -> float:
@@ -73,17 +76,18 @@ class Factor:
         X = np.zeros_like(C)
         for k in range(q - 1, -1, -1):
             y = C[k * b:(k + 1) * b].copy()
+            rk = y.shape[0]
             for j in range(k + 1, q):
                 Rv = self.r_val(k, j)
                 xj = X[j * b:(j + 1) * b]
-                y -= Rv[1] @ xj if Rv[0] == "D" else Rv[1] @ (Rv[2].T @ xj)
+                y -= (Rv[1] @ xj if Rv[0] == "D" else Rv[1] @ (Rv[2].T @ xj))[:rk]
             X[k * b:(k + 1) * b] = scipy.linalg.solve_triangular(
-                np.triu(self.A.D[(k, k)]), y, lower=False)
+                np.triu(self.A.D[(k, k)])[:rk], y, lower=False)
         return X
 
     def check_singular(self):
         """Reading: R is numerically singular when some |R_jj| <= n u ||R||_F."""
-        n = self.q * self.b
+        n = self.A.n
         thr = n * np.finfo(np.float64).eps * self.r_frob()
         for k in range(self.q):
             d = np.abs(np.diag(self.A.D[(k, k)]))
@@ -94,17 +98,17 @@ class Factor:
         """argmin ||A x - b|| per column: x = R^{-1} (Q^T b)[:n]."""
         self.check_singular()
         C = self.apply_qt(B)
-        return self.backsolve(C[: self.q * self.b])
+        return self.backsolve(C[: self.A.n])
 
     # metrics ---------------------------------------------------------------
     def q_times_r(self) -> np.ndarray:
-        m, n = self.p * self.b, self.q * self.b
+        m, n = self.A.m, self.A.n
         RR = np.zeros((m, n))
         RR[:n] = self.r_dense()
         return self.apply_q(RR)
 
     def thin_q(self) -> np.ndarray:
-        m, n = self.p * self.b, self.q * self.b
+        m, n = self.A.m, self.A.n
         E = np.zeros((m, n))
         E[:n] = np.eye(n)
         return self.apply_q(E)

@@ -182,11 +182,14 @@ class TiledFactor(Factor):
         return B[i * b:(i + 1) * b]
 
     def apply_qt(self, B: np.ndarray) -> np.ndarray:
-        """B <- Q^T B, replaying the factorization order."""
+        """B <- Q^T B, replaying the factorization order.  The TPQRT
+        reflectors of step k touch the first (width of block column k) rows
+        of block row k: all of them except in a narrower last block column."""
         B = np.array(B, dtype=np.float64, copy=True)
         for k in range(self.steps_done):
-            Bk = self._blk(B, k)
-            Bk[:] = dense.apply_qt_left(self.Ykk[k], self.Tkk[k], Bk)
+            Bd = self._blk(B, k)
+            Bd[:] = dense.apply_qt_left(self.Ykk[k], self.Tkk[k], Bd)
+            Bk = Bd[: self.Tkk[k].shape[0]]
             for i in range(k + 1, self.p):
                 Bi = self._blk(B, i)
                 Yr = self.ytilde(i, k)
@@ -200,14 +203,15 @@ class TiledFactor(Factor):
         as C <- (I - [I; Y] T [I; Y]^T) C (the printed formula lacks 'I -')."""
         B = np.array(B, dtype=np.float64, copy=True)
         for k in range(self.steps_done - 1, -1, -1):
-            Bk = self._blk(B, k)
+            Bd = self._blk(B, k)
+            Bk = Bd[: self.Tkk[k].shape[0]]
             for i in range(self.p - 1, k, -1):
                 Bi = self._blk(B, i)
                 Yr = self.ytilde(i, k)
                 W = self.Tik[(i, k)] @ (Bk + _yt_dense(Yr, Bi))
                 Bk -= W
                 Bi -= blrops.dense_of(blrops.y_times(Yr, ("D", W)))
-            Bk[:] = dense.apply_q_left(self.Ykk[k], self.Tkk[k], Bk)
+            Bd[:] = dense.apply_q_left(self.Ykk[k], self.Tkk[k], Bd)
         return B
 
 

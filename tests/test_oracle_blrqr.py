@@ -330,3 +330,81 @@ def test_lstsq_adjoint_closed_form_square():
     X, Bbar, Abar = adjoint.lstsq_adjoint(A, B, Xbar)
     assert np.allclose(Bbar, np.linalg.solve(A.T, Xbar))
     assert np.allclose(Abar, -Bbar @ X.T)
+
+
+# Ragged edges: b need not divide m or n; the last tile row or column is
+# narrower (rectangular blocks, Section 3.1) ---------------------------------
+def ceil_div(a, b):
+    return -(-a // b)
+
+
+@pytest.mark.parametrize("mod", VARIANTS)
+@pytest.mark.parametrize("shape", [(70, 45, 16), (64, 40, 16), (70, 48, 16), (50, 50, 16),
+                                   (37, 20, 8), (33, 33, 32), (20, 7, 16)])
+def test_ragged_all_dense_reduces_to_householder_qr(mod, shape):
+    m, n, b = shape
+    A = np.random.default_rng(m * n + b).standard_normal((m, n))
+    blr = blrmat.compress(A, b, 1e-12, b, np.zeros((ceil_div(m, b), ceil_div(n, b)), bool))
+    assert np.array_equal(blr.to_dense(), A)
+    f = mod.factor(blr, 1e-12, b)
+    R = f.r_dense()
+    assert R.shape == (n, n) and np.array_equal(R, np.triu(R))
+    kappa = np.linalg.cond(A)
+    assert metrics.r_rel_diff(R, np.linalg.qr(A, mode="r")) <= 10 * n * U * kappa
+    assert metrics.res(f, A) <= 10 * n * U
+    assert metrics.orth(f) <= 10 * np.sqrt(n) * U
+    Bm = np.random.default_rng(1).standard_normal((m, 3))
+    assert np.allclose(f.apply_qt(f.apply_q(Bm)), Bm, atol=1e-13)
+    X = f.lstsq(Bm)
+    Xl = np.linalg.lstsq(A, Bm, rcond=None)[0]
+    assert np.linalg.norm(X - Xl) / np.linalg.norm(Xl) <= 10 * n * U * kappa ** 2
+    if m > n:   # a square system has no least-squares residual to test
+        assert np.all(metrics.eta_ne(A, X, Bm) <= 10 * n * U)
+    else:
+        assert np.linalg.norm(A @ X - Bm) <= 10 * n * U * kappa * np.linalg.norm(Bm)
+
+
+def ragged_kernel_blr(seed, m, n, b, eps, cap, rule="adjacent", kern="log2d", dim=2):
+    x, y = synth.kernel_points(seed, m, n, dim)
+    A = blrmat.kernel_matrix(x, y, kern)
+    mask = blrmat.lowrank_mask(x, y, b, rule, ceil_div(m, b), ceil_div(n, b))
+    return A, blrmat.compress(A, b, eps, cap, mask)
+
+
+def test_ragged_cluster_boxes_cover_every_point():
+    pts = synth.points(3, 0, 70, 2)
+    lo, hi = blrmat.cluster_boxes(pts, 16)
+    assert lo.shape == (5, 2)
+    for c in range(5):
+        blk = pts[16 * c:16 * (c + 1)]
+        assert np.array_equal(lo[c], blk.min(axis=0)) and np.array_equal(hi[c], blk.max(axis=0))
+
+
+@pytest.mark.parametrize("mod", VARIANTS)
+def test_ragged_kernel_matrix_invariants(mod):
+    """Low-rank tiles on the narrow edge too: Res~ <= 10 eps, Orth, Q^T A~ =
+    [R; 0] and the least-squares normal equations."""
+    m, n, b, eps = 300, 170, 32, 1e-8
+    A, blr = ragged_kernel_blr(4, m, n, b, eps, 16)
+    assert blr.p == 10 and blr.q == 6
+    assert np.any(blr.fmt[-1] == LOWRANK) and np.any(blr.fmt[:, -1] == LOWRANK)
+    At = blr.to_dense()
+    f = mod.factor(blr, eps, 16)
+    assert metrics.res(f, At) <= 10 * eps
+    assert metrics.orth(f) <= 1e3 * U
+    QtA = f.apply_qt(At)
+    assert np.linalg.norm(QtA[n:]) <= 10 * eps * np.linalg.norm(At)
+    Bm = synth.rhs(4, m, 2)
+    X = f.lstsq(Bm)
+    assert np.all(metrics.eta_ne(At, X, Bm) <= 10 * eps * np.linalg.cond(At))
+
+
+def test_ragged_variants_agree_and_dag_order_is_irrelevant():
+    m, n, b, eps = 300, 170, 32, 1e-8
+    A, blr = ragged_kernel_blr(5, m, n, b, eps, 16)
+    ft = tiled.factor(blr, eps, 16)
+    fb = blockcol.factor(blr, eps, 16)
+    kappa = np.linalg.cond(blr.to_dense())
+    assert metrics.r_rel_diff(fb.r_dense(), ft.r_dense()) <= 10 * kappa * eps
+    fr = tiled.factor(blr, eps, 16, order="random", seed=3)
+    assert np.array_equal(fr.r_dense(), ft.r_dense())
