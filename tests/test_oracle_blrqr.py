@@ -408,3 +408,44 @@ def test_ragged_variants_agree_and_dag_order_is_irrelevant():
     assert metrics.r_rel_diff(fb.r_dense(), ft.r_dense()) <= 10 * kappa * eps
     fr = tiled.factor(blr, eps, 16, order="random", seed=3)
     assert np.array_equal(fr.r_dense(), ft.r_dense())
+
+
+def embed_ragged(A, b):
+    """A' = [A 0; 0 E] with tile-multiple sizes: zero rows below A, and for
+    each padded column a one in a padded row (E = [I; 0]); one more tile row
+    when the padded rows would not hold the identity."""
+    m, n = A.shape
+    n2 = ceil_div(n, b) * b
+    m2 = ceil_div(m, b) * b
+    if m2 - m < n2 - n:
+        m2 += b
+    Ap = np.zeros((m2, n2))
+    Ap[:m, :n] = A
+    for t in range(n2 - n):
+        Ap[m + t, n + t] = 1.0
+    return Ap
+
+
+@pytest.mark.parametrize("mod", VARIANTS)
+def test_ragged_embedding_keeps_r_and_least_squares(mod):
+    """The tile-multiple embedding A' factors to R' = diag(R, -I) up to row
+    signs, and its least-squares solution for [B; 0] is [X; 0] with the
+    ragged factorization's X and residual."""
+    m, n, b, eps = 300, 170, 32, 1e-8
+    A, blr = ragged_kernel_blr(6, m, n, b, eps, 16)
+    At = blr.to_dense()
+    f = mod.factor(blr, eps, 16)
+    Ap = embed_ragged(At, b)
+    fp = mod.factor(blrmat.compress(Ap, b, 1e-15, b, np.zeros((Ap.shape[0] // b, Ap.shape[1] // b), bool)),
+                    1e-15, b)
+    Rp = fp.r_dense()
+    kappa = np.linalg.cond(At)
+    assert metrics.r_rel_diff(Rp[:n, :n], f.r_dense()) <= 10 * kappa * eps
+    assert np.allclose(np.abs(np.diag(Rp)[n:]), 1.0) and np.all(Rp[:n, n:] == 0.0)
+    Bm = synth.rhs(6, m, 2)
+    Bp = np.zeros((Ap.shape[0], 2))
+    Bp[:m] = Bm
+    Xp = fp.lstsq(Bp)
+    X = f.lstsq(Bm)
+    assert np.linalg.norm(Xp[n:]) <= 1e-12 * np.linalg.norm(X)
+    assert np.linalg.norm(Xp[:n] - X) <= 10 * kappa * eps * np.linalg.norm(X)
