@@ -19,8 +19,13 @@ def declared_functions():
 def test_headers_declare_the_boundary():
     names = declared_functions()
     for fn in ["blr_compress", "blr_qr_factor", "blr_apply_qt", "blr_lstsq_solve", "blr_import",
-               "blr_export", "blr_query", "blr_destroy", "blr_status_string", "blr_last_error"]:
+               "blr_export", "blr_query", "blr_destroy", "blr_status_string", "blr_last_error",
+               "blr_qr_factor_batch", "blr_lstsq_solve_batch", "blr_rsolve", "blr_lstsq_adjoint",
+               "blr_form_q", "blr_morton_sort", "blr_matmul"]:
         assert fn in names
+    # the binding declares exactly the header's entry points
+    from paper_2208_06194_amd import _lib
+    assert set(_lib.EXPORTED) | set(_lib.SELFTEST) == names
 
 
 def test_library_exports_every_declared_symbol():
