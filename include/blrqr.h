@@ -225,9 +225,12 @@ blr_status blr_qr_factor(blr_matrix h, const blr_factor_opts* opts, void* hip_st
  * are merged so that one kernel launch serves the same step of many
  * matrices; each matrix ends exactly as blr_qr_factor with the same opts
  * leaves it (bit-identical factors, FACTORED state, own overflow counters;
- * blr_query reports the batch's launch count).  Enqueued on hip_stream
- * (asynchronous); the merged launch list lives in hs[0]'s workspace until
- * its next factorization or destruction.  Errors: BLR_ERR_INVALID for NULL
+ * blr_query reports the batch's launch count).  The matrices run in two
+ * groups of about equal work, each group's merged launches on a stream of
+ * hs[0] joined to hip_stream before and after.  Enqueued on hip_stream
+ * (asynchronous); a group's merged launch list lives in the workspace of its
+ * first member until that handle's next factorization or destruction (both
+ * synchronise).  Errors: BLR_ERR_INVALID for NULL
  * arguments, count < 1, a repeated or NULL handle, unequal tile size, cap or
  * tolerance, or another variant; BLR_ERR_STATE if a handle is not
  * COMPRESSED.  If the call fails after validation, the handles stay
@@ -264,10 +267,11 @@ blr_status blr_matmul(blr_matrix h, int32_t op, const double* X, int64_t ldx, do
  * g = -A~^T r and corrections from the stored factor, d = Q^T f,
  * h = R^{-T} g, dx = R^{-1}(d_1 - h), dr = Q [h; d_2]; the loop stops early
  * once every column's correction satisfies ||dx|| <= 2 u ||x|| or is more
- * than half the previous step's (it has reached the rounding noise).  It recovers FP64 accuracy for a
- * BLR_MIXED_FP32 factor.  resid_norms: optional device array of nrhs doubles
- * receiving the squared least-squares residual norm per column
- * (||(Q^T B)[n:m]||^2, or ||r||^2 of the refined residual).  Requires a complete factor.
+ * than half the previous step's (it has reached the rounding noise).  It
+ * recovers FP64 accuracy for a BLR_MIXED_FP32 factor.  resid_norms: optional
+ * device array of nrhs doubles receiving the squared least-squares residual
+ * norm per column (||(Q^T B)[n:m]||^2, or ||r||^2 of the refined residual).
+ * Requires a complete factor.
  * Synchronises the stream (the singularity check reads the diagonal of R). */
 blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X,
                            int64_t ldx, int32_t nrhs, int32_t max_refine,
