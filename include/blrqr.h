@@ -14,6 +14,15 @@
  * given stream completes; the library copies what it keeps.  Calls on one
  * handle must be serialised by the caller; different handles are independent.
  *
+ * Synchronisation and workspace.  Each handle keeps a grow-only device
+ * workspace for its plans and temporaries, reused by every later call (a
+ * call that repeats an earlier call's shapes allocates nothing), and records
+ * an event on the caller's stream at the end of each call's work.  A call
+ * that reuses the workspace, or reads results back, first waits on the host
+ * for that event: for this handle's previous work only.  No entry point
+ * waits for the whole device.  Where a declaration below says "synchronises
+ * the stream", the call returns after its own work on hip_stream is done.
+ *
  * Errors.  Argument errors are detected synchronously before any work is
  * enqueued.  A device fault surfaces as BLR_ERR_DEVICE at the next call that
  * synchronises.  Truncation at the rank cap is not an error: it is counted in
@@ -146,16 +155,17 @@ typedef struct blr_tiles_host {
  * is formed on the device, a block of 4096 columns at a time, then
  * compressed with the tile formats A~ had when the factor started as the
  * mask, tolerance and rank cap of A~ (a block whose rank exceeds the cap is
- * stored dense).  Needs m*n*8 bytes of temporary device memory.  *q_out is a
- * new handle in state COMPRESSED (its products and export work as for A~).
- * Synchronises the stream.  Errors: BLR_ERR_STATE if not (fully) factored. */
+ * stored dense).  Needs m*n*8 bytes of temporary device memory, stream-ordered
+ * (allocated and freed on hip_stream).  *q_out is a new handle in state
+ * COMPRESSED (its products and export work as for A~).  Synchronises the
+ * stream.  Errors: BLR_ERR_STATE if not (fully) factored. */
 blr_status blr_form_q(blr_matrix h, void* hip_stream, blr_matrix* q_out);
 
 /* X <- R^{-1} X (trans = 0) or X <- R^{-T} X (trans = 1) with the R factor of
  * a factored handle (Section 3.3 / 3.4: R has the tile structure of A~), for
  * X n x nrhs, column-major, device, ld ldx >= n, overwritten.  The blocked
- * back- or forward substitution of the least-squares solve.  Synchronises
- * the stream.  Errors: BLR_ERR_STATE if not (fully) factored. */
+ * back- or forward substitution of the least-squares solve.  Asynchronous on
+ * hip_stream.  Errors: BLR_ERR_STATE if not (fully) factored. */
 blr_status blr_rsolve(blr_matrix h, int32_t trans, double* X, int64_t ldx, int32_t nrhs, void* hip_stream);
 
 /* Adjoint of the least-squares solve X = argmin ||A~ X - B||_F (full column
@@ -171,8 +181,8 @@ blr_status blr_rsolve(blr_matrix h, int32_t trans, double* X, int64_t ldx, int32
  *       dU = dA_ij V and dV = dA_ij^T U, b x rc column-major at offset
  *       (i*q + j)*b*rc (columns past the rank are zero).
  * All pointers are device memory; dD, dU and dV may be NULL to skip, and
- * only the slots of tiles of the matching format are written.  Synchronises
- * the stream.  Errors: BLR_ERR_STATE if not factored or A~ was not kept. */
+ * only the slots of tiles of the matching format are written.  Asynchronous
+ * on hip_stream.  Errors: BLR_ERR_STATE if not factored or A~ was not kept. */
 blr_status blr_lstsq_adjoint(blr_matrix h, const double* B, int64_t ldb, const double* X, int64_t ldx,
                              const double* Xbar, int64_t ldxb, int32_t nrhs, double* Bbar, int64_t ldbb,
                              double* dD, double* dU, double* dV, void* hip_stream);
@@ -186,8 +196,9 @@ blr_status blr_lstsq_adjoint(blr_matrix h, const double* B, int64_t ldb, const d
  * significant first in coordinate order, and the points are sorted by key,
  * ties by original index.  perm (device, n int64, required) receives the
  * original index of the r-th point in that order; sorted (device, n x dim
- * row-major, may be NULL) receives the points in that order.  Allocates
- * temporary device memory and synchronises the stream.  Errors:
+ * row-major, may be NULL) receives the points in that order.  Its scratch is
+ * stream-ordered device memory (allocated and freed on hip_stream), and the
+ * call is asynchronous on hip_stream.  Errors:
  * BLR_ERR_INVALID for NULL pts/perm, n < 0 or dim outside 1..3. */
 blr_status blr_morton_sort(const double* pts, int64_t n, int32_t dim, int64_t* perm, double* sorted,
                            void* hip_stream);
@@ -207,7 +218,8 @@ blr_status blr_compress(const blr_source* src, const blr_compress_opts* opts,
 blr_status blr_import(const blr_compress_opts* opts, const blr_tiles_host* tiles,
                       void* hip_stream, blr_matrix* out);
 
-/* Copy the handle's tiles to host arrays (see blr_tiles_host).  Synchronises. */
+/* Copy the handle's tiles to host arrays (see blr_tiles_host).  Waits for the
+ * handle's previous work first. */
 blr_status blr_export(blr_matrix h, blr_tiles_host* tiles);
 
 /* Householder QR of the BLR matrix, in place (tiled: Alg. 4 with the
@@ -230,7 +242,7 @@ blr_status blr_qr_factor(blr_matrix h, const blr_factor_opts* opts, void* hip_st
  * hs[0] joined to hip_stream before and after.  Enqueued on hip_stream
  * (asynchronous); a group's merged launch list lives in the workspace of its
  * first member until that handle's next factorization or destruction (both
- * synchronise).  Errors: BLR_ERR_INVALID for NULL
+ * wait for the handle's previous work).  Errors: BLR_ERR_INVALID for NULL
  * arguments, count < 1, a repeated or NULL handle, unequal tile size, cap or
  * tolerance, or another variant; BLR_ERR_STATE if a handle is not
  * COMPRESSED.  If the call fails after validation, the handles stay
@@ -258,8 +270,10 @@ typedef enum { BLR_MATMUL_A = 0, BLR_MATMUL_AT = 1, BLR_MATMUL_R = 2 } blr_matmu
 blr_status blr_matmul(blr_matrix h, int32_t op, const double* X, int64_t ldx, double* Y, int64_t ldy,
                       int32_t nrhs, void* hip_stream);
 
-/* Least squares X = argmin ||A~ X - B||_F column by column, X = R^{-1}
- * (Q^T B)[0:n] with tile back-substitution through the BLR factor R.
+/* Least squares X = argmin ||A~ X - B||_F column by column, the problem the
+ * QR factorization serves (Section 1: with A = QR, the solution of an
+ * overdetermined system is R^{-1} (Q^T b)[0:n]): X = R^{-1} (Q^T B)[0:n]
+ * with tile back-substitution through the BLR factor R (Sections 3.3, 3.4).
  * B: device m x nrhs (ldb >= m), not modified.  X: device n x nrhs
  * (ldx >= n).  max_refine > 0 (needs a factor made with keep_a): up to that
  * many steps of iterative refinement of the augmented system
@@ -294,10 +308,12 @@ blr_status blr_lstsq_solve_batch(blr_matrix* hs, int32_t count, const double* co
                                  double* const* X, const int64_t* ldx, int32_t nrhs, int32_t max_refine,
                                  void* hip_stream);
 
-/* Shape, formats, state, memory and counters of a handle.  Synchronises. */
+/* Shape, formats, state, memory and counters of a handle.  Waits for the
+ * handle's previous work first. */
 blr_status blr_query(blr_matrix h, blr_info* info);
 
-/* Release the handle and all its device memory (synchronises first). */
+/* Release the handle and all its device memory (waits for the handle's
+ * previous work first). */
 void blr_destroy(blr_matrix h);
 
 const char* blr_status_string(blr_status s);
@@ -310,7 +326,7 @@ const char* blr_last_error(void);
  * (blr_qr_factor clears the record first).  blr_profile_read returns, for
  * kernel 0 (FP64 operands) or 1 (FP32 operands), the number of launches,
  * their total device time in milliseconds and their total algorithmic flops.
- * Synchronises. */
+ * blr_profile_read waits for the handle's previous work first. */
 blr_status blr_profile_enable(blr_matrix h, int32_t on);
 blr_status blr_profile_read(blr_matrix h, int32_t kernel, int64_t* launches, double* total_ms,
                             double* total_flops);

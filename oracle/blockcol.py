@@ -10,10 +10,14 @@ Step k:
      A_ij -= Ytilde_ik W_j (eq. blr_bch_apply_bc_reflector).  Reading of the
      accumulation: if any term is dense the sum is dense (OP1) and all terms
      are added exactly; otherwise the low-rank terms are accumulated by
-     rounded additions of two terms at a time (OP2, Alg. 6) in a pairwise
-     tree: the terms in order i = k, k+1, ... are the leaves, each level adds
-     neighbouring pairs (the left one first in the stack), an odd one out
-     passes to the next level unchanged.
+     rounded additions of two terms at a time (OP2, Alg. 6).  Section 3.1
+     fixes that every addition of two low-rank terms is recompressed, not the
+     order of the sum; the plain reading, and the default here, is the chain
+     in the order of the sum, i = k, k+1, ...: Z <- round(Z + term_i).
+     zsum="tree" instead adds the same terms in a pairwise tree (the terms are
+     the leaves, each level adds neighbouring pairs, the left one first in the
+     stack, an odd one out passes to the next level unchanged); both are
+     legal orders of the same rounded additions.
 """
 from __future__ import annotations
 
@@ -22,6 +26,16 @@ import numpy as np
 from . import blrops, dense
 from .blrmat import BLR, DENSE, LOWRANK
 from .factor import Factor
+
+
+def chain_sum(terms, add):
+    """Sum terms[0] + terms[1] + ... left to right, one rounded addition per
+    term: Z = add(...add(add(terms[0], terms[1]), terms[2])...)."""
+    terms = list(terms)
+    z = terms[0]
+    for t in terms[1:]:
+        z = add(z, t)
+    return z
 
 
 def pairwise_sum(terms, add):
@@ -38,8 +52,11 @@ def pairwise_sum(terms, add):
 
 
 class BlockColumnFactor(Factor):
-    def __init__(self, blr: BLR, eps: float, cap: int):
+    def __init__(self, blr: BLR, eps: float, cap: int, zsum: str = "chain"):
         super().__init__(blr, eps, cap)
+        if zsum not in ("chain", "tree"):
+            raise ValueError("zsum must be 'chain' or 'tree'")
+        self.zsum = chain_sum if zsum == "chain" else pairwise_sum
         self.Tk = {}
 
     def yrep(self, i, k):
@@ -77,7 +94,7 @@ class BlockColumnFactor(Factor):
         if any(t[0] == "D" for t in terms):
             Z = ("D", sum(blrops.dense_of(t) for t in terms))
         else:
-            Z = pairwise_sum(terms, lambda a, t: blrops.add(a, t, 1.0, e, c, st))
+            Z = self.zsum(terms, lambda a, t: blrops.add(a, t, 1.0, e, c, st))
         W = blrops.t_times(self.Tk[k], Z, True)
         for i in range(k, self.p):
             upd = blrops.y_times(self.yrep(i, k), W)
@@ -117,6 +134,6 @@ class BlockColumnFactor(Factor):
 
 
 def factor(blr: BLR, eps: float, cap: int, stop_after_k=None,
-           copy: bool = True) -> BlockColumnFactor:
-    f = BlockColumnFactor(blr.copy() if copy else blr, eps, cap)
+           copy: bool = True, zsum: str = "chain") -> BlockColumnFactor:
+    f = BlockColumnFactor(blr.copy() if copy else blr, eps, cap, zsum)
     return f.run(stop_after_k)

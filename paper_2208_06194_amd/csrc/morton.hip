@@ -43,9 +43,10 @@ hipError_t morton_sort(const double* pts, int64_t n, int dim, int64_t* perm, dou
   int64_t* i0 = nullptr;
   void* tmp = nullptr;
   size_t tmp_bytes = 0;
-  hipError_t e = hipMalloc(&k0, n * sizeof(uint64_t));
-  if (e == hipSuccess) e = hipMalloc(&k1, n * sizeof(uint64_t));
-  if (e == hipSuccess) e = hipMalloc(&i0, n * sizeof(int64_t));
+  // scratch is stream-ordered memory on s: nothing here waits for other work
+  hipError_t e = hipMallocAsync((void**)&k0, n * sizeof(uint64_t), s);
+  if (e == hipSuccess) e = hipMallocAsync((void**)&k1, n * sizeof(uint64_t), s);
+  if (e == hipSuccess) e = hipMallocAsync((void**)&i0, n * sizeof(int64_t), s);
   const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_morton_keys, dim3(blocks), dim3(256), 0, s, pts, n, dim, k0, i0);
@@ -54,7 +55,7 @@ hipError_t morton_sort(const double* pts, int64_t n, int dim, int64_t* perm, dou
   // radix sort is stable: equal keys keep the original index order
   if (e == hipSuccess)
     e = rocprim::radix_sort_pairs(nullptr, tmp_bytes, k0, k1, i0, perm, (size_t)n, 0, 21 * dim, s);
-  if (e == hipSuccess) e = hipMalloc(&tmp, std::max<size_t>(tmp_bytes, 1));
+  if (e == hipSuccess) e = hipMallocAsync(&tmp, std::max<size_t>(tmp_bytes, 1), s);
   if (e == hipSuccess)
     e = rocprim::radix_sort_pairs(tmp, tmp_bytes, k0, k1, i0, perm, (size_t)n, 0, 21 * dim, s);
   if (e == hipSuccess && sorted) {
@@ -62,10 +63,9 @@ hipError_t morton_sort(const double* pts, int64_t n, int dim, int64_t* perm, dou
     hipLaunchKernelGGL(k_gather_points, dim3(gb), dim3(256), 0, s, pts, n, dim, perm, sorted);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(tmp);
-  (void)hipFree(i0);
-  (void)hipFree(k1);
-  (void)hipFree(k0);
+  if (tmp) (void)hipFreeAsync(tmp, s);
+  if (i0) (void)hipFreeAsync(i0, s);
+  if (k1) (void)hipFreeAsync(k1, s);
+  if (k0) (void)hipFreeAsync(k0, s);
   return e;
 }

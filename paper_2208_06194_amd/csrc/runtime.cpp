@@ -55,6 +55,43 @@ void Arena::release() {
   bytes = 0;
 }
 
+void* Workspace::alloc(size_t n) {
+  if (n == 0) n = 256;
+  n = (n + 255) & ~(size_t)255;
+  for (; cur < chunks.size(); ++cur) {
+    Chunk& c = chunks[cur];
+    if (c.size - c.used >= n) {
+      void* p = c.p + c.used;
+      c.used += n;
+      return p;
+    }
+  }
+  // a new chunk: at least 64 MiB, so that small allocations share chunks
+  const size_t sz = std::max<size_t>(n, (size_t)64 << 20);
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, sz);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(BLR_ERR_OOM, "hipMalloc of " + std::to_string(sz) + " bytes of workspace failed");
+  }
+  chunks.push_back(Chunk{(char*)p, sz, n});
+  cur = chunks.size() - 1;
+  bytes += (int64_t)sz;
+  return p;
+}
+
+void Workspace::reset() {
+  for (Chunk& c : chunks) c.used = 0;
+  cur = 0;
+}
+
+void Workspace::release() {
+  for (Chunk& c : chunks) (void)hipFree(c.p);
+  chunks.clear();
+  cur = 0;
+  bytes = 0;
+}
+
 void Plan::gemm(double* C, int64_t ldc, const double* Cin, int64_t ldcin, double* D2, int64_t ldd2,
                 int M, int N, double alpha, double beta, const double* A, int64_t lda,
                 const double* B, int64_t ldb, int K, int segflags, int descflags) {
@@ -214,39 +251,27 @@ void Plan::flush_rc() {
   currc.clear();
 }
 
-void Plan::upload(Arena& arena) {
-  if (!descs.empty()) {
-    d_descs = (GemmDesc*)arena.alloc(descs.size() * sizeof(GemmDesc));
-    HIPCHECK(hipMemcpy(d_descs, descs.data(), descs.size() * sizeof(GemmDesc), hipMemcpyHostToDevice));
-  }
-  if (!segs.empty()) {
-    d_segs = (GemmSeg*)arena.alloc(segs.size() * sizeof(GemmSeg));
-    HIPCHECK(hipMemcpy(d_segs, segs.data(), segs.size() * sizeof(GemmSeg), hipMemcpyHostToDevice));
-  }
-  if (!copies.empty()) {
-    d_copies = (CopyDesc*)arena.alloc(copies.size() * sizeof(CopyDesc));
-    HIPCHECK(hipMemcpy(d_copies, copies.data(), copies.size() * sizeof(CopyDesc), hipMemcpyHostToDevice));
-  }
-  if (!rcs.empty()) {
-    d_rcs = (RcDesc*)arena.alloc(rcs.size() * sizeof(RcDesc));
-    HIPCHECK(hipMemcpy(d_rcs, rcs.data(), rcs.size() * sizeof(RcDesc), hipMemcpyHostToDevice));
-  }
-  if (!jobs.empty()) {
-    d_jobs = (PanelJob*)arena.alloc(jobs.size() * sizeof(PanelJob));
-    HIPCHECK(hipMemcpy(d_jobs, jobs.data(), jobs.size() * sizeof(PanelJob), hipMemcpyHostToDevice));
-  }
-  if (!tjobs.empty()) {
-    d_tjobs = (TrsmJob*)arena.alloc(tjobs.size() * sizeof(TrsmJob));
-    HIPCHECK(hipMemcpy(d_tjobs, tjobs.data(), tjobs.size() * sizeof(TrsmJob), hipMemcpyHostToDevice));
-  }
-  if (!lincs.empty()) {
-    d_lincs = (LincombDesc*)arena.alloc(lincs.size() * sizeof(LincombDesc));
-    HIPCHECK(hipMemcpy(d_lincs, lincs.data(), lincs.size() * sizeof(LincombDesc), hipMemcpyHostToDevice));
-  }
-  if (!frobs.empty()) {
-    d_frobs = (Frob2Desc*)arena.alloc(frobs.size() * sizeof(Frob2Desc));
-    HIPCHECK(hipMemcpy(d_frobs, frobs.data(), frobs.size() * sizeof(Frob2Desc), hipMemcpyHostToDevice));
-  }
+namespace {
+template <class T>
+T* upload_array(const std::vector<T>& v, DevAlloc& a, HostKeep& keep, hipStream_t s) {
+  if (v.empty()) return nullptr;
+  const size_t n = v.size() * sizeof(T);
+  T* d = (T*)a.alloc(n);
+  keep.emplace_back((const char*)v.data(), (const char*)v.data() + n);
+  HIPCHECK(hipMemcpyAsync(d, keep.back().data(), n, hipMemcpyHostToDevice, s));
+  return d;
+}
+}  // namespace
+
+void Plan::upload(DevAlloc& a, HostKeep& keep, hipStream_t s) {
+  d_descs = upload_array(descs, a, keep, s);
+  d_segs = upload_array(segs, a, keep, s);
+  d_copies = upload_array(copies, a, keep, s);
+  d_rcs = upload_array(rcs, a, keep, s);
+  d_jobs = upload_array(jobs, a, keep, s);
+  d_tjobs = upload_array(tjobs, a, keep, s);
+  d_lincs = upload_array(lincs, a, keep, s);
+  d_frobs = upload_array(frobs, a, keep, s);
 }
 
 void Plan::clear() { *this = Plan(); }
@@ -271,6 +296,46 @@ RcParams rc_params(blr_matrix h) {
 }
 
 constexpr int kStreams = 4;
+
+// Calls on one handle.  Every call that enqueues work records h->idle on the
+// caller's stream at its end (after the handle's own streams have been
+// joined to it).  The next call waits for that event only (the host waits
+// for this handle's work, never for the whole device) before it reuses the
+// workspace and drops the host copies of the previous uploads.
+void wait_idle(blr_matrix h) {
+  if (h->idle_set) HIPCHECK(hipEventSynchronize(h->idle));
+}
+
+void begin_call(blr_matrix h) {
+  wait_idle(h);
+  h->keep.clear();
+  h->work.reset();
+}
+
+void end_call(blr_matrix h, hipStream_t s) {
+  if (!h->idle) HIPCHECK(hipEventCreateWithFlags(&h->idle, hipEventDisableTiming));
+  HIPCHECK(hipEventRecord(h->idle, s));
+  h->idle_set = true;
+}
+
+// Reuse the workspace inside a call once the caller's stream s has been
+// synchronised (everything the call enqueued so far ran on s or was joined
+// to it).
+void reset_work_after_sync(blr_matrix h) {
+  h->keep.clear();
+  h->work.reset();
+}
+
+// Stream-ordered upload of a host array into the workspace.
+template <class T>
+T* upload_vec(blr_matrix h, const std::vector<T>& v, hipStream_t s) {
+  if (v.empty()) return nullptr;
+  const size_t n = v.size() * sizeof(T);
+  T* d = (T*)h->work.alloc(n);
+  h->keep.emplace_back((const char*)v.data(), (const char*)v.data() + n);
+  HIPCHECK(hipMemcpyAsync(d, h->keep.back().data(), n, hipMemcpyHostToDevice, s));
+  return d;
+}
 
 void ensure_streams(blr_matrix h) {
   while ((int)h->streams.size() < kStreams) {
@@ -414,6 +479,12 @@ void execute(blr_matrix h, Plan& P, hipStream_t s) {
   }
 }
 
+// Upload a plan's descriptors into the handle's workspace and enqueue it.
+void run_plan(blr_matrix h, Plan& P, hipStream_t s) {
+  P.upload(h->work, h->keep, s);
+  execute(h, P, s);
+}
+
 // ---------------------------------------------------------------------------
 // Workspace of one factorization / application (single stream: reused by
 // every step, since the ops of consecutive steps are ordered on the stream).
@@ -431,7 +502,7 @@ Work make_work(blr_matrix h, int nrhs_cols) {
   Work w;
   const int b = h->b, rc = h->rc, q = std::max(h->q, 1);
   const int wcols = std::max(b, nrhs_cols);
-  Arena& A = h->work;
+  Workspace& A = h->work;
   w.Wx = (double*)A.alloc((size_t)b * wcols * 8);
   w.Wx2 = (double*)A.alloc((size_t)b * wcols * 8);
   w.Wg = (double*)A.alloc((size_t)b * b * 8);
@@ -886,7 +957,7 @@ std::vector<int> bc_simulate(blr_matrix h, int kend, int* max_pairs) {
 BcWork make_bc_work(blr_matrix h, int npairs) {
   BcWork bw;
   const int b = h->b, rc = h->rc;
-  Arena& A = h->work;
+  Workspace& A = h->work;
   bw.stack = (double*)A.alloc((size_t)h->m * b * 8);
   bw.Yf[0] = (double*)A.alloc((size_t)b * b * 8);
   bw.Yf[1] = (double*)A.alloc((size_t)b * b * 8);
@@ -1671,7 +1742,7 @@ void run_batch_plans(std::vector<Plan>& plans, const std::vector<blr_matrix>& hv
       gh.push_back(hv[i]);
     }
     M[g] = merge_plans(gp, gh);
-    M[g].upload(gh[0]->work);
+    M[g].upload(gh[0]->work, gh[0]->keep, s);
   }
   blr_matrix h0 = hv[0];
   std::vector<hipEvent_t> none;
@@ -1935,8 +2006,7 @@ void plan_rsolve(blr_matrix h, Plan& Q, const RsolveWork& rw, double* X, int64_t
 void run_rsolve(blr_matrix h, double* X, int64_t ldx, int nrhs, int trans, hipStream_t s) {
   Plan Q;
   plan_rsolve(h, Q, make_rsolve_work(h, nrhs), X, ldx, nrhs, trans);
-  Q.upload(h->work);
-  execute(h, Q, s);
+  run_plan(h, Q, s);
 }
 
 // Singularity check of a complete factor: min |R_jj| against n u ||R||_F.
@@ -1950,9 +2020,8 @@ SingCheck sing_launch(blr_matrix h, hipStream_t s) {
   SingCheck c;
   std::vector<DiagDesc> dd(q);
   for (int k = 0; k < q; ++k) dd[k].R = h->t(k, k).D;
-  DiagDesc* ddd = (DiagDesc*)h->work.alloc(q * sizeof(DiagDesc));
+  DiagDesc* ddd = upload_vec(h, dd, s);
   double* out = (double*)h->work.alloc((size_t)2 * q * 8);
-  HIPCHECK(hipMemcpy(ddd, dd.data(), q * sizeof(DiagDesc), hipMemcpyHostToDevice));
   HIPCHECK(launch_diag_absmin(ddd, q, b, out, s));
   std::vector<Frob2Desc> fr;
   double* fo = (double*)h->work.alloc((size_t)q * q * 8 + 8);
@@ -1964,8 +2033,7 @@ SingCheck sing_launch(blr_matrix h, hipStream_t s) {
       else fr.push_back(Frob2Desc{t.Vt, rc, rc, b, o});
     }
   if (!fr.empty()) {
-    Frob2Desc* dfr = (Frob2Desc*)h->work.alloc(fr.size() * sizeof(Frob2Desc));
-    HIPCHECK(hipMemcpy(dfr, fr.data(), fr.size() * sizeof(Frob2Desc), hipMemcpyHostToDevice));
+    Frob2Desc* dfr = upload_vec(h, fr, s);
     HIPCHECK(launch_frob2(dfr, (int)fr.size(), s));
   }
   c.ho.resize(2 * q);
@@ -2030,8 +2098,7 @@ void keep_copy(blr_matrix h, hipStream_t s) {
     }
   }
   P.copy(cp);
-  P.upload(h->work);
-  execute(h, P, s);
+  run_plan(h, P, s);
 }
 
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
@@ -2111,10 +2178,7 @@ int prepare_factor(blr_matrix h, const blr_factor_opts* o, hipStream_t s, Plan& 
   h->precision = o->precision;
   h->fmt0.resize((size_t)p * q);
   for (size_t t = 0; t < h->fmt0.size(); ++t) h->fmt0[t] = h->tiles[t].fmt;
-  if (o->keep_a) {
-    keep_copy(h, s);
-    HIPCHECK(hipStreamSynchronize(s));
-  }
+  if (o->keep_a) keep_copy(h, s);
   const bool bc = o->variant == BLR_BLOCK_COLUMN;
   int bc_pairs = 0;
   // fill-in: simulate formats to find the tiles that need a dense slot
@@ -2157,7 +2221,6 @@ int prepare_factor(blr_matrix h, const blr_factor_opts* o, hipStream_t s, Plan& 
       h->tau[idx[a]] = tu + a * (size_t)b;
     }
   }
-  h->work.release();
   std::vector<Work> works;
   const int nstreams = bc ? 1 : kStreams;
   for (int a = 0; a < nstreams; ++a) works.push_back(make_work(h, 0));
@@ -2304,7 +2367,7 @@ blr_status blr_compress(const blr_source* src, const blr_compress_opts* o, void*
     if (!cand.empty()) {
       const int l = std::min(b, rc + 16);
       const int NB = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cand.size(), (int64_t)(256LL << 20) / ((int64_t)b * b * 8)));
-      Arena cw;
+      Workspace& cw = h->work;
       double* Om = (double*)cw.alloc((size_t)b * l * 8);
       HIPCHECK(launch_gaussian(Om, (int64_t)b * l, o->seed, 4, s));
       double* As = (double*)cw.alloc((size_t)NB * b * b * 8);
@@ -2347,9 +2410,11 @@ blr_status blr_compress(const blr_source* src, const blr_compress_opts* o, void*
           D.enorm2 = nrm + 2 * a + 1;
           P.gemm(D.Y, b, nullptr, 0, nullptr, 0, b, l, 1.0, 0.0, A, b, Om, b, b, 0);
         }
-        HIPCHECK(hipMemcpy(dfd, fd.data(), nb * sizeof(TileFillDesc), hipMemcpyHostToDevice));
-        HIPCHECK(hipMemcpy(dfr, fr.data(), 2 * nb * sizeof(Frob2Desc), hipMemcpyHostToDevice));
-        HIPCHECK(hipMemcpy(dcd, cd.data(), nb * sizeof(CompDesc), hipMemcpyHostToDevice));
+        // stream-ordered uploads; the host arrays live until the stream is
+        // synchronised at the end of this chunk of tiles
+        HIPCHECK(hipMemcpyAsync(dfd, fd.data(), nb * sizeof(TileFillDesc), hipMemcpyHostToDevice, s));
+        HIPCHECK(hipMemcpyAsync(dfr, fr.data(), 2 * nb * sizeof(Frob2Desc), hipMemcpyHostToDevice, s));
+        HIPCHECK(hipMemcpyAsync(dcd, cd.data(), nb * sizeof(CompDesc), hipMemcpyHostToDevice, s));
         P.flush_gemm(0, 0, false);
         for (int a = 0; a < nb; ++a)
           P.gemm(cd[a].B, l, nullptr, 0, nullptr, 0, l, b, 1.0, 0.0, cd[a].Q, b, cd[a].A, b, b, SEG_TRANS_A);
@@ -2358,8 +2423,8 @@ blr_status blr_compress(const blr_source* src, const blr_compress_opts* o, void*
           P.gemm(const_cast<double*>(cd[a].A), b, cd[a].A, b, nullptr, 0, b, b, -1.0, 1.0, cd[a].Q, b,
                  cd[a].B, l, l, 0);
         P.flush_gemm(0, 0, false);
-        HIPCHECK(hipMemcpy(dgd, P.descs.data(), P.descs.size() * sizeof(GemmDesc), hipMemcpyHostToDevice));
-        HIPCHECK(hipMemcpy(dgs, P.segs.data(), P.segs.size() * sizeof(GemmSeg), hipMemcpyHostToDevice));
+        HIPCHECK(hipMemcpyAsync(dgd, P.descs.data(), P.descs.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, s));
+        HIPCHECK(hipMemcpyAsync(dgs, P.segs.data(), P.segs.size() * sizeof(GemmSeg), hipMemcpyHostToDevice, s));
         HIPCHECK(launch_fill_tiles(dfd, nb, fp, s));
         HIPCHECK(launch_frob2(dfr, nb, s));
         HIPCHECK(launch_gemm(dgd + P.ops[0].off, P.ops[0].n, dgs, P.ops[0].ntiles, P.ops[0].big, 0, s));
@@ -2394,12 +2459,11 @@ blr_status blr_compress(const blr_source* src, const blr_compress_opts* o, void*
         const int t = dense[c0 + a];
         fd[a] = TileFillDesc{h->tiles[t].D, t / q, t % q};
       }
-      TileFillDesc* dfd = (TileFillDesc*)h->work.alloc(nb * sizeof(TileFillDesc));
-      HIPCHECK(hipMemcpy(dfd, fd.data(), nb * sizeof(TileFillDesc), hipMemcpyHostToDevice));
+      TileFillDesc* dfd = upload_vec(h, fd, s);
       HIPCHECK(launch_fill_tiles(dfd, nb, fp, s));
     }
     HIPCHECK(hipStreamSynchronize(s));
-    h->work.release();
+    reset_work_after_sync(h);
   });
   if (st != BLR_OK) {
     delete h;
@@ -2475,7 +2539,7 @@ blr_status blr_import(const blr_compress_opts* o, const blr_tiles_host* t, void*
 blr_status blr_export(blr_matrix h, blr_tiles_host* t) {
   if (!h || !t) return fail(BLR_ERR_INVALID, "NULL argument");
   return run_guarded([&] {
-    HIPCHECK(hipDeviceSynchronize());
+    wait_idle(h);
     const int b = h->b, rc = h->rc, q = h->q;
     const size_t nt = (size_t)h->p * h->q;
     std::vector<int> ranks(nt);
@@ -2513,11 +2577,12 @@ blr_status blr_qr_factor(blr_matrix h, const blr_factor_opts* o, void* stream) {
   if (o->precision != BLR_FP64 && o->precision != BLR_MIXED_FP32) return fail(BLR_ERR_INVALID, "bad precision");
   hipStream_t s = as_stream(stream);
   return run_guarded([&] {
+    begin_call(h);
     Plan P;
     const int kend = prepare_factor(h, o, s, P, true);
-    P.upload(h->work);
     HIPCHECK(hipMemsetAsync(h->d_counters, 0, 4 * sizeof(unsigned long long), s));
-    execute(h, P, s);
+    run_plan(h, P, s);
+    end_call(h, s);
     h->steps_done = kend;
     h->state = BLR_STATE_FACTORED;
   });
@@ -2538,6 +2603,7 @@ blr_status blr_qr_factor_batch(blr_matrix* hs, int32_t count, const blr_factor_o
   }
   hipStream_t s = as_stream(stream);
   return run_guarded([&] {
+    for (int i = 0; i < count; ++i) begin_call(v[i]);
     std::vector<Plan> plans(count);
     std::vector<int> kend(count);
     for (int i = 0; i < count; ++i) kend[i] = prepare_factor(v[i], o, s, plans[i], false);
@@ -2545,6 +2611,7 @@ blr_status blr_qr_factor_batch(blr_matrix* hs, int32_t count, const blr_factor_o
       HIPCHECK(hipMemsetAsync(v[i]->d_counters, 0, 4 * sizeof(unsigned long long), s));
     run_batch_plans(plans, v, s);
     plans.clear();
+    for (int i = 0; i < count; ++i) end_call(v[i], s);
     for (int i = 0; i < count; ++i) {
       v[i]->launches = v[0]->launches;
       v[i]->steps_done = kend[i];
@@ -2560,13 +2627,12 @@ blr_status blr_apply_qt(blr_matrix h, int32_t trans, double* B, int64_t ldb, int
   if (nrhs == 0) return BLR_OK;
   hipStream_t s = as_stream(stream);
   return run_guarded([&] {
-    HIPCHECK(hipDeviceSynchronize());
-    h->work.release();
+    begin_call(h);
     Work w = make_work(h, nrhs);
     Plan P;
     plan_apply(h, P, w, B, ldb, nrhs, trans);
-    P.upload(h->work);
-    execute(h, P, s);
+    run_plan(h, P, s);
+    end_call(h, s);
   });
 }
 
@@ -2583,26 +2649,23 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
   hipStream_t s = as_stream(stream);
   return run_guarded([&] {
     const int64_t m = h->m, n = h->n;
-    HIPCHECK(hipDeviceSynchronize());
-    h->work.release();
+    begin_call(h);
     {
       SingCheck sc = sing_launch(h, s);
       HIPCHECK(hipStreamSynchronize(s));
       if (!sing_ok(h, sc)) throw Error(BLR_ERR_SINGULAR, "R is numerically singular");
-      h->work.release();
+      reset_work_after_sync(h);
     }
     Work w = make_work(h, nrhs);
     auto apply = [&](double* C, int trans) {
       Plan P;
       plan_apply(h, P, w, C, m, nrhs, trans);
-      P.upload(h->work);
-      execute(h, P, s);
+      run_plan(h, P, s);
     };
     auto frob2 = [&](const double* C, int64_t ld, int64_t rows, double* out) {
       std::vector<Frob2Desc> fr(nrhs);
       for (int c = 0; c < nrhs; ++c) fr[c] = Frob2Desc{C + (int64_t)c * ld, ld, (int)rows, 1, out + c};
-      Frob2Desc* dfr = (Frob2Desc*)h->work.alloc(nrhs * sizeof(Frob2Desc));
-      HIPCHECK(hipMemcpy(dfr, fr.data(), nrhs * sizeof(Frob2Desc), hipMemcpyHostToDevice));
+      Frob2Desc* dfr = upload_vec(h, fr, s);
       if (rows > 0) HIPCHECK(launch_frob2(dfr, nrhs, s));
       else HIPCHECK(hipMemsetAsync(out, 0, nrhs * 8, s));
     };
@@ -2631,8 +2694,7 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
           Plan P;
           plan_matmul(h, P, BLR_MATMUL_A, X, ldx, f, m, nrhs);
           plan_matmul(h, P, BLR_MATMUL_AT, r, m, g, n, nrhs);
-          P.upload(h->work);
-          execute(h, P, s);
+          run_plan(h, P, s);
         }
         HIPCHECK(launch_lincomb(f, m, B, ldb, r, m, f, m, 1.0, -1.0, -1.0, (int)m, nrhs, s));
         // d = Q^T f (in f);  h = R^{-T} g with g = -A~^T r (in g)
@@ -2658,6 +2720,7 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
       }
       if (resid_norms) frob2(r, m, m, resid_norms);
     }
+    end_call(h, s);
     HIPCHECK(hipStreamSynchronize(s));
   });
 }
@@ -2682,17 +2745,14 @@ blr_status blr_lstsq_solve_batch(blr_matrix* hs, int32_t count, const double* co
   if (nrhs == 0) return BLR_OK;
   hipStream_t s = as_stream(stream);
   return run_guarded([&] {
-    HIPCHECK(hipDeviceSynchronize());
+    for (int i = 0; i < count; ++i) begin_call(v[i]);
     std::vector<SingCheck> sc(count);
-    for (int i = 0; i < count; ++i) {
-      v[i]->work.release();
-      sc[i] = sing_launch(v[i], s);
-    }
+    for (int i = 0; i < count; ++i) sc[i] = sing_launch(v[i], s);
     HIPCHECK(hipStreamSynchronize(s));
     for (int i = 0; i < count; ++i) {
       if (!sing_ok(v[i], sc[i]))
         throw Error(BLR_ERR_SINGULAR, "R of batch member " + std::to_string(i) + " is numerically singular");
-      v[i]->work.release();
+      reset_work_after_sync(v[i]);
     }
     struct Member {
       Work w;
@@ -2788,6 +2848,7 @@ blr_status blr_lstsq_solve_batch(blr_matrix* hs, int32_t count, const double* co
         if (e.active && refine_converged(e.hn, e.prev, nrhs, u)) e.active = false;
       }
     }
+    for (int i = 0; i < count; ++i) end_call(v[i], s);
     HIPCHECK(hipStreamSynchronize(s));
   });
 }
@@ -2801,10 +2862,9 @@ blr_status blr_rsolve(blr_matrix h, int32_t trans, double* X, int64_t ldx, int32
   if (nrhs == 0) return BLR_OK;
   hipStream_t s = as_stream(stream);
   return run_guarded([&] {
-    HIPCHECK(hipDeviceSynchronize());
-    h->work.release();
+    begin_call(h);
     run_rsolve(h, X, ldx, nrhs, trans, s);
-    HIPCHECK(hipStreamSynchronize(s));
+    end_call(h, s);
   });
 }
 
@@ -2826,8 +2886,7 @@ blr_status blr_lstsq_adjoint(blr_matrix h, const double* B, int64_t ldb, const d
   return run_guarded([&] {
     const int b = h->b, rc = h->rc, p = h->p, q = h->q;
     const int64_t m = h->m, n = h->n;
-    HIPCHECK(hipDeviceSynchronize());
-    h->work.release();
+    begin_call(h);
     double* Z = (double*)h->work.alloc((size_t)n * nrhs * 8);
     double* Rs = (double*)h->work.alloc((size_t)m * nrhs * 8);
     // Z = R^{-1} R^{-T} Xbar
@@ -2839,8 +2898,7 @@ blr_status blr_lstsq_adjoint(blr_matrix h, const double* B, int64_t ldb, const d
       Plan P;
       plan_matmul(h, P, BLR_MATMUL_A, X, ldx, Rs, m, nrhs);
       plan_matmul(h, P, BLR_MATMUL_A, Z, n, Bbar, ldbb, nrhs);
-      P.upload(h->work);
-      execute(h, P, s);
+      run_plan(h, P, s);
     }
     HIPCHECK(launch_lincomb(Rs, m, B, ldb, Rs, m, nullptr, 0, 1.0, -1.0, 0.0, (int)m, nrhs, s));
     // tile gradients
@@ -2923,9 +2981,8 @@ blr_status blr_lstsq_adjoint(blr_matrix h, const double* B, int64_t ldb, const d
         ++l;
       }
     P.flush_gemm(0, 0, false);
-    P.upload(h->work);
-    execute(h, P, s);
-    HIPCHECK(hipStreamSynchronize(s));
+    run_plan(h, P, s);
+    end_call(h, s);
   });
 }
 
@@ -2942,35 +2999,37 @@ blr_status blr_form_q(blr_matrix h, void* stream, blr_matrix* q_out) {
   blr_status st = run_guarded([&] {
     const int b = h->b, p = h->p, q = h->q;
     const int64_t m = h->m, n = h->n;
+    // the dense m x n block is stream-ordered memory: allocated and freed on
+    // s, so that neither waits for other work on the device
     struct DevBuf {
       double* p = nullptr;
+      hipStream_t s = nullptr;
       ~DevBuf() {
-        if (p) (void)hipFree(p);
+        if (p) (void)hipFreeAsync(p, s);
       }
     } E;
-    HIPCHECK(hipDeviceSynchronize());
-    h->work.release();
-    HIPCHECK(hipMalloc(&E.p, (size_t)m * n * 8));
+    begin_call(h);
+    E.s = s;
+    HIPCHECK(hipMallocAsync((void**)&E.p, (size_t)m * n * 8, s));
     HIPCHECK(hipMemsetAsync(E.p, 0, (size_t)m * n * 8, s));
     {
       Plan P;   // the identity in the top n x n block (unit-lower copy of zeros, in place)
       P.copy({CopyDesc{E.p, E.p, m, m, (int)n, (int)n, 1, 0}});
-      P.upload(h->work);
-      execute(h, P, s);
-      HIPCHECK(hipStreamSynchronize(s));
+      run_plan(h, P, s);
     }
+    // Q [I; 0], a block of columns at a time; the workspace of one block is
+    // reused for the next once the stream has finished it
     const int64_t nc = std::min<int64_t>(n, 4096);
     for (int64_t c0 = 0; c0 < n; c0 += nc) {
       const int cols = (int)std::min<int64_t>(nc, n - c0);
-      h->work.release();
+      HIPCHECK(hipStreamSynchronize(s));
+      reset_work_after_sync(h);
       Work w = make_work(h, cols);
       Plan P;
       plan_apply(h, P, w, E.p + c0 * m, m, cols, 1);
-      P.upload(h->work);
-      execute(h, P, s);
-      HIPCHECK(hipStreamSynchronize(s));
+      run_plan(h, P, s);
     }
-    h->work.release();
+    end_call(h, s);
     std::vector<int8_t> mask((size_t)p * q);
     for (size_t t = 0; t < mask.size(); ++t) mask[t] = h->fmt0[t] == LOWRANK ? 1 : 0;
     blr_source src{};
@@ -3022,19 +3081,18 @@ blr_status blr_matmul(blr_matrix h, int32_t op, const double* X, int64_t ldx, do
   }
   hipStream_t s = as_stream(stream);
   return run_guarded([&] {
-    HIPCHECK(hipDeviceSynchronize());
-    h->work.release();
+    begin_call(h);
     Plan P;
     plan_matmul(h, P, op, X, ldx, Y, ldy, nrhs);
-    P.upload(h->work);
-    execute(h, P, s);
+    run_plan(h, P, s);
+    end_call(h, s);
   });
 }
 
 blr_status blr_query(blr_matrix h, blr_info* info) {
   if (!h || !info) return fail(BLR_ERR_INVALID, "NULL argument");
   return run_guarded([&] {
-    HIPCHECK(hipDeviceSynchronize());
+    wait_idle(h);
     std::memset(info, 0, sizeof(*info));
     info->m = h->m;
     info->n = h->n;
@@ -3064,10 +3122,13 @@ blr_status blr_query(blr_matrix h, blr_info* info) {
 
 void blr_destroy(blr_matrix h) {
   if (!h) return;
-  (void)hipDeviceSynchronize();
+  // the handle's own work must end before its memory is freed
+  if (h->idle_set) (void)hipEventSynchronize(h->idle);
+  for (auto st : h->streams) (void)hipStreamSynchronize(st);
   for (int k = 0; k < 2; ++k)
     for (auto e : h->prof_ev[k]) (void)hipEventDestroy(e);
   for (auto st : h->streams) (void)hipStreamDestroy(st);
+  if (h->idle) (void)hipEventDestroy(h->idle);
   delete h;
 }
 
@@ -3082,7 +3143,7 @@ blr_status blr_profile_read(blr_matrix h, int32_t kernel, int64_t* launches, dou
   if (!h || !launches || !total_ms || !total_flops) return fail(BLR_ERR_INVALID, "NULL argument");
   if (kernel != 0 && kernel != 1) return fail(BLR_ERR_INVALID, "kernel must be 0 (FP64) or 1 (FP32)");
   return run_guarded([&] {
-    HIPCHECK(hipDeviceSynchronize());
+    wait_idle(h);
     double ms = 0.0;
     const auto& ev = h->prof_ev[kernel];
     for (size_t a = 0; a + 1 < ev.size(); a += 2) {
@@ -3106,11 +3167,12 @@ extern "C" blr_status blr_selftest_gemm(int32_t flags, int32_t M, int32_t N, int
   if (!A || !B || !C || M < 0 || N < 0 || K < 0) return fail(BLR_ERR_INVALID, "bad arguments");
   return run_guarded([&] {
     Arena ar;
+    HostKeep keep;
     Plan P;
     P.gemm(C, ldc, C, ldc, nullptr, 0, M, N, alpha, beta, A, lda, B, ldb, K, flags);
     P.flush_gemm(fp32);
     if (P.ops.empty()) return;
-    P.upload(ar);
+    P.upload(ar, keep, as_stream(stream));
     HIPCHECK(launch_gemm(P.d_descs, P.ops[0].n, P.d_segs, P.ops[0].ntiles, P.ops[0].big, P.ops[0].fp32,
                          as_stream(stream)));
     HIPCHECK(hipStreamSynchronize(as_stream(stream)));

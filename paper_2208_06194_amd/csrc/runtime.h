@@ -34,14 +34,43 @@ struct Tile {
   int* rank = nullptr;   // device rank
 };
 
+// Source of device memory for a plan's descriptor arrays.
+struct DevAlloc {
+  virtual void* alloc(size_t n) = 0;
+  virtual ~DevAlloc() = default;
+};
+
 // Device arena: every allocation is released by the owner's destructor.
-struct Arena {
+struct Arena : DevAlloc {
   std::vector<void*> blocks;
   int64_t bytes = 0;
-  void* alloc(size_t n);
+  void* alloc(size_t n) override;
   void release();
-  ~Arena() { release(); }
+  ~Arena() override { release(); }
 };
+
+// Grow-only device workspace of a handle: bump allocation over chunks that
+// are kept across calls.  reset() makes every chunk free again without
+// freeing it, so a call that repeats an earlier call's allocations allocates
+// nothing; only a larger demand adds a chunk.  The caller resets only after
+// the work that used the chunks has completed.
+struct Workspace : DevAlloc {
+  struct Chunk {
+    char* p;
+    size_t size, used;
+  };
+  std::vector<Chunk> chunks;
+  size_t cur = 0;
+  int64_t bytes = 0;
+  void* alloc(size_t n) override;
+  void reset();
+  void release();
+  ~Workspace() override { release(); }
+};
+
+// Host copies of uploaded descriptor arrays, kept until the handle's next
+// call has waited for the copies (stream-ordered uploads read them late).
+using HostKeep = std::vector<std::vector<char>>;
 
 // One enqueued operation of a plan.
 struct Op {
@@ -140,7 +169,9 @@ struct Plan {
   }
   void wait(int e) { Op o; o.kind = Op::WAIT; o.event = e; push(o); n_events = std::max(n_events, e + 1); }
   void record(int e) { Op o; o.kind = Op::RECORD; o.event = e; push(o); n_events = std::max(n_events, e + 1); }
-  void upload(Arena& arena);
+  // copy the descriptor arrays to device memory from a, enqueued on s; the
+  // host sources are copied into keep first
+  void upload(DevAlloc& a, HostKeep& keep, hipStream_t s);
   void clear();
 };
 
@@ -164,7 +195,10 @@ struct blr_matrix_s {
   int* d_rank = nullptr;
   unsigned long long* d_counters = nullptr;  // [0] overflow count, [1] max dropped bits
   blr::Arena mem;                        // tiles, T, ranks
-  blr::Arena work;                       // factor workspaces and plans
+  blr::Workspace work;                   // workspaces and plans of the calls, reused
+  blr::HostKeep keep;                    // host sources of the last call's uploads
+  hipEvent_t idle = nullptr;             // recorded at the end of every call's work
+  bool idle_set = false;
   int64_t compress_overflow = 0;
   int64_t n_fill = 0;
   double flops = 0.0;

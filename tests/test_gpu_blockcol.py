@@ -206,11 +206,16 @@ def random_blr(seed, m, n, b, rank, eps, cap):
 
 @pytest.mark.parametrize("b,cap", [(64, 64), (64, 32), (128, 128)])
 def test_blockcol_random_blr_matches_oracle(P, b, cap):
-    """Every off-diagonal tile low-rank: Z_j of each step is a pairwise tree of
-    up to 16 rounded additions.  cap = b never truncates (the ranks reach 44
-    at b = 64); cap 32 truncates (the oracle: 83 times, Res 1.7e-3) in both
-    factorizations, whose residuals then agree to six digits.  At b = 128
-    the rank capacity is 128, and the cores grow past the LDS-staged size."""
+    """Every off-diagonal tile low-rank: Z_j of each step sums up to 16
+    low-rank terms by rounded additions.  The oracle adds them in a chain in
+    the order of the sum (the plain reading); the library in a pairwise tree
+    of the same additions.  cap = b never truncates (the ranks reach 44 at
+    b = 64): R agrees with the chain to the compression tolerance.  cap 32
+    truncates (the chain 197 times, Res 1.9e-3; the tree 83 times, Res
+    1.7e-3): the residuals of the two orders agree within a factor of two,
+    and, as a check of the schedule alone, the library's tree agrees with
+    the oracle's tree to six digits.  At b = 128 the rank capacity is 128,
+    and the cores grow past the LDS-staged size."""
     m, n, eps = 1024, 512, 1e-10
     print("case: blockcol random BLR", m, n, b, cap, flush=True)
     A, blr = random_blr(9, m, n, b, 2, eps, cap)
@@ -236,9 +241,16 @@ def test_blockcol_random_blr_matches_oracle(P, b, cap):
         kappa = np.linalg.cond(At)
         assert np.linalg.norm(metrics.sign_fix(Rg, Ro) - Ro) / np.linalg.norm(Ro) <= 10 * kappa * eps
     else:
-        # the same truncations (up to ties at the threshold), the same residual
-        assert f.stats.overflow > 0 and abs(info["factor_overflow"] - f.stats.overflow) <= 2
-        assert abs(res - res_o) <= 1e-6 * res_o
+        # against the chain: both truncate, and the residuals agree in size
+        assert f.stats.overflow > 0 and info["factor_overflow"] > 0
+        assert 0.5 * res_o <= res <= 2.0 * res_o
+        # schedule check: the oracle's tree of the same additions gives the
+        # same truncations (up to ties at the threshold) and residual
+        ft = blockcol.factor(blr, eps, cap, zsum="tree")
+        res_t = metrics.res(ft, At)
+        print("oracle tree Res", res_t, "truncations", ft.stats.overflow, flush=True)
+        assert abs(info["factor_overflow"] - ft.stats.overflow) <= 2
+        assert abs(res - res_t) <= 1e-6 * res_t
 
 
 @pytest.mark.parametrize("b,cap", [(64, 64), (64, 32), (128, 128)])

@@ -270,15 +270,65 @@ def test_batch_rows_are_log_uniform_multiples():
     assert np.all(np.abs(hist - 1 / 8) < 0.01)
 
 
-def test_pairwise_sum_order():
-    """The block-column accumulation order: a pairwise tree over the terms
-    in index order (checked on strings, where the order is visible)."""
-    from oracle.blockcol import pairwise_sum
+def test_block_column_sum_orders():
+    """The two orders of the block-column accumulation of low-rank terms,
+    checked on strings, where the order is visible: the default chain in the
+    order of the sum, and the pairwise tree over the terms in index order."""
+    from oracle.blockcol import chain_sum, pairwise_sum
     cat = lambda a, b: "(" + a + "+" + b + ")"
+    assert chain_sum(["a"], cat) == "a"
+    assert chain_sum(list("abcd"), cat) == "(((a+b)+c)+d)"
     assert pairwise_sum(["a"], cat) == "a"
     assert pairwise_sum(["a", "b", "c"], cat) == "((a+b)+c)"
     assert pairwise_sum(list("abcde"), cat) == "(((a+b)+(c+d))+e)"
     assert pairwise_sum(list("abcdefgh"), cat) == "(((a+b)+(c+d))+((e+f)+(g+h)))"
+
+
+@pytest.mark.parametrize("t", [2, 3, 7, 16])
+def test_chain_and_tree_sums_agree_within_rounding_bound(t):
+    """Every rounded addition (Alg. 6) moves its sum by at most eps times the
+    sum's Frobenius norm (no cap binds here), so each order is within
+    (t-1) eps S of the exact sum of t terms, S = sum of the terms' norms, and
+    the two orders are within 2 (t-1) eps S of each other.  Both are checked
+    against the exact (dense) sum too."""
+    from oracle import blrops, lowrank
+    from oracle.blockcol import chain_sum, pairwise_sum
+    rng = np.random.default_rng(100 + t)
+    b, eps = 48, 1e-6
+    # terms with a shared decaying spectrum, so that truncation at eps drops
+    # a visible tail in every addition
+    terms = []
+    decay = 10.0 ** -np.arange(12)
+    for _ in range(t):
+        Uq, _ = np.linalg.qr(rng.standard_normal((b, 12)))
+        terms.append(("L", Uq, rng.standard_normal((b, 12)) * decay))
+    st = lowrank.Stats()
+    add = lambda a, x: blrops.add(a, x, 1.0, eps, b, st)
+    zc = blrops.dense_of(chain_sum(terms, add))
+    zt = blrops.dense_of(pairwise_sum(terms, add))
+    exact = sum(blrops.dense_of(x) for x in terms)
+    S = sum(np.linalg.norm(blrops.dense_of(x)) for x in terms)
+    assert st.overflow == 0
+    assert np.linalg.norm(zc - exact) <= (t - 1) * eps * S * (1 + 1e-6)
+    assert np.linalg.norm(zt - exact) <= (t - 1) * eps * S * (1 + 1e-6)
+    assert np.linalg.norm(zt - zc) <= 2 * (t - 1) * eps * S * (1 + 1e-6)
+    # the truncations are not vacuous: the rounded sums differ from the exact
+    assert np.linalg.norm(zc - exact) > 1e-3 * eps * S
+
+
+def test_block_column_chain_and_tree_factors_agree():
+    """Whole factorizations with the two accumulation orders: R agrees up to
+    the compression tolerance (C kappa eps) and both residuals are at eps."""
+    m, n, b, eps = 512, 256, 32, 1e-8
+    A, blr = kernel_blr(21, m, n, b, eps, b, rule="weak", kern="inv_r", dim=3)
+    At = blr.to_dense()
+    fc = blockcol.factor(blr, eps, b)
+    ft = blockcol.factor(blr, eps, b, zsum="tree")
+    assert fc.stats.recompressions > 0
+    kappa = np.linalg.cond(At)
+    Rc, Rt = fc.r_dense(), ft.r_dense()
+    assert np.linalg.norm(metrics.sign_fix(Rt, Rc) - Rc) / np.linalg.norm(Rc) <= 10 * kappa * eps
+    assert metrics.res(fc, At) <= 10 * eps and metrics.res(ft, At) <= 10 * eps
 
 
 def test_lstsq_adjoint_matches_finite_differences():
