@@ -279,9 +279,12 @@ blr_status blr_matmul(blr_matrix h, int32_t op, const double* X, int64_t ldx, do
  * many steps of iterative refinement of the augmented system
  * [I A~; A~^T 0][r; x] = [b; 0] with FP64 residuals f = b - r - A~ x and
  * g = -A~^T r and corrections from the stored factor, d = Q^T f,
- * h = R^{-T} g, dx = R^{-1}(d_1 - h), dr = Q [h; d_2]; the loop stops early
- * once every column's correction satisfies ||dx|| <= 2 u ||x|| or is more
- * than half the previous step's (it has reached the rounding noise).  It
+ * h = R^{-T} g, dx = R^{-1}(d_1 - h), dr = Q [h; d_2].  Per column, a step's
+ * correction is taken only while it is at most half the previous one taken;
+ * a larger one is dropped and the column stops with its current iterate
+ * (the residuals have reached their rounding noise, or the iteration
+ * diverges); a column also stops after taking a correction with
+ * ||dx|| <= 2 u ||x||.  The loop ends when no column is refining.  It
  * recovers FP64 accuracy for a BLR_MIXED_FP32 factor.  resid_norms: optional
  * device array of nrhs doubles receiving the squared least-squares residual
  * norm per column (||(Q^T B)[n:m]||^2, or ||r||^2 of the refined residual).

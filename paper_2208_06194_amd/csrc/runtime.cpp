@@ -2053,19 +2053,47 @@ bool sing_ok(blr_matrix h, const SingCheck& c) {
   return mn > thr;
 }
 
-// Convergence test of one refinement step from the squared norms hn[c] =
-// ||dx_c||^2 and hn[nrhs + c] = ||x_c||^2: a column has converged once its
-// correction is at the rounding level of x (||dx|| <= 2u ||x||) or no longer
-// at most half the previous one (the correction has reached the rounding
-// noise of the residuals); prev keeps the previous ||dx|| per column.
-bool refine_converged(const std::vector<double>& hn, std::vector<double>& prev, int nrhs, double u) {
+// Per-column decision after one refinement step, from the squared norms
+// hn[c] = ||dx_c||^2 and hn[nrhs + c] = ||x_c||^2 of the step's correction
+// and of the current iterate.  A column still refining (active) takes its
+// correction (take[c] = 1) only while the correction is at most half the
+// previous one taken; a larger one means the iteration has reached the
+// rounding noise of its residuals or diverges, so it is dropped and the
+// column stops with its current iterate (the rule LAPACK's refinement
+// routines use).  A column also stops after taking a correction at the
+// rounding level of x (||dx|| <= 2u ||x||).  prev keeps the last correction
+// taken.  Returns true when no column is still refining.
+bool refine_decide(const std::vector<double>& hn, std::vector<double>& prev, std::vector<char>& active,
+                   std::vector<char>& take, int nrhs, double u) {
   bool done = true;
   for (int c = 0; c < nrhs; ++c) {
+    take[c] = 0;
+    if (!active[c]) continue;
     const double dx = std::sqrt(hn[c]);
-    done = done && (dx <= 2.0 * u * std::sqrt(hn[nrhs + c]) || dx > 0.5 * prev[c]);
+    if (!(dx <= 0.5 * prev[c])) {   // no longer halving (or not finite): drop it
+      active[c] = 0;
+      continue;
+    }
+    take[c] = 1;
     prev[c] = dx;
+    if (dx <= 2.0 * u * std::sqrt(hn[nrhs + c])) active[c] = 0;
+    done = done && !active[c];
   }
   return done;
+}
+
+// Column runs of the columns a refinement step takes: [c0, c1) pairs.
+std::vector<std::pair<int, int>> take_runs(const std::vector<char>& take) {
+  std::vector<std::pair<int, int>> runs;
+  const int nrhs = (int)take.size();
+  for (int c = 0; c < nrhs;) {
+    if (!take[c]) { ++c; continue; }
+    int e = c;
+    while (e < nrhs && take[e]) ++e;
+    runs.emplace_back(c, e);
+    c = e;
+  }
+  return runs;
 }
 
 // Keep a device copy of A~ (all tiles and ranks) for products after the
@@ -2689,6 +2717,7 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
       apply(r, 1);
       const double u = 2.220446049250313e-16;
       std::vector<double> hn(2 * nrhs), prev(nrhs, HUGE_VAL);
+      std::vector<char> active(nrhs, 1), take(nrhs, 0);
       for (int it = 0; it < max_refine; ++it) {
         {  // f = b - r - A~ x,  g = -A~^T r
           Plan P;
@@ -2708,15 +2737,21 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
         // dx = R^{-1} (d_1 - h)  (in f[0:n])
         HIPCHECK(launch_lincomb(f, m, f, m, g, n, nullptr, 0, 1.0, -1.0, 0.0, (int)n, nrhs, s));
         run_rsolve(h, f, m, nrhs, 0, s);
-        // x += dx, r += dr
-        HIPCHECK(launch_lincomb(X, ldx, X, ldx, f, m, nullptr, 0, 1.0, 1.0, 0.0, (int)n, nrhs, s));
-        HIPCHECK(launch_lincomb(r, m, r, m, dr, m, nullptr, 0, 1.0, 1.0, 0.0, (int)m, nrhs, s));
-        // stop once every column has converged
+        // ||dx|| and ||x|| decide which columns take the step
         frob2(f, m, n, nrm);
         frob2(X, ldx, n, nrm + nrhs);
         HIPCHECK(hipMemcpyAsync(hn.data(), nrm, 2 * nrhs * 8, hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
-        if (refine_converged(hn, prev, nrhs, u)) break;
+        const bool done = refine_decide(hn, prev, active, take, nrhs, u);
+        // x += dx, r += dr on the columns that take it
+        for (auto [c0, c1] : take_runs(take)) {
+          const int nc = c1 - c0;
+          HIPCHECK(launch_lincomb(X + c0 * ldx, ldx, X + c0 * ldx, ldx, f + c0 * m, m, nullptr, 0, 1.0, 1.0, 0.0,
+                                  (int)n, nc, s));
+          HIPCHECK(launch_lincomb(r + c0 * m, m, r + c0 * m, m, dr + c0 * m, m, nullptr, 0, 1.0, 1.0, 0.0, (int)m,
+                                  nc, s));
+        }
+        if (done) break;
       }
       if (resid_norms) frob2(r, m, m, resid_norms);
     }
@@ -2759,6 +2794,7 @@ blr_status blr_lstsq_solve_batch(blr_matrix* hs, int32_t count, const double* co
       RsolveWork rw;
       double *C = nullptr, *r = nullptr, *f = nullptr, *g = nullptr, *dr = nullptr, *nrm = nullptr;
       std::vector<double> hn, prev;
+      std::vector<char> cact, take;
       bool active = true;
     };
     std::vector<Member> mb(count);
@@ -2798,6 +2834,8 @@ blr_status blr_lstsq_solve_batch(blr_matrix* hs, int32_t count, const double* co
         e.nrm = (double*)h->work.alloc((size_t)2 * nrhs * 8);
         e.hn.resize(2 * nrhs);
         e.prev.assign(nrhs, HUGE_VAL);
+        e.cact.assign(nrhs, 1);
+        e.take.assign(nrhs, 0);
         P.lincomb(lc(e.r, m, e.C, m, nullptr, 0, nullptr, 0, 0.0, 0.0, 0.0, n, nrhs));
         P.lincomb(lc(e.r + n, m, e.C + n, m, nullptr, 0, nullptr, 0, 1.0, 0.0, 0.0, m - n, nrhs));
         plan_apply(h, P, e.w, e.r, m, nrhs, 1);
@@ -2828,8 +2866,6 @@ blr_status blr_lstsq_solve_batch(blr_matrix* hs, int32_t count, const double* co
         plan_apply(h, P, e.w, e.dr, m, nrhs, 1);
         P.lincomb(lc(e.f, m, e.f, m, e.g, n, nullptr, 0, 1.0, -1.0, 0.0, n, nrhs));
         plan_rsolve(h, P, e.rw, e.f, m, nrhs, 0);
-        P.lincomb(lc(X[i], ldx[i], X[i], ldx[i], e.f, m, nullptr, 0, 1.0, 1.0, 0.0, n, nrhs));
-        P.lincomb(lc(e.r, m, e.r, m, e.dr, m, nullptr, 0, 1.0, 1.0, 0.0, m, nrhs));
         std::vector<Frob2Desc> fr(2 * nrhs);
         for (int c = 0; c < nrhs; ++c) {
           fr[c] = Frob2Desc{e.f + (int64_t)c * m, m, (int32_t)n, 1, e.nrm + c};
@@ -2843,10 +2879,22 @@ blr_status blr_lstsq_solve_batch(blr_matrix* hs, int32_t count, const double* co
         if (mb[i].active)
           HIPCHECK(hipMemcpyAsync(mb[i].hn.data(), mb[i].nrm, 2 * nrhs * 8, hipMemcpyDeviceToHost, s));
       HIPCHECK(hipStreamSynchronize(s));
+      // x += dx, r += dr on the columns that take the step
+      plans.assign(count, Plan());
       for (int i = 0; i < count; ++i) {
         Member& e = mb[i];
-        if (e.active && refine_converged(e.hn, e.prev, nrhs, u)) e.active = false;
+        if (!e.active) continue;
+        if (refine_decide(e.hn, e.prev, e.cact, e.take, nrhs, u)) e.active = false;
+        blr_matrix h = v[i];
+        const int64_t m = h->m, n = h->n;
+        for (auto [c0, c1] : take_runs(e.take)) {
+          const int nc = c1 - c0;
+          plans[i].lincomb(lc(X[i] + c0 * ldx[i], ldx[i], X[i] + c0 * ldx[i], ldx[i], e.f + c0 * m, m, nullptr, 0,
+                              1.0, 1.0, 0.0, n, nc));
+          plans[i].lincomb(lc(e.r + c0 * m, m, e.r + c0 * m, m, e.dr + c0 * m, m, nullptr, 0, 1.0, 1.0, 0.0, m, nc));
+        }
       }
+      run(plans);
     }
     for (int i = 0; i < count; ++i) end_call(v[i], s);
     HIPCHECK(hipStreamSynchronize(s));

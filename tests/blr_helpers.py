@@ -60,3 +60,20 @@ def export_dense(ex):
         for j in range(q):
             A[i * b:(i + 1) * b, j * b:(j + 1) * b] = export_tile(ex, i, j)
     return A
+
+
+def gpu_import(P, blr: BLR, eps: float, cap: int):
+    """The oracle-compressed matrix imported into the library (the oracle's
+    tiles are the input of both sides)."""
+    fmt, rank, dense, Uh, Vh = blr_to_host(blr, cap)
+    return P.BLRMatrix.import_tiles(blr.m, blr.n, blr.b, eps, cap, fmt, rank, dense, Uh, Vh)
+
+
+def kernel_blr(seed, m, n, b, eps, cap, kern="inv_r", dim=3, rule="dist_gt_diam", overflow="dense"):
+    """Seeded kernel matrix (Morton-sorted points) and the oracle's compression of it."""
+    import synth
+    from oracle import blrmat
+    x, y = synth.kernel_points(seed, m, n, dim)
+    A = blrmat.kernel_matrix(x, y, kern)
+    mask = blrmat.lowrank_mask(x, y, b, rule, m // b, n // b)
+    return A, blrmat.compress(A, b, eps, cap, mask, overflow)

@@ -264,6 +264,37 @@ def test_refinement_recovers_fp64_accuracy_from_mixed_factor(P, variant):
     assert np.linalg.norm(Y - At @ Xp) <= 1e-13 * np.linalg.norm(At) * np.linalg.norm(Xp)
 
 
+def test_refinement_stops_when_corrections_stop_halving(P):
+    """A matrix with kappa = 1e9 (singular values geometric from 1 to 1e-9,
+    all tiles dense) factored in the mixed form: kappa u32 >> 1, so the
+    corrections from the FP32-updated factor need not contract.  A
+    correction larger than half the previous one taken is dropped and the
+    column stops with its iterate, so whatever follows the first step adds
+    at most dx_1 (1/2 + 1/4 + ...): ||x_10 - x_1|| <= ||x_1 - x_0|| per
+    column (without the rule a diverging iteration keeps adding growing
+    corrections)."""
+    print("case: refinement stagnation", flush=True)
+    m, n, b = 512, 256, 64
+    rng = np.random.default_rng(31)
+    Qa, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    Qb, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = (Qa * np.logspace(0, -9, n)) @ Qb.T
+    blr = blrmat.compress(A, b, 1e-12, b, np.zeros((m // b, n // b), bool))
+    Bh = synth.rhs(31, m, 4)
+    Xr = np.linalg.lstsq(A, Bh, rcond=None)[0]
+    G = gpu_import(P, blr, 1e-12, b)
+    G.factor("block_column", precision="mixed", keep_a=True)
+    Bd = torch.tensor(Bh, device="cuda")
+    X0 = G.lstsq(Bd).cpu().numpy()
+    X1 = G.lstsq(Bd, max_refine=1).cpu().numpy()
+    X10 = G.lstsq(Bd, max_refine=10).cpu().numpy()
+    assert np.all(np.isfinite(X10))
+    err = [np.linalg.norm(X - Xr, axis=0) / np.linalg.norm(Xr, axis=0) for X in (X0, X1, X10)]
+    print("error unrefined", err[0], "after 1 step", err[1], "after up to 10", err[2], flush=True)
+    d1 = np.linalg.norm(X1 - X0, axis=0)
+    assert np.all(np.linalg.norm(X10 - X1, axis=0) <= d1 * (1 + 1e-9) + 1e-300)
+
+
 def test_refinement_requires_the_kept_copy(P):
     m, n, b, eps, cap = 256, 128, 64, 1e-8, 16
     A, blr = kernel_blr(14, m, n, b, eps, cap)
