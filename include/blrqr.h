@@ -256,6 +256,22 @@ blr_status blr_qr_factor_batch(blr_matrix* hs, int32_t count, const blr_factor_o
 blr_status blr_apply_qt(blr_matrix h, int32_t trans, double* B, int64_t ldb,
                         int32_t nrhs, void* hip_stream);
 
+/* blr_apply_qt for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, result and state rules as blr_apply_qt, and the same
+ * kernels; it calls no hipMalloc, hipFree or allocating library routine.
+ * Its temporaries and launch descriptors live in one static device array of
+ * BLR_NOALLOC_SCRATCH_BYTES per GPU (held from the first call on that GPU
+ * until the process ends).  A call whose matrix and nrhs need more returns
+ * BLR_ERR_INVALID before enqueuing anything (the message states the bytes
+ * needed); the need grows with nrhs (about 64 b + p rc doubles per right-hand
+ * side) plus the launch descriptors (a few MiB at 128 x 64 tiles).  Every
+ * call on one GPU shares the array: calls on the same stream are ordered,
+ * calls that overlap on one GPU (other streams or threads) race. */
+#define BLR_NOALLOC_SCRATCH_BYTES (64LL * 1024 * 1024)
+blr_status blr_apply_qt_noalloc(blr_matrix h, int32_t trans, double* B, int64_t ldb,
+                                int32_t nrhs, void* hip_stream);
+
 /* Products with the stored BLR matrix, for residual and orthogonality
  * checks and refinement (eq. blr_matrix_def, eq. qr_fact):
  *   BLR_MATMUL_A   Y = A~ X     requires COMPRESSED, or a factor made with keep_a;

@@ -14,7 +14,9 @@ EXPORTED = [
     "blr_lstsq_solve", "blr_query", "blr_destroy", "blr_status_string", "blr_last_error",
     "blr_profile_enable", "blr_profile_read", "blr_matmul", "blr_morton_sort", "blr_rsolve",
     "blr_lstsq_adjoint", "blr_form_q", "blr_qr_factor_batch", "blr_lstsq_solve_batch",
+    "blr_apply_qt_noalloc",
 ]
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024   # BLR_NOALLOC_SCRATCH_BYTES
 SELFTEST = ["blr_selftest_gemm"]
 MATMUL = {"A": 0, "AT": 1, "R": 2}
 
@@ -78,6 +80,7 @@ def load() -> ctypes.CDLL:
     lib.blr_lstsq_solve_batch.argtypes = [P(c_void_p), c_int32, P(c_void_p), P(c_int64), P(c_void_p),
                                           P(c_int64), c_int32, c_int32, c_void_p]
     lib.blr_apply_qt.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_int32, c_void_p]
+    lib.blr_apply_qt_noalloc.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_int32, c_void_p]
     lib.blr_lstsq_solve.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int32, c_int32,
                                     c_void_p, c_void_p]
     lib.blr_matmul.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_void_p, c_int64, c_int32, c_void_p]

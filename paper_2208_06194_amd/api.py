@@ -255,6 +255,14 @@ class BLRMatrix:
         _check(L.load().blr_apply_qt(self._h, 1 if trans else 0, Bc.data_ptr(), m, nrhs, _stream(stream)))
         return Bc.t()
 
+    def apply_qt_noalloc(self, B: torch.Tensor, trans: bool = False, stream=None) -> torch.Tensor:
+        """apply_qt through blr_apply_qt_noalloc (no device allocation inside the
+        library; its temporaries live in the per-GPU static scratch)."""
+        Bc = _colmajor(B.to(torch.float64), copy=True)   # overwritten in place by the library
+        nrhs, m = Bc.shape
+        _check(L.load().blr_apply_qt_noalloc(self._h, 1 if trans else 0, Bc.data_ptr(), m, nrhs, _stream(stream)))
+        return Bc.t()
+
     def lstsq(self, B: torch.Tensor, with_resid: bool = False, max_refine: int = 0, stream=None):
         """X = argmin ||A X - B||_F for a (m, nrhs) device tensor; returns (n, nrhs).
         max_refine > 0 refines with FP64 residuals (the factor must keep A~)."""

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <cstdlib>
 #include <functional>
+#include <mutex>
 
 namespace {
 thread_local std::string g_last_error;
@@ -272,6 +273,22 @@ void Plan::upload(DevAlloc& a, HostKeep& keep, hipStream_t s) {
   d_tjobs = upload_array(tjobs, a, keep, s);
   d_lincs = upload_array(lincs, a, keep, s);
   d_frobs = upload_array(frobs, a, keep, s);
+}
+
+size_t Plan::upload_bytes() const {
+  size_t n = 0;
+  auto add = [&n](size_t bytes) {
+    if (bytes) n += (bytes + 255) & ~(size_t)255;
+  };
+  add(descs.size() * sizeof(GemmDesc));
+  add(segs.size() * sizeof(GemmSeg));
+  add(copies.size() * sizeof(CopyDesc));
+  add(rcs.size() * sizeof(RcDesc));
+  add(jobs.size() * sizeof(PanelJob));
+  add(tjobs.size() * sizeof(TrsmJob));
+  add(lincs.size() * sizeof(LincombDesc));
+  add(frobs.size() * sizeof(Frob2Desc));
+  return n;
 }
 
 void Plan::clear() { *this = Plan(); }
@@ -1777,9 +1794,8 @@ void run_batch_plans(std::vector<Plan>& plans, const std::vector<blr_matrix>& hv
 // B <- Q^T B or Q B for the block-column factor (Alg. 3): per step k,
 // W = sum_i Ytilde_ik^T B_i, W = T_k^T W (or T_k W), B_i -= Ytilde_ik W.
 void plan_apply_blockcol(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, int nrhs, int trans,
-                         double* Sbuf) {
+                         double* Sbuf, double* Wpart) {
   const int b = h->b, rc = h->rc, p = h->p, q = h->q;
-  double* Wpart = (double*)h->work.alloc((size_t)kApplySlices * b * std::max(nrhs, 1) * 8);
   const int K = h->steps_done;
   auto step = [&](int k) {
     double* Tk = h->T[(size_t)k * q + k];
@@ -1847,13 +1863,30 @@ void plan_apply_blockcol(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb,
     for (int k = K - 1; k >= 0; --k) step(k);
 }
 
-void plan_apply(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, int nrhs, int trans) {
+// Q^T B or Q B; the block-column form's temporaries come from a (the
+// handle's workspace by default).
+void plan_apply(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, int nrhs, int trans,
+                DevAlloc* a = nullptr) {
+  DevAlloc& al = a ? *a : h->work;
   if (h->variant == BLR_BLOCK_COLUMN) {
-    double* S = (double*)h->work.alloc((size_t)h->p * h->rc * std::max(nrhs, 1) * 8);
-    plan_apply_blockcol(h, P, w, B, ldb, nrhs, trans, S);
+    double* S = (double*)al.alloc((size_t)h->p * h->rc * std::max(nrhs, 1) * 8);
+    double* Wpart = (double*)al.alloc((size_t)kApplySlices * h->b * std::max(nrhs, 1) * 8);
+    plan_apply_blockcol(h, P, w, B, ldb, nrhs, trans, S, Wpart);
   } else {
     plan_apply_tiled(h, P, w, B, ldb, nrhs, trans);
   }
+}
+
+// The part of a Work that plan_apply uses: Wx, Wx2 (b x nrhs) and X[0]
+// (rc x nrhs), from a.
+Work make_apply_work(blr_matrix h, DevAlloc& a, int nrhs) {
+  Work w;
+  const size_t cols = (size_t)std::max(nrhs, 1);
+  w.Wx = (double*)a.alloc((size_t)h->b * cols * 8);
+  w.Wx2 = (double*)a.alloc((size_t)h->b * cols * 8);
+  w.Wg = nullptr;
+  w.X.push_back((double*)a.alloc((size_t)h->rc * cols * 8));
+  return w;
 }
 
 // Products with the stored matrix (eq. blr_matrix_def): A~ X, A~^T X (the
@@ -2660,6 +2693,76 @@ blr_status blr_apply_qt(blr_matrix h, int32_t trans, double* B, int64_t ldb, int
     Plan P;
     plan_apply(h, P, w, B, ldb, nrhs, trans);
     run_plan(h, P, s);
+    end_call(h, s);
+  });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Q^T B / Q B with no device allocation: the temporaries and the launch
+// descriptors of the call live in one static device array.  Every GPU the
+// library runs on holds its own copy until the process ends; its device
+// address comes from hipGetSymbolAddress once per device (the array's name
+// is only a host-side stand-in).  All calls on one GPU share it.
+static __device__ __align__(256) char scratch[BLR_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_dev[kMaxDevices] = {};
+
+char* scratch_for_current_device() {
+  int dev = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw Error(BLR_ERR_DEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    HIPCHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_dev[dev] = (char*)ptr;
+  }
+  return g_scratch_dev[dev];
+}
+
+// Bump allocation over the static array.  Offsets past the end are handed
+// out but never used: the caller checks the total before enqueuing anything.
+struct ScratchAlloc : DevAlloc {
+  char* base = nullptr;
+  size_t used = 0;
+  void* alloc(size_t n) override {
+    if (n == 0) n = 256;
+    n = (n + 255) & ~(size_t)255;
+    char* p = base + used;
+    used += n;
+    return p;
+  }
+};
+}  // namespace
+
+extern "C" {
+
+blr_status blr_apply_qt_noalloc(blr_matrix h, int32_t trans, double* B, int64_t ldb, int32_t nrhs,
+                                void* stream) {
+  if (!h || !B) return fail(BLR_ERR_INVALID, "NULL argument");
+  if (h->state != BLR_STATE_FACTORED) return fail(BLR_ERR_STATE, "matrix is not factored");
+  if (ldb < h->m || nrhs < 0 || (trans != 0 && trans != 1)) return fail(BLR_ERR_INVALID, "bad B shape or trans");
+  if (nrhs == 0) return BLR_OK;
+  hipStream_t s = as_stream(stream);
+  return run_guarded([&] {
+    ScratchAlloc a;
+    a.base = scratch_for_current_device();
+    Work w = make_apply_work(h, a, nrhs);
+    Plan P;
+    plan_apply(h, P, w, B, ldb, nrhs, trans, &a);
+    const size_t need = a.used + P.upload_bytes();
+    if (need > (size_t)BLR_NOALLOC_SCRATCH_BYTES)
+      throw Error(BLR_ERR_INVALID, "blr_apply_qt_noalloc needs " + std::to_string(need) +
+                                       " bytes of scratch for this matrix and nrhs; the static scratch holds " +
+                                       std::to_string((size_t)BLR_NOALLOC_SCRATCH_BYTES));
+    begin_call(h);   // this handle's earlier work has finished with its uploads
+    P.upload(a, h->keep, s);
+    execute(h, P, s);
     end_call(h, s);
   });
 }

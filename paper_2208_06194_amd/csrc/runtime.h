@@ -172,6 +172,9 @@ struct Plan {
   // copy the descriptor arrays to device memory from a, enqueued on s; the
   // host sources are copied into keep first
   void upload(DevAlloc& a, HostKeep& keep, hipStream_t s);
+  // device bytes upload() takes from an allocator that rounds each array up
+  // to 256 bytes
+  size_t upload_bytes() const;
   void clear();
 };
 
