@@ -16,8 +16,11 @@ For a BLR matrix the gradient is restricted to the stored tiles: a dense tile
 (i, j) gets Abar_ij; a low-rank tile U V^T gets dL/dU = Abar_ij V and
 dL/dV = Abar_ij^T U (the chain rule through A_ij = U V^T).
 
-Everything is dense float64 numpy; the solves use the explicit normal-matrix
-solve, which is fine at the small sizes the tests use."""
+Everything is dense float64 numpy.  solve="normal" takes z from the normal
+matrix A^T A (fine for small, well-conditioned inputs); solve="qr" takes x
+and z from a dense Householder QR of A (LAPACK), z = R^{-1} (R^{-T} xbar),
+whose error grows with kappa(A)^2 u instead of through the squared matrix
+being formed (the reference gradient at larger sizes)."""
 from __future__ import annotations
 
 import numpy as np
@@ -25,11 +28,19 @@ import numpy as np
 from .blrmat import BLR, DENSE
 
 
-def lstsq_adjoint(A: np.ndarray, B: np.ndarray, Xbar: np.ndarray):
+def lstsq_adjoint(A: np.ndarray, B: np.ndarray, Xbar: np.ndarray, solve: str = "normal"):
     """Dense adjoint: returns (X, Bbar, Abar) for X = argmin ||A X - B||
     column by column and the loss gradient Xbar = dL/dX."""
-    X = np.linalg.lstsq(A, B, rcond=None)[0]
-    Z = np.linalg.solve(A.T @ A, Xbar)
+    if solve == "qr":
+        import scipy.linalg as sl
+        Q, R = np.linalg.qr(A)
+        X = sl.solve_triangular(R, Q.T @ B)
+        Z = sl.solve_triangular(R, sl.solve_triangular(R, Xbar, trans="T"))
+    elif solve == "normal":
+        X = np.linalg.lstsq(A, B, rcond=None)[0]
+        Z = np.linalg.solve(A.T @ A, Xbar)
+    else:
+        raise ValueError(solve)
     Rs = B - A @ X
     Bbar = A @ Z
     Abar = Rs @ Z.T - Bbar @ X.T

@@ -294,6 +294,30 @@ __global__ __launch_bounds__(256) void k_gemm_skinny(const GemmDesc* __restrict_
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) const d2v gd2v;
 
+// Order of the output tiles of a fast launch (128 x 128 tiles).  Workgroups
+// are dispatched to the eight XCDs in turn (workgroup w on XCD w mod 8), and
+// each XCD has its own L2.  Workgroup w takes position
+//   L = (w mod 8) * T8 + w / 8   (w < 8 T8, T8 = floor(T / 8); the rest keep L = w)
+// of the launch's T tiles, so every XCD works through one contiguous eighth of
+// them: a product split into one descriptor per block column lands whole on
+// one XCD, and no operand slab is fetched by all eight.  Inside a descriptor
+// the tiles run in groups of 8 tile columns, row-major inside a group, so the
+// workgroups resident on an XCD at one time cover about 8 x 8 tiles and share
+// their A and B slabs in its L2.
+__device__ __forceinline__ int xcd_tile_order(int w, int T) {
+  constexpr int X = 8;
+  const int T8 = T / X;
+  return w < X * T8 ? (w % X) * T8 + w / X : w;
+}
+__device__ __forceinline__ void grouped_tile(int t, int tilesM, int tilesN, int* mt, int* nt) {
+  constexpr int GN = 8;
+  const int gsz = tilesM * GN;
+  const int g = t / gsz, v = t - g * gsz;
+  const int gw = min(GN, tilesN - g * GN);
+  *mt = v / gw;
+  *nt = g * GN + v % gw;
+}
+
 // Fast path for full 128 x 128 output tiles with one K segment (K a multiple
 // of 16, 16-byte aligned operands, no masked triangles; an upper triangular A
 // only prunes the K range).  Transposes are compile-time; global loads are
@@ -311,7 +335,7 @@ __device__ __forceinline__ void gemm_fast_body(const GemmDesc* __restrict__ desc
   __shared__ CT As[2][BK][BM + PAD];
   __shared__ CT Bs[2][BK][BN + PAD];
 
-  const int wg = blockIdx.x;
+  const int wg = xcd_tile_order(blockIdx.x, gridDim.x);
   int lo = 0, hi = ndesc - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -319,9 +343,10 @@ __device__ __forceinline__ void gemm_fast_body(const GemmDesc* __restrict__ desc
     else hi = mid - 1;
   }
   const GemmDesc d = descs[lo];
-  const int t = wg - d.tile_begin;
-  const int m0 = (t % d.tilesM) * BM;
-  const int n0 = (t / d.tilesM) * BN;
+  int mt, nt;
+  grouped_tile(wg - d.tile_begin, d.tilesM, (d.N + BN - 1) / BN, &mt, &nt);
+  const int m0 = mt * BM;
+  const int n0 = nt * BN;
   if ((d.flags & DESC_LOWER_ONLY) && m0 + BM <= n0) return;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;

@@ -331,10 +331,12 @@ def test_block_column_chain_and_tree_factors_agree():
     assert metrics.res(fc, At) <= 10 * eps and metrics.res(ft, At) <= 10 * eps
 
 
-def test_lstsq_adjoint_matches_finite_differences():
+@pytest.mark.parametrize("solve", ["normal", "qr"])
+def test_lstsq_adjoint_matches_finite_differences(solve):
     """The adjoint of x = argmin ||A x - b|| against central differences of
     the exact least-squares map, for b, a dense entry of A and, through a
-    low-rank tile A_ij = U V^T, entries of U and V.  L = <Xbar, X>."""
+    low-rank tile A_ij = U V^T, entries of U and V.  L = <Xbar, X>.  Both
+    ways of solving (normal matrix, dense QR) give it."""
     from oracle import adjoint, blrmat
     rng = np.random.default_rng(17)
     m, n, b, nrhs = 48, 24, 8, 2
@@ -348,7 +350,7 @@ def test_lstsq_adjoint_matches_finite_differences():
     A = blr.to_dense()
     B = rng.standard_normal((m, nrhs))
     Xbar = rng.standard_normal((n, nrhs))
-    X, Bbar, Abar = adjoint.lstsq_adjoint(A, B, Xbar)
+    X, Bbar, Abar = adjoint.lstsq_adjoint(A, B, Xbar, solve)
     g = adjoint.tile_gradients(blr, Abar)
     loss = lambda A_, B_: float(np.sum(Xbar * np.linalg.lstsq(A_, B_, rcond=None)[0]))
     h = 1e-6
@@ -369,7 +371,8 @@ def test_lstsq_adjoint_matches_finite_differences():
         assert np.isclose(fd, an, rtol=1e-6, atol=1e-9), (which, fd, an)
 
 
-def test_lstsq_adjoint_closed_form_square():
+@pytest.mark.parametrize("solve", ["normal", "qr"])
+def test_lstsq_adjoint_closed_form_square(solve):
     """Square nonsingular A: x = A^{-1} b, so bbar = A^{-T} xbar and
     Abar = -bbar x^T (the residual is zero)."""
     from oracle import adjoint
@@ -377,7 +380,7 @@ def test_lstsq_adjoint_closed_form_square():
     A = rng.standard_normal((12, 12)) + 12 * np.eye(12)
     B = rng.standard_normal((12, 2))
     Xbar = rng.standard_normal((12, 2))
-    X, Bbar, Abar = adjoint.lstsq_adjoint(A, B, Xbar)
+    X, Bbar, Abar = adjoint.lstsq_adjoint(A, B, Xbar, solve)
     assert np.allclose(Bbar, np.linalg.solve(A.T, Xbar))
     assert np.allclose(Abar, -Bbar @ X.T)
 
