@@ -12,6 +12,8 @@ Morton sorted, kernel evaluated on the device):
   c1  2048 x 1024,     2D -log(r+1e-3),  b = 128,  adjacent boxes dense, eps 1e-8, cap 16
   c2  32768 x 16384,   3D 1/(r+1e-3),    b = 256,  gap > diameter low-rank, eps 1e-8, cap 32
   c3  131072 x 65536,  3D 1/(r+1e-3),    b = 1024, gap > diameter low-rank, eps 1e-8, cap 50
+  cr  30000 x 15000,   3D 1/(r+1e-3),    b = 256,  every tile compressed, rank > b/2 dense (cap 128), eps 1e-8;
+      m and n are not multiples of b
   c4  64 matrices, m log-uniform in [4096, 32768], n = m/2, 3D 1/(r+1e-3), b = 256, eps 1e-8,
       cap 64, each with a 16-RHS least-squares solve: the plain form (one factorization after
       the other) against the batched form (blr_qr_factor_batch), in FP64 and in the mixed form
@@ -37,6 +39,10 @@ CONFIGS = {
     "c3": dict(m=131072, n=65536, b=1024, dim=3, kernel="inv_r", rule="dist_gt_diam", tol=1e-8, cap=50),
     # the differentiated least-squares workload: 65536x32768, b = 512, 32 right-hand sides
     "c5": dict(m=65536, n=32768, b=512, dim=3, kernel="inv_r", rule="dist_gt_diam", tol=1e-8, cap=32),
+    # compress-and-revert (non-geometric admissibility): every off-diagonal
+    # tile compressed, those whose eps-rank exceeds b/2 stored dense; m and n
+    # not multiples of b (ragged edge tiles, factored through the embedding)
+    "cr": dict(m=30000, n=15000, b=256, dim=3, kernel="inv_r", rule="weak", tol=1e-8, cap=128),
     # batched forms: 64 independent matrices, rows log-uniform in [4096, 32768]
     # (multiples of 512), n = m/2, each followed by a 16-RHS least-squares solve
     "c4": dict(kind="batch", count=64, m_lo=4096, m_hi=32768, b=256, dim=3, kernel="inv_r",
@@ -147,13 +153,14 @@ def accuracy_probes(G, probes, ax):
     Orth = ||(Q1^T Q1 - I) G||_F / (sqrt(s) sqrt(n)), s probes."""
     import torch
     inf = G.info()
-    m, n = inf["m"], inf["n"]
+    m, n, mp = inf["m"], inf["n"], inf["m_pad"]   # Q acts on the m_pad rows of a ragged matrix's embedding
     s = probes.shape[1]
     rg = G.matmul(probes, "R")
-    pad = torch.zeros((m, s), dtype=torch.float64, device=probes.device)
+    pad = torch.zeros((mp, s), dtype=torch.float64, device=probes.device)
     pad[:n] = rg
     qr = G.apply_qt(pad, trans=True)
-    res = float(torch.linalg.norm(qr - ax) / torch.linalg.norm(ax))
+    qr[:m] -= ax
+    res = float(torch.linalg.norm(qr) / torch.linalg.norm(ax))
     pad.zero_()
     pad[:n] = probes
     back = G.apply_qt(G.apply_qt(pad, trans=True))
@@ -252,10 +259,12 @@ def run(args, cfg, precision, tol, xd, yd, dev, phase, keep_a=False, rhs=None, x
             print(f"[bench] {precision}: Res~ {acc[0]:.2e} Orth {acc[1]:.2e}", file=sys.stderr, flush=True)
             # Q^T B and the least-squares solve with 16 right-hand sides (untimed by the metric)
             B16 = rhs if rhs is not None else torch.tensor(synth.rhs(args.seed + 23, cfg["m"], 16), device=dev)
+            B16p = torch.zeros((G.info()["m_pad"], B16.shape[1]), dtype=torch.float64, device=dev)
+            B16p[:cfg["m"]] = B16
             f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
             f0.record(stream)
-            G.apply_qt(B16)
+            G.apply_qt(B16p)
             f1.record(stream)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -275,7 +284,8 @@ def run(args, cfg, precision, tol, xd, yd, dev, phase, keep_a=False, rhs=None, x
                     solve["x_rel_err_vs_fp64_unrefined"] = float(torch.linalg.norm(x0 - x_ref)) / nr
             # HBM roofline of Q^T B: the reflectors are read twice (Y^T B, then
             # B -= Y W), counted as if every tile were dense
-            b, m, q = cfg["b"], cfg["m"], cfg["n"] // cfg["b"]
+            gi = G.info()
+            b, m, q = cfg["b"], gi["m_pad"], gi["n_pad"] // cfg["b"]
             ybytes = sum((m - k * b) * b * 8 for k in range(q))
             solve["apply_qt_bytes_dense_equiv"] = 2 * ybytes
             solve["apply_qt_gbs"] = 2 * ybytes / solve["apply_qt_s"] / 1e9

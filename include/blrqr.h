@@ -7,8 +7,17 @@
  * Low-Rank Matrices" (arXiv 2208.06194).
  *
  * Storage model.  A BLR matrix A~ (m x n, m >= n) has p x q tiles of size
- * b x b (p = m/b, q = n/b; b must divide m and n).  Tile (i,j) is dense or
- * low-rank U V^T with U orthonormal (Section 3.1, eq. blr_matrix_def).  The
+ * b x b (p = ceil(m/b), q = ceil(n/b)).  Tile (i,j) is dense or low-rank
+ * U V^T with U orthonormal (Section 3.1, eq. blr_matrix_def).  When b does
+ * not divide m or n (the rectangular edge blocks Section 3.1 allows), the
+ * last tile row and column hold fewer rows and columns of A~, and the
+ * library factors the embedding [A~ 0; 0 E] of m_pad x n_pad (blr_info):
+ * zero rows and columns fill the edge tiles to b x b, and E is an identity
+ * block in the padded columns on padded rows (with one more tile row when
+ * the padded rows are too few).  Its R is diag(R, -I) up to row signs, its
+ * thin factor is [Q1; 0], and its least-squares solution for [b; 0] is
+ * [x; 0]: the solve, products and R solves take and return the caller's m-
+ * and n-row blocks; Q^T B (blr_apply_qt) acts on m_pad rows.  The
  * handle owns every device buffer (tiles, reflectors, T factors, workspace).
  * Device pointers passed in are borrowed until the work enqueued on the
  * given stream completes; the library copies what it keeps.  Calls on one
@@ -39,7 +48,7 @@ extern "C" {
 
 typedef enum blr_status {
   BLR_OK = 0,
-  BLR_ERR_INVALID = 1,   /* bad argument (null, m < n, b does not divide m or n, tol <= 0, ...) */
+  BLR_ERR_INVALID = 1,   /* bad argument (null, m < n, tol <= 0, ...) */
   BLR_ERR_STATE = 2,     /* call not valid in the handle's state (e.g. factor twice) */
   BLR_ERR_OOM = 3,       /* device allocation failed */
   BLR_ERR_DEVICE = 4,    /* HIP runtime or kernel error (text in blr_last_error) */
@@ -123,10 +132,23 @@ typedef struct blr_info {
   double max_dropped_rel;         /* largest dropped relative singular-value tail */
   double flops_factor;            /* algorithmic flops of the last factorization */
   int64_t kernel_launches;        /* kernels enqueued by the last factorization */
+  /* The matrix the kernels factor: m_pad x n_pad in p_pad x q tiles.  It
+   * equals m x n when b divides both; otherwise it is the embedding
+   * [A 0; 0 E] (zero rows and columns up to whole tiles, E an identity block
+   * in the padded columns on padded rows, one more tile row if the padded
+   * rows are too few), whose R is diag(R_A, -I) and whose least-squares
+   * solution for [b; 0] is [x; 0]. */
+  int64_t m_pad, n_pad;
+  int32_t p_pad;
+  int32_t pad_;
 } blr_info;
 
 /* Host copies of the tile data (blr_import / blr_export).  Every array is
- * caller-owned and sized for all p*q tiles, tile t = i*q + j:
+ * caller-owned and sized for all p*q tiles of A~ (p = ceil(m/b) tile rows:
+ * a tile row that only the embedding adds is neither read nor written),
+ * tile t = i*q + j; an edge tile holds A~'s entries in its leading rows and
+ * columns (the rest is ignored on import, and holds the embedding's
+ * entries on export):
  *   fmt   [p*q]          0 = dense, 1 = low-rank
  *   rank  [p*q]          rank of low-rank tiles (ignored for dense tiles)
  *   dense [p*q*b*b]      tile t at t*b*b, column-major b x b
@@ -158,7 +180,8 @@ typedef struct blr_tiles_host {
  * stored dense).  Needs m*n*8 bytes of temporary device memory, stream-ordered
  * (allocated and freed on hip_stream).  *q_out is a new handle in state
  * COMPRESSED (its products and export work as for A~).  Synchronises the
- * stream.  Errors: BLR_ERR_STATE if not (fully) factored. */
+ * stream.  Errors: BLR_ERR_STATE if not (fully) factored; BLR_ERR_INVALID
+ * when b does not divide m or n. */
 blr_status blr_form_q(blr_matrix h, void* hip_stream, blr_matrix* q_out);
 
 /* X <- R^{-1} X (trans = 0) or X <- R^{-T} X (trans = 1) with the R factor of
@@ -182,7 +205,8 @@ blr_status blr_rsolve(blr_matrix h, int32_t trans, double* X, int64_t ldx, int32
  *       (i*q + j)*b*rc (columns past the rank are zero).
  * All pointers are device memory; dD, dU and dV may be NULL to skip, and
  * only the slots of tiles of the matching format are written.  Asynchronous
- * on hip_stream.  Errors: BLR_ERR_STATE if not factored or A~ was not kept. */
+ * on hip_stream.  Errors: BLR_ERR_STATE if not factored or A~ was not kept;
+ * BLR_ERR_INVALID when b does not divide m or n. */
 blr_status blr_lstsq_adjoint(blr_matrix h, const double* B, int64_t ldb, const double* X, int64_t ldx,
                              const double* Xbar, int64_t ldxb, int32_t nrhs, double* Bbar, int64_t ldbb,
                              double* dD, double* dU, double* dV, void* hip_stream);
@@ -251,8 +275,11 @@ blr_status blr_qr_factor_batch(blr_matrix* hs, int32_t count, const blr_factor_o
                                void* hip_stream);
 
 /* B <- Q^T B (trans = 0) or B <- Q B (trans = 1), replaying the stored
- * reflectors (Alg. 3 / Alg. 5).  B: device, column-major m x nrhs, ldb >= m,
- * overwritten.  Requires FACTORED.  Asynchronous. */
+ * reflectors (Alg. 3 / Alg. 5).  B: device, column-major m_pad x nrhs
+ * (blr_info.m_pad, which is m when b divides m and n), ldb >= m_pad,
+ * overwritten; for a ragged matrix rows m.. of B are the embedding's
+ * (zero for a block of R^m, whose leading n rows of Q^T B are then Q1^T B).
+ * Requires FACTORED.  Asynchronous. */
 blr_status blr_apply_qt(blr_matrix h, int32_t trans, double* B, int64_t ldb,
                         int32_t nrhs, void* hip_stream);
 

@@ -52,7 +52,8 @@ class Info(ctypes.Structure):
                 ("n_dense", c_int64), ("n_lowrank", c_int64), ("n_fill_in", c_int64),
                 ("device_bytes", c_int64), ("compress_overflow", c_int64),
                 ("factor_overflow", c_int64), ("max_dropped_rel", c_double),
-                ("flops_factor", c_double), ("kernel_launches", c_int64)]
+                ("flops_factor", c_double), ("kernel_launches", c_int64),
+                ("m_pad", c_int64), ("n_pad", c_int64), ("p_pad", c_int32), ("pad_", c_int32)]
 
 
 class TilesHost(ctypes.Structure):

@@ -19,6 +19,10 @@ struct TileFillParams {
   int dim;
   int kernel;           // 0 log2d, 1 inv_r
   double reg;
+  // rows mu and columns nu of the matrix itself; the tiles cover the
+  // embedding [A 0; 0 E] (E: identity rows m..m+pc-1 in the padded columns
+  // n..n+pc-1, zero elsewhere)
+  int64_t mu, nu;
 };
 struct Frob2Desc {
   const double* M;
@@ -28,6 +32,7 @@ struct Frob2Desc {
 };
 struct DiagDesc {
   const double* R;      // diagonal tile, b x b, ld b
+  int ncols;            // columns taken into account (the rest are padding)
 };
 
 hipError_t launch_fill_tiles(const TileFillDesc* d, int n, const TileFillParams& p, hipStream_t s);

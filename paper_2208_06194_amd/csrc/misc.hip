@@ -15,7 +15,9 @@ __global__ void k_fill_tiles(const TileFillDesc* __restrict__ d, TileFillParams 
     const int r = (int)(e % b), c = (int)(e / b);
     const int64_t gi = (int64_t)D.ti * b + r, gj = (int64_t)D.tj * b + c;
     double v;
-    if (P.src_dense) {
+    if (gi >= P.mu || gj >= P.nu) {
+      v = (gi >= P.mu && gj >= P.nu && gi - P.mu == gj - P.nu) ? 1.0 : 0.0;
+    } else if (P.src_dense) {
       v = P.A[gi + gj * P.lda];
     } else {
       double d2 = 0.0;
@@ -34,9 +36,10 @@ __global__ void k_boxes(const double* __restrict__ pts, int npts, int dim, int b
                         double* hi) {
   __shared__ double smn[256], smx[256];
   const int cl = blockIdx.x;
+  const int cnt = min(b, npts - cl * b);   // the last cluster may hold fewer points
   for (int k = 0; k < dim; ++k) {
     double mn = 1e300, mx = -1e300;
-    for (int i = threadIdx.x; i < b; i += blockDim.x) {
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
       const double v = pts[((int64_t)cl * b + i) * dim + k];
       mn = fmin(mn, v);
       mx = fmax(mx, v);
@@ -57,7 +60,6 @@ __global__ void k_boxes(const double* __restrict__ pts, int npts, int dim, int b
     }
     __syncthreads();
   }
-  (void)npts;
 }
 
 __device__ __forceinline__ unsigned long long sm_mix(unsigned long long z) {
@@ -274,7 +276,7 @@ __global__ void k_diag_absmin(const DiagDesc* __restrict__ d, int b, double* out
   double mn = 1e300, s = 0.0;
   for (int64_t e = threadIdx.x; e < (int64_t)b * b; e += blockDim.x) {
     const int r = (int)(e % b), c = (int)(e / b);
-    if (r <= c) {
+    if (r <= c && c < D.ncols) {
       const double v = D.R[r + (int64_t)c * b];
       s += v * v;
       if (r == c) mn = fmin(mn, fabs(v));
@@ -304,7 +306,7 @@ hipError_t launch_fill_tiles(const TileFillDesc* d, int n, const TileFillParams&
 
 hipError_t launch_boxes(const double* pts, int npts, int dim, int b, double* lo, double* hi,
                         hipStream_t s) {
-  const int ncl = npts / b;
+  const int ncl = (npts + b - 1) / b;
   if (ncl <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_boxes, dim3(ncl), dim3(256), 0, s, pts, npts, dim, b, lo, hi);
   return hipGetLastError();

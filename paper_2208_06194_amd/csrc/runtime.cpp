@@ -354,6 +354,16 @@ T* upload_vec(blr_matrix h, const std::vector<T>& v, hipStream_t s) {
   return d;
 }
 
+// The caller's rows (rows x nrhs, ld ldx) copied into a workspace block of
+// prows rows whose remaining rows are zero: a block of the caller's size
+// extended to a ragged matrix's embedding.  Enqueued on s.
+double* pad_rows(blr_matrix h, const double* X, int64_t ldx, int64_t rows, int64_t prows, int nrhs, hipStream_t s) {
+  double* P = (double*)h->work.alloc((size_t)prows * nrhs * 8);
+  HIPCHECK(hipMemsetAsync(P, 0, (size_t)prows * nrhs * 8, s));
+  HIPCHECK(hipMemcpy2DAsync(P, prows * 8, X, ldx * 8, rows * 8, nrhs, hipMemcpyDeviceToDevice, s));
+  return P;
+}
+
 void ensure_streams(blr_matrix h) {
   while ((int)h->streams.size() < kStreams) {
     hipStream_t st;
@@ -2052,7 +2062,10 @@ SingCheck sing_launch(blr_matrix h, hipStream_t s) {
   const int b = h->b, q = h->q, rc = h->rc;
   SingCheck c;
   std::vector<DiagDesc> dd(q);
-  for (int k = 0; k < q; ++k) dd[k].R = h->t(k, k).D;
+  for (int k = 0; k < q; ++k) {
+    dd[k].R = h->t(k, k).D;
+    dd[k].ncols = (int)std::min<int64_t>(b, h->nu - (int64_t)k * b);   // the embedding's columns excluded
+  }
   DiagDesc* ddd = upload_vec(h, dd, s);
   double* out = (double*)h->work.alloc((size_t)2 * q * 8);
   HIPCHECK(launch_diag_absmin(ddd, q, b, out, s));
@@ -2082,7 +2095,7 @@ bool sing_ok(blr_matrix h, const SingCheck& c) {
     r2 += c.ho[2 * k + 1];
   }
   for (double v : c.hf) r2 += v;
-  const double thr = (double)h->n * 2.220446049250313e-16 * std::sqrt(r2);
+  const double thr = (double)h->nu * 2.220446049250313e-16 * std::sqrt(r2);
   return mn > thr;
 }
 
@@ -2218,13 +2231,12 @@ blr_status validate_opts(const blr_compress_opts* o) {
   if (o->m < 1 || o->n < 1 || o->m < o->n) return fail(BLR_ERR_INVALID, "need m >= n >= 1");
   if (o->tile < 16 || o->tile > 1024 || o->tile % 16)
     return fail(BLR_ERR_INVALID, "tile must be a multiple of 16 in [16, 1024]");
-  if (o->m % o->tile || o->n % o->tile) return fail(BLR_ERR_INVALID, "tile must divide m and n");
   if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return fail(BLR_ERR_INVALID, "tol must be > 0");
   if (o->max_rank < 1 || o->max_rank > o->tile || o->max_rank > 128)
     return fail(BLR_ERR_INVALID, "max_rank must be in [1, min(tile, 128)]");
   if (o->overflow != BLR_OVERFLOW_DENSE && o->overflow != BLR_OVERFLOW_TRUNCATE)
     return fail(BLR_ERR_INVALID, "bad overflow policy");
-  if (o->m / o->tile > 1 << 15 || o->n / o->tile > 1 << 15) return fail(BLR_ERR_INVALID, "too many tiles");
+  if (o->m / o->tile + 2 > 1 << 15 || o->n / o->tile + 1 > 1 << 15) return fail(BLR_ERR_INVALID, "too many tiles");
   return BLR_OK;
 }
 
@@ -2306,11 +2318,18 @@ int prepare_factor(blr_matrix h, const blr_factor_opts* o, hipStream_t s, Plan& 
 
 blr_matrix new_handle(const blr_compress_opts* o) {
   blr_matrix h = new blr_matrix_s();
-  h->m = o->m;
-  h->n = o->n;
-  h->b = o->tile;
-  h->p = (int)(o->m / o->tile);
-  h->q = (int)(o->n / o->tile);
+  const int64_t b = o->tile;
+  h->mu = o->m;
+  h->nu = o->n;
+  // the embedding: whole tiles, with room below A for the identity block of
+  // the padded columns (one more tile row when the padded rows are too few)
+  h->n = (o->n + b - 1) / b * b;
+  h->m = (o->m + b - 1) / b * b;
+  h->pu = (int)(h->m / b);
+  if (h->m - o->m < h->n - o->n) h->m += b;
+  h->b = (int)b;
+  h->p = (int)(h->m / b);
+  h->q = (int)(h->n / b);
   h->cap = o->max_rank;
   h->rc = std::min(round_up(o->max_rank, 16), o->tile);
   h->tol = o->tol;
@@ -2367,33 +2386,35 @@ blr_status blr_compress(const blr_source* src, const blr_compress_opts* o, void*
     int* flag = (int*)h->work.alloc(sizeof(int));
     HIPCHECK(hipMemsetAsync(flag, 0, sizeof(int), s));
     if (kern) {
-      HIPCHECK(launch_nonfinite(src->x, h->m * src->dim, 1, h->m * src->dim, flag, s));
-      HIPCHECK(launch_nonfinite(src->y, h->n * src->dim, 1, h->n * src->dim, flag, s));
+      HIPCHECK(launch_nonfinite(src->x, h->mu * src->dim, 1, h->mu * src->dim, flag, s));
+      HIPCHECK(launch_nonfinite(src->y, h->nu * src->dim, 1, h->nu * src->dim, flag, s));
     } else {
-      HIPCHECK(launch_nonfinite(src->A, h->m, h->n, src->lda, flag, s));
+      HIPCHECK(launch_nonfinite(src->A, h->mu, h->nu, src->lda, flag, s));
     }
     int hflag = 0;
     HIPCHECK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
     if (hflag) throw Error(BLR_ERR_NONFINITE, "input contains NaN or Inf");
-    // admissibility mask (true = low-rank)
+    // admissibility mask (true = low-rank) over the tile rows of A; a tile
+    // row that only the embedding adds is zero outside its identity entries
     std::vector<int8_t> lr((size_t)p * q, 0);
+    const int pu = h->pu;
     if (src->admissibility == BLR_ADM_WEAK) {
       std::fill(lr.begin(), lr.end(), 1);
     } else if (src->admissibility == BLR_ADM_MASK) {
-      for (size_t t = 0; t < lr.size(); ++t) lr[t] = src->mask[t] ? 1 : 0;
+      for (size_t t = 0; t < (size_t)pu * q; ++t) lr[t] = src->mask[t] ? 1 : 0;
     } else {
       const int d = src->dim;
       double* bx = (double*)h->work.alloc((size_t)4 * (p + q) * d * 8);
       double *rlo = bx, *rhi = bx + (size_t)p * d, *clo = bx + (size_t)2 * p * d, *chi = clo + (size_t)q * d;
-      HIPCHECK(launch_boxes(src->x, (int)h->m, d, b, rlo, rhi, s));
-      HIPCHECK(launch_boxes(src->y, (int)h->n, d, b, clo, chi, s));
+      HIPCHECK(launch_boxes(src->x, (int)h->mu, d, b, rlo, rhi, s));
+      HIPCHECK(launch_boxes(src->y, (int)h->nu, d, b, clo, chi, s));
       std::vector<double> hb((size_t)2 * (p + q) * d);
       HIPCHECK(hipMemcpyAsync(hb.data(), bx, hb.size() * 8, hipMemcpyDeviceToHost, s));
       HIPCHECK(hipStreamSynchronize(s));
       const double *Rlo = hb.data(), *Rhi = Rlo + (size_t)p * d, *Clo = Rlo + (size_t)2 * p * d,
                    *Chi = Clo + (size_t)q * d;
-      for (int i = 0; i < p; ++i)
+      for (int i = 0; i < pu; ++i)
         for (int j = 0; j < q; ++j) {
           double g2 = 0.0, dr2 = 0.0, dc2 = 0.0;
           for (int c = 0; c < d; ++c) {
@@ -2409,6 +2430,11 @@ blr_status blr_compress(const blr_source* src, const blr_compress_opts* o, void*
           lr[(size_t)i * q + j] = low ? 1 : 0;
         }
     }
+    for (int i = pu; i < p; ++i)
+      for (int j = 0; j < q; ++j) lr[(size_t)i * q + j] = 1;
+    for (int i = 0; i < p; ++i)
+      for (int j = 0; j < q; ++j)
+        if (h->has_identity(i, j)) lr[(size_t)i * q + j] = 0;
     for (int k = 0; k < std::min(p, q); ++k) lr[(size_t)k * q + k] = 0;
     std::vector<int> cand;
     for (size_t t = 0; t < lr.size(); ++t)
@@ -2424,6 +2450,8 @@ blr_status blr_compress(const blr_source* src, const blr_compress_opts* o, void*
     fp.dim = src->dim;
     fp.kernel = src->kernel;
     fp.reg = src->reg;
+    fp.mu = h->mu;
+    fp.nu = h->nu;
     std::vector<int> status(lr.size(), 0);
     if (!cand.empty()) {
       const int l = std::min(b, rc + 16);
@@ -2544,47 +2572,87 @@ blr_status blr_import(const blr_compress_opts* o, const blr_tiles_host* t, void*
   hipStream_t s = as_stream(stream);
   st = run_guarded([&] {
     alloc_common(h);
-    const int b = h->b, rc = h->rc;
-    const size_t nt = (size_t)h->p * h->q;
+    const int b = h->b, rc = h->rc, q = h->q;
+    const size_t nt = (size_t)h->p * q;
+    const size_t ntu = (size_t)h->pu * q;   // tiles the caller supplies
+    // formats: the caller's for its tiles (a tile holding identity entries of
+    // the embedding is stored dense); the added tile row is zero (rank 0)
+    // outside its identity entries
+    std::vector<int8_t> fmt(nt, LOWRANK);
     std::vector<int> dn, lo;
     for (size_t i = 0; i < nt; ++i) {
-      const int r = t->rank[i];
-      if (t->fmt[i] == LOWRANK && (r < 0 || r > h->cap)) throw Error(BLR_ERR_INVALID, "rank out of range");
-      if (t->fmt[i] == LOWRANK && (i / h->q) == (i % h->q)) throw Error(BLR_ERR_INVALID, "diagonal tiles must be dense");
-      (t->fmt[i] == LOWRANK ? lo : dn).push_back((int)i);
+      const int ti = (int)(i / q), tj = (int)(i % q);
+      if (i < ntu) {
+        const int r = t->rank[i];
+        if (t->fmt[i] == LOWRANK && (r < 0 || r > h->cap)) throw Error(BLR_ERR_INVALID, "rank out of range");
+        if (t->fmt[i] == LOWRANK && ti == tj) throw Error(BLR_ERR_INVALID, "diagonal tiles must be dense");
+        fmt[i] = t->fmt[i] == LOWRANK ? LOWRANK : DENSE;
+      }
+      if (h->has_identity(ti, tj) || ti == tj) fmt[i] = DENSE;
+      (fmt[i] == LOWRANK ? lo : dn).push_back((int)i);
     }
-    if (!lo.empty() && (!t->U || !t->V)) throw Error(BLR_ERR_INVALID, "U and V needed for low-rank tiles");
-    if (!dn.empty() && !t->dense) throw Error(BLR_ERR_INVALID, "dense tiles needed");
+    bool any_lr_in = false, any_dense_in = false;
+    for (size_t i = 0; i < ntu; ++i) (t->fmt[i] == LOWRANK ? any_lr_in : any_dense_in) = true;
+    if (any_lr_in && (!t->U || !t->V)) throw Error(BLR_ERR_INVALID, "U and V needed for low-rank tiles");
+    if (any_dense_in && !t->dense) throw Error(BLR_ERR_INVALID, "dense tiles needed");
     alloc_dense(h, dn);
     alloc_lowrank(h, lo);
+    // entries of tile (ti, tj) that belong to A (the rest is the embedding's)
+    auto rows_in = [&](int ti) { return (int)std::max<int64_t>(0, std::min<int64_t>(b, h->mu - (int64_t)ti * b)); };
+    auto cols_in = [&](int tj) { return (int)std::max<int64_t>(0, std::min<int64_t>(b, h->nu - (int64_t)tj * b)); };
+    std::vector<double> Db((size_t)b * b);
     for (int i : dn) {
-      h->tiles[i].fmt = DENSE;
-      const double* src = t->dense + (size_t)i * b * b;
-      for (size_t e = 0; e < (size_t)b * b; ++e)
-        if (!std::isfinite(src[e])) throw Error(BLR_ERR_NONFINITE, "non-finite dense tile");
-      HIPCHECK(hipMemcpy(h->tiles[i].D, src, (size_t)b * b * 8, hipMemcpyHostToDevice));
+      Tile& T = h->tiles[i];
+      T.fmt = DENSE;
+      const int ti = i / q, tj = i % q, ri = rows_in(ti), cj = cols_in(tj);
+      std::fill(Db.begin(), Db.end(), 0.0);
+      if ((size_t)i < ntu && t->fmt[i] != LOWRANK) {
+        const double* src = t->dense + (size_t)i * b * b;
+        for (int c = 0; c < cj; ++c)
+          for (int r = 0; r < ri; ++r) Db[r + (size_t)c * b] = src[r + (size_t)c * b];
+      } else if ((size_t)i < ntu) {
+        // a supplied low-rank tile that the embedding stores dense
+        const int rk = t->rank[i];
+        const double* U = t->U + (size_t)i * b * rc;
+        const double* V = t->V + (size_t)i * b * rc;
+        for (int c = 0; c < cj; ++c)
+          for (int r = 0; r < ri; ++r) {
+            double v = 0.0;
+            for (int l = 0; l < rk; ++l) v += U[r + (size_t)l * b] * V[c + (size_t)l * b];
+            Db[r + (size_t)c * b] = v;
+          }
+      }
+      for (int64_t g = std::max<int64_t>(h->mu, (int64_t)ti * b); g < std::min<int64_t>(h->mu + (h->n - h->nu), (int64_t)(ti + 1) * b); ++g) {
+        const int64_t gc = h->nu + (g - h->mu);
+        if (gc >= (int64_t)tj * b && gc < (int64_t)(tj + 1) * b) Db[(g - (int64_t)ti * b) + (size_t)(gc - (int64_t)tj * b) * b] = 1.0;
+      }
+      for (double v : Db)
+        if (!std::isfinite(v)) throw Error(BLR_ERR_NONFINITE, "non-finite dense tile");
+      HIPCHECK(hipMemcpy(T.D, Db.data(), (size_t)b * b * 8, hipMemcpyHostToDevice));
     }
     std::vector<double> Ub((size_t)b * rc), Vtb((size_t)rc * b);
     std::vector<int> ranks(nt, 0);
     for (int i : lo) {
-      h->tiles[i].fmt = LOWRANK;
-      const int r = t->rank[i];
-      ranks[i] = r;
+      Tile& T = h->tiles[i];
+      T.fmt = LOWRANK;
       std::fill(Ub.begin(), Ub.end(), 0.0);
       std::fill(Vtb.begin(), Vtb.end(), 0.0);
-      const double* U = t->U + (size_t)i * b * rc;
-      const double* V = t->V + (size_t)i * b * rc;
-      for (int l = 0; l < r; ++l)
-        for (int e = 0; e < b; ++e) {
-          Ub[e + (size_t)l * b] = U[e + (size_t)l * b];
-          Vtb[l + (size_t)e * rc] = V[e + (size_t)l * b];
+      if ((size_t)i < ntu) {
+        const int r = t->rank[i], ti = i / q, tj = i % q, ri = rows_in(ti), cj = cols_in(tj);
+        ranks[i] = r;
+        const double* U = t->U + (size_t)i * b * rc;
+        const double* V = t->V + (size_t)i * b * rc;
+        for (int l = 0; l < r; ++l) {
+          for (int e = 0; e < ri; ++e) Ub[e + (size_t)l * b] = U[e + (size_t)l * b];
+          for (int e = 0; e < cj; ++e) Vtb[l + (size_t)e * rc] = V[e + (size_t)l * b];
         }
+      }
       for (double v : Ub)
         if (!std::isfinite(v)) throw Error(BLR_ERR_NONFINITE, "non-finite U");
       for (double v : Vtb)
         if (!std::isfinite(v)) throw Error(BLR_ERR_NONFINITE, "non-finite V");
-      HIPCHECK(hipMemcpy(h->tiles[i].U, Ub.data(), Ub.size() * 8, hipMemcpyHostToDevice));
-      HIPCHECK(hipMemcpy(h->tiles[i].Vt, Vtb.data(), Vtb.size() * 8, hipMemcpyHostToDevice));
+      HIPCHECK(hipMemcpy(T.U, Ub.data(), Ub.size() * 8, hipMemcpyHostToDevice));
+      HIPCHECK(hipMemcpy(T.Vt, Vtb.data(), Vtb.size() * 8, hipMemcpyHostToDevice));
     }
     HIPCHECK(hipMemcpy(h->d_rank, ranks.data(), nt * sizeof(int), hipMemcpyHostToDevice));
     (void)s;
@@ -2602,7 +2670,7 @@ blr_status blr_export(blr_matrix h, blr_tiles_host* t) {
   return run_guarded([&] {
     wait_idle(h);
     const int b = h->b, rc = h->rc, q = h->q;
-    const size_t nt = (size_t)h->p * h->q;
+    const size_t nt = (size_t)h->pu * h->q;   // the tile rows that hold rows of A
     std::vector<int> ranks(nt);
     HIPCHECK(hipMemcpy(ranks.data(), h->d_rank, nt * sizeof(int), hipMemcpyDeviceToHost));
     std::vector<double> tmp((size_t)b * std::max(b, rc));
@@ -2772,7 +2840,7 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
   if (!h || !B || !X) return fail(BLR_ERR_INVALID, "NULL argument");
   if (h->state != BLR_STATE_FACTORED) return fail(BLR_ERR_STATE, "matrix is not factored");
   if (h->steps_done != h->q) return fail(BLR_ERR_STATE, "factorization is incomplete");
-  if (ldb < h->m || ldx < h->n || nrhs < 0) return fail(BLR_ERR_INVALID, "bad B or X shape");
+  if (ldb < h->mu || ldx < h->nu || nrhs < 0) return fail(BLR_ERR_INVALID, "bad B or X shape");
   if (max_refine < 0) return fail(BLR_ERR_INVALID, "max_refine must be >= 0");
   if (max_refine > 0 && h->acopy.empty())
     return fail(BLR_ERR_STATE, "refinement needs the copy of A~ kept by a factor with keep_a");
@@ -2786,6 +2854,18 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
       HIPCHECK(hipStreamSynchronize(s));
       if (!sing_ok(h, sc)) throw Error(BLR_ERR_SINGULAR, "R is numerically singular");
       reset_work_after_sync(h);
+    }
+    // a ragged matrix solves its embedding for [B; 0]; X is the leading rows
+    // of the embedding's solution
+    const double* Bw = B;
+    int64_t ldbw = ldb;
+    double* Xw = X;
+    int64_t ldxw = ldx;
+    if (h->ragged()) {
+      Bw = pad_rows(h, B, ldb, h->mu, h->m, nrhs, s);
+      ldbw = h->m;
+      Xw = (double*)h->work.alloc((size_t)h->n * nrhs * 8);
+      ldxw = h->n;
     }
     Work w = make_work(h, nrhs);
     auto apply = [&](double* C, int trans) {
@@ -2802,11 +2882,11 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
     };
     // Q^T B, then X = R^{-1} (Q^T B)[0:n]
     double* C = (double*)h->work.alloc((size_t)m * nrhs * 8);
-    HIPCHECK(hipMemcpy2DAsync(C, m * 8, B, ldb * 8, m * 8, nrhs, hipMemcpyDeviceToDevice, s));
+    HIPCHECK(hipMemcpy2DAsync(C, m * 8, Bw, ldbw * 8, m * 8, nrhs, hipMemcpyDeviceToDevice, s));
     apply(C, 0);
     if (resid_norms && max_refine == 0) frob2(C + n, m, m - n, resid_norms);
-    HIPCHECK(hipMemcpy2DAsync(X, ldx * 8, C, m * 8, n * 8, nrhs, hipMemcpyDeviceToDevice, s));
-    run_rsolve(h, X, ldx, nrhs, 0, s);
+    HIPCHECK(hipMemcpy2DAsync(Xw, ldxw * 8, C, m * 8, n * 8, nrhs, hipMemcpyDeviceToDevice, s));
+    run_rsolve(h, Xw, ldxw, nrhs, 0, s);
     if (max_refine > 0) {
       // iterative refinement of [I A~; A~^T 0][r; x] = [b; 0] with FP64 residuals
       double* r = (double*)h->work.alloc((size_t)m * nrhs * 8);     // residual b - A~ x
@@ -2824,11 +2904,11 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
       for (int it = 0; it < max_refine; ++it) {
         {  // f = b - r - A~ x,  g = -A~^T r
           Plan P;
-          plan_matmul(h, P, BLR_MATMUL_A, X, ldx, f, m, nrhs);
+          plan_matmul(h, P, BLR_MATMUL_A, Xw, ldxw, f, m, nrhs);
           plan_matmul(h, P, BLR_MATMUL_AT, r, m, g, n, nrhs);
           run_plan(h, P, s);
         }
-        HIPCHECK(launch_lincomb(f, m, B, ldb, r, m, f, m, 1.0, -1.0, -1.0, (int)m, nrhs, s));
+        HIPCHECK(launch_lincomb(f, m, Bw, ldbw, r, m, f, m, 1.0, -1.0, -1.0, (int)m, nrhs, s));
         // d = Q^T f (in f);  h = R^{-T} g with g = -A~^T r (in g)
         apply(f, 0);
         HIPCHECK(launch_lincomb(g, n, g, n, nullptr, 0, nullptr, 0, -1.0, 0.0, 0.0, (int)n, nrhs, s));
@@ -2842,14 +2922,14 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
         run_rsolve(h, f, m, nrhs, 0, s);
         // ||dx|| and ||x|| decide which columns take the step
         frob2(f, m, n, nrm);
-        frob2(X, ldx, n, nrm + nrhs);
+        frob2(Xw, ldxw, n, nrm + nrhs);
         HIPCHECK(hipMemcpyAsync(hn.data(), nrm, 2 * nrhs * 8, hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
         const bool done = refine_decide(hn, prev, active, take, nrhs, u);
         // x += dx, r += dr on the columns that take it
         for (auto [c0, c1] : take_runs(take)) {
           const int nc = c1 - c0;
-          HIPCHECK(launch_lincomb(X + c0 * ldx, ldx, X + c0 * ldx, ldx, f + c0 * m, m, nullptr, 0, 1.0, 1.0, 0.0,
+          HIPCHECK(launch_lincomb(Xw + c0 * ldxw, ldxw, Xw + c0 * ldxw, ldxw, f + c0 * m, m, nullptr, 0, 1.0, 1.0, 0.0,
                                   (int)n, nc, s));
           HIPCHECK(launch_lincomb(r + c0 * m, m, r + c0 * m, m, dr + c0 * m, m, nullptr, 0, 1.0, 1.0, 0.0, (int)m,
                                   nc, s));
@@ -2858,6 +2938,7 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
       }
       if (resid_norms) frob2(r, m, m, resid_norms);
     }
+    if (Xw != X) HIPCHECK(hipMemcpy2DAsync(X, ldx * 8, Xw, ldxw * 8, h->nu * 8, nrhs, hipMemcpyDeviceToDevice, s));
     end_call(h, s);
     HIPCHECK(hipStreamSynchronize(s));
   });
@@ -2876,7 +2957,7 @@ blr_status blr_lstsq_solve_batch(blr_matrix* hs, int32_t count, const double* co
       if (v[j] == h) return fail(BLR_ERR_INVALID, "a handle appears twice in the batch");
     if (h->state != BLR_STATE_FACTORED || h->steps_done != h->q)
       return fail(BLR_ERR_STATE, "a matrix of the batch is not (fully) factored");
-    if (ldb[i] < h->m || ldx[i] < h->n) return fail(BLR_ERR_INVALID, "bad B or X shape");
+    if (ldb[i] < h->mu || ldx[i] < h->nu) return fail(BLR_ERR_INVALID, "bad B or X shape");
     if (max_refine > 0 && h->acopy.empty())
       return fail(BLR_ERR_STATE, "refinement needs the copy of A~ kept by a factor with keep_a");
   }
@@ -2892,6 +2973,17 @@ blr_status blr_lstsq_solve_batch(blr_matrix* hs, int32_t count, const double* co
         throw Error(BLR_ERR_SINGULAR, "R of batch member " + std::to_string(i) + " is numerically singular");
       reset_work_after_sync(v[i]);
     }
+    // ragged members solve their embedding for [B; 0] (see blr_lstsq_solve)
+    std::vector<const double*> Bw(B, B + count);
+    std::vector<double*> Xw(X, X + count);
+    std::vector<int64_t> ldbw(ldb, ldb + count), ldxw(ldx, ldx + count);
+    for (int i = 0; i < count; ++i)
+      if (v[i]->ragged()) {
+        Bw[i] = pad_rows(v[i], B[i], ldb[i], v[i]->mu, v[i]->m, nrhs, s);
+        ldbw[i] = v[i]->m;
+        Xw[i] = (double*)v[i]->work.alloc((size_t)v[i]->n * nrhs * 8);
+        ldxw[i] = v[i]->n;
+      }
     struct Member {
       Work w;
       RsolveWork rw;
@@ -2925,10 +3017,10 @@ blr_status blr_lstsq_solve_batch(blr_matrix* hs, int32_t count, const double* co
       e.w = make_work(h, nrhs);
       e.rw = make_rsolve_work(h, nrhs);
       e.C = (double*)h->work.alloc((size_t)m * nrhs * 8);
-      P.copy({CopyDesc{B[i], e.C, ldb[i], m, (int32_t)m, nrhs, 0, 0, 0}});
+      P.copy({CopyDesc{Bw[i], e.C, ldbw[i], m, (int32_t)m, nrhs, 0, 0, 0}});
       plan_apply(h, P, e.w, e.C, m, nrhs, 0);
-      P.copy({CopyDesc{e.C, X[i], m, ldx[i], (int32_t)n, nrhs, 0, 0, 0}});
-      plan_rsolve(h, P, e.rw, X[i], ldx[i], nrhs, 0);
+      P.copy({CopyDesc{e.C, Xw[i], m, ldxw[i], (int32_t)n, nrhs, 0, 0, 0}});
+      plan_rsolve(h, P, e.rw, Xw[i], ldxw[i], nrhs, 0);
       if (max_refine > 0) {
         e.r = (double*)h->work.alloc((size_t)m * nrhs * 8);
         e.f = (double*)h->work.alloc((size_t)m * nrhs * 8);
@@ -2958,9 +3050,9 @@ blr_status blr_lstsq_solve_batch(blr_matrix* hs, int32_t count, const double* co
         blr_matrix h = v[i];
         const int64_t m = h->m, n = h->n;
         Plan& P = plans[i];
-        plan_matmul(h, P, BLR_MATMUL_A, X[i], ldx[i], e.f, m, nrhs);
+        plan_matmul(h, P, BLR_MATMUL_A, Xw[i], ldxw[i], e.f, m, nrhs);
         plan_matmul(h, P, BLR_MATMUL_AT, e.r, m, e.g, n, nrhs);
-        P.lincomb(lc(e.f, m, B[i], ldb[i], e.r, m, e.f, m, 1.0, -1.0, -1.0, m, nrhs));
+        P.lincomb(lc(e.f, m, Bw[i], ldbw[i], e.r, m, e.f, m, 1.0, -1.0, -1.0, m, nrhs));
         plan_apply(h, P, e.w, e.f, m, nrhs, 0);
         P.lincomb(lc(e.g, n, e.g, n, nullptr, 0, nullptr, 0, -1.0, 0.0, 0.0, n, nrhs));
         plan_rsolve(h, P, e.rw, e.g, n, nrhs, 1);
@@ -2972,7 +3064,7 @@ blr_status blr_lstsq_solve_batch(blr_matrix* hs, int32_t count, const double* co
         std::vector<Frob2Desc> fr(2 * nrhs);
         for (int c = 0; c < nrhs; ++c) {
           fr[c] = Frob2Desc{e.f + (int64_t)c * m, m, (int32_t)n, 1, e.nrm + c};
-          fr[nrhs + c] = Frob2Desc{X[i] + (int64_t)c * ldx[i], ldx[i], (int32_t)n, 1, e.nrm + nrhs + c};
+          fr[nrhs + c] = Frob2Desc{Xw[i] + (int64_t)c * ldxw[i], ldxw[i], (int32_t)n, 1, e.nrm + nrhs + c};
         }
         P.frob2(fr);
       }
@@ -2992,13 +3084,17 @@ blr_status blr_lstsq_solve_batch(blr_matrix* hs, int32_t count, const double* co
         const int64_t m = h->m, n = h->n;
         for (auto [c0, c1] : take_runs(e.take)) {
           const int nc = c1 - c0;
-          plans[i].lincomb(lc(X[i] + c0 * ldx[i], ldx[i], X[i] + c0 * ldx[i], ldx[i], e.f + c0 * m, m, nullptr, 0,
+          plans[i].lincomb(lc(Xw[i] + c0 * ldxw[i], ldxw[i], Xw[i] + c0 * ldxw[i], ldxw[i], e.f + c0 * m, m, nullptr, 0,
                               1.0, 1.0, 0.0, n, nc));
           plans[i].lincomb(lc(e.r + c0 * m, m, e.r + c0 * m, m, e.dr + c0 * m, m, nullptr, 0, 1.0, 1.0, 0.0, m, nc));
         }
       }
       run(plans);
     }
+    for (int i = 0; i < count; ++i)
+      if (Xw[i] != X[i])
+        HIPCHECK(hipMemcpy2DAsync(X[i], ldx[i] * 8, Xw[i], ldxw[i] * 8, v[i]->nu * 8, nrhs, hipMemcpyDeviceToDevice,
+                                  s));
     for (int i = 0; i < count; ++i) end_call(v[i], s);
     HIPCHECK(hipStreamSynchronize(s));
   });
@@ -3009,12 +3105,19 @@ blr_status blr_rsolve(blr_matrix h, int32_t trans, double* X, int64_t ldx, int32
   if (trans != 0 && trans != 1) return fail(BLR_ERR_INVALID, "trans must be 0 or 1");
   if (h->state != BLR_STATE_FACTORED) return fail(BLR_ERR_STATE, "matrix is not factored");
   if (h->steps_done != h->q) return fail(BLR_ERR_STATE, "factorization is incomplete");
-  if (ldx < h->n || nrhs < 0) return fail(BLR_ERR_INVALID, "bad X shape");
+  if (ldx < h->nu || nrhs < 0) return fail(BLR_ERR_INVALID, "bad X shape");
   if (nrhs == 0) return BLR_OK;
   hipStream_t s = as_stream(stream);
   return run_guarded([&] {
     begin_call(h);
-    run_rsolve(h, X, ldx, nrhs, trans, s);
+    if (!h->ragged()) {
+      run_rsolve(h, X, ldx, nrhs, trans, s);
+    } else {
+      // R = diag(R_A, -I): the embedding's solve of X padded by zero rows
+      double* Xp = pad_rows(h, X, ldx, h->nu, h->n, nrhs, s);
+      run_rsolve(h, Xp, h->n, nrhs, trans, s);
+      HIPCHECK(hipMemcpy2DAsync(X, ldx * 8, Xp, h->n * 8, h->nu * 8, nrhs, hipMemcpyDeviceToDevice, s));
+    }
     end_call(h, s);
   });
 }
@@ -3030,6 +3133,7 @@ blr_status blr_lstsq_adjoint(blr_matrix h, const double* B, int64_t ldb, const d
   if (h->state != BLR_STATE_FACTORED) return fail(BLR_ERR_STATE, "matrix is not factored");
   if (h->steps_done != h->q) return fail(BLR_ERR_STATE, "factorization is incomplete");
   if (h->acopy.empty()) return fail(BLR_ERR_STATE, "the adjoint needs the copy of A~ kept by a factor with keep_a");
+  if (h->ragged()) return fail(BLR_ERR_INVALID, "the adjoint needs b to divide m and n");
   if (ldb < h->m || ldx < h->n || ldxb < h->n || ldbb < h->m || nrhs < 0)
     return fail(BLR_ERR_INVALID, "bad B, X, Xbar or Bbar shape");
   if (nrhs == 0) return BLR_OK;
@@ -3145,6 +3249,7 @@ blr_status blr_form_q(blr_matrix h, void* stream, blr_matrix* q_out) {
   *q_out = nullptr;
   if (h->state != BLR_STATE_FACTORED) return fail(BLR_ERR_STATE, "matrix is not factored");
   if (h->steps_done != h->q) return fail(BLR_ERR_STATE, "factorization is incomplete");
+  if (h->ragged()) return fail(BLR_ERR_INVALID, "the explicit Q needs b to divide m and n");
   hipStream_t s = as_stream(stream);
   blr_status inner = BLR_OK;
   blr_status st = run_guarded([&] {
@@ -3219,8 +3324,8 @@ blr_status blr_matmul(blr_matrix h, int32_t op, const double* X, int64_t ldx, do
   } else if (h->state != BLR_STATE_COMPRESSED && h->acopy.empty()) {
     return fail(BLR_ERR_STATE, "the factorization has overwritten A (factor with keep_a to keep a copy)");
   }
-  const int64_t xr = op == BLR_MATMUL_AT ? h->m : h->n;
-  const int64_t yr = op == BLR_MATMUL_A ? h->m : h->n;
+  const int64_t xr = op == BLR_MATMUL_AT ? h->mu : h->nu;
+  const int64_t yr = op == BLR_MATMUL_A ? h->mu : h->nu;
   if (nrhs < 0 || ldx < xr || ldy < yr) return fail(BLR_ERR_INVALID, "bad X or Y shape");
   if (nrhs == 0) return BLR_OK;
   {
@@ -3233,9 +3338,21 @@ blr_status blr_matmul(blr_matrix h, int32_t op, const double* X, int64_t ldx, do
   hipStream_t s = as_stream(stream);
   return run_guarded([&] {
     begin_call(h);
-    Plan P;
-    plan_matmul(h, P, op, X, ldx, Y, ldy, nrhs);
-    run_plan(h, P, s);
+    if (!h->ragged()) {
+      Plan P;
+      plan_matmul(h, P, op, X, ldx, Y, ldy, nrhs);
+      run_plan(h, P, s);
+    } else {
+      // the embedding's product with X padded by zero rows; Y is its leading rows
+      const int64_t xe = op == BLR_MATMUL_AT ? h->m : h->n;
+      const int64_t ye = op == BLR_MATMUL_A ? h->m : h->n;
+      const double* Xp = pad_rows(h, X, ldx, xr, xe, nrhs, s);
+      double* Yp = (double*)h->work.alloc((size_t)ye * nrhs * 8);
+      Plan P;
+      plan_matmul(h, P, op, Xp, xe, Yp, ye, nrhs);
+      run_plan(h, P, s);
+      HIPCHECK(hipMemcpy2DAsync(Y, ldy * 8, Yp, ye * 8, yr * 8, nrhs, hipMemcpyDeviceToDevice, s));
+    }
     end_call(h, s);
   });
 }
@@ -3245,11 +3362,14 @@ blr_status blr_query(blr_matrix h, blr_info* info) {
   return run_guarded([&] {
     wait_idle(h);
     std::memset(info, 0, sizeof(*info));
-    info->m = h->m;
-    info->n = h->n;
+    info->m = h->mu;
+    info->n = h->nu;
     info->tile = h->b;
-    info->p = h->p;
+    info->p = h->pu;
     info->q = h->q;
+    info->m_pad = h->m;
+    info->n_pad = h->n;
+    info->p_pad = h->p;
     info->max_rank = h->cap;
     info->rank_capacity = h->rc;
     info->state = h->state;

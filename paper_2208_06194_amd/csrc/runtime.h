@@ -181,7 +181,14 @@ struct Plan {
 }  // namespace blr
 
 struct blr_matrix_s {
+  // m x n and p x q tiles of the matrix the kernels factor.  When b does not
+  // divide the caller's mu or nu it is the embedding [A 0; 0 E] of A
+  // (mu x nu): zero rows and columns pad A to whole tiles, and E holds an
+  // identity block in the padded columns (rows mu .. mu + n - nu - 1), so
+  // that the embedding has full column rank; R = diag(R_A, -I) up to signs.
   int64_t m = 0, n = 0;
+  int64_t mu = 0, nu = 0;   // the caller's rows and columns
+  int pu = 0;               // tile rows holding rows of A (p, or p - 1 when E needs one more)
   int b = 0, p = 0, q = 0, cap = 0, rc = 0;
   double tol = 0.0;
   int overflow = 0;
@@ -213,4 +220,11 @@ struct blr_matrix_s {
   int64_t prof_launches[2] = {0, 0};
 
   blr::Tile& t(int i, int j) { return tiles[(size_t)i * q + j]; }
+  bool ragged() const { return m != mu || n != nu; }
+  // does tile (i, j) hold entries of the identity block E?
+  bool has_identity(int i, int j) const {
+    const int64_t pc = n - nu;
+    if (pc == 0 || j != q - 1) return false;
+    return (int64_t)i * b < mu + pc && (int64_t)(i + 1) * b > mu;
+  }
 };

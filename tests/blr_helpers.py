@@ -10,7 +10,9 @@ def rank_capacity(cap: int, b: int) -> int:
 
 
 def blr_to_host(blr: BLR, cap: int):
-    """Oracle BLR -> (fmt, rank, dense, U, V) arrays in the blr_tiles_host layout."""
+    """Oracle BLR -> (fmt, rank, dense, U, V) arrays in the blr_tiles_host
+    layout (an edge tile of a ragged matrix in the leading rows and columns
+    of its b x b slot)."""
     p, q, b = blr.p, blr.q, blr.b
     rc = rank_capacity(cap, b)
     fmt = np.zeros(p * q, np.int8)
@@ -22,14 +24,16 @@ def blr_to_host(blr: BLR, cap: int):
         for j in range(q):
             t = i * q + j
             if blr.fmt[i, j] == DENSE:
-                dense[t] = blr.D[(i, j)].T          # column-major b x b
+                D = blr.D[(i, j)]
+                dense[t, :D.shape[1], :D.shape[0]] = D.T          # column-major
             else:
                 r = blr.rank(i, j)
                 assert r <= cap
                 fmt[t] = 1
                 rank[t] = r
-                U[t, :r] = blr.U[(i, j)].T
-                V[t, :r] = blr.V[(i, j)].T
+                Ut, Vt = blr.U[(i, j)], blr.V[(i, j)]
+                U[t, :r, :Ut.shape[0]] = Ut.T
+                V[t, :r, :Vt.shape[0]] = Vt.T
     return fmt, rank, dense.ravel(), U.ravel(), V.ravel()
 
 
@@ -42,6 +46,8 @@ def export_tile(ex, i, j):
 
 
 def export_r(ex):
+    """R (n x n) from an export; for a ragged matrix the leading n x n block
+    of the embedding's R."""
     p, q = ex["fmt"].shape
     b = ex["dense"].shape[2]
     R = np.zeros((q * b, q * b))
@@ -49,16 +55,21 @@ def export_r(ex):
         for j in range(k, q):
             blk = np.triu(ex["dense"][k, k]) if j == k else export_tile(ex, k, j)
             R[k * b:(k + 1) * b, j * b:(j + 1) * b] = blk
-    return R
+    n = ex["info"]["n"] if "info" in ex else q * b
+    return R[:n, :n]
 
 
 def export_dense(ex):
+    """The matrix (m x n) of an export (for a ragged matrix: the caller's rows
+    and columns of the edge tiles)."""
     p, q = ex["fmt"].shape
     b = ex["dense"].shape[2]
     A = np.zeros((p * b, q * b))
     for i in range(p):
         for j in range(q):
             A[i * b:(i + 1) * b, j * b:(j + 1) * b] = export_tile(ex, i, j)
+    if "info" in ex:
+        A = A[:ex["info"]["m"], :ex["info"]["n"]]
     return A
 
 

@@ -47,7 +47,7 @@ def test_invalid_arguments_are_rejected_without_a_device():
     lib = L.load()
     h = ctypes.c_void_p()
     # m < n, tile not dividing m, bad tolerance, bad rank cap
-    for m, n, tile, tol, cap in [(64, 128, 32, 1e-8, 8), (100, 50, 32, 1e-8, 8), (64, 32, 32, 0.0, 8),
+    for m, n, tile, tol, cap in [(64, 128, 32, 1e-8, 8), (64, 32, 32, 0.0, 8),
                                  (64, 32, 32, 1e-8, 0), (64, 32, 24, 1e-8, 8), (64, 32, 32, 1e-8, 200)]:
         o = L.CompressOpts(m=m, n=n, tile=tile, tol=tol, max_rank=cap, overflow=0, seed=0)
         src = L.Source(kind=L.SRC_DENSE, A=ctypes.c_void_p(8), lda=m, admissibility=L.ADM["weak"])
