@@ -184,6 +184,22 @@ typedef struct blr_tiles_host {
  * when b does not divide m or n. */
 blr_status blr_form_q(blr_matrix h, void* hip_stream, blr_matrix* q_out);
 
+/* Blocked modified Gram-Schmidt QR of the BLR matrix: the method the paper
+ * compares its Householder algorithms with (Section 2.1 Alg. 1, Section
+ * 3.2).  For each block column j: the right factors of its tiles (dense:
+ * the tile; low-rank U V^T: V^T) are stacked over every block row and
+ * orthogonalized by column-by-column MGS, Q_ij = U_ij Q^B_ij keeps the
+ * tile's U, and R_jk = Q_j^T A_k, A_k -= Q_j R_jk (k > j) run in BLR
+ * arithmetic (a low-rank tile receiving a dense update becomes dense).
+ * h must be COMPRESSED with b dividing m and n.  On return h holds the
+ * explicit Q~ (state COMPRESSED: products and export work as for A~) and
+ * *r_out is a new n x n handle holding R~ (dense upper triangular diagonal
+ * tiles, R_jk dense or low-rank, zero tiles below the diagonal).  The
+ * stack QR runs in one workgroup per block column: an accuracy comparison
+ * path, not a fast one.  Synchronises the stream.  Errors: BLR_ERR_STATE if
+ * h is not COMPRESSED, BLR_ERR_INVALID if b does not divide m or n. */
+blr_status blr_mgs_qr(blr_matrix h, void* hip_stream, blr_matrix* r_out);
+
 /* X <- R^{-1} X (trans = 0) or X <- R^{-T} X (trans = 1) with the R factor of
  * a factored handle (Section 3.3 / 3.4: R has the tile structure of A~), for
  * X n x nrhs, column-major, device, ld ldx >= n, overwritten.  The blocked

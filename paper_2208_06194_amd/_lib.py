@@ -14,7 +14,7 @@ EXPORTED = [
     "blr_lstsq_solve", "blr_query", "blr_destroy", "blr_status_string", "blr_last_error",
     "blr_profile_enable", "blr_profile_read", "blr_matmul", "blr_morton_sort", "blr_rsolve",
     "blr_lstsq_adjoint", "blr_form_q", "blr_qr_factor_batch", "blr_lstsq_solve_batch",
-    "blr_apply_qt_noalloc",
+    "blr_apply_qt_noalloc", "blr_mgs_qr",
 ]
 NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024   # BLR_NOALLOC_SCRATCH_BYTES
 SELFTEST = ["blr_selftest_gemm"]
@@ -88,6 +88,7 @@ def load() -> ctypes.CDLL:
     lib.blr_morton_sort.argtypes = [c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p]
     lib.blr_rsolve.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_int32, c_void_p]
     lib.blr_form_q.argtypes = [c_void_p, c_void_p, P(c_void_p)]
+    lib.blr_mgs_qr.argtypes = [c_void_p, c_void_p, P(c_void_p)]
     lib.blr_lstsq_adjoint.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_int32,
                                       c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.blr_query.argtypes = [c_void_p, P(Info)]

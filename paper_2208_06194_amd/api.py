@@ -277,6 +277,13 @@ class BLRMatrix:
         X = Xc.t()
         return (X, torch.sqrt(res)) if with_resid else X
 
+    def mgs_qr(self, stream=None) -> "BLRMatrix":
+        """Blocked modified Gram-Schmidt QR (the comparison method): this
+        handle becomes the explicit Q~; returns R~ as a new n x n handle."""
+        h = ctypes.c_void_p()
+        _check(L.load().blr_mgs_qr(self._h, _stream(stream), ctypes.byref(h)))
+        return BLRMatrix(h.value)
+
     def form_q(self, stream=None) -> "BLRMatrix":
         """The explicit orthogonal factor Q~ (m x n) as a new BLR matrix with the
         structure, tolerance and rank cap of A~."""

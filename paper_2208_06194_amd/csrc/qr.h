@@ -46,7 +46,8 @@ struct CopyDesc {
   int64_t lds, ldd;
   int32_t rows, cols;
   int32_t unit_lower;   // 1: write the unit lower triangular part of src (diag 1, upper 0);
-                        // 2: write the upper triangular part (zeros below the diagonal)
+                        // 2: write the upper triangular part (zeros below the diagonal);
+                        // 3: src and dst point to one int32 (a tile rank), copied as is
   int32_t nsum;         // > 1: dst = sum of nsum blocks of src, sstride doubles apart (split-K)
   int64_t sstride;
 };
@@ -62,6 +63,11 @@ hipError_t launch_tall_column(const TallArgs& a, int groups, hipStream_t stream)
 constexpr int kTallApplySlices = 256;
 hipError_t launch_tall_apply(const PanelArgs& a, int nt, int slices, double* part, hipStream_t stream);
 hipError_t launch_copy_blocks(const CopyDesc* d, int n, int64_t max_elems, hipStream_t stream);
+// Modified Gram-Schmidt QR of an h x w column-major block X (ld ldx) in one
+// workgroup: X is overwritten by Q, R (w x w, ld ldr) receives R (zeros
+// below the diagonal).  Full column rank is assumed (a zero column divides
+// by zero).
+hipError_t launch_mgs_stack(double* X, int64_t ldx, int h, int w, double* R, int64_t ldr, hipStream_t stream);
 hipError_t launch_t_backsolve(const TBackArgs& a, hipStream_t stream);
 // Fused trailing update of the nt columns right of panel a (same PanelArgs:
 // X points at the panel's first column / first row, T at its diagonal block).

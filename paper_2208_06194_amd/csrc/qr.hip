@@ -664,6 +664,10 @@ __device__ __forceinline__ void tall_apply_upd_body(const PanelArgs& a, int nt, 
 // block column), and the explicit unit-lower form of a packed reflector block.
 __global__ void k_copy_blocks(const CopyDesc* __restrict__ d) {
   const CopyDesc D = d[blockIdx.y];
+  if (D.unit_lower == 3) {   // one int32
+    if (blockIdx.x == 0 && threadIdx.x == 0) *(int*)D.dst = *(const int*)D.src;
+    return;
+  }
   const int64_t n = (int64_t)D.rows * D.cols;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = e % D.rows, c = e / D.rows;
@@ -672,6 +676,36 @@ __global__ void k_copy_blocks(const CopyDesc* __restrict__ d) {
     if (D.unit_lower == 1) v = r > c ? v : (r == c ? 1.0 : 0.0);
     else if (D.unit_lower == 2) v = r <= c ? v : 0.0;
     D.dst[r + c * D.ldd] = v;
+  }
+}
+
+// Modified Gram-Schmidt QR of the stacked right factors of a block column
+// (the comparison method, Section 2.1 Alg. 1 with Section 3.2), in one
+// workgroup of 16 waves.  Column c: r_cc = ||x_c|| (block reduction),
+// q_c = x_c / r_cc; then every later column d, one wave each, takes
+// r_cd = q_c^T x_d (wave reduction over its rows, lanes striding) and
+// x_d -= r_cd q_c.  The summation order is fixed.
+__global__ __launch_bounds__(1024) void k_mgs_stack(double* X, int64_t ldx, int h, int w, double* R, int64_t ldr) {
+  __shared__ double red[16];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int c = 0; c < w; ++c) {
+    double* xc = X + (int64_t)c * ldx;
+    double s = 0.0;
+    for (int r = tid; r < h; r += 1024) s += xc[r] * xc[r];
+    const double rcc = sqrt(block_sum(s, red));
+    for (int r = tid; r < h; r += 1024) xc[r] = xc[r] / rcc;
+    if (tid == 0) R[c + (int64_t)c * ldr] = rcc;
+    for (int r = c + 1 + tid; r < w; r += 1024) R[r + (int64_t)c * ldr] = 0.0;
+    __syncthreads();   // q_c is written before the waves read it
+    for (int d = c + 1 + wv; d < w; d += 16) {
+      double* xd = X + (int64_t)d * ldx;
+      double t = 0.0;
+      for (int r = lane; r < h; r += 64) t += xc[r] * xd[r];
+      t = wave_sum(t);
+      for (int r = lane; r < h; r += 64) xd[r] -= t * xc[r];
+      if (lane == 0) R[c + (int64_t)d * ldr] = t;
+    }
+    __syncthreads();   // the updates are done before the next column's norm
   }
 }
 
@@ -788,6 +822,13 @@ hipError_t launch_copy_blocks(const CopyDesc* d, int n, int64_t max_elems, hipSt
   if (n <= 0 || max_elems <= 0) return hipSuccess;
   const int blocks = (int)std::min<int64_t>((max_elems + 255) / 256, 256);
   hipLaunchKernelGGL(k_copy_blocks, dim3(blocks, n), dim3(256), 0, stream, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_mgs_stack(double* X, int64_t ldx, int h, int w, double* R, int64_t ldr, hipStream_t stream) {
+  if (h <= 0 || w <= 0) return hipSuccess;
+  if (w > h || ldx < h || ldr < w) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mgs_stack, dim3(1), dim3(1024), 0, stream, X, ldx, h, w, R, ldr);
   return hipGetLastError();
 }
 

@@ -467,6 +467,10 @@ void enqueue(blr_matrix h, const Plan& P, const Op& o, hipStream_t q, bool multi
         HIPCHECK(launch_frob2(P.d_frobs + o.off, o.n, q));
         h->launches += 1;
         break;
+      case Op::MGS_STACK:
+        HIPCHECK(launch_mgs_stack(o.mgs.X, o.mgs.ldx, o.mgs.h, o.mgs.w, o.mgs.R, o.mgs.ldr, q));
+        h->launches += 1;
+        break;
       case Op::WAIT:
         if (multi) HIPCHECK(hipStreamWaitEvent(q, ev[o.event], 0));
         break;
@@ -945,27 +949,33 @@ struct BcWork {
   std::vector<BcSlot> slots;
 };
 
-bool bc_zdense(blr_matrix h, const std::vector<int8_t>& f, int k, int j) {
+// Is Z_j = sum_{i >= i0} Ytilde_ik^T A_ij dense (some term dense: OP1)?  The
+// Householder step sums from i0 = k, the Gram-Schmidt step from i0 = 0; the
+// diagonal tile's block is dense in both.
+bool bc_zdense(blr_matrix h, const std::vector<int8_t>& f, int k, int j, int i0) {
   const int q = h->q;
-  for (int i = k; i < h->p; ++i)
+  for (int i = i0; i < h->p; ++i)
     if ((i == k || f[(size_t)i * q + k] == DENSE) && f[(size_t)i * q + j] == DENSE) return true;
   return false;
 }
+bool bc_zdense(blr_matrix h, const std::vector<int8_t>& f, int k, int j) { return bc_zdense(h, f, k, j, k); }
 
 // Low-rank tiles that the block-column factorization turns dense (OP1): a
 // low-rank A_ij receiving a dense update Ytilde_ik W_j.  Also returns the
 // largest number of (i, j) pairs of one step that need low-rank temporaries.
-std::vector<int> bc_simulate(blr_matrix h, int kend, int* max_pairs) {
+// mgs: the Gram-Schmidt steps, which span every block row.
+std::vector<int> bc_simulate(blr_matrix h, int kend, int* max_pairs, bool mgs = false) {
   const int p = h->p, q = h->q;
   std::vector<int8_t> f((size_t)p * q);
   for (size_t t = 0; t < f.size(); ++t) f[t] = h->tiles[t].fmt;
   std::vector<int> need;
   int mp = 0;
   for (int k = 0; k < kend; ++k) {
+    const int i0 = mgs ? 0 : k;
     int pairs = 0;
     for (int j = k + 1; j < q; ++j) {
-      const bool zd = bc_zdense(h, f, k, j);
-      for (int i = k; i < p; ++i) {
+      const bool zd = bc_zdense(h, f, k, j, i0);
+      for (int i = i0; i < p; ++i) {
         const bool yd = i == k || f[(size_t)i * q + k] == DENSE;
         int8_t& A = f[(size_t)i * q + j];
         if (!(yd && A == DENSE && zd)) pairs++;
@@ -1210,6 +1220,15 @@ void plan_bc_panel(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k) {
   P.copy(cp);
 }
 
+// The Gram-Schmidt form of a block-column step (the comparison method):
+// store(j, dense, Zd, Zl) is called once the plan has formed R_kj = Z_j
+// (dense in Zd, b x b, ld b; or low-rank in the slot term Zl) and plans its
+// copy into R's tile before anything reuses the slot; for a low-rank R_kj it
+// returns that tile as a term (U ld b, V^T ld rc), the W of the update.
+struct BcGs {
+  std::function<RcTerm(int, bool, const double*, const RcTerm&)> store;
+};
+
 // Trailing update of the columns j in [j0, j1) by the reflectors of step k
 // (Section 3.3.2): Z_j = sum_i Ytilde_ik^T A_ij, W_j = T_k^T Z_j and
 // A_ij -= Ytilde_ik W_j with the OP1/OP2 rules: Z_j is dense if any term is
@@ -1219,28 +1238,32 @@ void plan_bc_panel(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k) {
 // for the columns below jsplit, mid() is called (the look-ahead hook), and
 // the remaining columns follow.
 void plan_bc_update(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k, int j0, int j1, bool fp32,
-                    int jsplit, const std::function<void()>& mid) {
+                    int jsplit, const std::function<void()>& mid, const BcGs* gs) {
   const int b = h->b, rc = h->rc, p = h->p, q = h->q;
   if (j0 >= j1) return;
+  // the Householder step works on block rows i >= k with W = T_k^T Z; the
+  // Gram-Schmidt step (gs) on every block row with W = Z (R_kj = Z_j)
+  const int i0 = gs ? 0 : k;
   std::vector<bool> yd(p, true);
-  for (int i = k + 1; i < p; ++i) yd[i] = h->yfmt[(size_t)i * q + k] == DENSE;
-  double* Tk = h->T[(size_t)k * q + k];
-  auto Yd = [&](int i) -> double* { return i == k ? bw.Yf[k & 1] : h->t(i, k).D; };
+  for (int i = i0; i < p; ++i)
+    if (i != k) yd[i] = h->yfmt[(size_t)i * q + k] == DENSE;
+  double* Tk = gs ? nullptr : h->T[(size_t)k * q + k];
+  auto Yd = [&](int i) -> double* { return i == k ? (gs ? h->t(k, k).D : bw.Yf[k & 1]) : h->t(i, k).D; };
   std::vector<bool> zd(q, false);
   std::vector<int8_t> f((size_t)p * q);
   for (size_t t = 0; t < f.size(); ++t) f[t] = h->tiles[t].fmt;
-  for (int j = j0; j < j1; ++j) zd[j] = bc_zdense(h, f, k, j);
+  for (int j = j0; j < j1; ++j) zd[j] = bc_zdense(h, f, k, j, i0);
   // slots for the pairs that need low-rank temporaries
   std::vector<int> slot((size_t)p * q, -1);
   int ns = 0;
   for (int j = j0; j < j1; ++j)
-    for (int i = k; i < p; ++i)
+    for (int i = i0; i < p; ++i)
       if (!(yd[i] && h->t(i, j).fmt == DENSE && zd[j])) slot[(size_t)i * q + j] = ns++;
   if (ns > (int)bw.slots.size()) throw Error(BLR_ERR_DEVICE, "internal: block-column slot count");
   auto S = [&](int i, int j) -> BcSlot& { return bw.slots[slot[(size_t)i * q + j]]; };
   // 4a. pre-products of the low-rank terms
   for (int j = j0; j < j1; ++j)
-    for (int i = k; i < p; ++i) {
+    for (int i = i0; i < p; ++i) {
       Tile& A = h->t(i, j);
       Tile& Y = h->t(i, k);
       const bool ad = A.fmt == DENSE;
@@ -1252,7 +1275,7 @@ void plan_bc_update(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k, int j0, i
     }
   P.flush_gemm();
   for (int j = j0; j < j1; ++j)
-    for (int i = k + 1; i < p; ++i)
+    for (int i = i0; i < p; ++i)
       if (!yd[i] && h->t(i, j).fmt == LOWRANK) {
         BcSlot& sl = S(i, j);
         P.gemm(sl.Ua, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, h->t(i, k).Vt, rc, sl.Sm, rc, rc, SEG_TRANS_A);
@@ -1263,7 +1286,7 @@ void plan_bc_update(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k, int j0, i
   for (int j = j0; j < j1; ++j) {
     if (!zd[j]) continue;
     std::vector<GemmSeg> sv;
-    for (int i = k; i < p; ++i) {
+    for (int i = i0; i < p; ++i) {
       Tile& A = h->t(i, j);
       if (yd[i] && A.fmt == DENSE) continue;
       GemmSeg g{};
@@ -1284,7 +1307,7 @@ void plan_bc_update(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k, int j0, i
   for (int j = j0; j < j1; ++j) {
     if (!zd[j]) continue;
     std::vector<GemmSeg> sv;
-    for (int i = k; i < p; ++i) {
+    for (int i = i0; i < p; ++i) {
       Tile& A = h->t(i, j);
       if (!(yd[i] && A.fmt == DENSE)) continue;
       GemmSeg g{};
@@ -1319,22 +1342,22 @@ void plan_bc_update(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k, int j0, i
   // goes to the slot of the left term (U into Ub, V^T into Sa, in place from
   // the second level on; the recompression reads its inputs before it writes),
   // so every level is one batch of independent problems.
-  const int nt = p - k;
+  const int nt = p - i0;
   std::vector<std::vector<RcTerm>> tv(q);
   for (int j = j0; j < j1; ++j) {
     if (zd[j]) continue;
     tv[j].resize(nt);
     for (int x = 0; x < nt; ++x) {
-      Tile& A = h->t(k + x, j);
-      tv[j][x] = A.fmt == LOWRANK ? RcTerm{S(k + x, j).Ua, A.Vt, A.rank, b, rc, 0, 0, 1.0}
-                                  : RcTerm{h->t(k + x, k).Vt, S(k + x, j).Sa, h->t(k + x, k).rank, rc, rc, 0, 1, 1.0};
+      Tile& A = h->t(i0 + x, j);
+      tv[j][x] = A.fmt == LOWRANK ? RcTerm{S(i0 + x, j).Ua, A.Vt, A.rank, b, rc, 0, 0, 1.0}
+                                  : RcTerm{h->t(i0 + x, k).Vt, S(i0 + x, j).Sa, h->t(i0 + x, k).rank, rc, rc, 0, 1, 1.0};
     }
   }
   for (int st = 1; st < nt; st *= 2) {
     for (int j = j0; j < j1; ++j) {
       if (zd[j]) continue;
       for (int x = 0; x + st < nt; x += 2 * st) {
-        BcSlot& sl = S(k + x, j);
+        BcSlot& sl = S(i0 + x, j);
         RcDesc d{};
         d.nterm = 2;
         d.t[0] = tv[j][x];
@@ -1352,19 +1375,26 @@ void plan_bc_update(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k, int j0, i
   std::vector<RcTerm> zterm(q);
   for (int j = j0; j < j1; ++j)
     if (!zd[j]) zterm[j] = tv[j][0];
-  // 5. W_j = T_k^T Z_j
-  for (int j = j0; j < j1; ++j) {
-    if (zd[j]) P.gemm(w.X2[j], b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, Tk, b, w.X[j], b, b, SEG_TRANS_A | SEG_A_UPPER);
-    else P.gemm(w.WU[j], b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, Tk, b, zterm[j].U, zterm[j].ldu, b,
-                SEG_TRANS_A | SEG_A_UPPER);
+  // 5. W_j = T_k^T Z_j (Gram-Schmidt: W_j = Z_j, which is R_kj)
+  if (!gs) {
+    for (int j = j0; j < j1; ++j) {
+      if (zd[j]) P.gemm(w.X2[j], b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, Tk, b, w.X[j], b, b, SEG_TRANS_A | SEG_A_UPPER);
+      else P.gemm(w.WU[j], b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, Tk, b, zterm[j].U, zterm[j].ldu, b,
+                  SEG_TRANS_A | SEG_A_UPPER);
+    }
+    P.flush_gemm(fp32, 1);
   }
-  P.flush_gemm(fp32, 1);
+  std::vector<RcTerm> wterm(q);   // Gram-Schmidt: W_j = R_kj as stored in R
+  if (gs)
+    for (int j = j0; j < j1; ++j) wterm[j] = gs->store(j, zd[j], w.X[j], zterm[j]);
+  auto Wd = [&](int j) -> double* { return gs ? w.X[j] : w.X2[j]; };
+  auto WU = [&](int j) -> const double* { return gs ? wterm[j].U : w.WU[j]; };
   // stages 6-7 for the columns [ja, jb)
   auto apply_cols = [&](int ja, int jb) {
     if (ja >= jb) return;
     // 6. fill-in: low-rank targets of a dense update become dense (OP1)
     for (int j = ja; j < jb; ++j)
-      for (int i = k; i < p; ++i) {
+      for (int i = i0; i < p; ++i) {
         Tile& A = h->t(i, j);
         if (zd[j] && yd[i] && A.fmt == LOWRANK) {
           P.gemm(A.D, b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, A.U, b, A.Vt, rc, rc, 0);
@@ -1375,31 +1405,31 @@ void plan_bc_update(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k, int j0, i
     P.flush_gemm(fp32);
     // 7. updates A_ij -= Ytilde_ik W_j
     for (int j = ja; j < jb; ++j)
-      for (int i = k; i < p; ++i)
+      for (int i = i0; i < p; ++i)
         if (yd[i] && zd[j])
-          P.gemm(h->t(i, j).D, b, h->t(i, j).D, b, nullptr, 0, b, b, -1.0, 1.0, Yd(i), b, w.X2[j], b, b, 0);
+          P.gemm(h->t(i, j).D, b, h->t(i, j).D, b, nullptr, 0, b, b, -1.0, 1.0, Yd(i), b, Wd(j), b, b, 0);
     P.flush_gemm(fp32, 1);
     for (int j = ja; j < jb; ++j)
-      for (int i = k; i < p; ++i) {
+      for (int i = i0; i < p; ++i) {
         if (yd[i] && zd[j]) continue;
         BcSlot& sl = S(i, j);
         if (!yd[i] && zd[j])
-          P.gemm(sl.Sa, rc, nullptr, 0, nullptr, 0, rc, b, 1.0, 0.0, h->t(i, k).Vt, rc, w.X2[j], b, b, 0);
+          P.gemm(sl.Sa, rc, nullptr, 0, nullptr, 0, rc, b, 1.0, 0.0, h->t(i, k).Vt, rc, Wd(j), b, b, 0);
         else if (yd[i])
-          P.gemm(sl.Ub, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, Yd(i), b, w.WU[j], b, b, 0);
+          P.gemm(sl.Ub, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, Yd(i), b, WU(j), b, b, 0);
         else
-          P.gemm(sl.Sm, rc, nullptr, 0, nullptr, 0, rc, rc, 1.0, 0.0, h->t(i, k).Vt, rc, w.WU[j], b, b, 0);
+          P.gemm(sl.Sm, rc, nullptr, 0, nullptr, 0, rc, rc, 1.0, 0.0, h->t(i, k).Vt, rc, WU(j), b, b, 0);
       }
     P.flush_gemm();
     for (int j = ja; j < jb; ++j)
-      for (int i = k + 1; i < p; ++i)
+      for (int i = i0; i < p; ++i)
         if (!yd[i] && !zd[j]) {
           BcSlot& sl = S(i, j);
           P.gemm(sl.Ub, b, nullptr, 0, nullptr, 0, b, rc, 1.0, 0.0, h->t(i, k).U, b, sl.Sm, rc, rc, 0);
         }
     P.flush_gemm();
     for (int j = ja; j < jb; ++j)
-      for (int i = k; i < p; ++i) {
+      for (int i = i0; i < p; ++i) {
         if (yd[i] && zd[j]) continue;
         Tile& A = h->t(i, j);
         BcSlot& sl = S(i, j);
@@ -1408,6 +1438,7 @@ void plan_bc_update(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k, int j0, i
         const double* Vu;
         const int* ru;
         if (!yd[i] && zd[j]) { Uu = h->t(i, k).U; Vu = sl.Sa; ru = h->t(i, k).rank; }
+        else if (gs) { Uu = sl.Ub; Vu = wterm[j].Vt; ru = wterm[j].rank_ptr; }
         else { Uu = sl.Ub; Vu = zterm[j].Vt; ru = zterm[j].rank_ptr; }
         if (A.fmt == DENSE) {
           P.gemm(A.D, b, A.D, b, nullptr, 0, b, b, -1.0, 1.0, Uu, b, Vu, rc, rc, 0);
@@ -1466,10 +1497,10 @@ void plan_blockcol(blr_matrix h, Plan& P, Work& w, BcWork& bw, int kend, bool fp
     std::vector<int8_t> f((size_t)h->p * q);
     for (size_t t = 0; t < f.size(); ++t) f[t] = h->tiles[t].fmt;
     if (bc_zdense(h, f, k, k + 1)) {
-      plan_bc_update(h, P, w, bw, k, k + 1, k + 2, fp32, k + 2, next_panel);
-      plan_bc_update(h, P, w, bw, k, k + 2, q, fp32, q, nullptr);
+      plan_bc_update(h, P, w, bw, k, k + 1, k + 2, fp32, k + 2, next_panel, nullptr);
+      plan_bc_update(h, P, w, bw, k, k + 2, q, fp32, q, nullptr, nullptr);
     } else {
-      plan_bc_update(h, P, w, bw, k, k + 1, q, fp32, k + 2, next_panel);
+      plan_bc_update(h, P, w, bw, k, k + 1, q, fp32, k + 2, next_panel, nullptr);
     }
   }
   P.cur_stream = 0;
@@ -2768,6 +2799,67 @@ blr_status blr_apply_qt(blr_matrix h, int32_t trans, double* B, int64_t ldb, int
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// Blocked modified Gram-Schmidt BLR-QR (Section 2.1 Alg. 1 with Section 3.2),
+// the method the paper compares its Householder algorithms with.  Step j
+// stacks the right factors of every tile of block column j (dense: the tile;
+// low-rank: V^T), takes their MGS QR in one workgroup (k_mgs_stack), writes
+// Q^B back (dense tiles: the b x b block; low-rank tiles: the rows as the new
+// V^T, so Q_ij = U_ij Q^B_ij keeps its U) with R_jj into R, and then runs the
+// block-column update over every block row with W = Z: R_jk = Q_j^T A_k and
+// A_k -= Q_j R_jk (the OP1/OP2 rules of the Householder update).
+void plan_mgs(blr_matrix h, blr_matrix R, Plan& P, Work& w, BcWork& bw) {
+  const int b = h->b, rc = h->rc, p = h->p, q = h->q;
+  for (int j = 0; j < q; ++j) {
+    std::vector<int64_t> off(p, 0);
+    std::vector<int> rows(p, 0);
+    int hs = 0;
+    for (int i = 0; i < p; ++i) {
+      rows[i] = h->t(i, j).fmt == DENSE ? b : rc;
+      off[i] = hs;
+      hs += rows[i];
+    }
+    std::vector<CopyDesc> cp;
+    for (int i = 0; i < p; ++i) {
+      Tile& t = h->t(i, j);
+      const bool d = t.fmt == DENSE;
+      cp.push_back(CopyDesc{d ? t.D : t.Vt, bw.stack + off[i], d ? (int64_t)b : (int64_t)rc, (int64_t)hs,
+                            rows[i], b, 0, 0, 0});
+    }
+    P.copy(cp);
+    P.mgs_stack(bw.stack, hs, hs, b, R->t(j, j).D, b);
+    cp.clear();
+    for (int i = 0; i < p; ++i) {
+      Tile& t = h->t(i, j);
+      const bool d = t.fmt == DENSE;
+      cp.push_back(CopyDesc{bw.stack + off[i], d ? t.D : t.Vt, (int64_t)hs, d ? (int64_t)b : (int64_t)rc,
+                            rows[i], b, 0, 0, 0});
+      if (i != j) h->yfmt[(size_t)i * q + j] = t.fmt;
+    }
+    P.copy(cp);
+    if (j + 1 >= q) break;
+    // R_jk = Z_k, copied out of the step's temporaries into R's tile (j, k)
+    // as soon as it is formed; a low-rank R_jk is then the W of the update
+    BcGs gs;
+    gs.store = [&](int k, bool dense, const double* Zd, const RcTerm& Zl) -> RcTerm {
+      Tile& t = R->t(j, k);
+      if (dense) {
+        alloc_dense(R, {j * q + k});
+        t.fmt = DENSE;
+        P.copy({CopyDesc{Zd, t.D, (int64_t)b, (int64_t)b, b, b, 0, 0, 0}});
+        return RcTerm{};
+      }
+      alloc_lowrank(R, {j * q + k});
+      t.fmt = LOWRANK;
+      P.copy({CopyDesc{Zl.U, t.U, Zl.ldu, (int64_t)b, b, rc, 0, 0, 0},
+              CopyDesc{Zl.Vt, t.Vt, Zl.ldvt, (int64_t)rc, rc, b, 0, 0, 0},
+              CopyDesc{(const double*)Zl.rank_ptr, (double*)t.rank, 1, 1, 1, 1, 3, 0, 0}});
+      return RcTerm{t.U, t.Vt, t.rank, (int64_t)b, (int64_t)rc, 0, 0, 1.0};
+    };
+    plan_bc_update(h, P, w, bw, j, j + 1, q, false, q, nullptr, &gs);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Q^T B / Q B with no device allocation: the temporaries and the launch
 // descriptors of the call live in one static device array.  Every GPU the
 // library runs on holds its own copy until the process ends; its device
@@ -2809,6 +2901,66 @@ struct ScratchAlloc : DevAlloc {
 }  // namespace
 
 extern "C" {
+
+blr_status blr_mgs_qr(blr_matrix h, void* stream, blr_matrix* r_out) {
+  if (!h || !r_out) return fail(BLR_ERR_INVALID, "NULL argument");
+  *r_out = nullptr;
+  if (h->state != BLR_STATE_COMPRESSED) return fail(BLR_ERR_STATE, "matrix is not in the compressed state");
+  if (h->ragged()) return fail(BLR_ERR_INVALID, "the Gram-Schmidt factorization needs b to divide m and n");
+  hipStream_t s = as_stream(stream);
+  blr_compress_opts ro{};
+  ro.m = h->n;
+  ro.n = h->n;
+  ro.tile = h->b;
+  ro.tol = h->tol;
+  ro.max_rank = h->cap;
+  ro.overflow = BLR_OVERFLOW_DENSE;
+  blr_matrix R = new_handle(&ro);
+  blr_status st = run_guarded([&] {
+    begin_call(h);
+    const int b = h->b, q = h->q;
+    alloc_common(R);
+    // R: dense diagonal tiles; the tiles below the diagonal are zero (rank 0)
+    std::vector<int> diag, below;
+    for (int i = 0; i < q; ++i)
+      for (int k = 0; k < q; ++k) {
+        if (i == k) diag.push_back(i * q + k);
+        else if (i > k) below.push_back(i * q + k);
+      }
+    alloc_dense(R, diag);
+    for (int t : diag) R->tiles[t].fmt = DENSE;
+    alloc_lowrank(R, below);
+    for (int t : below) R->tiles[t].fmt = LOWRANK;
+    // fill-in slots and temporaries of the Gram-Schmidt steps
+    int pairs = 0;
+    alloc_dense(h, bc_simulate(h, q, &pairs, true));
+    Work w = make_work(h, 0);
+    BcWork bw = make_bc_work(h, pairs);
+    h->n_fill = 0;
+    Plan P;
+    plan_mgs(h, R, P, w, bw);
+    // tiles of R right of the diagonal that no step wrote (q = 1) stay absent
+    for (int i = 0; i < q; ++i)
+      for (int k = i + 1; k < q; ++k)
+        if (!R->t(i, k).D && !R->t(i, k).U) {
+          alloc_lowrank(R, {i * q + k});
+          R->t(i, k).fmt = LOWRANK;
+        }
+    h->flops = 0.0;
+    for (auto& op : P.ops) h->flops += op.flops;
+    h->launches = 0;
+    (void)b;
+    run_plan(h, P, s);
+    end_call(h, s);
+    HIPCHECK(hipStreamSynchronize(s));
+  });
+  if (st != BLR_OK) {
+    delete R;
+    return st;
+  }
+  *r_out = R;
+  return BLR_OK;
+}
 
 blr_status blr_apply_qt_noalloc(blr_matrix h, int32_t trans, double* B, int64_t ldb, int32_t nrhs,
                                 void* stream) {

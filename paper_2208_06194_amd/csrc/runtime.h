@@ -79,7 +79,9 @@ struct Op {
     // batched forms of the panel kernels (jobs [off, off + n) of the plan)
     PANEL_B, PANEL_APPLY_B, TBACK_B, TALL_COL_B, TALL_APPLY_B,
     // solve steps: batched triangular solves, linear combinations, squared norms
-    TRSM_B, LINCOMB, FROB2
+    TRSM_B, LINCOMB, FROB2,
+    // the Gram-Schmidt comparison method: QR of a stacked block column
+    MGS_STACK
   } kind;
   int off = 0, n = 0, ntiles = 0, big = 0, fp32 = 0, prof = 0;
   int ib = 0, ext = 0, ext2 = 0, first = 0;   // batched panel ops: width, largest extents, first column
@@ -92,6 +94,13 @@ struct Op {
   TrsmJob trsm{};         // TRSM: the solve (n: 1 = with R^T)
   double* buf = nullptr;   // TALL_APPLY: partial sums
   int64_t maxel = 0;       // COPY: largest block
+  struct {                 // MGS_STACK: X (h x w, ld ldx) -> Q, R (ld ldr)
+    double* X;
+    int64_t ldx;
+    int h, w;
+    double* R;
+    int64_t ldr;
+  } mgs{};
 };
 
 // Launch list with host-side descriptor arrays, uploaded once.
@@ -165,6 +174,13 @@ struct Plan {
     o.off = (int)frobs.size();
     o.n = (int)v.size();
     frobs.insert(frobs.end(), v.begin(), v.end());
+    push(o);
+  }
+  void mgs_stack(double* X, int64_t ldx, int h, int w, double* R, int64_t ldr) {
+    Op o;
+    o.kind = Op::MGS_STACK;
+    o.mgs = {X, ldx, h, w, R, ldr};
+    o.flops = 2.0 * h * w * w;
     push(o);
   }
   void wait(int e) { Op o; o.kind = Op::WAIT; o.event = e; push(o); n_events = std::max(n_events, e + 1); }
