@@ -12,7 +12,7 @@ Morton sorted, kernel evaluated on the device):
   c1  2048 x 1024,     2D -log(r+1e-3),  b = 128,  adjacent boxes dense, eps 1e-8, cap 16
   c2  32768 x 16384,   3D 1/(r+1e-3),    b = 256,  gap > diameter low-rank, eps 1e-8, cap 32
   c3  131072 x 65536,  3D 1/(r+1e-3),    b = 1024, gap > diameter low-rank, eps 1e-8, cap 50
-  cr  30000 x 15000,   3D 1/(r+1e-3),    b = 256,  every tile compressed, rank > b/2 dense (cap 128), eps 1e-8;
+  cr  6000 x 3000,     3D 1/(r+1e-3),    b = 128,  every tile compressed, rank > b/2 dense (cap 64), eps 1e-8;
       m and n are not multiples of b
   c4  64 matrices, m log-uniform in [4096, 32768], n = m/2, 3D 1/(r+1e-3), b = 256, eps 1e-8,
       cap 64, each with a 16-RHS least-squares solve: the plain form (one factorization after
@@ -42,7 +42,7 @@ CONFIGS = {
     # compress-and-revert (non-geometric admissibility): every off-diagonal
     # tile compressed, those whose eps-rank exceeds b/2 stored dense; m and n
     # not multiples of b (ragged edge tiles, factored through the embedding)
-    "cr": dict(m=30000, n=15000, b=256, dim=3, kernel="inv_r", rule="weak", tol=1e-8, cap=128),
+    "cr": dict(m=6000, n=3000, b=128, dim=3, kernel="inv_r", rule="weak", tol=1e-8, cap=64),
     # batched forms: 64 independent matrices, rows log-uniform in [4096, 32768]
     # (multiples of 512), n = m/2, each followed by a 16-RHS least-squares solve
     "c4": dict(kind="batch", count=64, m_lo=4096, m_hi=32768, b=256, dim=3, kernel="inv_r",
@@ -61,8 +61,8 @@ HBM_PEAK_TBS = 8.0                                # MI355X HBM3E bandwidth, TB/s
 # the counters were taken on (sha256 of csrc/gemm.hip); otherwise null.
 TRAFFIC = {
     ("c3", "fp64", "block_column"): {
-        "gemm_sha256": "44b99667909767a3c5dccc9e2959ecb03f79b3cbd70f075dca30acf38ef68d67",
-        "bytes_per_launch": 9709666765,
+        "gemm_sha256": "ae5de4b4e24c3fdd2128dd283bddfd16717c3887726933f375c791c591f4ecd5",
+        "bytes_per_launch": 21913494436,
     },
 }
 
@@ -282,6 +282,21 @@ def run(args, cfg, precision, tol, xd, yd, dev, phase, keep_a=False, rhs=None, x
                 solve["x_rel_err_vs_fp64"] = float(torch.linalg.norm(x_out - x_ref)) / nr
                 if refine > 0:
                     solve["x_rel_err_vs_fp64_unrefined"] = float(torch.linalg.norm(x0 - x_ref)) / nr
+            if keep_a and ax is not None:
+                # the normal-equation residual of each solution against A~ itself
+                # (the kept copy): eta = ||A~^T (b - A~ x)|| / (||A~||_F ||b - A~ x||)
+                # per column, the largest reported; ||A~||_F from A~ times the probes
+                anorm = float(torch.linalg.norm(ax)) / np.sqrt(probes.shape[1])
+
+                def eta(x):
+                    r = B16 - G.matmul(x, "A")
+                    return float((torch.linalg.norm(G.matmul(r, "AT"), dim=0)
+                                  / (anorm * torch.linalg.norm(r, dim=0))).max())
+                solve["eta_ne"] = eta(x_out)
+                if refine > 0:
+                    solve["eta_ne_unrefined"] = eta(x0)
+                if x_ref is not None:
+                    solve["eta_ne_fp64_solution"] = eta(x_ref)
             # HBM roofline of Q^T B: the reflectors are read twice (Y^T B, then
             # B -= Y W), counted as if every tile were dense
             gi = G.info()
@@ -308,6 +323,29 @@ def run(args, cfg, precision, tol, xd, yd, dev, phase, keep_a=False, rhs=None, x
                 del Qt
                 print(f"[bench] {precision}: explicit Q~ {tq:.3f}s, Orth~ {orth_q:.2e}, Res~ {res_q:.2e}",
                       file=sys.stderr, flush=True)
+            if args.mgs:
+                # the comparison method on the same compressed matrix: blocked
+                # modified Gram-Schmidt, Q~ explicit, with the same probes
+                if cfg.get("kind") == "random_blr":
+                    Gm = P.BLRMatrix.compress_dense(xd, cfg["b"], tol, cfg["cap"], admissibility="weak",
+                                                    overflow="dense", seed=args.seed)
+                else:
+                    Gm = P.BLRMatrix.compress_kernel(xd, yd, cfg["kernel"], cfg["b"], tol, cfg["cap"],
+                                                     admissibility=cfg["rule"], overflow="dense", seed=args.seed)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                Rm = Gm.mgs_qr()
+                torch.cuda.synchronize()
+                tm = time.perf_counter() - t0
+                res_m = float(torch.linalg.norm(Gm.matmul(Rm.matmul(probes, "A"), "A") - ax) / torch.linalg.norm(ax))
+                orth_m = float(torch.linalg.norm(Gm.matmul(Gm.matmul(probes, "A"), "AT") - probes)
+                               / np.sqrt(probes.shape[1]) / np.sqrt(cfg["n"]))
+                solve["mgs"] = {"factor_s": tm, "res_est": res_m, "orth_est": orth_m,
+                                "note": "blocked modified Gram-Schmidt BLR-QR of the same compressed matrix "
+                                        "(Q~ explicit); Gaussian-probe estimates as for the Householder factor"}
+                del Gm, Rm
+                print(f"[bench] {precision}: MGS {tm:.3f}s Res~ {res_m:.2e} Orth {orth_m:.2e}", file=sys.stderr,
+                      flush=True)
             if args.adjoint:
                 # backward pass of the least-squares solve: dL/dB and dL/dtiles
                 nr = args.adjoint_rhs
@@ -471,7 +509,7 @@ def main():
     ap.add_argument("--mixed-tol", type=float, default=1e-6,
                     help="compression tolerance of the mixed form's second, looser accuracy point (the first "
                          "uses the FP64 tolerance)")
-    ap.add_argument("--refine", type=int, default=5,
+    ap.add_argument("--refine", type=int, default=10,
                     help="FP64 refinement steps of the mixed form's least-squares solve")
     ap.add_argument("--variant", default="block_column", choices=["tiled", "block_column"])
     ap.add_argument("--probes", type=int, default=8, help="Gaussian probes for the Res / Orth estimates")
@@ -480,6 +518,9 @@ def main():
     ap.add_argument("--adjoint", action="store_true",
                     help="also time the least-squares adjoint (the factor keeps a copy of A~)")
     ap.add_argument("--adjoint-rhs", type=int, default=32)
+    ap.add_argument("--mgs", action="store_true",
+                    help="also time the blocked modified Gram-Schmidt BLR-QR of the same matrix (the paper's "
+                         "comparison method) and estimate its Res and Orth")
     ap.add_argument("--explicit-q", action="store_true",
                     help="also form the explicit BLR Q~ and estimate the paper's Orth and Res on it")
     ap.add_argument("--batch-form", default="both", choices=["plain", "batched", "both"],
@@ -637,6 +678,9 @@ def main():
             "refine_steps_max": args.refine,
             "x_rel_err_mixed_refined_vs_fp64": mx["solve"].get("x_rel_err_vs_fp64"),
             "x_rel_err_mixed_unrefined_vs_fp64": mx["solve"].get("x_rel_err_vs_fp64_unrefined"),
+            "eta_ne_mixed_refined": mx["solve"].get("eta_ne"),
+            "eta_ne_mixed_unrefined": mx["solve"].get("eta_ne_unrefined"),
+            "eta_ne_fp64": mx["solve"].get("eta_ne_fp64_solution"),
             "note": "16 Gaussian right-hand sides; both solve min ||A~ x - b|| for the same A~ (same compression "
                     "tolerance and seed); the mixed solution is refined with FP64 residuals",
         }
