@@ -525,6 +525,9 @@ def main():
                     help="also form the explicit BLR Q~ and estimate the paper's Orth and Res on it")
     ap.add_argument("--batch-form", default="both", choices=["plain", "batched", "both"],
                     help="c4: the forms to run (both: one factorization after the other, then the batch)")
+    ap.add_argument("--tune", action="store_true",
+                    help="kernel-matrix configs: first run the autotuner of tile size, variant and ib on a "
+                         "leading sample and report its table (the reported value keeps the config's tile size)")
     ap.add_argument("--stop-after-k", type=int, default=-1,
                     help="exploration only: factor the first K block columns (not a valid metric)")
     args = ap.parse_args()
@@ -580,6 +583,18 @@ def main():
         xd, yd = torch.tensor(x, device=dev), torch.tensor(y, device=dev)
         print(f"[bench] {args.config}: points ready in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
               flush=True)
+
+    tuned = None
+    if args.tune and yd is not None:
+        from paper_2208_06194_amd import tune
+        tiles = tuple(t for t in (128, 256, 512, 1024) if cfg["b"] // 4 <= t <= cfg["b"] * 2)
+        tuned = tune.tune_kernel_matrix(
+            xd, yd, cfg["kernel"], cfg["tol"], cfg["cap"], admissibility=cfg["rule"],
+            precision="mixed" if args.precision == "mixed" else "fp64",
+            candidates=tune.default_candidates(cfg["n"], tiles=tiles, variants=(args.variant,)),
+            log=lambda s: print(s, file=sys.stderr, flush=True))
+        tuned["note"] = ("factor seconds of each candidate on the leading sample (median of 2), scaled to the "
+                         "full size by dense-equivalent flops; the reported value keeps the config's tile size")
 
     # wall-clock plan: the forms share what is left of the budget after the
     # set-up, less a reserve for the CPU baseline; each form gets at least
@@ -643,6 +658,8 @@ def main():
                   "compress_overflow": info["compress_overflow"], "factor_overflow": info["factor_overflow"]},
         "kernel_launches": info["kernel_launches"],
     }
+    if tuned:
+        out["tune"] = tuned
     # the dominant kernel of the reported value: its launches in the timed
     # factorizations of the reported form
     main_k = "fp64" if main_prec == "fp64" else "fp32"

@@ -100,7 +100,7 @@ typedef struct blr_source {
 
 typedef struct blr_compress_opts {
   int64_t m, n;             /* matrix size, m >= n >= 1 */
-  int32_t tile;             /* b: 16 <= b <= 1024, multiple of 16, divides m and n */
+  int32_t tile;             /* b: 16 <= b <= 1024, multiple of 16 (need not divide m or n) */
   double tol;               /* eps > 0: per-tile ||A~_ij - A_ij||_F <= eps ||A_ij||_F */
   int32_t max_rank;         /* rank cap, 1 <= max_rank <= min(b, 128) */
   int32_t overflow;         /* BLR_OVERFLOW_* */
@@ -110,7 +110,8 @@ typedef struct blr_compress_opts {
 typedef struct blr_factor_opts {
   int32_t variant;          /* BLR_TILED or BLR_BLOCK_COLUMN */
   int32_t precision;        /* BLR_FP64 or BLR_MIXED_FP32 */
-  int32_t ib;               /* inner block of reflector generation (0 = default 32) */
+  int32_t ib;               /* widest inner block of reflector generation: 16 or 32 (0 = 32);
+                               panels taller than 512 rows use 16 whatever is asked */
   int32_t stop_after_k;     /* debug: factor only block columns 0..K-1 (-1 = all) */
   int32_t keep_a;           /* 1: keep a device copy of A~ (doubles the tile memory) so that
                                blr_matmul with A~ and refined least squares work after the

@@ -574,7 +574,7 @@ void plan_tile_qr(Plan& P, blr_matrix h, Work& w, bool tp, double* X, int64_t ld
                   double* T, double* tau) {
   const int b = h->b;
   const int rowsh = tp ? hb : b;
-  int ib = (rowsh > 512) ? 16 : 32;
+  int ib = (rowsh > 512) ? 16 : std::min(32, h->ib);   // register panels hold 32 columns up to 512 rows
   if (b % ib) ib = 16;
   ib = std::min(ib, b);
   for (int c0 = 0; c0 < b; c0 += ib) {
@@ -1119,7 +1119,7 @@ void plan_stack_qr(Plan& P, blr_matrix h, Work& w, BcWork& bw, int hs, double* T
   const int b = h->b;
   double* X = bw.stack;
   const bool tall = hs > 1024;
-  int ib = (hs > 512 && !tall) ? 16 : 32;
+  int ib = (hs > 512 && !tall) ? 16 : std::min(32, h->ib);
   if (tall) ib = 16;   // 16-column sub-panels: the column kernel's rows stay in registers at 512 threads
   if (b % ib) ib = 16;
   ib = std::min(ib, b);
@@ -2280,6 +2280,7 @@ int prepare_factor(blr_matrix h, const blr_factor_opts* o, hipStream_t s, Plan& 
 
   h->variant = o->variant;
   h->precision = o->precision;
+  h->ib = o->ib > 0 ? o->ib : 32;
   h->fmt0.resize((size_t)p * q);
   for (size_t t = 0; t < h->fmt0.size(); ++t) h->fmt0[t] = h->tiles[t].fmt;
   if (o->keep_a) keep_copy(h, s);
@@ -2735,6 +2736,7 @@ blr_status blr_qr_factor(blr_matrix h, const blr_factor_opts* o, void* stream) {
   if (h->state != BLR_STATE_COMPRESSED) return fail(BLR_ERR_STATE, "matrix is already factored");
   if (o->variant != BLR_TILED && o->variant != BLR_BLOCK_COLUMN) return fail(BLR_ERR_INVALID, "bad variant");
   if (o->precision != BLR_FP64 && o->precision != BLR_MIXED_FP32) return fail(BLR_ERR_INVALID, "bad precision");
+  if (o->ib != 0 && o->ib != 16 && o->ib != 32) return fail(BLR_ERR_INVALID, "ib must be 0, 16 or 32");
   hipStream_t s = as_stream(stream);
   return run_guarded([&] {
     begin_call(h);
@@ -2752,6 +2754,7 @@ blr_status blr_qr_factor_batch(blr_matrix* hs, int32_t count, const blr_factor_o
   if (!hs || !o || count < 1) return fail(BLR_ERR_INVALID, "NULL argument or count < 1");
   if (o->variant != BLR_BLOCK_COLUMN) return fail(BLR_ERR_INVALID, "the batched factor runs the block-column variant");
   if (o->precision != BLR_FP64 && o->precision != BLR_MIXED_FP32) return fail(BLR_ERR_INVALID, "bad precision");
+  if (o->ib != 0 && o->ib != 16 && o->ib != 32) return fail(BLR_ERR_INVALID, "ib must be 0, 16 or 32");
   std::vector<blr_matrix> v(hs, hs + count);
   for (int i = 0; i < count; ++i) {
     if (!v[i]) return fail(BLR_ERR_INVALID, "NULL handle in the batch");
