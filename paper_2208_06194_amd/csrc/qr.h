@@ -28,18 +28,6 @@ struct TBackArgs {
   int64_t ldt;
 };
 
-struct TallArgs {
-  double* X;       // panel pivot (c0, c0) of the stack
-  int64_t ldx;
-  int h;           // rows from the pivot down
-  int ib;          // panel width (<= 32)
-  int jj;          // column of the panel being factored
-  double* part;    // partials: 2 x (G + 1) x 2*ib doubles
-  double* T;       // T element (c0, c0)
-  int64_t ldt;
-  double* tau;     // tau[c0 ..]
-};
-
 struct CopyDesc {
   const double* src;
   double* dst;
@@ -53,15 +41,56 @@ struct CopyDesc {
 };
 
 hipError_t launch_panel(const PanelArgs& a, hipStream_t stream);
-// One launch per column of a tall panel (two for its first column), over
-// groups row groups (1 .. kTallMaxGroups); ib must be 16 or 32.
-constexpr int kTallMaxGroups = 512;
-constexpr int kTallThreads = 256;   // threads per row group (two rows each for 512-row groups)
-hipError_t launch_tall_column(const TallArgs& a, int groups, hipStream_t stream);
 // Split-K trailing update of a tall panel over 1 .. kTallApplySlices row
 // slices; part: slices * ceil(nt/32) * ib * 32 doubles.
 constexpr int kTallApplySlices = 256;
 hipError_t launch_tall_apply(const PanelArgs& a, int nt, int slices, double* part, hipStream_t stream);
+
+// Tall panels as a tree (TSQR) with Householder reconstruction.  A tall
+// panel of h rows and kTsqrIB columns is cut into count[0] leaves of at most
+// kTsqrRows rows (balanced: the first h % count[0] leaves get one row more);
+// every leaf is factored, the leaves' R factors are stacked in S[1] (leaf g
+// in rows 16 g .. 16 g + 15) and factored in groups of at most 16 (count[1]
+// nodes, balanced like the leaves), and so on up to the single root
+// (count[levels] == 1).  Every factor is a Householder QR with LAPACK's
+// larfg convention, its reflectors left in place and its T in Tn[level]
+// (16 x 16 per node, ld 16); each leaf also keeps a unit-lower copy of its
+// top 16 x 16 reflector block in Y1.  The final step forms each leaf's rows
+// of the explicit Q and turns them into the Householder vectors, T and tau
+// of the whole panel (an LU factorization of Q's top block with the sign
+// choice that avoids cancellation), with R = D R_root written on the top
+// rows of the panel: the same reflectors, T, tau and R (up to rounding) as
+// the column-by-column Householder QR.  levels == 0: the single leaf's QR is
+// the panel's.
+constexpr int kTsqrIB = 16;
+constexpr int kTsqrRows = 256;
+constexpr int kTsqrFan = 16;
+constexpr int kTsqrMaxLevels = 6;
+struct TsqrTree {
+  double* X;      // panel pivot (c0, c0)
+  int64_t ldx;
+  int h;          // rows from the pivot down
+  int levels;
+  double* T;      // output: 16 x 16 upper triangular block (ld ldt)
+  int64_t ldt;
+  double* tau;    // output: 16 values
+  double* Y1;     // count[0] x 256
+  int count[kTsqrMaxLevels + 1];
+  double* S[kTsqrMaxLevels + 1];    // S[l], l >= 1: 16 count[l-1] rows x 16, column-major
+  double* Tn[kTsqrMaxLevels + 1];   // Tn[l]: count[l] x 256
+};
+// One tree level (QR launch: every node of that level; final launch: every
+// leaf) of a batched launch; wg_begin is the first workgroup of the item.
+struct TsqrItem {
+  int tree;
+  int level;
+  int wg_begin;
+  int pad;
+};
+hipError_t launch_tsqr_qr(const TsqrTree* trees, const TsqrItem* items, int n, int total_wg, hipStream_t stream);
+hipError_t launch_tsqr_final(const TsqrTree* trees, const TsqrItem* items, int n, int total_wg,
+                             hipStream_t stream);
+
 hipError_t launch_copy_blocks(const CopyDesc* d, int n, int64_t max_elems, hipStream_t stream);
 // Modified Gram-Schmidt QR of an h x w column-major block X (ld ldx) in one
 // workgroup: X is overwritten by Q, R (w x w, ld ldr) receives R (zeros
@@ -79,10 +108,9 @@ hipError_t launch_panel_apply(const PanelArgs& a, int nt, hipStream_t stream);
 // launch.  Job arrays are device memory.
 struct PanelJob {
   PanelArgs a;     // panel, panel update, tall update
-  TallArgs t;      // tall column
   TBackArgs tb;    // T back-substitution (order tb.n > tb.ib)
   int nt;          // panel update / tall update: trailing columns (> 0)
-  int groups;      // tall column: row groups; tall update: row slices
+  int groups;      // tall update: row slices
   double* part;    // tall update: partial sums
 };
 // max_rows selects the register-tile template: every job's h must fall in
@@ -90,8 +118,5 @@ struct PanelJob {
 hipError_t launch_panel_batch(const PanelJob* d, int n, int ib, int max_rows, hipStream_t stream);
 hipError_t launch_panel_apply_batch(const PanelJob* d, int n, int ib, int max_nt, hipStream_t stream);
 hipError_t launch_t_backsolve_batch(const PanelJob* d, int n, int max_n, hipStream_t stream);
-// first = 1: the jobs are the first column of their panels (jj = 0)
-hipError_t launch_tall_column_batch(const PanelJob* d, int n, int ib, int first, int max_groups,
-                                    hipStream_t stream);
 hipError_t launch_tall_apply_batch(const PanelJob* d, int n, int ib, int max_nt, int max_slices,
                                    hipStream_t stream);

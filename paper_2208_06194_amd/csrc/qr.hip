@@ -331,189 +331,6 @@ __device__ __forceinline__ void t_backsolve_body(const TBackArgs& a, int cb) {
 }
 
 
-// ---------------------------------------------------------------------------
-// Tall panels (block-column variant, stacks taller than 1024 rows).  The
-// panel is IB columns of the stack starting at its pivot (c0, c0): X points
-// there, h rows below it.  The rows are split into G fixed groups (one
-// workgroup each).  One launch per column jj:
-//   - every group sums the G partial results of the previous launch (tail sum
-//     of squares of column jj, its dot products with the other panel columns,
-//     and the pivot row jj) and forms the larfg scalars and
-//     w_t = X(jj,t) + v^T x_t;
-//   - it scales its rows of column jj into the reflector, applies the
-//     rank-one update to the later columns, and on the same rows already
-//     accumulates the partials of column jj + 1 (the group holding row jj + 1
-//     also snapshots that row);
-//   - the group holding row jj writes the pivot row, tau and column jj of T.
-// Partials are double buffered: launch jj reads buffer jj % 2 and writes
-// buffer (jj + 1) % 2, each (G + 1) x 2 IB doubles.  k_tall_first seeds
-// buffer 0 for column 0.  The summation order is fixed, so the result does
-// not depend on timing.
-__device__ __forceinline__ void tall_rows(int h, int G, int g, int* rs, int* re) {
-  const int chunk = (h + G - 1) / G;
-  *rs = min(h, g * chunk);
-  *re = min(h, *rs + chunk);
-}
-
-template <int IB, int NT>
-__device__ __forceinline__ void tall_store_partials(double (&part)[IB], double (*red)[IB], double* out, int g) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-#pragma unroll
-  for (int t = 0; t < IB; ++t) {
-    const double s = wave_sum(part[t]);
-    if (lane == 0) red[w][t] = s;
-  }
-  __syncthreads();
-  if (tid < IB) {
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < NT / 64; ++q) s += red[q][tid];
-    out[(int64_t)g * (2 * IB) + tid] = s;
-  }
-}
-
-template <int IB>
-__device__ __forceinline__ void tall_first_body(const TallArgs& a, int G, int g) {
-  constexpr int NT = kTallThreads;
-  __shared__ double red[NT / 64][IB];
-  const int tid = threadIdx.x;
-  const int64_t ld = a.ldx;
-  int rs, re;
-  tall_rows(a.h, G, g, &rs, &re);
-  double* out = a.part;
-  double part[IB];
-#pragma unroll
-  for (int t = 0; t < IB; ++t) part[t] = 0.0;
-  for (int r = max(rs, 1) + tid; r < re; r += NT) {
-    const double v = a.X[r];
-#pragma unroll
-    for (int t = 0; t < IB; ++t) part[t] += (t == 0) ? v * v : v * a.X[r + (int64_t)t * ld];
-  }
-  tall_store_partials<IB, NT>(part, red, out, g);
-  if (rs == 0 && re > 0 && tid < IB) out[(int64_t)G * (2 * IB) + tid] = a.X[(int64_t)tid * ld];
-}
-
-template <int IB>
-__device__ __forceinline__ void tall_step_body(const TallArgs& a, int G, int g) {
-  constexpr int NT = kTallThreads;
-  __shared__ double acc[NT / IB][2 * IB];
-  __shared__ double sv[2 * IB];   // [0, IB): dots of column jj (its tail sum of squares at jj); [IB, 2 IB): pivot row
-  __shared__ double wv[IB];
-  const int tid = threadIdx.x;
-  const int jj = a.jj;
-  const int64_t ld = a.ldx;
-  const int64_t bufsz = (int64_t)(G + 1) * (2 * IB);
-  const double* in = a.part + (jj & 1) * bufsz;
-  double* out = a.part + ((jj + 1) & 1) * bufsz;
-  // 1. sum the partials of column jj (fixed order: slice of groups per thread, then slices)
-  {
-    constexpr int NS = NT / IB;
-    const int e = tid % IB, sl = tid / IB;
-    const int per = (G + NS - 1) / NS;
-    const int qb = sl * per, qe = min(G, (sl + 1) * per);
-    // eight independent partial sums keep eight loads in flight
-    double s8[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) s8[u] = 0.0;
-    int q = qb;
-    for (; q + 8 <= qe; q += 8) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) s8[u] += in[(int64_t)(q + u) * (2 * IB) + e];
-    }
-    for (; q < qe; ++q) s8[0] += in[(int64_t)q * (2 * IB) + e];
-    acc[sl][e] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
-    __syncthreads();
-    if (tid < IB) {
-      double t = 0.0;
-      for (int q = 0; q < NS; ++q) t += acc[q][tid];
-      sv[tid] = t;
-      sv[IB + tid] = in[(int64_t)G * (2 * IB) + tid];
-    }
-    __syncthreads();
-  }
-  double beta, tau, scal;
-  larfg_scalars(sv[IB + jj], sv[jj], &beta, &tau, &scal);
-  if (tid < IB) wv[tid] = sv[IB + tid] + scal * sv[tid];   // t > jj: w_t; t < jj: Gram entry g_t
-  __syncthreads();
-  int rs, re;
-  tall_rows(a.h, G, g, &rs, &re);
-  const int nx = jj + 1;   // next column
-  const bool more = nx < IB;
-  // 2. reflector column jj and rank-one update of the later columns on this
-  // group's rows.  Lanes take consecutive rows, wave w the columns
-  // t = w, w + NW, ...: each thread keeps one partial sum per column it owns
-  // and recomputes v and the updated next column for its row (the other
-  // waves' loads of those two columns hit the cache), so the kernel needs few
-  // registers and shares compute units with long-running GEMM workgroups.
-  // The trip count of the row loop is the same for every thread (it holds a
-  // barrier).
-  constexpr int NW = NT / 64, CPW = IB / NW;
-  static_assert(IB % NW == 0, "columns per wave");
-  const int lane = tid & 63, w = tid >> 6;
-  double part[CPW];
-#pragma unroll
-  for (int u = 0; u < CPW; ++u) part[u] = 0.0;
-  const double twn = more ? tau * wv[nx] : 0.0;
-  for (int r0 = rs; r0 < re; r0 += 64) {
-    const int r = r0 + lane;
-    const bool act = r < re && r > jj;
-    double vr = 0.0, xr = 0.0;
-    if (act) {
-      vr = a.X[r + (int64_t)jj * ld];
-      if (more) xr = a.X[r + (int64_t)nx * ld];
-    }
-    // every wave has read columns jj and nx of these rows before the waves
-    // owning them write them back
-    __syncthreads();
-    if (!act) continue;
-    const double v = vr * scal;
-    const double xn = more ? xr - twn * v : 0.0;
-    const bool pivot = more && r == nx;   // the next pivot row: snapshot it after this update
-#pragma unroll
-    for (int u = 0; u < CPW; ++u) {
-      const int t = w + NW * u;
-      double x;
-      if (t == jj) {
-        x = v;
-        a.X[r + (int64_t)t * ld] = v;
-      } else if (t > jj) {
-        if (!more) continue;
-        x = a.X[r + (int64_t)t * ld] - tau * wv[t] * v;
-        a.X[r + (int64_t)t * ld] = x;
-      } else {   // t < jj: final reflector entries
-        if (!more) continue;
-        x = a.X[r + (int64_t)t * ld];
-      }
-      if (pivot) out[(int64_t)G * (2 * IB) + t] = x;
-      else part[u] += xn * x;
-    }
-  }
-  // 3. the group holding row jj: pivot row, tau, column jj of T
-  if (rs <= jj && jj < re) {
-    if (tid == 0) {
-      a.X[jj + (int64_t)jj * ld] = beta;
-      a.tau[jj] = tau;
-      a.T[jj + (int64_t)jj * a.ldt] = tau;
-    }
-    if (tid > jj && tid < IB) a.X[jj + (int64_t)tid * ld] = sv[IB + tid] - tau * wv[tid];
-    // T[u][jj] = -tau * sum_{v=u}^{jj-1} T[u][v] g_v
-    if (tid < jj) {
-      double s = 0.0;
-      for (int v = tid; v < jj; ++v) s += a.T[tid + (int64_t)v * a.ldt] * wv[v];
-      a.T[tid + (int64_t)jj * a.ldt] = -tau * s;
-    }
-  }
-  // 4. partials of the next column: each column's sum over this group's rows
-  // lives in one wave
-  if (more) {
-#pragma unroll
-    for (int u = 0; u < CPW; ++u) {
-      const double s = wave_sum(part[u]);
-      if (lane == 0) out[(int64_t)g * (2 * IB) + w + NW * u] = s;
-    }
-  }
-}
-
 // Split-K trailing update of a tall panel (V unit lower, h rows, IB columns)
 // applied to the nt columns right of it: grid (nt/32 column blocks) x S row
 // slices.  k_tall_apply_part writes each slice's V^T C into part;
@@ -660,6 +477,355 @@ __device__ __forceinline__ void tall_apply_upd_body(const PanelArgs& a, int nt, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Tall panels as a tree (TSQR) with Householder reconstruction (the tree and
+// its buffers are described with TsqrTree in qr.h).  Row split of n items
+// into parts balanced groups: group g covers [g base + min(g, rem), ...).
+__device__ __forceinline__ int tsqr_first(int n, int parts, int g) {
+  const int base = n / parts, rem = n % parts;
+  return g * base + min(g, rem);
+}
+__device__ __forceinline__ int tsqr_parent(int i, int n, int parts) {
+  const int base = n / parts, rem = n % parts, edge = rem * (base + 1);
+  return i < edge ? i / (base + 1) : rem + (i - edge) / base;
+}
+
+// Householder QR (larfg convention) of one block of at most kTsqrRows rows
+// and 16 columns: thread r holds row r.  Column j: one block reduction of
+// the 16 dot products of the column's tail (rows below j) with every column
+// gives the tail norm, the update coefficients w_t = x_jt + s d_t of the
+// later columns and the Gram entries of the forward T recurrence.  The wave
+// part of the reduction is a butterfly that halves the values at each
+// exchange (8 + 4 + 2 + 1 + 2 shuffles instead of 16 x 6).
+__device__ __forceinline__ void tsqr_qr_body(const TsqrTree& tr, int level, int node) {
+  constexpr int IB = kTsqrIB, NT = kTsqrRows, NW = NT / 64;
+  __shared__ double red[NW][IB];
+  __shared__ double piv[IB];
+  __shared__ double wv[IB];
+  __shared__ double sc[3];
+  __shared__ double Ts[IB][IB + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int L = tr.levels;
+  double* X;
+  int64_t ld;
+  int rows;
+  if (level == 0) {
+    const int s0 = tsqr_first(tr.h, tr.count[0], node), s1 = tsqr_first(tr.h, tr.count[0], node + 1);
+    X = tr.X + s0;
+    ld = tr.ldx;
+    rows = s1 - s0;
+  } else {
+    const int np = tr.count[level - 1], nc = tr.count[level];
+    const int c0 = tsqr_first(np, nc, node), c1 = tsqr_first(np, nc, node + 1);
+    ld = (int64_t)np * IB;
+    X = tr.S[level] + (int64_t)c0 * IB;
+    rows = (c1 - c0) * IB;
+  }
+  const bool own = tid < rows;
+  double x[IB];
+#pragma unroll
+  for (int t = 0; t < IB; ++t) x[t] = own ? X[tid + (int64_t)t * ld] : 0.0;
+  for (int e = tid; e < IB * (IB + 1); e += NT) (&Ts[0][0])[e] = 0.0;
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+#pragma unroll
+  for (int j = 0; j < IB; ++j) {
+    if (tid == j) {
+#pragma unroll
+      for (int t = 0; t < IB; ++t) piv[t] = x[t];
+    }
+    // d_t = sum over rows r > j of x_rj x_rt, reduced over the wave
+    const double xj = (own && tid > j) ? x[j] : 0.0;
+    double a8[8], a4[4], a2[2], a1;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double lo = xj * x[u], hi = xj * x[u + 8];
+      a8[u] = (b5 ? hi : lo) + __shfl_xor(b5 ? lo : hi, 32, 64);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a4[u] = (b4 ? a8[u + 4] : a8[u]) + __shfl_xor(b4 ? a8[u] : a8[u + 4], 16, 64);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) a2[u] = (b3 ? a4[u + 2] : a4[u]) + __shfl_xor(b3 ? a4[u] : a4[u + 2], 8, 64);
+    a1 = (b2 ? a2[1] : a2[0]) + __shfl_xor(b2 ? a2[0] : a2[1], 4, 64);
+    a1 += __shfl_xor(a1, 2, 64);
+    a1 += __shfl_xor(a1, 1, 64);
+    if ((lane & 3) == 0) red[wave][lane >> 2] = a1;
+    __syncthreads();
+    if (tid < IB) {
+      double d = 0.0, dj = 0.0;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) {
+        d += red[q][tid];
+        dj += red[q][j];
+      }
+      double beta, tau, scal;
+      larfg_scalars(piv[j], dj, &beta, &tau, &scal);
+      wv[tid] = piv[tid] + scal * d;   // t > j: w_t; t < j: Gram entry
+      if (tid == 0) {
+        sc[0] = beta;
+        sc[1] = tau;
+        sc[2] = scal;
+      }
+    }
+    __syncthreads();
+    const double beta = sc[0], tau = sc[1], scal = sc[2];
+    if (own && tid > j) {
+      const double v = x[j] * scal;
+#pragma unroll
+      for (int t = j + 1; t < IB; ++t) x[t] -= tau * wv[t] * v;
+      x[j] = v;
+    } else if (tid == j) {
+#pragma unroll
+      for (int t = j + 1; t < IB; ++t) x[t] -= tau * wv[t];
+      x[j] = beta;
+    }
+    // column j of T: T[u][j] = -tau sum_{v=u}^{j-1} T[u][v] g_v (row u is
+    // only touched by thread u)
+    if (tid < j) {
+      double s = 0.0;
+      for (int v = tid; v < j; ++v) s += Ts[tid][v] * wv[v];
+      Ts[tid][j] = -tau * s;
+    } else if (tid == j) {
+      Ts[j][j] = tau;
+    }
+  }
+  if (own) {
+#pragma unroll
+    for (int t = 0; t < IB; ++t) X[tid + (int64_t)t * ld] = x[t];
+  }
+  if (tid < IB) {
+    const int r = tid;
+    double* Tout;
+    int64_t ldt;
+    if (L == 0) {
+      Tout = tr.T;
+      ldt = tr.ldt;
+      tr.tau[r] = Ts[r][r];
+    } else {
+      Tout = tr.Tn[level] + (int64_t)node * IB * IB;
+      ldt = IB;
+    }
+    for (int c = r; c < IB; ++c) Tout[r + (int64_t)c * ldt] = Ts[r][c];
+    if (level < L) {
+      // R of this block into the next level's stack (zeros below the diagonal)
+      double* Rn = tr.S[level + 1] + (int64_t)node * IB;
+      const int64_t ldn = (int64_t)tr.count[level] * IB;
+#pragma unroll
+      for (int c = 0; c < IB; ++c) Rn[r + (int64_t)c * ldn] = c >= r ? x[c] : 0.0;
+    }
+    if (level == 0 && L > 0) {
+      double* Y1 = tr.Y1 + (int64_t)node * IB * IB;
+#pragma unroll
+      for (int c = 0; c < IB; ++c) Y1[r + c * IB] = c < r ? x[c] : (c == r ? 1.0 : 0.0);
+    }
+  }
+}
+
+// C of the leaf gg: the 16 rows of the explicit Q of each tree node above
+// it, from the root (C = I) down, C_child = E_j C - Y_j T Y_1^T C with Y_j
+// the node's reflector rows of child j and Y_1 its top (unit lower) block.
+// Thread (i, k) = (tid / 16, tid % 16) holds one element.
+__device__ __forceinline__ void tsqr_walk(const TsqrTree& tr, int gg, double (*C)[kTsqrIB + 1],
+                                          double (*P)[kTsqrIB + 1], double (*M)[kTsqrIB + 1]) {
+  constexpr int IB = kTsqrIB;
+  const int tid = threadIdx.x, i = tid >> 4, k = tid & 15;
+  C[i][k] = i == k ? 1.0 : 0.0;
+  __syncthreads();
+#pragma unroll 1
+  for (int l = tr.levels; l >= 1; --l) {
+    int child = gg;   // ancestor of gg at level l - 1
+#pragma unroll 1
+    for (int m = 1; m < l; ++m) child = tsqr_parent(child, tr.count[m - 1], tr.count[m]);
+    const int np = tr.count[l - 1], nc = tr.count[l];
+    const int node = tsqr_parent(child, np, nc);
+    const int fc = tsqr_first(np, nc, node);
+    const int j = child - fc;
+    const int64_t ld = (int64_t)np * IB;
+    const double* Y = tr.S[l] + (int64_t)fc * IB;
+    const double* T = tr.Tn[l] + (int64_t)node * IB * IB;
+    // fixed trip counts with masks: the loops unroll without versions
+    double s = C[i][k];
+#pragma unroll
+    for (int m = 0; m < IB; ++m)
+      if (m > i) s += Y[m + (int64_t)i * ld] * C[m][k];
+    P[i][k] = s;
+    __syncthreads();
+    s = 0.0;
+#pragma unroll
+    for (int m = 0; m < IB; ++m)
+      if (m >= i) s += T[i + m * IB] * P[m][k];
+    M[i][k] = s;
+    __syncthreads();
+    double cn;
+    if (j == 0) {
+      cn = C[i][k] - M[i][k];
+#pragma unroll
+      for (int m = 0; m < IB; ++m)
+        if (m < i) cn -= Y[i + (int64_t)m * ld] * M[m][k];
+    } else {
+      cn = 0.0;
+      const double* Yr = Y + (int64_t)j * IB + i;
+#pragma unroll
+      for (int m = 0; m < IB; ++m) cn -= Yr[(int64_t)m * ld] * M[m][k];
+    }
+    __syncthreads();
+    C[i][k] = cn;
+    __syncthreads();
+  }
+}
+
+// Leaf level of the same step: M = T_g Y1_g^T C (Y1_g explicit unit lower).
+__device__ __forceinline__ void tsqr_leaf_m(const TsqrTree& tr, int g, double (*C)[kTsqrIB + 1],
+                                            double (*P)[kTsqrIB + 1], double (*M)[kTsqrIB + 1]) {
+  constexpr int IB = kTsqrIB;
+  const int tid = threadIdx.x, i = tid >> 4, k = tid & 15;
+  const double* Y1 = tr.Y1 + (int64_t)g * IB * IB;
+  const double* T = tr.Tn[0] + (int64_t)g * IB * IB;
+  double s = 0.0;
+#pragma unroll
+  for (int m = 0; m < IB; ++m)
+    if (m >= i) s += Y1[m + i * IB] * C[m][k];
+  P[i][k] = s;
+  __syncthreads();
+  s = 0.0;
+#pragma unroll
+  for (int m = 0; m < IB; ++m)
+    if (m >= i) s += T[i + m * IB] * P[m][k];
+  M[i][k] = s;
+  __syncthreads();
+}
+
+// Final step for leaf g (levels >= 1): its rows of Q = H_g [C_g; 0], then
+// the reconstruction.  Q's top block A = Q(0:16, :) (leaf 0's first rows)
+// is factored A - D = L U with d_i = -sign of the current pivot, so that
+// the pivot U_ii = a_ii - d_i has magnitude at least 1; then the panel's
+// Householder vectors are [L; Q(16:, :) U^-1], T = -U D L^-T, tau = diag(T)
+// and R = D R_root.  Every leaf factors A itself (16 x 16, from leaf 0's
+// side copies), so the step is one launch; leaf 0 writes the top rows, T
+// and tau.
+__device__ __forceinline__ void tsqr_final_body(const TsqrTree& tr, int g) {
+  constexpr int IB = kTsqrIB;
+  __shared__ double Cb[IB][IB + 1];
+  __shared__ double Pb[IB][IB + 1];
+  __shared__ double Mb[IB][IB + 1];
+  __shared__ double A[IB][IB + 1];
+  __shared__ double Lb[IB][IB + 1];
+  __shared__ double dsg[IB], ipd[IB];
+  const int tid = threadIdx.x, i = tid >> 4, k = tid & 15;
+  const int s0 = tsqr_first(tr.h, tr.count[0], g), s1 = tsqr_first(tr.h, tr.count[0], g + 1);
+  const int rows = s1 - s0;
+  const bool own = tid < rows;
+  double* X = tr.X + s0;
+  const int64_t ld = tr.ldx;
+  // 1. Q's top block from leaf 0, and its signed LU
+  tsqr_walk(tr, 0, Cb, Pb, Mb);
+  tsqr_leaf_m(tr, 0, Cb, Pb, Mb);
+  {
+    const double* Y10 = tr.Y1;
+    double a = Cb[i][k];
+#pragma unroll
+    for (int m = 0; m < IB; ++m)
+      if (m <= i) a -= Y10[i + m * IB] * Mb[m][k];
+    A[i][k] = a;
+    Lb[i][k] = i == k ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int c = 0; c < IB; ++c) {
+    const double acc = A[c][c];
+    const double d = acc >= 0.0 ? -1.0 : 1.0;
+    const double p = acc - d;
+    const double aic = A[i][c], aci = A[c][k];
+    __syncthreads();
+    if (i > c) {
+      const double l = aic / p;
+      if (k == c) Lb[i][c] = l;
+      else if (k > c) A[i][k] -= l * aci;
+    }
+    if (tid == 0) {
+      dsg[c] = d;
+      ipd[c] = 1.0 / p;
+      A[c][c] = p;
+    }
+    __syncthreads();
+  }
+  // 2. this leaf's C and M
+  tsqr_walk(tr, g, Cb, Pb, Mb);
+  tsqr_leaf_m(tr, g, Cb, Pb, Mb);
+  // 3. rows of the reconstructed reflectors: (E - y M) U^-1 with E this
+  // row of [C_g; 0] and y its row of the leaf's reflectors (unit lower).
+  // W = M U^-1 and E U^-1 (= C_g U^-1 on the leaf's first rows) are formed
+  // once, by forward substitution, so that every row is one product with W.
+  if (tid < 2 * IB) {
+    double (*src)[IB + 1] = tid < IB ? Mb : Cb;
+    const int r = tid & 15;
+    for (int t = 0; t < IB; ++t) {
+      double s = src[r][t];
+      for (int m = 0; m < t; ++m) s -= src[r][m] * A[m][t];
+      src[r][t] = s * ipd[t];
+    }
+  }
+  __syncthreads();
+  if (own) {
+    if (s0 + tid >= IB) {
+      double y[IB];
+#pragma unroll
+      for (int t = 0; t < IB; ++t) {
+        const double v = X[tid + (int64_t)t * ld];
+        y[t] = tid > t ? v : (tid == t ? 1.0 : 0.0);
+      }
+#pragma unroll
+      for (int t = 0; t < IB; ++t) {
+        double z = (tid < IB) ? Cb[tid][t] : 0.0;
+#pragma unroll
+        for (int m = 0; m < IB; ++m) z -= y[m] * Mb[m][t];
+        X[tid + (int64_t)t * ld] = z;
+      }
+    } else {
+      // top rows (leaf 0): L below the diagonal, D R_root on and above it
+      const int r = tid;
+      const double* Rr = tr.S[tr.levels];
+      const int64_t ldr = (int64_t)tr.count[tr.levels - 1] * IB;
+#pragma unroll
+      for (int t = 0; t < IB; ++t)
+        X[r + (int64_t)t * ld] = t < r ? Lb[r][t] : dsg[r] * Rr[r + (int64_t)t * ldr];
+    }
+  }
+  // 4. T = -U D L^-T and tau (leaf 0): row r solves t L^T = -(U D)_r (the
+  // row is built in Pb, which only thread r touches)
+  if (g == 0 && tid < IB) {
+    const int r = tid;
+    for (int c = 0; c < IB; ++c) {
+      double s = c >= r ? -A[r][c] * dsg[c] : 0.0;
+      for (int m = 0; m < c; ++m) s -= Pb[r][m] * Lb[c][m];
+      Pb[r][c] = s;
+    }
+    for (int c = r; c < IB; ++c) tr.T[r + (int64_t)c * tr.ldt] = Pb[r][c];
+    tr.tau[r] = Pb[r][r];
+  }
+}
+
+__device__ __forceinline__ int tsqr_item(const TsqrItem* items, int n, int wg) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].wg_begin <= wg) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kTsqrRows, 6) void k_tsqr_qr(const TsqrTree* __restrict__ trees,
+                                                       const TsqrItem* __restrict__ items, int n) {
+  const int it = tsqr_item(items, n, blockIdx.x);
+  const TsqrItem I = items[it];
+  tsqr_qr_body(trees[I.tree], I.level, blockIdx.x - I.wg_begin);
+}
+__global__ __launch_bounds__(kTsqrRows, 6) void k_tsqr_final(const TsqrTree* __restrict__ trees,
+                                                          const TsqrItem* __restrict__ items, int n) {
+  const int it = tsqr_item(items, n, blockIdx.x);
+  const TsqrItem I = items[it];
+  tsqr_final_body(trees[I.tree], blockIdx.x - I.wg_begin);
+}
+
 // Batched copy of column-major blocks (gather / scatter of the stacked
 // block column), and the explicit unit-lower form of a packed reflector block.
 __global__ void k_copy_blocks(const CopyDesc* __restrict__ d) {
@@ -716,14 +882,6 @@ template <int IB>
 __global__ __launch_bounds__(256) void k_panel_apply(PanelArgs a, int nt) { panel_apply_body<IB>(a, nt, blockIdx.x); }
 __global__ __launch_bounds__(256) void k_t_backsolve(TBackArgs a) { t_backsolve_body(a, blockIdx.x); }
 template <int IB>
-__global__ __launch_bounds__(kTallThreads) void k_tall_first(TallArgs a) {
-  tall_first_body<IB>(a, gridDim.x, blockIdx.x);
-}
-template <int IB>
-__global__ __launch_bounds__(kTallThreads) void k_tall_step(TallArgs a) {
-  tall_step_body<IB>(a, gridDim.x, blockIdx.x);
-}
-template <int IB>
 __global__ __launch_bounds__(256) void k_tall_apply_part(PanelArgs a, int nt, double* part) {
   tall_apply_part_body<IB>(a, nt, part, blockIdx.x, blockIdx.y, gridDim.x, gridDim.y);
 }
@@ -754,20 +912,6 @@ __global__ __launch_bounds__(256) void k_t_backsolve_batch(const PanelJob* __res
   t_backsolve_body(a, blockIdx.x);
 }
 template <int IB>
-__global__ __launch_bounds__(kTallThreads) void k_tall_first_batch(const PanelJob* __restrict__ jobs) {
-  const TallArgs a = jobs[blockIdx.y].t;
-  const int G = jobs[blockIdx.y].groups;
-  if ((int)blockIdx.x >= G) return;
-  tall_first_body<IB>(a, G, blockIdx.x);
-}
-template <int IB>
-__global__ __launch_bounds__(kTallThreads) void k_tall_step_batch(const PanelJob* __restrict__ jobs) {
-  const TallArgs a = jobs[blockIdx.y].t;
-  const int G = jobs[blockIdx.y].groups;
-  if ((int)blockIdx.x >= G) return;
-  tall_step_body<IB>(a, G, blockIdx.x);
-}
-template <int IB>
 __global__ __launch_bounds__(256) void k_tall_apply_part_batch(const PanelJob* __restrict__ jobs) {
   const PanelJob& J = jobs[blockIdx.z];
   const PanelArgs a = J.a;
@@ -788,20 +932,6 @@ __global__ __launch_bounds__(256) void k_tall_apply_upd_batch(const PanelJob* __
 
 }  // namespace
 
-hipError_t launch_tall_column(const TallArgs& a, int groups, hipStream_t stream) {
-  if (groups < 1 || groups > kTallMaxGroups) return hipErrorInvalidValue;
-  if (a.ib == 32) {
-    if (a.jj == 0) hipLaunchKernelGGL(k_tall_first<32>, dim3(groups), dim3(kTallThreads), 0, stream, a);
-    hipLaunchKernelGGL(k_tall_step<32>, dim3(groups), dim3(kTallThreads), 0, stream, a);
-  } else if (a.ib == 16) {
-    if (a.jj == 0) hipLaunchKernelGGL(k_tall_first<16>, dim3(groups), dim3(kTallThreads), 0, stream, a);
-    hipLaunchKernelGGL(k_tall_step<16>, dim3(groups), dim3(kTallThreads), 0, stream, a);
-  } else {
-    return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
 hipError_t launch_tall_apply(const PanelArgs& a, int nt, int slices, double* part, hipStream_t stream) {
   if (nt <= 0) return hipSuccess;
   if (slices < 1 || slices > kTallApplySlices) return hipErrorInvalidValue;
@@ -815,6 +945,19 @@ hipError_t launch_tall_apply(const PanelArgs& a, int nt, int slices, double* par
   } else {
     return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_tsqr_qr(const TsqrTree* trees, const TsqrItem* items, int n, int total_wg, hipStream_t stream) {
+  if (n <= 0 || total_wg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tsqr_qr, dim3(total_wg), dim3(kTsqrRows), 0, stream, trees, items, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_tsqr_final(const TsqrTree* trees, const TsqrItem* items, int n, int total_wg,
+                             hipStream_t stream) {
+  if (n <= 0 || total_wg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tsqr_final, dim3(total_wg), dim3(kTsqrRows), 0, stream, trees, items, n);
   return hipGetLastError();
 }
 
@@ -910,23 +1053,6 @@ hipError_t launch_t_backsolve_batch(const PanelJob* d, int n, int max_n, hipStre
   if (n <= 0 || max_n <= 0) return hipSuccess;
   dim3 grid((max_n + 3) / 4, n), block(256);
   hipLaunchKernelGGL(k_t_backsolve_batch, grid, block, (size_t)4 * max_n * sizeof(double), stream, d);
-  return hipGetLastError();
-}
-
-hipError_t launch_tall_column_batch(const PanelJob* d, int n, int ib, int first, int max_groups,
-                                    hipStream_t stream) {
-  if (n <= 0) return hipSuccess;
-  if (max_groups < 1 || max_groups > kTallMaxGroups) return hipErrorInvalidValue;
-  dim3 grid(max_groups, n), block(kTallThreads);
-  if (ib == 32) {
-    if (first) hipLaunchKernelGGL(k_tall_first_batch<32>, grid, block, 0, stream, d);
-    hipLaunchKernelGGL(k_tall_step_batch<32>, grid, block, 0, stream, d);
-  } else if (ib == 16) {
-    if (first) hipLaunchKernelGGL(k_tall_first_batch<16>, grid, block, 0, stream, d);
-    hipLaunchKernelGGL(k_tall_step_batch<16>, grid, block, 0, stream, d);
-  } else {
-    return hipErrorInvalidValue;
-  }
   return hipGetLastError();
 }
 

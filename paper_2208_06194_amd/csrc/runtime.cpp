@@ -273,6 +273,8 @@ void Plan::upload(DevAlloc& a, HostKeep& keep, hipStream_t s) {
   d_tjobs = upload_array(tjobs, a, keep, s);
   d_lincs = upload_array(lincs, a, keep, s);
   d_frobs = upload_array(frobs, a, keep, s);
+  d_trees = upload_array(trees, a, keep, s);
+  d_titems = upload_array(titems, a, keep, s);
 }
 
 size_t Plan::upload_bytes() const {
@@ -288,6 +290,8 @@ size_t Plan::upload_bytes() const {
   add(tjobs.size() * sizeof(TrsmJob));
   add(lincs.size() * sizeof(LincombDesc));
   add(frobs.size() * sizeof(Frob2Desc));
+  add(trees.size() * sizeof(TsqrTree));
+  add(titems.size() * sizeof(TsqrItem));
   return n;
 }
 
@@ -416,10 +420,6 @@ void enqueue(blr_matrix h, const Plan& P, const Op& o, hipStream_t q, bool multi
         HIPCHECK(launch_recompress(P.d_rcs + o.off, o.n, rc_params(h), q));
         h->launches += 1;
         break;
-      case Op::TALL_COL:
-        HIPCHECK(launch_tall_column(o.tall, o.n, q));
-        h->launches += 2;
-        break;
       case Op::TALL_APPLY:
         HIPCHECK(launch_tall_apply(o.panel, o.ntiles, o.n, o.buf, q));
         h->launches += 2;
@@ -439,10 +439,6 @@ void enqueue(blr_matrix h, const Plan& P, const Op& o, hipStream_t q, bool multi
       case Op::TBACK_B:
         HIPCHECK(launch_t_backsolve_batch(P.d_jobs + o.off, o.n, o.ext, q));
         h->launches += 1;
-        break;
-      case Op::TALL_COL_B:
-        HIPCHECK(launch_tall_column_batch(P.d_jobs + o.off, o.n, o.ib, o.first, o.ext, q));
-        h->launches += o.first ? 2 : 1;
         break;
       case Op::TALL_APPLY_B:
         HIPCHECK(launch_tall_apply_batch(P.d_jobs + o.off, o.n, o.ib, o.ext, o.ext2, q));
@@ -469,6 +465,14 @@ void enqueue(blr_matrix h, const Plan& P, const Op& o, hipStream_t q, bool multi
         break;
       case Op::MGS_STACK:
         HIPCHECK(launch_mgs_stack(o.mgs.X, o.mgs.ldx, o.mgs.h, o.mgs.w, o.mgs.R, o.mgs.ldr, q));
+        h->launches += 1;
+        break;
+      case Op::TSQR_QR:
+        HIPCHECK(launch_tsqr_qr(P.d_trees, P.d_titems + o.off, o.n, o.ext, q));
+        h->launches += 1;
+        break;
+      case Op::TSQR_FIN:
+        HIPCHECK(launch_tsqr_final(P.d_trees, P.d_titems + o.off, o.n, o.ext, q));
         h->launches += 1;
         break;
       case Op::WAIT:
@@ -938,7 +942,6 @@ struct BcSlot {
 struct BcWork {
   double* stack = nullptr;      // m x b
   double* Yf[2] = {nullptr, nullptr};  // b x b explicit unit-lower Y_kk (steps alternate)
-  double* tallpart = nullptr;   // 2 x (kTallMaxGroups + 1) x 64
   double* gpart = nullptr;      // kGramSlices x b x b split-K Gram partials
   int64_t gpart_doubles = 0;
   double* wblk = nullptr;       // 128 x b: W of a block reflector
@@ -946,8 +949,81 @@ struct BcWork {
   double* wpart = nullptr;      // kApplySlices x 128 x b split-K partials of W
   double* zpart = nullptr;      // kZSlices x b x b partial sums of the look-ahead column's Z
   double* applypart = nullptr;  // kTallApplySlices x ceil(b/32) x 32 x 32
+  double* tsqr = nullptr;       // tree buffers of a tall panel (tsqr_doubles)
   std::vector<BcSlot> slots;
 };
+
+// Leaves and tree levels of a tall panel of h rows (TsqrTree in qr.h).
+int tsqr_levels(int64_t h, int* count) {
+  int L = 0;
+  count[0] = (int)((h + kTsqrRows - 1) / kTsqrRows);
+  while (count[L] > 1) {
+    if (L == kTsqrMaxLevels) throw Error(BLR_ERR_INVALID, "tall panel exceeds the tree depth");
+    count[L + 1] = (count[L] + kTsqrFan - 1) / kTsqrFan;
+    ++L;
+  }
+  return L;
+}
+
+// Doubles of the tree buffers for panels of up to h rows.
+size_t tsqr_doubles(int64_t h) {
+  int count[kTsqrMaxLevels + 1];
+  const int L = tsqr_levels(h, count);
+  constexpr size_t blk = (size_t)kTsqrIB * kTsqrIB;
+  size_t n = 2 * (size_t)count[0] * blk;
+  for (int l = 1; l <= L; ++l) n += ((size_t)count[l - 1] + count[l]) * blk;
+  return n;
+}
+
+// QR of a tall panel (X: pivot of kTsqrIB columns, h rows, ld ldx) as a tree:
+// one QR launch per level, then the reconstruction of the panel's
+// reflectors, T (ld ldt) and tau.  buf holds tsqr_doubles(h) doubles.
+void plan_tsqr(Plan& P, double* buf, double* X, int64_t ldx, int h, double* T, int64_t ldt, double* tau,
+               double flops) {
+  TsqrTree t{};
+  t.X = X;
+  t.ldx = ldx;
+  t.h = h;
+  t.T = T;
+  t.ldt = ldt;
+  t.tau = tau;
+  const int L = tsqr_levels(h, t.count);
+  t.levels = L;
+  constexpr size_t blk = (size_t)kTsqrIB * kTsqrIB;
+  double* p = buf;
+  t.Y1 = p;
+  p += (size_t)t.count[0] * blk;
+  t.Tn[0] = p;
+  p += (size_t)t.count[0] * blk;
+  for (int l = 1; l <= L; ++l) {
+    t.S[l] = p;
+    p += (size_t)t.count[l - 1] * blk;
+    t.Tn[l] = p;
+    p += (size_t)t.count[l] * blk;
+  }
+  const int idx = (int)P.trees.size();
+  P.trees.push_back(t);
+  for (int l = 0; l <= L; ++l) {
+    Op o;
+    o.kind = Op::TSQR_QR;
+    o.off = (int)P.titems.size();
+    o.n = 1;
+    o.ext = t.count[l];
+    o.flops = (L == 0) ? flops : 0.0;
+    P.titems.push_back(TsqrItem{idx, l, 0, 0});
+    P.push(o);
+  }
+  if (L > 0) {
+    Op o;
+    o.kind = Op::TSQR_FIN;
+    o.off = (int)P.titems.size();
+    o.n = 1;
+    o.ext = t.count[0];
+    o.flops = flops;
+    P.titems.push_back(TsqrItem{idx, 0, 0, 0});
+    P.push(o);
+  }
+}
 
 // Is Z_j = sum_{i >= i0} Ytilde_ik^T A_ij dense (some term dense: OP1)?  The
 // Householder step sums from i0 = k, the Gram-Schmidt step from i0 = 0; the
@@ -998,7 +1074,6 @@ BcWork make_bc_work(blr_matrix h, int npairs) {
   bw.stack = (double*)A.alloc((size_t)h->m * b * 8);
   bw.Yf[0] = (double*)A.alloc((size_t)b * b * 8);
   bw.Yf[1] = (double*)A.alloc((size_t)b * b * 8);
-  bw.tallpart = (double*)A.alloc((size_t)2 * (kTallMaxGroups + 1) * 64 * 8);
   bw.gpart_doubles = (int64_t)kGramSlices * b * b;
   bw.gpart = (double*)A.alloc((size_t)bw.gpart_doubles * 8);
   bw.wblk = (double*)A.alloc((size_t)128 * b * 8);
@@ -1006,6 +1081,7 @@ BcWork make_bc_work(blr_matrix h, int npairs) {
   bw.wpart = (double*)A.alloc((size_t)kApplySlices * 128 * b * 8);
   bw.zpart = (double*)A.alloc((size_t)kZSlices * b * b * 8);
   bw.applypart = (double*)A.alloc((size_t)kTallApplySlices * ((b + 31) / 32) * 32 * 32 * 8);
+  bw.tsqr = (double*)A.alloc(tsqr_doubles(h->m) * 8);
   const size_t rcwd = rc_work_doubles(b, rc);
   const size_t per = 2 * (size_t)b * rc + (size_t)rc * b + (size_t)rc * rc + rcwd;
   if (npairs > 0) {
@@ -1111,16 +1187,17 @@ void plan_block_apply(Plan& P, BcWork& bw, const double* X, double* C, int64_t l
 
 // Householder QR of the hs x b stack (ld hs) into T (b x b) and tau.
 // Stacks of up to 512 (ib 32) or 1024 (ib 16) rows stay in the registers of
-// the one-workgroup panel kernel.  Taller stacks: 32-column sub-panels by
-// the row-split column kernels, each applied within its 128-column block by
-// the split-K sub-panel update; each finished 128-column block is applied to
-// the rest of the stack as a block reflector on the matrix cores.
+// the one-workgroup panel kernel.  Taller stacks: 16-column sub-panels
+// factored as a tree (TSQR, a few launches each, with the Householder
+// vectors reconstructed), each applied within its 128-column block by the
+// split-K sub-panel update; each finished 128-column block is applied to the
+// rest of the stack as a block reflector on the matrix cores.
 void plan_stack_qr(Plan& P, blr_matrix h, Work& w, BcWork& bw, int hs, double* T, double* tau) {
   const int b = h->b;
   double* X = bw.stack;
   const bool tall = hs > 1024;
   int ib = (hs > 512 && !tall) ? 16 : std::min(32, h->ib);
-  if (tall) ib = 16;   // 16-column sub-panels: the column kernel's rows stay in registers at 512 threads
+  if (tall) ib = kTsqrIB;   // 16-column sub-panels factored as a tree of 256-row blocks
   if (b % ib) ib = 16;
   ib = std::min(ib, b);
   const int OB = (tall && b % 128 == 0) ? 128 : b;   // outer block of the tall path
@@ -1146,15 +1223,7 @@ void plan_stack_qr(Plan& P, blr_matrix h, Work& w, BcWork& bw, int hs, double* T
           P.ops.back().flops = 4.0 * hl * ib * nt;
         }
       } else {
-        const int G = std::min(kTallMaxGroups, std::max(1, (hl + 511) / 512));
-        for (int jj = 0; jj < ib; ++jj) {
-          Op o;
-          o.kind = Op::TALL_COL;
-          o.tall = TallArgs{a.X, (int64_t)hs, hl, ib, jj, bw.tallpart, a.T, (int64_t)b, a.tau};
-          o.n = G;
-          o.flops = 4.0 * hl * ib;
-          P.push(o);
-        }
+        plan_tsqr(P, bw.tsqr, a.X, hs, hl, a.T, b, a.tau, 4.0 * hl * ib * ib);
         if (nt > 0) {
           Op o;
           o.kind = Op::TALL_APPLY;
@@ -1181,7 +1250,7 @@ void plan_stack_qr(Plan& P, blr_matrix h, Work& w, BcWork& bw, int hs, double* T
 // Panel of block-column step k (Section 3.3.1): gather the stack
 // [A_kk; Av_{k+1,k}; ...] (Av = A for dense tiles, V^T for low-rank tiles)
 // into one column-major buffer, take its Householder QR (the tile panel
-// kernels while it has at most 1024 rows, the row-split kernels otherwise),
+// kernels while it has at most 1024 rows, the tree (TSQR) kernels otherwise),
 // build T_k and scatter R_kk and the reflector rows Y_ik back into the tiles,
 // with an explicit unit-lower copy of Y_kk.
 void plan_bc_panel(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k) {
@@ -1537,8 +1606,9 @@ bool op_launches(const Op& o) {
     case Op::GEMM:
     case Op::RC: return o.n > 0;
     case Op::COPY: return o.n > 0 && o.maxel > 0;
-    case Op::PANEL:
-    case Op::TALL_COL: return true;
+    case Op::PANEL: return true;
+    case Op::TSQR_QR:
+    case Op::TSQR_FIN: return o.n > 0 && o.ext > 0;
     case Op::PANEL_APPLY: return o.n > 0;
     case Op::TBACK: return o.tback.n > o.tback.ib;
     case Op::TALL_APPLY: return o.ntiles > 0;
@@ -1559,7 +1629,6 @@ OpSig op_sig(const Op& o) {
     case Op::PANEL: g.a = o.panel.ib; g.b = panel_bucket(o.panel.h); break;
     case Op::PANEL_APPLY:
     case Op::TALL_APPLY: g.a = o.panel.ib; break;
-    case Op::TALL_COL: g.a = o.tall.ib; g.b = o.tall.jj == 0; break;
     case Op::TRSM: g.a = o.n; break;
     default: break;
   }
@@ -1640,6 +1709,29 @@ void emit_merged(Plan& M, const std::vector<Plan>& plans, const std::vector<blr_
         m.n += o.n;
       }
       break;
+    case Op::TSQR_QR:
+    case Op::TSQR_FIN: {
+      // the items' trees are copied into the merged plan; workgroups are
+      // numbered across all items
+      m.off = (int)M.titems.size();
+      int wg = 0;
+      for (auto& sp : src) {
+        const Plan& pl = plans[sp.first];
+        const Op& o = pl.ops[sp.second];
+        for (int x = 0; x < o.n; ++x) {
+          TsqrItem it = pl.titems[(size_t)o.off + x];
+          M.trees.push_back(pl.trees[it.tree]);
+          it.tree = (int)M.trees.size() - 1;
+          it.wg_begin = wg;
+          wg += o0.kind == Op::TSQR_QR ? M.trees.back().count[it.level] : M.trees.back().count[0];
+          M.titems.push_back(it);
+          m.n += 1;
+        }
+        m.flops += o.flops;
+      }
+      m.ext = wg;
+      break;
+    }
     case Op::TRSM:
       if (single) {
         m = o0;
@@ -1684,14 +1776,6 @@ void emit_merged(Plan& M, const std::vector<Plan>& plans, const std::vector<blr_
             m.kind = Op::TBACK_B;
             j.tb = o.tback;
             m.ext = std::max(m.ext, o.tback.n);
-            break;
-          case Op::TALL_COL:
-            m.kind = Op::TALL_COL_B;
-            j.t = o.tall;
-            j.groups = o.n;
-            m.ib = o.tall.ib;
-            m.first = o.tall.jj == 0;
-            m.ext = std::max(m.ext, o.n);
             break;
           case Op::TALL_APPLY:
             m.kind = Op::TALL_APPLY_B;

@@ -75,13 +75,16 @@ using HostKeep = std::vector<std::vector<char>>;
 // One enqueued operation of a plan.
 struct Op {
   enum Kind {
-    GEMM, PANEL, PANEL_APPLY, TBACK, RC, TRSM, WAIT, RECORD, TALL_COL, TALL_APPLY, COPY,
+    GEMM, PANEL, PANEL_APPLY, TBACK, RC, TRSM, WAIT, RECORD, TALL_APPLY, COPY,
     // batched forms of the panel kernels (jobs [off, off + n) of the plan)
-    PANEL_B, PANEL_APPLY_B, TBACK_B, TALL_COL_B, TALL_APPLY_B,
+    PANEL_B, PANEL_APPLY_B, TBACK_B, TALL_APPLY_B,
     // solve steps: batched triangular solves, linear combinations, squared norms
     TRSM_B, LINCOMB, FROB2,
     // the Gram-Schmidt comparison method: QR of a stacked block column
-    MGS_STACK
+    MGS_STACK,
+    // tall panels as a tree: one level's QR launch, the reconstruction
+    // (items [off, off + n) of the plan, ext workgroups)
+    TSQR_QR, TSQR_FIN
   } kind;
   int off = 0, n = 0, ntiles = 0, big = 0, fp32 = 0, prof = 0;
   int ib = 0, ext = 0, ext2 = 0, first = 0;   // batched panel ops: width, largest extents, first column
@@ -90,7 +93,6 @@ struct Op {
   double flops = 0.0;
   PanelArgs panel{};
   TBackArgs tback{};
-  TallArgs tall{};
   TrsmJob trsm{};         // TRSM: the solve (n: 1 = with R^T)
   double* buf = nullptr;   // TALL_APPLY: partial sums
   int64_t maxel = 0;       // COPY: largest block
@@ -114,6 +116,10 @@ struct Plan {
   std::vector<TrsmJob> tjobs;
   std::vector<LincombDesc> lincs;
   std::vector<Frob2Desc> frobs;
+  std::vector<TsqrTree> trees;
+  std::vector<TsqrItem> titems;
+  TsqrTree* d_trees = nullptr;
+  TsqrItem* d_titems = nullptr;
   CopyDesc* d_copies = nullptr;
   PanelJob* d_jobs = nullptr;
   TrsmJob* d_tjobs = nullptr;

@@ -5,7 +5,7 @@ factored alone by blr_qr_factor, and agree with the oracle's block-column
 factor (Alg. 2 with Section 3.3) like the single-matrix path.  The members
 cover every panel path: stacks of up to 512 rows (32-column register
 panels), up to 1024 rows (16-column register panels), taller stacks
-(row-split column kernels) and, with 256-column tiles, 128-column blocks
+(tree panels, batched across members) and, with 256-column tiles, 128-column blocks
 applied as block reflectors; low-rank reflector rows and recompressions come
 from the kernel matrices' far-field tiles."""
 import numpy as np

@@ -2,9 +2,11 @@
 application (Alg. 3): the HIP path through the C ABI against the oracle's
 block-column factor on the same seeded inputs.  Stacks of up to 512 rows
 take the one-workgroup panel kernel with 32-column panels, up to 1024 rows
-with 16-column panels, taller stacks the row-split kernels (and, for tiles of
-256 or more columns, 128-column blocks applied as block reflectors): the
-shapes below cover all of them and ragged stacks of low-rank row factors."""
+with 16-column panels.  Taller stacks factor 16-column panels as a tree of
+blocks of at most 256 rows with the Householder vectors reconstructed, and
+(for tiles of 256 or more columns) apply 128-column blocks as block
+reflectors.  The shapes below cover all of them, trees of one to three
+levels above the leaves, and ragged stacks of low-rank row factors."""
 import numpy as np
 import pytest
 
@@ -41,9 +43,11 @@ def kernel_blr(seed, m, n, b, eps, cap, kern="inv_r", dim=3, rule="dist_gt_diam"
     (256, 128, 64),     # stacks <= 512 rows: 32-column register panels
     (768, 256, 64),     # 512 < rows <= 1024: 16-column register panels
     (192, 96, 48),      # b not a multiple of 32
-    (2048, 128, 64),    # stacks of 2048 .. 1984 rows: row-split panels
+    (2048, 128, 64),    # stacks of 2048 .. 1984 rows: one-level tree panels
     (1536, 512, 128),   # tall first stacks, register panels for the last
     (2048, 512, 256),   # tall stacks with b = 256: 128-column blocks applied as block reflectors
+    (65536, 64, 64),    # a 256-leaf panel: two tree levels above the leaves
+    (70016, 128, 64),   # 274 leaves: three tree levels, ragged leaf and node groups
 ])
 def test_all_dense_blockcol_matches_oracle(P, m, n, b):
     print("case: blockcol all dense", m, n, b, flush=True)
