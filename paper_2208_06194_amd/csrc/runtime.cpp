@@ -234,6 +234,7 @@ void Plan::flush_gemm(int fp32, int prof, bool allow_fast) {
   segs.insert(segs.end(), curseg.begin(), curseg.end());
   o.ntiles = tiles;
   o.stream = cur_stream;
+  o.prio = cur_prio;
   ops.push_back(o);
   cur.clear();
   curseg.clear();
@@ -247,6 +248,7 @@ void Plan::flush_rc() {
   o.off = (int)rcs.size();
   o.n = (int)currc.size();
   o.stream = cur_stream;
+  o.prio = cur_prio;
   rcs.insert(rcs.end(), currc.begin(), currc.end());
   ops.push_back(o);
   currc.clear();
@@ -317,6 +319,9 @@ RcParams rc_params(blr_matrix h) {
 }
 
 constexpr int kStreams = 4;
+// block columns of the tiled factor in flight at once (one chain each; the
+// chains are merged into one launch list)
+constexpr int kTiledChains = 32;
 
 // Calls on one handle.  Every call that enqueues work records h->idle on the
 // caller's stream at its end (after the handle's own streams have been
@@ -533,6 +538,15 @@ struct Work {
   std::vector<double*> rcw;                 // recompression workspaces (2 per j)
 };
 
+// Device bytes make_work(h, nrhs_cols) takes.
+size_t work_bytes(blr_matrix h, int nrhs_cols) {
+  const size_t b = h->b, rc = h->rc, q = std::max(h->q, 1);
+  const size_t wcols = std::max<size_t>(b, nrhs_cols);
+  const size_t d = 2 * b * wcols + b * b + 2 * q * b * wcols + q * (5 * b * rc + 3 * rc * b + 2 * rc * rc) +
+                   2 * q * rc_work_doubles((int)b, (int)rc);
+  return d * 8 + q * sizeof(int);
+}
+
 Work make_work(blr_matrix h, int nrhs_cols) {
   Work w;
   const int b = h->b, rc = h->rc, q = std::max(h->q, 1);
@@ -642,6 +656,7 @@ void plan_tiled(blr_matrix h, Plan& P, std::vector<Work>& works, int kend, bool 
   auto ev = [&](int i, int k) { return i * q + k; };
   for (int k = 0; k < kend; ++k) {
     P.cur_stream = k % ns;
+    P.cur_prio = k;
     Work& w = works[k % ns];
     if (k > 0) P.wait(ev(k, k - 1));
     Tile& Dkk = h->t(k, k);
@@ -1636,9 +1651,9 @@ OpSig op_sig(const Op& o) {
 }
 
 // One merged op from the ops src[a] = (plan, op index), all of one signature.
-void emit_merged(Plan& M, const std::vector<Plan>& plans, const std::vector<blr_matrix>& hs,
+void emit_merged(Plan& M, const std::vector<const Plan*>& plans, const std::vector<blr_matrix>& hs,
                  const std::vector<std::pair<int, int>>& src) {
-  const Op& o0 = plans[src[0].first].ops[src[0].second];
+  const Op& o0 = plans[src[0].first]->ops[src[0].second];
   Op m;
   m.kind = o0.kind;
   m.stream = 0;
@@ -1651,7 +1666,7 @@ void emit_merged(Plan& M, const std::vector<Plan>& plans, const std::vector<blr_
       m.prof = o0.prof;
       m.off = (int)M.descs.size();
       for (auto& sp : src) {
-        const Plan& S = plans[sp.first];
+        const Plan& S = *plans[sp.first];
         const Op& o = S.ops[sp.second];
         for (int d = o.off; d < o.off + o.n; ++d) {
           GemmDesc e = S.descs[d];
@@ -1669,7 +1684,7 @@ void emit_merged(Plan& M, const std::vector<Plan>& plans, const std::vector<blr_
     case Op::RC:
       m.off = (int)M.rcs.size();
       for (auto& sp : src) {
-        const Plan& S = plans[sp.first];
+        const Plan& S = *plans[sp.first];
         const Op& o = S.ops[sp.second];
         for (int d = o.off; d < o.off + o.n; ++d) {
           RcDesc e = S.rcs[d];
@@ -1683,7 +1698,7 @@ void emit_merged(Plan& M, const std::vector<Plan>& plans, const std::vector<blr_
     case Op::COPY:
       m.off = (int)M.copies.size();
       for (auto& sp : src) {
-        const Plan& S = plans[sp.first];
+        const Plan& S = *plans[sp.first];
         const Op& o = S.ops[sp.second];
         M.copies.insert(M.copies.end(), S.copies.begin() + o.off, S.copies.begin() + o.off + o.n);
         m.n += o.n;
@@ -1693,7 +1708,7 @@ void emit_merged(Plan& M, const std::vector<Plan>& plans, const std::vector<blr_
     case Op::LINCOMB:
       m.off = (int)M.lincs.size();
       for (auto& sp : src) {
-        const Plan& S = plans[sp.first];
+        const Plan& S = *plans[sp.first];
         const Op& o = S.ops[sp.second];
         M.lincs.insert(M.lincs.end(), S.lincs.begin() + o.off, S.lincs.begin() + o.off + o.n);
         m.n += o.n;
@@ -1703,7 +1718,7 @@ void emit_merged(Plan& M, const std::vector<Plan>& plans, const std::vector<blr_
     case Op::FROB2:
       m.off = (int)M.frobs.size();
       for (auto& sp : src) {
-        const Plan& S = plans[sp.first];
+        const Plan& S = *plans[sp.first];
         const Op& o = S.ops[sp.second];
         M.frobs.insert(M.frobs.end(), S.frobs.begin() + o.off, S.frobs.begin() + o.off + o.n);
         m.n += o.n;
@@ -1716,7 +1731,7 @@ void emit_merged(Plan& M, const std::vector<Plan>& plans, const std::vector<blr_
       m.off = (int)M.titems.size();
       int wg = 0;
       for (auto& sp : src) {
-        const Plan& pl = plans[sp.first];
+        const Plan& pl = *plans[sp.first];
         const Op& o = pl.ops[sp.second];
         for (int x = 0; x < o.n; ++x) {
           TsqrItem it = pl.titems[(size_t)o.off + x];
@@ -1742,7 +1757,7 @@ void emit_merged(Plan& M, const std::vector<Plan>& plans, const std::vector<blr_
       m.first = o0.n;   // transposed solves
       m.off = (int)M.tjobs.size();
       for (auto& sp : src) {
-        const Op& o = plans[sp.first].ops[sp.second];
+        const Op& o = plans[sp.first]->ops[sp.second];
         M.tjobs.push_back(o.trsm);
         m.n += 1;
         m.ext = std::max(m.ext, o.trsm.nrhs);
@@ -1756,7 +1771,7 @@ void emit_merged(Plan& M, const std::vector<Plan>& plans, const std::vector<blr_
       }
       m.off = (int)M.jobs.size();
       for (auto& sp : src) {
-        const Op& o = plans[sp.first].ops[sp.second];
+        const Op& o = plans[sp.first]->ops[sp.second];
         PanelJob j{};
         switch (o.kind) {
           case Op::PANEL:
@@ -1814,6 +1829,8 @@ Plan merge_plans(const std::vector<Plan>& plans, const std::vector<blr_matrix>& 
   for (int i = 0; i < nb; ++i)
     if (!chain[i].empty()) hsig[i] = op_sig(plans[i].ops[chain[i][0]]);
   Plan M;
+  std::vector<const Plan*> pp(nb);
+  for (int i = 0; i < nb; ++i) pp[i] = &plans[i];
   std::vector<std::pair<OpSig, int64_t>> score;
   std::vector<std::pair<int, int>> src;
   for (;;) {
@@ -1838,11 +1855,87 @@ Plan merge_plans(const std::vector<Plan>& plans, const std::vector<blr_matrix>& 
     src.clear();
     for (int i = 0; i < nb; ++i)
       if (head[i] < chain[i].size() && hsig[i] == g) src.push_back({i, chain[i][head[i]]});
-    emit_merged(M, plans, hs, src);
+    emit_merged(M, pp, hs, src);
     for (auto& sp : src) {
       const int i = sp.first;
       if (++head[i] < chain[i].size()) hsig[i] = op_sig(plans[i].ops[chain[i][head[i]]]);
     }
+  }
+  return M;
+}
+
+// One launch list from a plan on several streams (the tiled factor's task
+// graph): each stream's ops form a chain, and a wait on an event holds its
+// chain until the op recording that event has been reached in the recording
+// chain.  Each round advances every chain whose head is ready by one op: the
+// ready ops are grouped by kernel and shape, and each group is one batched
+// launch, the group holding the oldest block column (the critical path)
+// first.  Rounds run in order on one stream, so every dependency of the plan
+// holds, and every job is computed exactly as by its own launch.
+Plan merge_streams(const Plan& P, blr_matrix h) {
+  int ns = 1;
+  for (const Op& o : P.ops) ns = std::max(ns, o.stream + 1);
+  std::vector<std::vector<int>> chain(ns);
+  for (int x = 0; x < (int)P.ops.size(); ++x) {
+    const Op& o = P.ops[x];
+    if (o.kind == Op::WAIT || o.kind == Op::RECORD || op_launches(o)) chain[o.stream].push_back(x);
+  }
+  std::vector<size_t> head(ns, 0);
+  std::vector<char> rec(std::max(P.n_events, 1), 0);
+  const std::vector<const Plan*> pp{&P};
+  const std::vector<blr_matrix> hv{h};
+  Plan M;
+  std::vector<std::pair<int, int>> src;
+  std::vector<int> ready;
+  for (;;) {
+    // pass records and satisfied waits until nothing moves
+    bool moved = true;
+    while (moved) {
+      moved = false;
+      for (int c = 0; c < ns; ++c)
+        while (head[c] < chain[c].size()) {
+          const Op& o = P.ops[chain[c][head[c]]];
+          if (o.kind == Op::RECORD) {
+            rec[o.event] = 1;
+          } else if (o.kind == Op::WAIT) {
+            if (!rec[o.event]) break;
+          } else {
+            break;
+          }
+          ++head[c];
+          moved = true;
+        }
+    }
+    // the ready heads, grouped by kernel and shape, oldest group first
+    ready.clear();
+    bool blocked = false;
+    for (int c = 0; c < ns; ++c) {
+      if (head[c] >= chain[c].size()) continue;
+      const Op& o = P.ops[chain[c][head[c]]];
+      if (o.kind == Op::WAIT) blocked = true;
+      else ready.push_back(c);
+    }
+    if (ready.empty()) {
+      if (blocked) throw Error(BLR_ERR_DEVICE, "internal: merged plan waits on an event never recorded");
+      break;
+    }
+    std::sort(ready.begin(), ready.end(), [&](int a, int b2) {
+      const int pa = P.ops[chain[a][head[a]]].prio, pb = P.ops[chain[b2][head[b2]]].prio;
+      return pa < pb || (pa == pb && a < b2);
+    });
+    std::vector<char> done(ready.size(), 0);
+    for (size_t r = 0; r < ready.size(); ++r) {
+      if (done[r]) continue;
+      const OpSig g = op_sig(P.ops[chain[ready[r]][head[ready[r]]]]);
+      src.clear();
+      for (size_t t = r; t < ready.size(); ++t)
+        if (!done[t] && op_sig(P.ops[chain[ready[t]][head[ready[t]]]]) == g) {
+          src.push_back({0, chain[ready[t]][head[ready[t]]]});
+          done[t] = 1;
+        }
+      emit_merged(M, pp, hv, src);
+    }
+    for (int c : ready) ++head[c];
   }
   return M;
 }
@@ -2411,7 +2504,15 @@ int prepare_factor(blr_matrix h, const blr_factor_opts* o, hipStream_t s, Plan& 
     }
   }
   std::vector<Work> works;
-  const int nstreams = bc ? 1 : kStreams;
+  int nstreams = bc ? 1 : std::min(q, kTiledChains);
+  if (!bc) {
+    // each chain holds a workspace of two b x b blocks per tile column: keep
+    // them within half of the free device memory
+    size_t fr = 0, tot = 0;
+    HIPCHECK(hipMemGetInfo(&fr, &tot));
+    const size_t per = work_bytes(h, 0);
+    while (nstreams > 4 && (size_t)nstreams * per > fr / 2) nstreams /= 2;
+  }
   for (int a = 0; a < nstreams; ++a) works.push_back(make_work(h, 0));
   h->n_fill = 0;
   if (bc) {
@@ -2419,6 +2520,7 @@ int prepare_factor(blr_matrix h, const blr_factor_opts* o, hipStream_t s, Plan& 
     plan_blockcol(h, P, works[0], bw, kend, o->precision == BLR_MIXED_FP32, lookahead);
   } else {
     plan_tiled(h, P, works, kend, o->precision == BLR_MIXED_FP32);
+    P = merge_streams(P, h);
   }
   h->flops = 0.0;
   for (auto& op : P.ops) h->flops += op.flops;

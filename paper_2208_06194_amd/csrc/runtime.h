@@ -89,6 +89,7 @@ struct Op {
   int off = 0, n = 0, ntiles = 0, big = 0, fp32 = 0, prof = 0;
   int ib = 0, ext = 0, ext2 = 0, first = 0;   // batched panel ops: width, largest extents, first column
   int stream = 0;   // index into the plan's streams
+  int prio = 0;     // merge order of a multi-stream plan: lower goes first (the block column)
   int event = -1;   // WAIT / RECORD: event index
   double flops = 0.0;
   PanelArgs panel{};
@@ -134,6 +135,7 @@ struct Plan {
   double curflops = 0.0;
   std::vector<RcDesc> currc;
   int cur_stream = 0;
+  int cur_prio = 0;
   int n_events = 0;
 
   // add one descriptor with a single K segment
@@ -148,7 +150,11 @@ struct Plan {
   void flush_gemm(int fp32 = 0, int prof = 0, bool allow_fast = true);
   void rc(const RcDesc& d) { currc.push_back(d); }
   void flush_rc();
-  void push(Op o) { o.stream = cur_stream; ops.push_back(o); }
+  void push(Op o) {
+    o.stream = cur_stream;
+    o.prio = cur_prio;
+    ops.push_back(o);
+  }
   void panel(const PanelArgs& a) { Op o; o.kind = Op::PANEL; o.panel = a; push(o); }
   void panel_apply(const PanelArgs& a, int nt) { Op o; o.kind = Op::PANEL_APPLY; o.panel = a; o.n = nt; push(o); }
   void tback(const TBackArgs& a) { Op o; o.kind = Op::TBACK; o.tback = a; push(o); }
