@@ -33,13 +33,16 @@ def gpu_import(P, blr, eps, cap):
     return P.BLRMatrix.import_tiles(blr.m, blr.n, blr.b, eps, cap, fmt, rank, dense, Uh, Vh)
 
 
-@pytest.mark.parametrize("m,n,b", [(64, 64, 32), (256, 128, 64), (192, 96, 48), (512, 256, 64), (256, 256, 128)])
+@pytest.mark.parametrize("m,n,b", [(64, 64, 32), (256, 128, 64), (192, 96, 48), (512, 256, 64), (256, 256, 128),
+                                   # wide tiles: 8 and 16 panels of 32 columns per tile QR
+                                   (768, 512, 256), (1024, 512, 512)])
 def test_all_dense_tiled_matches_oracle(lib, m, n, b):
     log_case(test="all_dense", m=m, n=n, b=b)
     A = np.random.default_rng(m + b).standard_normal((m, n))
-    blr = blrmat.compress(A, b, 1e-12, b, np.zeros((m // b, n // b), bool))
-    f = tiled.factor(blr, 1e-12, b)
-    G = gpu_import(lib, blr, 1e-12, b)
+    cap = min(b, 128)
+    blr = blrmat.compress(A, b, 1e-12, cap, np.zeros((m // b, n // b), bool))
+    f = tiled.factor(blr, 1e-12, cap)
+    G = gpu_import(lib, blr, 1e-12, cap)
     G.factor("tiled")
     ex = G.export(with_factor=True)
     kappa = np.linalg.cond(A)
@@ -75,6 +78,7 @@ CASES = [
     (0, 512, 256, 64, 1e-8, 16, "log2d", 2, "adjacent"),
     (1, 512, 256, 32, 1e-8, 32, "inv_r", 3, "dist_gt_diam"),
     (2, 384, 192, 48, 1e-6, 16, "log2d", 2, "weak"),
+    (3, 1024, 512, 256, 1e-6, 64, "log2d", 2, "weak"),   # b = 256 with low-rank tiles: TPQRT on [R; V^T]
 ]
 
 
