@@ -494,16 +494,18 @@ __device__ __forceinline__ int tsqr_parent(int i, int n, int parts) {
 // and 16 columns: thread r holds row r.  Column j: one block reduction of
 // the 16 dot products of the column's tail (rows below j) with every column
 // gives the tail norm, the update coefficients w_t = x_jt + s d_t of the
-// later columns and the Gram entries of the forward T recurrence.  The wave
-// part of the reduction is a butterfly that halves the values at each
-// exchange (8 + 4 + 2 + 1 + 2 shuffles instead of 16 x 6).
+// later columns and the Gram entries g_v = Y_v^T v_j of the T recurrence.
+// The wave part of the reduction is a butterfly that halves the values at
+// each exchange (8 + 4 + 2 + 1 + 2 shuffles instead of 16 x 6); the four
+// wave partials and the pivot row go through double-buffered LDS, and every
+// thread forms the larfg scalars itself, so a column costs one barrier.  T is
+// formed after the last column from the saved Gram entries and taus.
 __device__ __forceinline__ void tsqr_qr_body(const TsqrTree& tr, int level, int node) {
   constexpr int IB = kTsqrIB, NT = kTsqrRows, NW = NT / 64;
-  __shared__ double red[NW][IB];
-  __shared__ double piv[IB];
-  __shared__ double wv[IB];
-  __shared__ double sc[3];
-  __shared__ double Ts[IB][IB + 1];
+  __shared__ double red[2][NW][IB];
+  __shared__ double piv[2][IB];
+  __shared__ double Gs[IB][IB + 1];   // Gs[v][j]: Gram entry of reflector v with reflector j
+  __shared__ double taus[IB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int L = tr.levels;
   double* X;
@@ -525,13 +527,13 @@ __device__ __forceinline__ void tsqr_qr_body(const TsqrTree& tr, int level, int 
   double x[IB];
 #pragma unroll
   for (int t = 0; t < IB; ++t) x[t] = own ? X[tid + (int64_t)t * ld] : 0.0;
-  for (int e = tid; e < IB * (IB + 1); e += NT) (&Ts[0][0])[e] = 0.0;
   const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
 #pragma unroll
   for (int j = 0; j < IB; ++j) {
+    const int bf = j & 1;
     if (tid == j) {
 #pragma unroll
-      for (int t = 0; t < IB; ++t) piv[t] = x[t];
+      for (int t = 0; t < IB; ++t) piv[bf][t] = x[t];
     }
     // d_t = sum over rows r > j of x_rj x_rt, reduced over the wave
     const double xj = (own && tid > j) ? x[j] : 0.0;
@@ -548,63 +550,42 @@ __device__ __forceinline__ void tsqr_qr_body(const TsqrTree& tr, int level, int 
     a1 = (b2 ? a2[1] : a2[0]) + __shfl_xor(b2 ? a2[0] : a2[1], 4, 64);
     a1 += __shfl_xor(a1, 2, 64);
     a1 += __shfl_xor(a1, 1, 64);
-    if ((lane & 3) == 0) red[wave][lane >> 2] = a1;
+    if ((lane & 3) == 0) red[bf][wave][lane >> 2] = a1;
     __syncthreads();
-    if (tid < IB) {
-      double d = 0.0, dj = 0.0;
+    // every thread: the larfg scalars of column j (the same sums in the same
+    // order in every thread)
+    double dj = 0.0;
 #pragma unroll
-      for (int q = 0; q < NW; ++q) {
-        d += red[q][tid];
-        dj += red[q][j];
-      }
-      double beta, tau, scal;
-      larfg_scalars(piv[j], dj, &beta, &tau, &scal);
-      wv[tid] = piv[tid] + scal * d;   // t > j: w_t; t < j: Gram entry
-      if (tid == 0) {
-        sc[0] = beta;
-        sc[1] = tau;
-        sc[2] = scal;
-      }
-    }
-    __syncthreads();
-    const double beta = sc[0], tau = sc[1], scal = sc[2];
-    if (own && tid > j) {
-      const double v = x[j] * scal;
-#pragma unroll
-      for (int t = j + 1; t < IB; ++t) x[t] -= tau * wv[t] * v;
-      x[j] = v;
-    } else if (tid == j) {
-#pragma unroll
-      for (int t = j + 1; t < IB; ++t) x[t] -= tau * wv[t];
-      x[j] = beta;
-    }
-    // column j of T: T[u][j] = -tau sum_{v=u}^{j-1} T[u][v] g_v (row u is
-    // only touched by thread u)
+    for (int q = 0; q < NW; ++q) dj += red[bf][q][j];
+    double beta, tau, scal;
+    larfg_scalars(piv[bf][j], dj, &beta, &tau, &scal);
     if (tid < j) {
-      double s = 0.0;
-      for (int v = tid; v < j; ++v) s += Ts[tid][v] * wv[v];
-      Ts[tid][j] = -tau * s;
+      double d = 0.0;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) d += red[bf][q][tid];
+      Gs[tid][j] = piv[bf][tid] + scal * d;
     } else if (tid == j) {
-      Ts[j][j] = tau;
+      taus[j] = tau;
+    }
+    if (own && tid >= j) {
+      const double v = tid > j ? x[j] * scal : 1.0;
+#pragma unroll
+      for (int t = j + 1; t < IB; ++t) {
+        double d = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) d += red[bf][q][t];
+        x[t] -= tau * (piv[bf][t] + scal * d) * v;
+      }
+      x[j] = tid > j ? v : beta;
     }
   }
   if (own) {
 #pragma unroll
     for (int t = 0; t < IB; ++t) X[tid + (int64_t)t * ld] = x[t];
   }
+  __syncthreads();
   if (tid < IB) {
     const int r = tid;
-    double* Tout;
-    int64_t ldt;
-    if (L == 0) {
-      Tout = tr.T;
-      ldt = tr.ldt;
-      tr.tau[r] = Ts[r][r];
-    } else {
-      Tout = tr.Tn[level] + (int64_t)node * IB * IB;
-      ldt = IB;
-    }
-    for (int c = r; c < IB; ++c) Tout[r + (int64_t)c * ldt] = Ts[r][c];
     if (level < L) {
       // R of this block into the next level's stack (zeros below the diagonal)
       double* Rn = tr.S[level + 1] + (int64_t)node * IB;
@@ -616,6 +597,27 @@ __device__ __forceinline__ void tsqr_qr_body(const TsqrTree& tr, int level, int 
       double* Y1 = tr.Y1 + (int64_t)node * IB * IB;
 #pragma unroll
       for (int c = 0; c < IB; ++c) Y1[r + c * IB] = c < r ? x[c] : (c == r ? 1.0 : 0.0);
+    }
+    // row r of T: T[r][r] = tau_r, T[r][j] = -tau_j sum_{v=r}^{j-1} T[r][v] g_v^(j)
+    double* Tout;
+    int64_t ldt;
+    if (L == 0) {
+      Tout = tr.T;
+      ldt = tr.ldt;
+      tr.tau[r] = taus[r];
+    } else {
+      Tout = tr.Tn[level] + (int64_t)node * IB * IB;
+      ldt = IB;
+    }
+    double trow[IB];
+#pragma unroll
+    for (int jj = 0; jj < IB; ++jj) {
+      double sum = 0.0;
+#pragma unroll
+      for (int v = 0; v < jj; ++v)
+        if (v >= r) sum += trow[v] * Gs[v][jj];
+      trow[jj] = jj < r ? 0.0 : (jj == r ? taus[r] : -taus[jj] * sum);
+      if (jj >= r) Tout[r + (int64_t)jj * ldt] = trow[jj];
     }
   }
 }
