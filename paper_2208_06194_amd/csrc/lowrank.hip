@@ -211,8 +211,11 @@ __device__ void record_overflow(const RcParams& P, unsigned long long* own, doub
 
 __global__ __launch_bounds__(256) void k_recompress(const RcDesc* __restrict__ descs, RcParams P) {
   __shared__ double red[16];
-  __shared__ double zl[RC_LDS_DIM * RC_LDS_DIM];
-  __shared__ double jl[RC_LDS_DIM * RC_LDS_DIM];
+  // the core Z and the rotations J in LDS up to order RC_LDS_DIM; beyond
+  // that (up to order 135) Z alone, J in global memory
+  __shared__ double zjl[2 * RC_LDS_DIM * RC_LDS_DIM];
+  double* zl = zjl;
+  double* jl = zjl + RC_LDS_DIM * RC_LDS_DIM;
   __shared__ double sig[384];
   __shared__ int perm[384];
   __shared__ int ranks[3];
@@ -304,6 +307,12 @@ __global__ __launch_bounds__(256) void k_recompress(const RcDesc* __restrict__ d
     }
   }
   __syncthreads();
+  if (!lds && (int64_t)k * k <= 2 * RC_LDS_DIM * RC_LDS_DIM) {
+    // the rotations touch Z's columns four times for each of J's: Z into LDS
+    for (int e = tid; e < k * k; e += 256) zjl[e] = Zg[e];
+    __syncthreads();
+    Z = zjl;
+  }
   wg_jacobi(Z, ldz, k, k, J, ldj, &flag);
   wg_sort_sigma(Z, ldz, k, k, sig, perm);
   if (tid == 0) {
