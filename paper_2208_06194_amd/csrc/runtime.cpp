@@ -3242,28 +3242,70 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
       const double u = 2.220446049250313e-16;
       std::vector<double> hn(2 * nrhs), prev(nrhs, HUGE_VAL);
       std::vector<char> active(nrhs, 1), take(nrhs, 0);
-      for (int it = 0; it < max_refine; ++it) {
-        {  // f = b - r - A~ x,  g = -A~^T r
-          Plan P;
-          plan_matmul(h, P, BLR_MATMUL_A, Xw, ldxw, f, m, nrhs);
-          plan_matmul(h, P, BLR_MATMUL_AT, r, m, g, n, nrhs);
-          run_plan(h, P, s);
+      // one refinement step as one launch list, planned and uploaded once:
+      // f = b - r - A~ x, g = -A~^T r; d = Q^T f; h = R^{-T} g;
+      // dr = Q [h; d_2]; dx = R^{-1} (d_1 - h); the squared norms of dx and x
+      auto lc = [](double* out, int64_t ldo, const double* x, int64_t lx, const double* y, int64_t ly,
+                   const double* z, int64_t lz, double a, double b, double c, int64_t rows, int cols) {
+        return LincombDesc{out, ldo, x, lx, y, ly, z, lz, a, b, c, (int32_t)rows, cols};
+      };
+      Plan RP;
+      const RsolveWork rw = make_rsolve_work(h, nrhs);
+      plan_matmul(h, RP, BLR_MATMUL_A, Xw, ldxw, f, m, nrhs);
+      plan_matmul(h, RP, BLR_MATMUL_AT, r, m, g, n, nrhs);
+      RP.lincomb(lc(f, m, Bw, ldbw, r, m, f, m, 1.0, -1.0, -1.0, m, nrhs));
+      plan_apply(h, RP, w, f, m, nrhs, 0);
+      RP.lincomb(lc(g, n, g, n, nullptr, 0, nullptr, 0, -1.0, 0.0, 0.0, n, nrhs));
+      plan_rsolve(h, RP, rw, g, n, nrhs, 1);
+      RP.lincomb(lc(dr, m, g, n, nullptr, 0, nullptr, 0, 1.0, 0.0, 0.0, n, nrhs));
+      RP.lincomb(lc(dr + n, m, f + n, m, nullptr, 0, nullptr, 0, 1.0, 0.0, 0.0, m - n, nrhs));
+      plan_apply(h, RP, w, dr, m, nrhs, 1);
+      RP.lincomb(lc(f, m, f, m, g, n, nullptr, 0, 1.0, -1.0, 0.0, n, nrhs));
+      plan_rsolve(h, RP, rw, f, m, nrhs, 0);
+      {
+        std::vector<Frob2Desc> fr(2 * nrhs);
+        for (int c = 0; c < nrhs; ++c) {
+          fr[c] = Frob2Desc{f + (int64_t)c * m, m, (int32_t)n, 1, nrm + c};
+          fr[nrhs + c] = Frob2Desc{Xw + (int64_t)c * ldxw, ldxw, (int32_t)n, 1, nrm + nrhs + c};
         }
-        HIPCHECK(launch_lincomb(f, m, Bw, ldbw, r, m, f, m, 1.0, -1.0, -1.0, (int)m, nrhs, s));
-        // d = Q^T f (in f);  h = R^{-T} g with g = -A~^T r (in g)
-        apply(f, 0);
-        HIPCHECK(launch_lincomb(g, n, g, n, nullptr, 0, nullptr, 0, -1.0, 0.0, 0.0, (int)n, nrhs, s));
-        run_rsolve(h, g, n, nrhs, 1, s);
-        // dr = Q [h; d_2]
-        HIPCHECK(launch_lincomb(dr, m, g, n, nullptr, 0, nullptr, 0, 1.0, 0.0, 0.0, (int)n, nrhs, s));
-        HIPCHECK(launch_lincomb(dr + n, m, f + n, m, nullptr, 0, nullptr, 0, 1.0, 0.0, 0.0, (int)(m - n), nrhs, s));
-        apply(dr, 1);
-        // dx = R^{-1} (d_1 - h)  (in f[0:n])
-        HIPCHECK(launch_lincomb(f, m, f, m, g, n, nullptr, 0, 1.0, -1.0, 0.0, (int)n, nrhs, s));
-        run_rsolve(h, f, m, nrhs, 0, s);
-        // ||dx|| and ||x|| decide which columns take the step
-        frob2(f, m, n, nrm);
-        frob2(Xw, ldxw, n, nrm + nrhs);
+        RP.frob2(fr);
+      }
+      RP.upload(h->work, h->keep, s);
+      // the step is captured into a graph on one of the handle's own streams
+      // (capturing launches nothing; the caller's stream may be the legacy
+      // default stream, which cannot be captured) and replayed on s; every
+      // op is a kernel, so the graph holds kernel nodes only
+      ensure_streams(h);
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t gexec = nullptr;
+      int64_t step_launches = 0;
+      {
+        const bool prof = h->prof_on;
+        h->prof_on = false;
+        const int64_t l0 = h->launches;
+        hipStream_t cs = h->streams[0];
+        HIPCHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        struct CaptureGuard {   // an error inside the capture still ends it
+          hipStream_t st;
+          bool open = true;
+          ~CaptureGuard() {
+            if (!open) return;
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(st, &g);
+            if (g) (void)hipGraphDestroy(g);
+          }
+        } guard{cs};
+        execute(h, RP, cs);
+        guard.open = false;
+        HIPCHECK(hipStreamEndCapture(cs, &graph));
+        h->prof_on = prof;
+        step_launches = h->launches - l0;
+        h->launches = l0;
+        HIPCHECK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+      }
+      for (int it = 0; it < max_refine; ++it) {
+        HIPCHECK(hipGraphLaunch(gexec, s));
+        h->launches += step_launches;
         HIPCHECK(hipMemcpyAsync(hn.data(), nrm, 2 * nrhs * 8, hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
         const bool done = refine_decide(hn, prev, active, take, nrhs, u);
@@ -3277,6 +3319,8 @@ blr_status blr_lstsq_solve(blr_matrix h, const double* B, int64_t ldb, double* X
         }
         if (done) break;
       }
+      HIPCHECK(hipGraphExecDestroy(gexec));
+      HIPCHECK(hipGraphDestroy(graph));
       if (resid_norms) frob2(r, m, m, resid_norms);
     }
     if (Xw != X) HIPCHECK(hipMemcpy2DAsync(X, ldx * 8, Xw, ldxw * 8, h->nu * 8, nrhs, hipMemcpyDeviceToDevice, s));

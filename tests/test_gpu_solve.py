@@ -295,6 +295,26 @@ def test_refinement_stops_when_corrections_stop_halving(P):
     assert np.all(np.linalg.norm(X10 - X1, axis=0) <= d1 * (1 + 1e-9) + 1e-300)
 
 
+def test_refinement_graph_replays_match_eager_steps(P):
+    """The single solve captures one refinement step into a graph and replays
+    it, with the step decisions and updates as ordinary launches between the
+    replays; the batched solve runs the same steps as ordinary launches.
+    Repeated solves on one handle (each capturing its own graph, other calls
+    in between) give the batched solve's result bit for bit every time."""
+    print("case: refinement graph replays", flush=True)
+    m, n, b, eps, cap = 1024, 512, 128, 1e-10, 32
+    A, blr = kernel_blr(15, m, n, b, eps, cap)
+    G = gpu_import(P, blr, eps, cap)
+    G.factor("block_column", precision="mixed", keep_a=True)
+    Bd = torch.tensor(synth.rhs(15, m, 3), device="cuda")
+    ref = P.lstsq_batch([G], [Bd], max_refine=6)[0]
+    for _ in range(3):
+        X = G.lstsq(Bd, max_refine=6)
+        G.apply_qt(Bd)
+        torch.cuda.synchronize()
+        assert torch.equal(X, ref)
+
+
 def test_refinement_requires_the_kept_copy(P):
     m, n, b, eps, cap = 256, 128, 64, 1e-8, 16
     A, blr = kernel_blr(14, m, n, b, eps, cap)
