@@ -583,11 +583,47 @@ Work make_work(blr_matrix h, int nrhs_cols) {
   return w;
 }
 
+// From this order up the full T of a tile QR is built by doubling; below it
+// one back-substitution launch is cheaper than the 2 log2(n / ib) products.
+constexpr int kTDoublingMin = 512;
+
+// The full upper triangular T (n x n, ld ldt) of n reflectors from its ib x ib
+// diagonal blocks (already in T) and the Gram matrix G = Y^T Y (strictly lower
+// part read, ld ldg), by recursive doubling on the matrix cores (the compact
+// WY merge of Schreiber and Van Loan): for adjacent blocks B1, B2 of width s
+// (B2 possibly narrower at the end) T(B1, B2) = -T(B1, B1) G(B1, B2) T(B2, B2),
+// for s = ib, 2 ib, 4 ib, ...; every level is two batched products
+// (G(B2, B1)^T T22 into Mb, then -T11 Mb).  Mb needs n * n / 4 doubles.  T11
+// is read as upper triangular with the zeros stored below its diagonal, which
+// T's storage keeps.
+
+void plan_t_doubling(Plan& P, const double* G, int64_t ldg, double* T, int64_t ldt, int n, int ib, double* Mb) {
+  for (int s = ib; s < n; s *= 2) {
+    size_t off = 0;
+    std::vector<std::pair<int, size_t>> pairs;
+    for (int a = 0; a + s < n; a += 2 * s) {
+      const int s2 = std::min(s, n - a - s);
+      P.gemm(Mb + off, s, nullptr, 0, nullptr, 0, s, s2, 1.0, 0.0, G + (a + s) + (int64_t)a * ldg, ldg,
+             T + (a + s) + (int64_t)(a + s) * ldt, ldt, s2, SEG_TRANS_A);
+      pairs.push_back({a, off});
+      off += (size_t)s * s2;
+    }
+    P.flush_gemm();
+    for (auto [a, o] : pairs) {
+      const int s2 = std::min(s, n - a - s);
+      P.gemm(T + a + (int64_t)(a + s) * ldt, ldt, nullptr, 0, nullptr, 0, s, s2, -1.0, 0.0, T + a + (int64_t)a * ldt,
+             ldt, Mb + o, s, s, SEG_A_UPPER);
+    }
+    P.flush_gemm();
+  }
+}
+
 // Householder QR of one tile (GEQRT, Section 3.4.1) or of [R; B] (TPQRT,
 // Section 3.4.3), with inner blocking ib: a panel kernel generates ib
 // reflectors and their T block, three products update the rest of the tile,
 // and at the end the off-diagonal blocks of the full T come from the Gram
-// matrix of all reflectors.
+// matrix of all reflectors (by doubling for large tiles, else by one
+// back-substitution).
 void plan_tile_qr(Plan& P, blr_matrix h, Work& w, bool tp, double* X, int64_t ldx, int hb, double* R,
                   double* T, double* tau) {
   const int b = h->b;
@@ -629,16 +665,20 @@ void plan_tile_qr(Plan& P, blr_matrix h, Work& w, bool tp, double* X, int64_t ld
       P.gemm(w.Wg, b, nullptr, 0, nullptr, 0, b, b, 1.0, 0.0, X, ldx, X, ldx, hb, SEG_TRANS_A,
              DESC_LOWER_ONLY);
     P.flush_gemm();
-    TBackArgs t{};
-    t.n = b;
-    t.ib = ib;
-    t.G = w.Wg;
-    t.ldg = b;
-    t.tau = tau;
-    t.T = T;
-    t.ldt = b;
-    P.tback(t);
-    P.ops.back().flops = (double)b * b * b / 3.0;
+    if (b >= kTDoublingMin) {
+      plan_t_doubling(P, w.Wg, b, T, b, b, ib, w.Wx2);
+    } else {
+      TBackArgs t{};
+      t.n = b;
+      t.ib = ib;
+      t.G = w.Wg;
+      t.ldg = b;
+      t.tau = tau;
+      t.T = T;
+      t.ldt = b;
+      P.tback(t);
+      P.ops.back().flops = (double)b * b * b / 3.0;
+    }
   }
 }
 
