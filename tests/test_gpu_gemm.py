@@ -97,3 +97,14 @@ def test_gemm_fp32_long_k_accumulates_in_fp64(lib, flags):
     rel = np.linalg.norm(out - ref) / np.linalg.norm(ref)
     print("normwise error / 2^-24:", rel / 2.0 ** -24, flush=True)
     assert rel <= 24 * 2.0 ** -24
+
+
+@pytest.mark.parametrize("flags", [0, 1, 2])
+@pytest.mark.parametrize("K", [1040, 2064, 3072])
+def test_gemm_fp32_long_k_alpha_beta_in_place(lib, flags, K):
+    """FP32 operands with K over 1024, alpha = 0.5 and beta = 2 with C both
+    input and output: the FP64 sums of the 1024-long chunks are added into the
+    output tile, the first addition starting from beta C.  K = 1040 and 2064
+    end on a partial chunk."""
+    print("case: gemm fp32 long K alpha beta", flags, K, flush=True)
+    assert run(lib, flags, 256, 384, K, fp32=1) <= 4 * 1024 * 2.0 ** -24
