@@ -191,6 +191,9 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   }
 }
 
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const d2v gd2v;
+
 // Skinny products (N <= 16, FP64): the applications of Q^T / Q and the
 // back-substitution sums with a few right-hand sides.  These read each tile of
 // A once and do 2 * N flops per element, so they are bound by HBM; the
@@ -200,7 +203,11 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
 // order.  Operands go straight from global memory into the MFMA registers:
 // for A transposed a lane reads four consecutive k of one column (lane group
 // g takes k = 4g .. 4g + 3 of each block and steps through them), otherwise
-// sixteen lanes read sixteen consecutive rows of one k column.
+// sixteen lanes read sixteen consecutive rows of one k column.  On full
+// 64-row tiles of segments whose K is a multiple of 16 (no unit-lower mask,
+// 16-byte aligned operands, even leading dimensions) each wave keeps the
+// next K block's loads in flight while it multiplies the current one, and
+// the four consecutive k of a lane are read as two 16-byte vectors.
 template <bool TA>
 __global__ __launch_bounds__(256) void k_gemm_skinny(const GemmDesc* __restrict__ descs, int ndesc,
                                                      const GemmSeg* __restrict__ segs) {
@@ -216,7 +223,8 @@ __global__ __launch_bounds__(256) void k_gemm_skinny(const GemmDesc* __restrict_
   const GemmDesc d = descs[lo];
   const int m0 = (wg - d.tile_begin) * BM;
   const int M = d.M, N = d.N;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: K-block loops run on scalars
   const int lm = lane & 15, lg = lane >> 4;
   v4d acc[BM / 16];
 #pragma unroll
@@ -233,6 +241,62 @@ __global__ __launch_bounds__(256) void k_gemm_skinny(const GemmDesc* __restrict_
     const double* __restrict__ Ap = sg.A;
     const double* __restrict__ Bp = sg.B;
     const int64_t lda = sg.lda, ldb = sg.ldb;
+    const bool fast = !aul && m0 + BM <= M && kend % BKS == 0 && ((lda | ldb) & 1) == 0 &&
+                      (((uintptr_t)Ap | (uintptr_t)Bp) & 15) == 0;
+    if (fast) {
+      // every load has a valid address (column min(lm, N - 1), the last block
+      // again past the end), so each K block issues the same loads and the
+      // wait before its products covers exactly the block before it
+      const int bcol = min(lm, N - 1);
+      auto ld = [&](int k0, double (&av)[BM / 16][4], double (&bv)[4]) {
+        const int kb = k0 + 4 * lg;
+        const d2v b0 = *(const gd2v*)(Bp + kb + (int64_t)bcol * ldb);
+        const d2v b1 = *(const gd2v*)(Bp + kb + 2 + (int64_t)bcol * ldb);
+        bv[0] = b0[0]; bv[1] = b0[1]; bv[2] = b1[0]; bv[3] = b1[1];
+#pragma unroll
+        for (int i = 0; i < BM / 16; ++i) {
+          const int m = m0 + 16 * i + lm;
+          if (TA) {
+            const d2v a0 = *(const gd2v*)(Ap + kb + (int64_t)m * lda);
+            const d2v a1 = *(const gd2v*)(Ap + kb + 2 + (int64_t)m * lda);
+            av[i][0] = a0[0]; av[i][1] = a0[1]; av[i][2] = a1[0]; av[i][3] = a1[1];
+          } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) av[i][u] = Ap[m + (int64_t)(kb + u) * lda];
+          }
+        }
+      };
+      auto mm = [&](const double (&av)[BM / 16][4], const double (&bv)[4]) {
+        const bool live = lm < N;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double bu = live ? bv[u] : 0.0;
+#pragma unroll
+          for (int i = 0; i < BM / 16; ++i) acc[i] = mfma_op(av[i][u], bu, acc[i]);
+        }
+      };
+      int k0 = kbeg + wave * BKS;
+      if (k0 < kend) {
+        double a0[BM / 16][4], b0[4], a1[BM / 16][4], b1[4];
+        ld(k0, a0, b0);
+        for (;;) {
+          // the scheduling barriers keep each block's loads ahead of the
+          // products of the block before it
+          const int k1 = k0 + 4 * BKS;
+          ld(k1 < kend ? k1 : k0, a1, b1);
+          __builtin_amdgcn_sched_barrier(0);
+          mm(a0, b0);
+          if (k1 >= kend) break;
+          const int k2 = k1 + 4 * BKS;
+          ld(k2 < kend ? k2 : k1, a0, b0);
+          __builtin_amdgcn_sched_barrier(0);
+          mm(a1, b1);
+          if (k2 >= kend) break;
+          k0 = k2;
+        }
+      }
+      continue;
+    }
     for (int k0 = kbeg + wave * BKS; k0 < kend; k0 += 4 * BKS) {
       // B: lane (n = lm, group lg) holds k = k0 + 4 lg + u, u = 0..3
       double bv[4];
@@ -291,8 +355,6 @@ __global__ __launch_bounds__(256) void k_gemm_skinny(const GemmDesc* __restrict_
   }
 }
 
-typedef double d2v __attribute__((ext_vector_type(2)));
-typedef __attribute__((address_space(1))) const d2v gd2v;
 
 // Order of the output tiles of a fast launch (128 x 128 tiles).  Workgroups
 // are dispatched to the eight XCDs in turn (workgroup w on XCD w mod 8), and
