@@ -193,6 +193,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
 
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) const d2v gd2v;
+typedef __attribute__((address_space(1))) const double gdbl;
 
 // Skinny products (N <= 16, FP64): the applications of Q^T / Q and the
 // back-substitution sums with a few right-hand sides.  These read each tile of
@@ -247,22 +248,26 @@ __global__ __launch_bounds__(256) void k_gemm_skinny(const GemmDesc* __restrict_
       // every load has a valid address (column min(lm, N - 1), the last block
       // again past the end), so each K block issues the same loads and the
       // wait before its products covers exactly the block before it
-      const int bcol = min(lm, N - 1);
+      // per-lane base addresses; a K block adds one uniform offset
+      const double* bl = Bp + (int64_t)min(lm, N - 1) * ldb + 4 * lg;
+      const double* al = TA ? Ap + (int64_t)(m0 + lm) * lda + 4 * lg : Ap + m0 + lm + (int64_t)(4 * lg) * lda;
+      const int64_t ai = TA ? 16 * lda : 16;      // next 16 rows of C
+      const int64_t ak = TA ? 1 : lda;            // next k
       auto ld = [&](int k0, double (&av)[BM / 16][4], double (&bv)[4]) {
-        const int kb = k0 + 4 * lg;
-        const d2v b0 = *(const gd2v*)(Bp + kb + (int64_t)bcol * ldb);
-        const d2v b1 = *(const gd2v*)(Bp + kb + 2 + (int64_t)bcol * ldb);
+        const double* bk = bl + k0;
+        const d2v b0 = *(const gd2v*)bk;
+        const d2v b1 = *(const gd2v*)(bk + 2);
         bv[0] = b0[0]; bv[1] = b0[1]; bv[2] = b1[0]; bv[3] = b1[1];
+        const double* ak0 = al + (int64_t)k0 * ak;
 #pragma unroll
         for (int i = 0; i < BM / 16; ++i) {
-          const int m = m0 + 16 * i + lm;
           if (TA) {
-            const d2v a0 = *(const gd2v*)(Ap + kb + (int64_t)m * lda);
-            const d2v a1 = *(const gd2v*)(Ap + kb + 2 + (int64_t)m * lda);
+            const d2v a0 = *(const gd2v*)(ak0 + i * ai);
+            const d2v a1 = *(const gd2v*)(ak0 + i * ai + 2);
             av[i][0] = a0[0]; av[i][1] = a0[1]; av[i][2] = a1[0]; av[i][3] = a1[1];
           } else {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) av[i][u] = Ap[m + (int64_t)(kb + u) * lda];
+            for (int u = 0; u < 4; ++u) av[i][u] = *(const gdbl*)(ak0 + i * ai + u * ak);
           }
         }
       };
