@@ -912,9 +912,26 @@ void plan_tiled(blr_matrix h, Plan& P, std::vector<Work>& works, int kend, bool 
 
 // B <- Q^T B (trans = 0) or Q B (trans = 1) for the tiled factor (Alg. 5,
 // update read as C <- (I - [I; Y] T [I; Y]^T) C).
-void plan_apply_tiled(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, int nrhs, int trans) {
+// Q^T B (trans 0) or Q B (trans 1) from the tiled factor's reflectors
+// (Alg. 5): step k applies the GEQRT reflector of (k,k) to B_k and the TPQRT
+// reflectors of (i,k), i > k, to [B_k; B_i].  Within step k every B_i, i > k,
+// is touched only by its own reflector, so the products with the reflector
+// rows, c_i = Ytilde_ik^T B_i, are taken for all i in one batched launch; the
+// chain through B_k is W_i = op(T_ik) (B_k + c_i), B_k -= W_i, one launch per
+// i (two K segments, B_k ping-ponged between two buffers because every
+// workgroup reads all of it); then B_i -= Ytilde_ik W_i for all i in one
+// launch.  The i are taken in groups whose c_i and W_i fit in `budget` bytes.
+void plan_apply_tiled(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, int nrhs, int trans, DevAlloc& al,
+                      size_t budget) {
   const int b = h->b, rc = h->rc, p = h->p, q = h->q;
   const int K = h->steps_done;
+  const size_t bn = (size_t)b * nrhs, rn = (size_t)rc * nrhs;
+  const int G = (int)std::max<size_t>(1, std::min<size_t>(std::max(p - 1, 1), budget / (2 * bn * 8)));
+  double* Cs = (double*)al.alloc((size_t)G * bn * 8);    // c_i
+  double* Ws = (double*)al.alloc((size_t)G * bn * 8);    // W_i
+  double* Xs = (double*)al.alloc((size_t)G * rn * 8);    // low-rank Ytilde: U^T B_i, then V^T W_i
+  double* Pb[2] = {(double*)al.alloc(bn * 8), (double*)al.alloc(bn * 8)};
+  const int tflag = (trans ? 0 : SEG_TRANS_A) | SEG_A_UPPER;
   auto diag = [&](int k) {
     Tile& Dkk = h->t(k, k);
     double* Tkk = h->T[(size_t)k * q + k];
@@ -922,49 +939,66 @@ void plan_apply_tiled(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, in
     P.gemm(w.Wx, b, nullptr, 0, nullptr, 0, b, nrhs, 1.0, 0.0, Dkk.D, b, Bk, ldb, b,
            SEG_TRANS_A | SEG_A_UNIT_LOWER);
     P.flush_gemm();
-    P.gemm(w.Wx2, b, nullptr, 0, nullptr, 0, b, nrhs, 1.0, 0.0, Tkk, b, w.Wx, b, b,
-           (trans ? 0 : SEG_TRANS_A) | SEG_A_UPPER);
+    P.gemm(w.Wx2, b, nullptr, 0, nullptr, 0, b, nrhs, 1.0, 0.0, Tkk, b, w.Wx, b, b, tflag);
     P.flush_gemm();
     P.gemm(Bk, ldb, Bk, ldb, nullptr, 0, b, nrhs, -1.0, 1.0, Dkk.D, b, w.Wx2, b, b, SEG_A_UNIT_LOWER);
     P.flush_gemm();
   };
-  auto pair = [&](int i, int k) {
-    Tile& Aik = h->t(i, k);
-    const size_t ik = (size_t)i * q + k;
-    const bool yd = h->yfmt[ik] == DENSE;
+  auto pairs = [&](int k) {
+    std::vector<int> order;
+    for (int i = k + 1; i < p; ++i) order.push_back(i);
+    if (trans) std::reverse(order.begin(), order.end());
     double* Bk = B + (int64_t)k * b;
-    double* Bi = B + (int64_t)i * b;
-    double* Xs = w.X[0];    // rc x nrhs scratch
-    if (yd) {
-      P.gemm(w.Wx, b, Bk, ldb, nullptr, 0, b, nrhs, 1.0, 1.0, Aik.D, b, Bi, ldb, b, SEG_TRANS_A);
+    for (size_t g0 = 0; g0 < order.size(); g0 += G) {
+      const int ng = (int)std::min<size_t>(G, order.size() - g0);
+      auto yd = [&](int x) { return h->yfmt[(size_t)order[g0 + x] * q + k] == DENSE; };
+      auto Bi = [&](int x) { return B + (int64_t)order[g0 + x] * b; };
+      auto Y = [&](int x) -> Tile& { return h->t(order[g0 + x], k); };
+      // c_i = Ytilde_ik^T B_i
+      for (int x = 0; x < ng; ++x)
+        if (!yd(x)) P.gemm(Xs + x * rn, rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, Y(x).U, b, Bi(x), ldb, b, SEG_TRANS_A);
       P.flush_gemm();
-    } else {
-      P.gemm(Xs, rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, Aik.U, b, Bi, ldb, b, SEG_TRANS_A);
+      for (int x = 0; x < ng; ++x) {
+        if (yd(x)) P.gemm(Cs + x * bn, b, nullptr, 0, nullptr, 0, b, nrhs, 1.0, 0.0, Y(x).D, b, Bi(x), ldb, b, SEG_TRANS_A);
+        else P.gemm(Cs + x * bn, b, nullptr, 0, nullptr, 0, b, nrhs, 1.0, 0.0, Y(x).Vt, rc, Xs + x * rn, rc, rc, SEG_TRANS_A);
+      }
       P.flush_gemm();
-      P.gemm(w.Wx, b, Bk, ldb, nullptr, 0, b, nrhs, 1.0, 1.0, Aik.Vt, rc, Xs, rc, rc, SEG_TRANS_A);
+      // the chain through B_k
+      const double* src = Bk;
+      int64_t lds = ldb;
+      for (int x = 0; x < ng; ++x) {
+        const size_t ik = (size_t)order[g0 + x] * q + k;
+        double* dst = Pb[x & 1];
+        GemmSeg s0{}, s1{};
+        s0.A = h->T[ik]; s0.lda = b; s0.B = src; s0.ldb = lds; s0.K = b; s0.flags = tflag;
+        s1.A = h->T[ik]; s1.lda = b; s1.B = Cs + x * bn; s1.ldb = b; s1.K = b; s1.flags = tflag;
+        P.gemm_multi(dst, b, src, lds, b, nrhs, -1.0, 1.0, {s0, s1});
+        P.cur.back().D2 = Ws + x * bn;
+        P.cur.back().ldd2 = b;
+        P.flush_gemm();
+        src = dst;
+        lds = b;
+      }
+      P.copy({CopyDesc{src, Bk, (int64_t)b, ldb, b, nrhs, 0, 0, 0}});
+      // B_i -= Ytilde_ik W_i
+      for (int x = 0; x < ng; ++x) {
+        if (yd(x)) P.gemm(Bi(x), ldb, Bi(x), ldb, nullptr, 0, b, nrhs, -1.0, 1.0, Y(x).D, b, Ws + x * bn, b, b, 0);
+        else P.gemm(Xs + x * rn, rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, Y(x).Vt, rc, Ws + x * bn, b, b, 0);
+      }
       P.flush_gemm();
-    }
-    P.gemm(Bk, ldb, Bk, ldb, w.Wx2, b, b, nrhs, -1.0, 1.0, h->T[ik], b, w.Wx, b, b,
-           (trans ? 0 : SEG_TRANS_A) | SEG_A_UPPER);
-    P.flush_gemm();
-    if (yd) {
-      P.gemm(Bi, ldb, Bi, ldb, nullptr, 0, b, nrhs, -1.0, 1.0, Aik.D, b, w.Wx2, b, b, 0);
-      P.flush_gemm();
-    } else {
-      P.gemm(Xs, rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, Aik.Vt, rc, w.Wx2, b, b, 0);
-      P.flush_gemm();
-      P.gemm(Bi, ldb, Bi, ldb, nullptr, 0, b, nrhs, -1.0, 1.0, Aik.U, b, Xs, rc, rc, 0);
+      for (int x = 0; x < ng; ++x)
+        if (!yd(x)) P.gemm(Bi(x), ldb, Bi(x), ldb, nullptr, 0, b, nrhs, -1.0, 1.0, Y(x).U, b, Xs + x * rn, rc, rc, 0);
       P.flush_gemm();
     }
   };
   if (!trans) {
     for (int k = 0; k < K; ++k) {
       diag(k);
-      for (int i = k + 1; i < p; ++i) pair(i, k);
+      pairs(k);
     }
   } else {
     for (int k = K - 1; k >= 0; --k) {
-      for (int i = p - 1; i > k; --i) pair(i, k);
+      pairs(k);
       diag(k);
     }
   }
@@ -2131,7 +2165,10 @@ void plan_apply(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, int nrhs
     double* Wpart = (double*)al.alloc((size_t)kApplySlices * h->b * std::max(nrhs, 1) * 8);
     plan_apply_blockcol(h, P, w, B, ldb, nrhs, trans, S, Wpart);
   } else {
-    plan_apply_tiled(h, P, w, B, ldb, nrhs, trans);
+    // without a caller's allocator the batched reflector products may take
+    // up to 256 MiB of the handle's workspace; the no-allocation entry keeps
+    // them within 16 MiB of its static scratch
+    plan_apply_tiled(h, P, w, B, ldb, nrhs, trans, al, a ? (16u << 20) : (256u << 20));
   }
 }
 
