@@ -309,9 +309,10 @@ blr_status blr_apply_qt(blr_matrix h, int32_t trans, double* B, int64_t ldb,
  * until the process ends).  A call whose matrix and nrhs need more returns
  * BLR_ERR_INVALID before enqueuing anything (the message states the bytes
  * needed); the need grows with nrhs (block column: about 64 b + p rc
- * doubles per right-hand side; tiled: about 2 (p - 1) b + p rc, the
- * batched reflector products capped at 16 MiB) plus the launch descriptors
- * (a few MiB at 128 x 64 tiles).  Every
+ * doubles per right-hand side; tiled: about 6 b + rc per right-hand side
+ * for each of up to 64 merged step chains, at most 16 MiB in all, at least
+ * one chain) plus the launch descriptors (a few MiB at 128 x 64 tiles).
+ * Every
  * call on one GPU shares the array: calls on the same stream are ordered,
  * calls that overlap on one GPU (other streams or threads) race. */
 #define BLR_NOALLOC_SCRATCH_BYTES (64LL * 1024 * 1024)

@@ -912,96 +912,115 @@ void plan_tiled(blr_matrix h, Plan& P, std::vector<Work>& works, int kend, bool 
 
 // B <- Q^T B (trans = 0) or Q B (trans = 1) for the tiled factor (Alg. 5,
 // update read as C <- (I - [I; Y] T [I; Y]^T) C).
+Plan merge_streams(const Plan& P, blr_matrix h);
+void merge_streams_into(const Plan& P, blr_matrix h, Plan& M);
+
 // Q^T B (trans 0) or Q B (trans 1) from the tiled factor's reflectors
-// (Alg. 5): step k applies the GEQRT reflector of (k,k) to B_k and the TPQRT
-// reflectors of (i,k), i > k, to [B_k; B_i].  Within step k every B_i, i > k,
-// is touched only by its own reflector, so the products with the reflector
-// rows, c_i = Ytilde_ik^T B_i, are taken for all i in one batched launch; the
-// chain through B_k is W_i = op(T_ik) (B_k + c_i), B_k -= W_i, one launch per
-// i (two K segments, B_k ping-ponged between two buffers because every
-// workgroup reads all of it); then B_i -= Ytilde_ik W_i for all i in one
-// launch.  The i are taken in groups whose c_i and W_i fit in `budget` bytes.
-void plan_apply_tiled(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, int nrhs, int trans, DevAlloc& al,
+// (Alg. 5).  Step k applies the GEQRT reflector of (k,k) to B_k and the
+// TPQRT reflectors of (i,k), i > k, to [B_k; B_i]: for each i, in factor
+// order for Q^T and reversed for Q, c_i = Ytilde_ik^T B_i, then
+// W_i = op(T_ik) (B_k + c_i) and B_k -= W_i in one two-segment launch (B_k
+// ping-ponged between two buffers, since every workgroup of the launch reads
+// all of it), then B_i -= Ytilde_ik W_i.  Every step is planned as a chain
+// of its own; before it touches row i it waits for the event the previous
+// step (k - 1 for Q^T, k + 1 for Q) recorded when it was done with that row,
+// so step k + 1 works on row i as soon as step k has updated it.  The chains
+// are merged into one launch list (each round advances every ready chain by
+// one op, batched by kernel and shape), as the tiled factor's are.  Chains
+// k and k + ns share a stream and a workspace; ns is chosen so that the
+// workspaces fit in `budget` bytes.
+void plan_apply_tiled(blr_matrix h, Plan& P, double* B, int64_t ldb, int nrhs, int trans, DevAlloc& al,
                       size_t budget) {
   const int b = h->b, rc = h->rc, p = h->p, q = h->q;
   const int K = h->steps_done;
+  if (K <= 0) return;
   const size_t bn = (size_t)b * nrhs, rn = (size_t)rc * nrhs;
-  const int G = (int)std::max<size_t>(1, std::min<size_t>(std::max(p - 1, 1), budget / (2 * bn * 8)));
-  double* Cs = (double*)al.alloc((size_t)G * bn * 8);    // c_i
-  double* Ws = (double*)al.alloc((size_t)G * bn * 8);    // W_i
-  double* Xs = (double*)al.alloc((size_t)G * rn * 8);    // low-rank Ytilde: U^T B_i, then V^T W_i
-  double* Pb[2] = {(double*)al.alloc(bn * 8), (double*)al.alloc(bn * 8)};
+  const size_t per = (6 * bn + rn) * 8;
+  const int ns = (int)std::max<size_t>(1, std::min<size_t>(std::min(K, 64), budget / per));
+  struct ChainWork { double *Wx, *Wx2, *C, *W, *X, *Pb[2]; };
+  std::vector<ChainWork> cw(ns);
+  for (auto& c : cw) {
+    c.Wx = (double*)al.alloc(bn * 8);
+    c.Wx2 = (double*)al.alloc(bn * 8);
+    c.C = (double*)al.alloc(bn * 8);
+    c.W = (double*)al.alloc(bn * 8);
+    c.X = (double*)al.alloc(rn * 8);
+    c.Pb[0] = (double*)al.alloc(bn * 8);
+    c.Pb[1] = (double*)al.alloc(bn * 8);
+  }
   const int tflag = (trans ? 0 : SEG_TRANS_A) | SEG_A_UPPER;
-  auto diag = [&](int k) {
+  auto ev = [&](int i, int k) { return i * q + k; };   // step k is done with row i
+  Plan L;
+  auto diag = [&](int k, ChainWork& c) {
     Tile& Dkk = h->t(k, k);
     double* Tkk = h->T[(size_t)k * q + k];
     double* Bk = B + (int64_t)k * b;
-    P.gemm(w.Wx, b, nullptr, 0, nullptr, 0, b, nrhs, 1.0, 0.0, Dkk.D, b, Bk, ldb, b,
-           SEG_TRANS_A | SEG_A_UNIT_LOWER);
-    P.flush_gemm();
-    P.gemm(w.Wx2, b, nullptr, 0, nullptr, 0, b, nrhs, 1.0, 0.0, Tkk, b, w.Wx, b, b, tflag);
-    P.flush_gemm();
-    P.gemm(Bk, ldb, Bk, ldb, nullptr, 0, b, nrhs, -1.0, 1.0, Dkk.D, b, w.Wx2, b, b, SEG_A_UNIT_LOWER);
-    P.flush_gemm();
+    L.gemm(c.Wx, b, nullptr, 0, nullptr, 0, b, nrhs, 1.0, 0.0, Dkk.D, b, Bk, ldb, b, SEG_TRANS_A | SEG_A_UNIT_LOWER);
+    L.flush_gemm();
+    L.gemm(c.Wx2, b, nullptr, 0, nullptr, 0, b, nrhs, 1.0, 0.0, Tkk, b, c.Wx, b, b, tflag);
+    L.flush_gemm();
+    L.gemm(Bk, ldb, Bk, ldb, nullptr, 0, b, nrhs, -1.0, 1.0, Dkk.D, b, c.Wx2, b, b, SEG_A_UNIT_LOWER);
+    L.flush_gemm();
   };
-  auto pairs = [&](int k) {
-    std::vector<int> order;
-    for (int i = k + 1; i < p; ++i) order.push_back(i);
-    if (trans) std::reverse(order.begin(), order.end());
+  for (int t = 0; t < K; ++t) {
+    const int k = trans ? K - 1 - t : t;
+    const int prev = trans ? k + 1 : k - 1;
+    const bool has_prev = t > 0;
+    L.cur_stream = t % ns;
+    L.cur_prio = t;
+    ChainWork& c = cw[t % ns];
     double* Bk = B + (int64_t)k * b;
-    for (size_t g0 = 0; g0 < order.size(); g0 += G) {
-      const int ng = (int)std::min<size_t>(G, order.size() - g0);
-      auto yd = [&](int x) { return h->yfmt[(size_t)order[g0 + x] * q + k] == DENSE; };
-      auto Bi = [&](int x) { return B + (int64_t)order[g0 + x] * b; };
-      auto Y = [&](int x) -> Tile& { return h->t(order[g0 + x], k); };
+    if (!trans) {
+      if (has_prev) L.wait(ev(k, prev));
+      diag(k, c);
+    }
+    const double* src = Bk;
+    int64_t lds = ldb;
+    int x = 0;
+    for (int r = 0; r < p - 1 - k; ++r) {
+      const int i = trans ? p - 1 - r : k + 1 + r;
+      if (has_prev) L.wait(ev(i, prev));
+      const size_t ik = (size_t)i * q + k;
+      const bool yd = h->yfmt[ik] == DENSE;
+      Tile& Y = h->t(i, k);
+      double* Bi = B + (int64_t)i * b;
       // c_i = Ytilde_ik^T B_i
-      for (int x = 0; x < ng; ++x)
-        if (!yd(x)) P.gemm(Xs + x * rn, rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, Y(x).U, b, Bi(x), ldb, b, SEG_TRANS_A);
-      P.flush_gemm();
-      for (int x = 0; x < ng; ++x) {
-        if (yd(x)) P.gemm(Cs + x * bn, b, nullptr, 0, nullptr, 0, b, nrhs, 1.0, 0.0, Y(x).D, b, Bi(x), ldb, b, SEG_TRANS_A);
-        else P.gemm(Cs + x * bn, b, nullptr, 0, nullptr, 0, b, nrhs, 1.0, 0.0, Y(x).Vt, rc, Xs + x * rn, rc, rc, SEG_TRANS_A);
+      if (yd) {
+        L.gemm(c.C, b, nullptr, 0, nullptr, 0, b, nrhs, 1.0, 0.0, Y.D, b, Bi, ldb, b, SEG_TRANS_A);
+      } else {
+        L.gemm(c.X, rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, Y.U, b, Bi, ldb, b, SEG_TRANS_A);
+        L.flush_gemm();
+        L.gemm(c.C, b, nullptr, 0, nullptr, 0, b, nrhs, 1.0, 0.0, Y.Vt, rc, c.X, rc, rc, SEG_TRANS_A);
       }
-      P.flush_gemm();
-      // the chain through B_k
-      const double* src = Bk;
-      int64_t lds = ldb;
-      for (int x = 0; x < ng; ++x) {
-        const size_t ik = (size_t)order[g0 + x] * q + k;
-        double* dst = Pb[x & 1];
-        GemmSeg s0{}, s1{};
-        s0.A = h->T[ik]; s0.lda = b; s0.B = src; s0.ldb = lds; s0.K = b; s0.flags = tflag;
-        s1.A = h->T[ik]; s1.lda = b; s1.B = Cs + x * bn; s1.ldb = b; s1.K = b; s1.flags = tflag;
-        P.gemm_multi(dst, b, src, lds, b, nrhs, -1.0, 1.0, {s0, s1});
-        P.cur.back().D2 = Ws + x * bn;
-        P.cur.back().ldd2 = b;
-        P.flush_gemm();
-        src = dst;
-        lds = b;
-      }
-      P.copy({CopyDesc{src, Bk, (int64_t)b, ldb, b, nrhs, 0, 0, 0}});
+      L.flush_gemm();
+      // W_i = op(T_ik) (B_k + c_i); B_k -= W_i
+      double* dst = c.Pb[x & 1];
+      GemmSeg s0{}, s1{};
+      s0.A = h->T[ik]; s0.lda = b; s0.B = src; s0.ldb = lds; s0.K = b; s0.flags = tflag;
+      s1.A = h->T[ik]; s1.lda = b; s1.B = c.C; s1.ldb = b; s1.K = b; s1.flags = tflag;
+      L.gemm_multi(dst, b, src, lds, b, nrhs, -1.0, 1.0, {s0, s1});
+      L.cur.back().D2 = c.W;
+      L.cur.back().ldd2 = b;
+      L.flush_gemm();
+      src = dst;
+      lds = b;
+      ++x;
       // B_i -= Ytilde_ik W_i
-      for (int x = 0; x < ng; ++x) {
-        if (yd(x)) P.gemm(Bi(x), ldb, Bi(x), ldb, nullptr, 0, b, nrhs, -1.0, 1.0, Y(x).D, b, Ws + x * bn, b, b, 0);
-        else P.gemm(Xs + x * rn, rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, Y(x).Vt, rc, Ws + x * bn, b, b, 0);
+      if (yd) {
+        L.gemm(Bi, ldb, Bi, ldb, nullptr, 0, b, nrhs, -1.0, 1.0, Y.D, b, c.W, b, b, 0);
+      } else {
+        L.gemm(c.X, rc, nullptr, 0, nullptr, 0, rc, nrhs, 1.0, 0.0, Y.Vt, rc, c.W, b, b, 0);
+        L.flush_gemm();
+        L.gemm(Bi, ldb, Bi, ldb, nullptr, 0, b, nrhs, -1.0, 1.0, Y.U, b, c.X, rc, rc, 0);
       }
-      P.flush_gemm();
-      for (int x = 0; x < ng; ++x)
-        if (!yd(x)) P.gemm(Bi(x), ldb, Bi(x), ldb, nullptr, 0, b, nrhs, -1.0, 1.0, Y(x).U, b, Xs + x * rn, rc, rc, 0);
-      P.flush_gemm();
+      L.flush_gemm();
+      L.record(ev(i, k));
     }
-  };
-  if (!trans) {
-    for (int k = 0; k < K; ++k) {
-      diag(k);
-      pairs(k);
-    }
-  } else {
-    for (int k = K - 1; k >= 0; --k) {
-      pairs(k);
-      diag(k);
-    }
+    if (x > 0) L.copy({CopyDesc{src, Bk, (int64_t)b, ldb, b, nrhs, 0, 0, 0}});
+    if (trans) diag(k, c);
+    L.record(ev(k, k));
   }
+  merge_streams_into(L, h, P);
 }
 
 
@@ -1947,6 +1966,14 @@ Plan merge_plans(const std::vector<Plan>& plans, const std::vector<blr_matrix>& 
 // first.  Rounds run in order on one stream, so every dependency of the plan
 // holds, and every job is computed exactly as by its own launch.
 Plan merge_streams(const Plan& P, blr_matrix h) {
+  Plan M;
+  merge_streams_into(P, h, M);
+  return M;
+}
+
+// merge_streams appending the merged ops to M (whose own ops come first).
+void merge_streams_into(const Plan& P, blr_matrix h, Plan& M) {
+  if (!M.cur.empty()) throw Error(BLR_ERR_DEVICE, "internal: merge into a plan with an unflushed product");
   int ns = 1;
   for (const Op& o : P.ops) ns = std::max(ns, o.stream + 1);
   std::vector<std::vector<int>> chain(ns);
@@ -1958,7 +1985,6 @@ Plan merge_streams(const Plan& P, blr_matrix h) {
   std::vector<char> rec(std::max(P.n_events, 1), 0);
   const std::vector<const Plan*> pp{&P};
   const std::vector<blr_matrix> hv{h};
-  Plan M;
   std::vector<std::pair<int, int>> src;
   std::vector<int> ready;
   for (;;) {
@@ -2011,7 +2037,6 @@ Plan merge_streams(const Plan& P, blr_matrix h) {
     }
     for (int c : ready) ++head[c];
   }
-  return M;
 }
 
 // Run the one-stream plans of independent matrices as a batch.  The members
@@ -2165,10 +2190,10 @@ void plan_apply(blr_matrix h, Plan& P, Work& w, double* B, int64_t ldb, int nrhs
     double* Wpart = (double*)al.alloc((size_t)kApplySlices * h->b * std::max(nrhs, 1) * 8);
     plan_apply_blockcol(h, P, w, B, ldb, nrhs, trans, S, Wpart);
   } else {
-    // without a caller's allocator the batched reflector products may take
-    // up to 256 MiB of the handle's workspace; the no-allocation entry keeps
-    // them within 16 MiB of its static scratch
-    plan_apply_tiled(h, P, w, B, ldb, nrhs, trans, al, a ? (16u << 20) : (256u << 20));
+    // without a caller's allocator the chains' workspaces may take up to
+    // 256 MiB of the handle's workspace; the no-allocation entry keeps them
+    // within 16 MiB of its static scratch
+    plan_apply_tiled(h, P, B, ldb, nrhs, trans, al, a ? (16u << 20) : (256u << 20));
   }
 }
 

@@ -70,23 +70,21 @@ def test_noalloc_apply_refuses_more_than_the_scratch(P):
     assert torch.equal(G.apply_qt_noalloc(Bs), G.apply_qt(Bs))
 
 
-def test_noalloc_tiled_apply_in_groups_matches_apply_qt(P):
-    """The tiled form takes its batched reflector-row products for at most
-    16 MiB of c_i and W_i at a time in the no-allocation call (256 MiB
-    otherwise): at 4096 rows, b = 128 and 1024 right-hand sides (2 MiB per
-    tile) the 31 TPQRT reflectors of the first step go in four groups of at
-    most 8 there and in one group in blr_apply_qt.  A smaller batch may take
-    a different product kernel (64- instead of 128-row tiles), so the two
-    agree to rounding (Q is orthogonal: each entry's error is a few units of
-    2^-52 times max |B| per reflector), and Q (Q^T B) returns B."""
-    print("case: no-alloc tiled apply in groups", flush=True)
+def test_noalloc_tiled_apply_with_fewer_chains_matches_apply_qt(P):
+    """The tiled form plans every step of the application as a chain of its
+    own and merges the chains into one launch list; chains k and k + ns share
+    a workspace.  At 4096 rows, b = 128 and 1024 right-hand sides a chain's
+    workspace is about 6.5 MiB, so the no-allocation call (16 MiB for them)
+    runs 2 chains and blr_apply_qt all 8.  Every op keeps the kernel chosen
+    for it before the merge, so the results are equal bit for bit, and
+    Q (Q^T B) returns B."""
+    print("case: no-alloc tiled apply with fewer chains", flush=True)
     G = factored(P, "tiled", 44, 4096, 1024, 128)
     B = torch.tensor(synth.rhs(44, 4096, 1024), device="cuda")
-    tol = 1e-11 * float(B.abs().max())
     for trans in (False, True):
         ref = G.apply_qt(B, trans=trans)
         out = G.apply_qt_noalloc(B, trans=trans)
         torch.cuda.synchronize()
-        assert float((out - ref).abs().max()) <= tol, trans
+        assert torch.equal(out, ref), trans
     back = G.apply_qt(G.apply_qt(B), trans=True)
-    assert float((back - B).abs().max()) <= tol
+    assert float((back - B).abs().max()) <= 1e-11 * float(B.abs().max())
