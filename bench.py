@@ -61,8 +61,8 @@ HBM_PEAK_TBS = 8.0                                # MI355X HBM3E bandwidth, TB/s
 # the counters were taken on (sha256 of csrc/gemm.hip); otherwise null.
 TRAFFIC = {
     ("c3", "fp64", "block_column"): {
-        "gemm_sha256": "ae5de4b4e24c3fdd2128dd283bddfd16717c3887726933f375c791c591f4ecd5",
-        "bytes_per_launch": 21913494436,
+        "gemm_sha256": "3f4373a2f9485e0571df44419252c73c34ece5d4a830b57dd9e233db0528d6a7",
+        "bytes_per_launch": 15870986701,
     },
 }
 

@@ -568,6 +568,47 @@ __device__ __forceinline__ void gemm_fast_body(const GemmDesc* __restrict__ desc
     if (ACC64 && nsteps % kFlushSteps != 0) flush();
   }
 
+  // FP64 epilogue through LDS (the A tile buffers, free after the last K
+  // step): in four passes of 16 rows of every wave's 64-row half, the
+  // accumulators go to a column-major 128 x 32 staging tile, and each thread
+  // then moves two consecutive rows of one column, so C, Cin and D2 are read
+  // and written as 16-byte vectors, 256 contiguous bytes per 16 lanes,
+  // instead of 8 bytes per lane spread over 16 columns.
+  if constexpr (sizeof(CT) == 8 && !ACC64) {
+    const bool al16 = ((((uintptr_t)d.C) | ((uintptr_t)d.Cin) | ((uintptr_t)d.D2)) & 15) == 0 &&
+                      ((d.ldc | d.ldcin | d.ldd2) & 1) == 0;
+    if (al16) {
+      constexpr int LDW = 34;                   // staging column stride (doubles)
+      static_assert(BN * LDW <= 2 * BK * (BM + PAD), "staging tile exceeds the A buffers");
+      double* cs = &As[0][0][0];
+      const int rr = (tid & 15) * 2;            // staging row pair: 0-15 from wm = 0, 16-31 from wm = 1
+      const int grow = rr < 16 ? rr : 64 + rr - 16;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        __syncthreads();   // the last K step's reads of As (or the previous pass's reads of cs) are done
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            cs[(wn * 64 + j * 16 + (lane & 15)) * LDW + wm * 16 + 4 * v + (lane >> 4)] = acc[i][j][v];
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < BN / 16; ++it) {
+          const int c = it * 16 + (tid >> 4);
+          const d2v raw = *(const d2v*)(cs + c * LDW + rr);
+          const int row = m0 + grow + i * 16;
+          const int col = n0 + c;
+          if (d.C) {
+            d2v cv = raw * d.alpha;
+            if (d.Cin) cv += *(const gd2v*)(d.Cin + row + (int64_t)col * d.ldcin) * d.beta;
+            *(d2v*)(d.C + row + (int64_t)col * d.ldc) = cv;
+          }
+          if (d.D2) *(d2v*)(d.D2 + row + (int64_t)col * d.ldd2) = raw;
+        }
+      }
+      return;
+    }
+  }
   constexpr bool f64out = sizeof(CT) == 8;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
