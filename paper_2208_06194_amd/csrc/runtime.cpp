@@ -1481,6 +1481,16 @@ void plan_bc_update(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k, int j0, i
   }
   P.flush_gemm();
   std::vector<CopyDesc> zred;
+#ifndef BLR_MIXED_ZCHUNK
+#define BLR_MIXED_ZCHUNK 8
+#endif
+  // the mixed form's long Z_j sums (FP32 products, FP64 accumulation) go in
+  // launches of at most BLR_MIXED_ZCHUNK tile rows, each adding into the
+  // previous one's FP64 result: their workgroups, which hold every register
+  // of a SIMD, then retire often enough for the look-ahead panel's kernels
+  // to find free slots
+  std::vector<std::vector<GemmSeg>> zlong;
+  std::vector<int> zlong_j;
   for (int j = j0; j < j1; ++j) {
     if (!zd[j]) continue;
     std::vector<GemmSeg> sv;
@@ -1496,6 +1506,11 @@ void plan_bc_update(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k, int j0, i
     // finishes in a fraction of one long K sweep
     const int ng = (j1 - j0 == 1) ? std::min<int>((int)sv.size(), kZSlices - 1) : 1;
     if (ng <= 1) {
+      if (fp32 && BLR_MIXED_ZCHUNK > 0 && (int)sv.size() > BLR_MIXED_ZCHUNK) {
+        zlong.push_back(sv);
+        zlong_j.push_back(j);
+        continue;
+      }
       P.gemm_multi(w.X[j], b, zlr[j] ? w.X[j] : nullptr, b, b, b, 1.0, zlr[j] ? 1.0 : 0.0, sv);
       continue;
     }
@@ -1512,6 +1527,22 @@ void plan_bc_update(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k, int j0, i
     zred.push_back(CopyDesc{bw.zpart, w.X[j], (int64_t)b, (int64_t)b, b, b, 0, nd, (int64_t)b * b});
   }
   P.flush_gemm(fp32, 1);
+  if (!zlong.empty()) {
+    const int S = BLR_MIXED_ZCHUNK;
+    size_t smax = 0;
+    for (auto& v : zlong) smax = std::max(smax, v.size());
+    for (size_t c0 = 0; c0 < smax; c0 += S) {
+      for (size_t x = 0; x < zlong.size(); ++x) {
+        const auto& v = zlong[x];
+        if (c0 >= v.size()) continue;
+        const int j = zlong_j[x];
+        std::vector<GemmSeg> part(v.begin() + c0, v.begin() + std::min(v.size(), c0 + S));
+        const bool acc = c0 > 0 || zlr[j];
+        P.gemm_multi(w.X[j], b, acc ? w.X[j] : nullptr, b, b, b, 1.0, acc ? 1.0 : 0.0, part);
+      }
+      P.flush_gemm(fp32, 1);
+    }
+  }
   if (!zred.empty()) P.copy(zred);
   // 4c. low-rank Z_j: rounded additions of two terms at a time in a pairwise
   // tree whose leaves are the terms in order i = k, k+1, ...: at stride
