@@ -1488,7 +1488,8 @@ void plan_bc_update(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k, int j0, i
   // launches of at most BLR_MIXED_ZCHUNK tile rows, each adding into the
   // previous one's FP64 result: their workgroups, which hold every register
   // of a SIMD, then retire often enough for the look-ahead panel's kernels
-  // to find free slots
+  // to find free slots (the FP64 products, whose update stream is the
+  // critical path, lose more to the extra launches than the panel gains)
   std::vector<std::vector<GemmSeg>> zlong;
   std::vector<int> zlong_j;
   for (int j = j0; j < j1; ++j) {
@@ -1506,7 +1507,7 @@ void plan_bc_update(blr_matrix h, Plan& P, Work& w, BcWork& bw, int k, int j0, i
     // finishes in a fraction of one long K sweep
     const int ng = (j1 - j0 == 1) ? std::min<int>((int)sv.size(), kZSlices - 1) : 1;
     if (ng <= 1) {
-      if (fp32 && BLR_MIXED_ZCHUNK > 0 && (int)sv.size() > BLR_MIXED_ZCHUNK) {
+      if (fp32 && (int)sv.size() > BLR_MIXED_ZCHUNK) {
         zlong.push_back(sv);
         zlong_j.push_back(j);
         continue;
