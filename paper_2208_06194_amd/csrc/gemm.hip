@@ -609,6 +609,50 @@ __device__ __forceinline__ void gemm_fast_body(const GemmDesc* __restrict__ desc
       return;
     }
   }
+  // FP32 operands, FP64 output: the same staging in the (FP32) A buffers,
+  // which hold a 128 x 16 FP64 tile: eight passes of 8 rows of every wave's
+  // half; the FP32 accumulator layout puts rows 4 g + v (g = lane / 16) in
+  // lane group g, so a pass takes two of the four lane groups.
+  if constexpr (sizeof(CT) == 4 && !ACC64) {
+    const bool al16 = ((((uintptr_t)d.C) | ((uintptr_t)d.Cin) | ((uintptr_t)d.D2)) & 15) == 0 &&
+                      ((d.ldc | d.ldcin | d.ldd2) & 1) == 0;
+    if (al16) {
+      constexpr int LDW = 18;
+      static_assert(BN * LDW * 8 <= 2 * BK * (BM + PAD) * (int)sizeof(CT), "staging tile exceeds the A buffers");
+      double* cs = (double*)&As[0][0][0];
+      const int rr = (tid & 7) * 2;             // staging row pair: 0-7 from wm = 0, 8-15 from wm = 1
+      const int grow = (rr < 8 ? rr : 64 + rr - 8);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          __syncthreads();
+          if ((lane >> 5) == hh) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+              for (int v = 0; v < 4; ++v)
+                cs[(wn * 64 + j * 16 + (lane & 15)) * LDW + wm * 8 + ((lane >> 4) & 1) * 4 + v] = (double)acc[i][j][v];
+          }
+          __syncthreads();
+#pragma unroll
+          for (int it = 0; it < BN / 32; ++it) {
+            const int c = it * 32 + (tid >> 3);
+            const d2v raw = *(const d2v*)(cs + c * LDW + rr);
+            const int row = m0 + grow + i * 16 + hh * 8;
+            const int col = n0 + c;
+            if (d.C) {
+              d2v cv = raw * d.alpha;
+              if (d.Cin) cv += *(const gd2v*)(d.Cin + row + (int64_t)col * d.ldcin) * d.beta;
+              *(d2v*)(d.C + row + (int64_t)col * d.ldc) = cv;
+            }
+            if (d.D2) *(d2v*)(d.D2 + row + (int64_t)col * d.ldd2) = raw;
+          }
+        }
+      }
+      return;
+    }
+  }
   constexpr bool f64out = sizeof(CT) == 8;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -634,7 +678,7 @@ __device__ __forceinline__ void gemm_fast_body(const GemmDesc* __restrict__ desc
 #define BLR_F64_WAVES 2
 #endif
 template <typename CT, bool TA, bool TB>
-__global__ __launch_bounds__(256, sizeof(CT) == 8 ? BLR_F64_WAVES : 1) void k_gemm_fast(
+__global__ __launch_bounds__(256, sizeof(CT) == 8 ? BLR_F64_WAVES : 3) void k_gemm_fast(
     const GemmDesc* __restrict__ descs, int ndesc, const GemmSeg* __restrict__ segs) {
   gemm_fast_body<CT, TA, TB, false, sizeof(CT) == 8 ? kFastKStep64 : kFastKStep32>(descs, ndesc, segs);
 }
